@@ -1,0 +1,205 @@
+/*
+ * bsrht.h - C ABI of the MI355X (gfx950) block SRHT library.
+ *
+ * Operation (Balabanov, Beaupere, Grigori, Lederer, "Block subsampled
+ * randomized Hadamard transform for low-rank approximation on distributed
+ * architectures", section 2, eq. (2.3)-(2.4)):
+ *
+ *   Omega = [Omega^(1) ... Omega^(p)],  Omega^(i) = sqrt(r/l) Dt^(i) R H D^(i),
+ *   r = n/p,  H = Walsh-Hadamard matrix of order r scaled by 1/sqrt(r),
+ *   D^(i) (r x r) and Dt^(i) (l x l) diagonal Rademacher signs, independent
+ *   for every block, R an l x r uniform row sample shared by all blocks
+ *   (with replacement by default), and
+ *
+ *   Y = Omega A = sum_i Omega^(i) A^(i)   for a tall n x m matrix A.
+ *
+ * Entry by entry, with H_r[y,x] = (-1)^popcount(y & x) (Kronecker power of
+ * [[1,1],[1,-1]], natural order), Omega[j, i*r+x] =
+ * Dt^(i)_j (-1)^popcount(R_j & x) D^(i)_x / sqrt(l).
+ *
+ * Conventions shared by every call
+ *   - Matrices are row-major.  A leading dimension is the distance, in
+ *     elements, between the starts of consecutive rows (>= the row length).
+ *   - Every pointer named "device" is HIP device memory owned by the caller;
+ *     the library never frees it.  The library allocates no device memory in
+ *     bsrht_apply, rsvd or nystrom: all scratch comes from the caller's
+ *     workspace, sized by the matching *_workspace query.
+ *   - "stream" is a hipStream_t (NULL = the legacy default stream).  Work is
+ *     enqueued on it and the call returns without waiting, except where a
+ *     call says it synchronises.
+ *   - Argument errors are detected before anything is enqueued and returned
+ *     as a negative status; nothing is written in that case.  Numerical
+ *     events are reported through the int32 `info` word (device memory),
+ *     readable once the stream has completed.  No C++ exception crosses
+ *     this interface.
+ *   - A plan is immutable once built; several streams may apply the same
+ *     plan concurrently, each with its own workspace and outputs.
+ */
+#ifndef BSRHT_H
+#define BSRHT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define BSRHT_OK 0
+#define BSRHT_EINVAL (-1)       /* invalid argument (shape, pointer, mode) */
+#define BSRHT_ENOMEM (-2)       /* caller-provided buffer too small        */
+#define BSRHT_EDEVICE (-3)      /* a HIP call failed                        */
+#define BSRHT_EUNSUPPORTED (-4) /* valid but not supported by this build    */
+
+/* Sampling mode of R (section 2: the block SRHT samples with replacement;
+ * the SRHT of eq. (2.1) allows either). */
+#define BSRHT_WITH_REPLACEMENT 0
+#define BSRHT_WITHOUT_REPLACEMENT 1
+
+/* Arithmetic of the transform.  FP32: radix-2 butterflies in FP32.
+ * SPLIT_BF16: Hadamard tiles on BF16 matrix cores with A split into a BF16
+ * high and low part and FP32 accumulation. */
+#define BSRHT_FP32 0
+#define BSRHT_SPLIT_BF16 1
+
+/* info word bits written by rsvd / nystrom. */
+#define BSRHT_INFO_CHOL_FALLBACK 1 /* Remark 3.1 square-root fallback taken   */
+#define BSRHT_INFO_RANK_CLAMPED 2  /* k reduced to the available rank          */
+#define BSRHT_INFO_QB_FALLBACK 4   /* range basis built from an eigen split    */
+#define BSRHT_INFO_JACOBI_NOCONV 8 /* Jacobi SVD stopped at its sweep limit    */
+
+typedef struct bsrht_plan_s *bsrht_plan_t;
+
+/* Library version string (static storage). */
+const char *bsrht_version(void);
+
+/* Text for a status code (static storage). */
+const char *bsrht_strerror(int status);
+
+/*
+ * Device bytes needed for the random tables of a plan with these sizes
+ * (R: l int32; D: n bits; Dt: p*l bits, each region 256-byte aligned).
+ * Returns 0 if the sizes are invalid (see bsrht_plan).
+ */
+size_t bsrht_plan_bytes(int64_t n, int64_t p, int64_t l);
+
+/*
+ * Build the tables of Omega (eq. (2.3)) from (seed, sampling) with the
+ * library's counter-based generator (Philox4x64-10, SC'11):
+ *   key = (seed, 0); one call gives 256 bits, bit b in word b/64, bit b%64;
+ *   D^(i)_x  = bit (x%256) of philox((x/256, i, 2, 0)), bit 1 -> -1;
+ *   Dt^(i)_j = bit (j%256) of philox((j/256, i, 3, 0)), bit 1 -> -1;
+ *   R_j (with replacement)    = word0(philox((j, 0, 1, 0))) mod r;
+ *   R_j (without replacement) = partial Fisher-Yates over [0, r) with
+ *       t = j + floor(word0(philox((j,0,1,0))) * (r - j) / 2^64).
+ *
+ * n, p, l     : Omega is l x n with p blocks of r = n/p columns.  Requires
+ *               p >= 1, p | n, r a power of two, 1 <= l <= n, and l <= r
+ *               for sampling without replacement.  n < 2^31.
+ * seed        : 64-bit seed.
+ * sampling    : BSRHT_WITH_REPLACEMENT or BSRHT_WITHOUT_REPLACEMENT.
+ * precision   : BSRHT_FP32 or BSRHT_SPLIT_BF16 (used by bsrht_apply).
+ * dev_mem     : device buffer of >= bsrht_plan_bytes(n,p,l) bytes, owned by
+ *               the caller and kept alive for the plan's lifetime.
+ * stream      : the tables are written on this stream; later calls on other
+ *               streams must be ordered after it by the caller.  Sampling
+ *               without replacement synchronises the stream once.
+ * out         : receives the host-side plan handle.
+ * Returns BSRHT_OK, BSRHT_EINVAL, BSRHT_ENOMEM (dev_bytes too small) or
+ * BSRHT_EDEVICE.
+ */
+int bsrht_plan(int64_t n, int64_t p, int64_t l, uint64_t seed, int sampling,
+               int precision, void *dev_mem, size_t dev_bytes, void *stream,
+               bsrht_plan_t *out);
+
+/* Free the host handle (not the caller's table memory). NULL is accepted. */
+int bsrht_plan_destroy(bsrht_plan_t plan);
+
+/* Sizes and mode recorded in a plan.  Any output pointer may be NULL. */
+int bsrht_plan_info(bsrht_plan_t plan, int64_t *n, int64_t *p, int64_t *l,
+                    int *sampling, int *precision);
+
+/*
+ * Copy the plan's tables to host memory (synchronises the plan's stream).
+ * R     : host int32[l]            sample indices in [0, r), draw order.
+ * Dbits : host uint32[ceil(n/32)]  bit (g%32) of word g/32 is the sign bit of
+ *                                  D for global row g = i*r + x (1 -> -1).
+ * Dtbits: host uint32[p*ceil(l/32)] bit (j%32) of word i*ceil(l/32) + j/32
+ *                                  is the sign bit of Dt^(i)_j.
+ * Any pointer may be NULL to skip that table.
+ */
+int bsrht_plan_export(bsrht_plan_t plan, int32_t *R, uint32_t *Dbits,
+                      uint32_t *Dtbits);
+
+/* Workspace bytes bsrht_apply needs for an n x m input (0 is possible). */
+size_t bsrht_apply_workspace(bsrht_plan_t plan, int64_t m);
+
+/*
+ * Y = Omega A  (eq. (2.4)): every block's signs, Walsh-Hadamard transform,
+ * row sample and output signs, summed over the p blocks on the device.  A
+ * is read once from HBM; no block's full transform is stored.  The sum over
+ * blocks is taken in a fixed order, so results are bitwise repeatable.
+ *
+ * A   : device float32, n x m, leading dimension lda >= m.
+ * m   : number of columns, m >= 0 (m == 0 is a no-op).
+ * Y   : device float32, l x m, leading dimension ldy >= m; must not overlap A.
+ * ws  : device workspace of ws_bytes >= bsrht_apply_workspace(plan, m)
+ *       (may be NULL when that is 0).
+ */
+int bsrht_apply(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda,
+                float *Y, int64_t ldy, void *ws, size_t ws_bytes, void *stream);
+
+/* Workspace bytes rsvd needs for an n x m input and target rank k. */
+size_t rsvd_workspace(bsrht_plan_t plan, int64_t m, int64_t k);
+
+/*
+ * Randomized SVD (section 3.1, Algorithm 1) of the tall n x m matrix A,
+ * sketched on its n side by the plan's Omega (Algorithm 1 run on A^T):
+ *   W = Omega A; Q = orth(W^T) (m x l', l' = min(l, m); FP64 Cholesky-QR2,
+ *   Q = I when l >= m); Z = A Q (matrix cores); Z = P Rz (FP64 Gram +
+ *   Cholesky); Rz = Ut St Vt^T (FP64 one-sided Jacobi);
+ *   U = P Ut_k = Z Vt_k St_k^{-1}, S = St_k, V = Q Vt_k,  A ~= U diag(S) V^T.
+ *
+ * A    : device float32 n x m, lda >= m.        k: 1 <= k.
+ * U    : device float32 n x k (row-major, leading dimension k).
+ * S    : device float64 k, descending.
+ * V    : device float32 m x k (row-major, leading dimension k).
+ * info : device int32; BSRHT_INFO_* bits.  When the available rank k' is
+ *        below k, columns k'..k-1 of U, V and entries of S are zero and
+ *        BSRHT_INFO_RANK_CLAMPED is set.
+ * ws   : device workspace of >= rsvd_workspace(plan, m, k) bytes.
+ */
+int rsvd(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, int64_t k,
+         float *U, double *S, float *V, int32_t *info, void *ws,
+         size_t ws_bytes, void *stream);
+
+/* Workspace bytes nystrom needs for target rank k (A is n x n). */
+size_t nystrom_workspace(bsrht_plan_t plan, int64_t k);
+
+/*
+ * Nystrom approximation (section 3.2, Algorithm 2) of a symmetric positive
+ * semi-definite n x n matrix A:
+ *   Y = A Omega^T (= (Omega A)^T); B = Omega Y, symmetrised; B = C^T C (FP64
+ *   Cholesky, C upper); Z = Y C^{-1}; Z = Q~ R (FP64 Gram + Cholesky);
+ *   R = Ut St Vt^T (FP64 one-sided Jacobi); U = Z Vt_k St_k^{-1} (= Q~ Ut_k);
+ *   lambda = St_k^2;  A ~= U diag(lambda) U^T.
+ * Remark 3.1: when a Cholesky pivot of B is <= l * 2^-24 * max(diag(B)),
+ * B = V Lam V^T is used instead, keeping Lam_i > l * 2^-24 * Lam_max and
+ * Z = Y V_+ Lam_+^{-1/2}; BSRHT_INFO_CHOL_FALLBACK is set.
+ *
+ * A      : device float32 n x n, lda >= n (only read through Omega).
+ * U      : device float32 n x k (leading dimension k).
+ * lambda : device float64 k, descending.
+ * info   : device int32, BSRHT_INFO_* bits (as in rsvd).
+ * ws     : device workspace of >= nystrom_workspace(plan, k) bytes.
+ */
+int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k,
+            float *U, double *lambda, int32_t *info, void *ws,
+            size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSRHT_H */
