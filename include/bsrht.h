@@ -198,6 +198,21 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k,
             float *U, double *lambda, int32_t *info, void *ws,
             size_t ws_bytes, void *stream);
 
+/*
+ * Instrumentation (not part of the computation).  bsrht_timing_enable(which)
+ * makes the library record a pair of HIP events on the launching stream
+ * around every launch of the selected kernel, until called again with 0;
+ * bsrht_timing_read waits for the recorded events and returns the summed
+ * kernel time in milliseconds and the number of launches since the enable.
+ * Process-wide state, not thread-safe; for benchmarks.
+ */
+#define BSRHT_TIMING_OFF 0
+#define BSRHT_TIMING_APPLY_FP32 1 /* the fused FP32 sketch kernel          */
+#define BSRHT_TIMING_APPLY_BF16 2 /* the split-BF16 matrix-core kernel     */
+#define BSRHT_TIMING_GEMM_AQ 3    /* Z = A Q of the randomized SVD          */
+int bsrht_timing_enable(int which);
+int bsrht_timing_read(double *total_ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,249 @@
+"""Python binding of the gfx950 block SRHT library (libbsrht.so).
+
+Thin ctypes marshalling over the C ABI of include/bsrht.h: the same names,
+torch tensors for device memory and torch's current HIP stream by default.
+Every step of the sketch, the randomized SVD and the Nystrom method runs in
+the library's HIP kernels; this module only allocates buffers and passes
+pointers.  It raises if the library has not been built; there is no other
+execution path.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+__all__ = [
+    "BsrhtError", "lib", "library_path", "Plan", "bsrht_plan_bytes", "bsrht_plan",
+    "bsrht_apply", "bsrht_apply_workspace", "rsvd", "rsvd_workspace", "nystrom",
+    "nystrom_workspace", "WITH_REPLACEMENT", "WITHOUT_REPLACEMENT", "FP32",
+    "SPLIT_BF16", "INFO_CHOL_FALLBACK", "INFO_RANK_CLAMPED", "INFO_QB_FALLBACK",
+    "INFO_JACOBI_NOCONV", "EXPORTED_SYMBOLS",
+]
+
+WITH_REPLACEMENT = 0
+WITHOUT_REPLACEMENT = 1
+FP32 = 0
+SPLIT_BF16 = 1
+INFO_CHOL_FALLBACK = 1
+INFO_RANK_CLAMPED = 2
+INFO_QB_FALLBACK = 4
+INFO_JACOBI_NOCONV = 8
+TIMING_OFF = 0
+TIMING_APPLY_FP32 = 1
+TIMING_APPLY_BF16 = 2
+TIMING_GEMM_AQ = 3
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "_lib", "libbsrht.so")
+
+_c_i64 = ctypes.c_int64
+_c_vp = ctypes.c_void_p
+_c_sz = ctypes.c_size_t
+
+# name -> (restype, argtypes); the declarations of include/bsrht.h
+_SIGS = {
+    "bsrht_version": (ctypes.c_char_p, []),
+    "bsrht_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "bsrht_plan_bytes": (_c_sz, [_c_i64, _c_i64, _c_i64]),
+    "bsrht_plan": (ctypes.c_int, [_c_i64, _c_i64, _c_i64, ctypes.c_uint64, ctypes.c_int,
+                                  ctypes.c_int, _c_vp, _c_sz, _c_vp, ctypes.POINTER(_c_vp)]),
+    "bsrht_plan_destroy": (ctypes.c_int, [_c_vp]),
+    "bsrht_plan_info": (ctypes.c_int, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp]),
+    "bsrht_plan_export": (ctypes.c_int, [_c_vp, _c_vp, _c_vp, _c_vp]),
+    "bsrht_apply_workspace": (_c_sz, [_c_vp, _c_i64]),
+    "bsrht_apply": (ctypes.c_int, [_c_vp, _c_vp, _c_i64, _c_i64, _c_vp, _c_i64, _c_vp,
+                                   _c_sz, _c_vp]),
+    "rsvd_workspace": (_c_sz, [_c_vp, _c_i64, _c_i64]),
+    "rsvd": (ctypes.c_int, [_c_vp, _c_vp, _c_i64, _c_i64, _c_i64, _c_vp, _c_vp, _c_vp,
+                            _c_vp, _c_vp, _c_sz, _c_vp]),
+    "nystrom_workspace": (_c_sz, [_c_vp, _c_i64]),
+    "bsrht_timing_enable": (ctypes.c_int, [ctypes.c_int]),
+    "bsrht_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(_c_i64)]),
+    "nystrom": (ctypes.c_int, [_c_vp, _c_vp, _c_i64, _c_i64, _c_vp, _c_vp, _c_vp, _c_vp,
+                               _c_sz, _c_vp]),
+}
+EXPORTED_SYMBOLS = tuple(_SIGS)
+
+_lib = None
+
+
+class BsrhtError(RuntimeError):
+    def __init__(self, fn, status):
+        msg = lib().bsrht_strerror(status).decode()
+        super().__init__(f"{fn} failed: {msg} ({status})")
+        self.status = status
+
+
+def lib():
+    """The loaded libbsrht.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(library_path):
+            raise RuntimeError(
+                f"{library_path} is missing: build it with __graft_entry__.build() "
+                "(hipcc for gfx950); there is no fallback path")
+        handle = ctypes.CDLL(library_path)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def _check(fn, status):
+    if status != 0:
+        raise BsrhtError(fn, status)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _check_matrix(name, t, dtype=torch.float32):
+    if not isinstance(t, torch.Tensor) or t.dim() != 2:
+        raise ValueError(f"{name} must be a 2-D tensor")
+    if not t.is_cuda or t.dtype != dtype:
+        raise ValueError(f"{name} must be a {dtype} tensor on a GPU")
+    if t.stride(1) != 1 and t.shape[1] > 1:
+        raise ValueError(f"{name} must be row-major (unit column stride)")
+
+
+def timing_enable(which):
+    """Record HIP events around every launch of one library kernel (0 = off)."""
+    _check("bsrht_timing_enable", lib().bsrht_timing_enable(which))
+
+
+def timing_read():
+    """(summed kernel milliseconds, launches) since timing_enable."""
+    ms = ctypes.c_double()
+    n = _c_i64()
+    _check("bsrht_timing_read", lib().bsrht_timing_read(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def bsrht_plan_bytes(n, p, l):
+    return int(lib().bsrht_plan_bytes(n, p, l))
+
+
+class Plan:
+    """A block SRHT Omega (l x n, p blocks): device tables + library handle."""
+
+    def __init__(self, n, p, l, seed, sampling=WITH_REPLACEMENT, precision=FP32,
+                 device=None, stream=None):
+        L = lib()
+        nbytes = L.bsrht_plan_bytes(n, p, l)
+        if nbytes == 0:
+            raise ValueError(f"invalid block SRHT sizes n={n} p={p} l={l}")
+        dev = torch.device(device) if device is not None else torch.device("cuda")
+        self.tables = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+        self.n, self.p, self.l, self.r = int(n), int(p), int(l), int(n) // int(p)
+        self.seed, self.sampling, self.precision = int(seed), int(sampling), int(precision)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.tables.device):
+            st = L.bsrht_plan(n, p, l, ctypes.c_uint64(int(seed) & (2 ** 64 - 1)), sampling,
+                              precision, _ptr(self.tables), nbytes, _stream_ptr(stream),
+                              ctypes.byref(h))
+        _check("bsrht_plan", st)
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.bsrht_plan_destroy(h)
+            self.handle = None
+
+    def export(self):
+        """(R int32[l], Dbits uint32[ceil(n/32)], Dtbits uint32[p*ceil(l/32)])."""
+        R = np.zeros(self.l, dtype=np.int32)
+        Db = np.zeros((self.n + 31) // 32, dtype=np.uint32)
+        Dtb = np.zeros(self.p * ((self.l + 31) // 32), dtype=np.uint32)
+        _check("bsrht_plan_export", lib().bsrht_plan_export(
+            self.handle, R.ctypes.data_as(_c_vp), Db.ctypes.data_as(_c_vp),
+            Dtb.ctypes.data_as(_c_vp)))
+        return R, Db, Dtb
+
+
+def bsrht_plan(n, p, l, seed, sampling=WITH_REPLACEMENT, precision=FP32, device=None,
+               stream=None):
+    return Plan(n, p, l, seed, sampling, precision, device, stream)
+
+
+def _workspace(nbytes, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def bsrht_apply_workspace(plan, m):
+    return int(lib().bsrht_apply_workspace(plan.handle, m))
+
+
+def bsrht_apply(plan, A, Y=None, ws=None, stream=None):
+    """Y = Omega A for a row-major float32 n x m device tensor A."""
+    _check_matrix("A", A)
+    n, m = A.shape
+    if n != plan.n:
+        raise ValueError(f"A has {n} rows, the plan expects {plan.n}")
+    if Y is None:
+        Y = torch.empty(plan.l, m, dtype=torch.float32, device=A.device)
+    _check_matrix("Y", Y)
+    need = bsrht_apply_workspace(plan, m)
+    if ws is None:
+        ws = _workspace(need, A.device)
+    _check("bsrht_apply", lib().bsrht_apply(
+        plan.handle, _ptr(A), m, max(A.stride(0), m), _ptr(Y), max(Y.stride(0), m),
+        _ptr(ws), ws.numel(), _stream_ptr(stream)))
+    return Y
+
+
+def rsvd_workspace(plan, m, k):
+    return int(lib().rsvd_workspace(plan.handle, m, k))
+
+
+def rsvd(plan, A, k, ws=None, stream=None):
+    """Randomized SVD (Algorithm 1 on A^T): returns (U n x k, S k float64, V m x k, info)."""
+    _check_matrix("A", A)
+    n, m = A.shape
+    if n != plan.n:
+        raise ValueError(f"A has {n} rows, the plan expects {plan.n}")
+    dev = A.device
+    U = torch.empty(n, k, dtype=torch.float32, device=dev)
+    S = torch.empty(k, dtype=torch.float64, device=dev)
+    V = torch.empty(m, k, dtype=torch.float32, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = _workspace(rsvd_workspace(plan, m, k), dev)
+    _check("rsvd", lib().rsvd(plan.handle, _ptr(A), m, max(A.stride(0), m), k, _ptr(U),
+                              _ptr(S), _ptr(V), _ptr(info), _ptr(ws), ws.numel(),
+                              _stream_ptr(stream)))
+    return U, S, V, info
+
+
+def nystrom_workspace(plan, k):
+    return int(lib().nystrom_workspace(plan.handle, k))
+
+
+def nystrom(plan, A, k, ws=None, stream=None):
+    """Nystrom (Algorithm 2) of symmetric PSD A: returns (U n x k, lambda k float64, info)."""
+    _check_matrix("A", A)
+    n = A.shape[0]
+    if A.shape[1] != n or n != plan.n:
+        raise ValueError("A must be n x n with n = plan.n")
+    dev = A.device
+    U = torch.empty(n, k, dtype=torch.float32, device=dev)
+    lam = torch.empty(k, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = _workspace(nystrom_workspace(plan, k), dev)
+    _check("nystrom", lib().nystrom(plan.handle, _ptr(A), max(A.stride(0), n), k, _ptr(U),
+                                    _ptr(lam), _ptr(info), _ptr(ws), ws.numel(),
+                                    _stream_ptr(stream)))
+    return U, lam, info

@@ -1,0 +1,403 @@
+// Fused block SRHT apply, FP32 butterflies: Y = Omega A (section 2,
+// eq. (2.3)-(2.4)) for row-major A (n x m).
+//
+// Structure.  H_r factors as H_{r/b} (x) H_b for the index split
+// x = x_hi*b + x_lo (Kronecker form of H, section 2).  A workgroup of 8 waves
+// owns 64 columns (lane = column) and streams chunks of b = 8*BR consecutive
+// rows (one chunk = one x_hi of one block i); wave w holds chunk rows
+// x_lo = w*BR + t, t in [0, BR), in registers.  For each chunk:
+//   1. load  : buffer loads, one 256-byte row segment per wave instruction;
+//              the next chunk is already in flight;
+//   2. D^(i) : sign flips, wave-uniform per row (sign-bit xor);
+//   3. H_BR  : log2(BR) radix-2 stages over t, in registers;
+//   4. H_8   : one LDS exchange, 3 stages over w (rows t + BR*k);
+//              the chunk now holds H_b applied to each column;
+//   5. gather: lane = sample j; only the l sampled outputs are needed,
+//              (H_r v)[R_j] = sum_{x_hi} (-1)^popcount(R_j,hi & x_hi)
+//                             * (H_b v_{x_hi})[R_j,lo],
+//              so each sample adds +-row R_j,lo of the chunk (float4 LDS
+//              reads) with sign Dt^(i)_j * (-1)^popcount(R_j,hi & x_hi).
+// The accumulators run across chunks and across blocks, so the sum over
+// blocks (2.4) happens in registers; no transformed block is ever written to
+// HBM.  A is read exactly once.  Row splits (for parallelism) write l x m
+// partials that a second kernel sums in fixed split order and scales by
+// 1/sqrt(l) (the product sqrt(r/l) * 1/sqrt(r) of eq. (2.3)).
+#include <limits.h>
+
+#include "common.h"
+
+namespace bsrht {
+namespace {
+
+constexpr int kNW = 8;          // waves per workgroup
+constexpr int kCT = 64;         // columns per workgroup (one per lane)
+constexpr int kLDT = kCT + 4;   // LDS row stride in floats (272 B, float4 aligned)
+constexpr int kBufDword3 = 0x00020000;  // raw buffer resource word 3 (gfx9 family)
+
+constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x >> 1); }
+
+struct FusedArgs {
+  const float *A;
+  int64_t lda;
+  int m;
+  const int32_t *R;
+  const uint32_t *Dbits;
+  const uint32_t *Dtbits;
+  int dt_words;
+  int l;
+  int log2r;
+  int chunks_per_split;
+  int total_chunks;
+  float *out;
+  int64_t ldo;
+  int64_t split_stride;
+  float scale;
+};
+
+// Unscaled Walsh-Hadamard transform of N values held in registers.
+template <int N>
+__device__ __forceinline__ void fwht_regs(float (&v)[N]) {
+#pragma unroll
+  for (int h = 1; h < N; h <<= 1) {
+#pragma unroll
+    for (int x = 0; x < N; ++x) {
+      if ((x & h) == 0) {
+        const float a = v[x], b = v[x + h];
+        v[x] = a + b;
+        v[x + h] = a - b;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const float *base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), (short)0, -1, kBufDword3);
+}
+
+// Rows T0 .. T1-1 of the BR consecutive rows starting at `base`
+// (wave-uniform); voff = column bytes.
+template <int BR, int T0 = 0, int T1 = BR>
+__device__ __forceinline__ void load_rows(float (&v)[BR], const float *base, int voff,
+                                          int row_bytes) {
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(base);
+#pragma unroll
+  for (int t = T0; t < T1; ++t)
+    v[t] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, voff, t * row_bytes, 0));
+}
+
+// D^(i) for global rows g0 .. g0+BR-1 (g0 a multiple of BR, wave-uniform):
+// flip the sign bit where the table bit is set.
+template <int BR>
+__device__ __forceinline__ void apply_dsigns(float (&v)[BR], const uint32_t *__restrict__ Dbits,
+                                             int64_t g0) {
+  if constexpr (BR >= 32) {
+#pragma unroll
+    for (int wd = 0; wd < BR / 32; ++wd) {
+      const uint32_t bits = Dbits[(g0 >> 5) + wd];
+#pragma unroll
+      for (int b = 0; b < 32; ++b) {
+        const uint32_t msk = (bits << (31 - b)) & 0x80000000u;
+        v[wd * 32 + b] = __uint_as_float(__float_as_uint(v[wd * 32 + b]) ^ msk);
+      }
+    }
+  } else {
+    const uint32_t bits = Dbits[g0 >> 5] >> (uint32_t)(g0 & 31);
+#pragma unroll
+    for (int b = 0; b < BR; ++b) {
+      const uint32_t msk = (bits << (31 - b)) & 0x80000000u;
+      v[b] = __uint_as_float(__float_as_uint(v[b]) ^ msk);
+    }
+  }
+}
+
+template <int BR>
+struct FusedCta {
+  static constexpr int B = BR * kNW;
+  static constexpr int LOG2B = ilog2c(B);
+  static constexpr int G = BR / kNW;  // radix-8 groups per wave
+  static_assert(G >= 1, "need BR >= 8");
+
+  float *T;
+  const FusedArgs &a;
+  int lane, w, j, pos, cpb_log2, voff, row_bytes;
+  bool jok;
+  uint32_t rhi;
+  int cur_block;
+  uint32_t dtbit;
+  const float *wavebase;  // A + c0 + w*BR*lda (wave-uniform)
+  float acc[kCT];
+
+  __device__ __forceinline__ FusedCta(float *T_, const FusedArgs &a_) : T(T_), a(a_) {}
+
+  __device__ __forceinline__ const float *chunk_base(int q) const {
+    return wavebase + (int64_t)q * B * a.lda;
+  }
+
+  __device__ __forceinline__ void step(int q, int q1, float (&cur)[BR], float (&nxt)[BR]) {
+    // The next chunk is prefetched in two halves: the second half is issued
+    // once this chunk's rows have left the registers for LDS, which keeps
+    // the accumulators, one chunk and half a chunk within 256 VGPRs.
+    const bool more = q + 1 < q1;
+    if (more) load_rows<BR, 0, BR / 2>(nxt, chunk_base(q + 1), voff, row_bytes);
+    apply_dsigns<BR>(cur, a.Dbits, (int64_t)q * B + w * BR);
+    fwht_regs<BR>(cur);
+    {
+      float *Tw = T + (w * BR) * kLDT + lane;
+#pragma unroll
+      for (int t = 0; t < BR; ++t) Tw[t * kLDT] = cur[t];
+    }
+    if (more) load_rows<BR, BR / 2, BR>(nxt, chunk_base(q + 1), voff, row_bytes);
+    __syncthreads();
+    // H_8 over w: group t holds rows t, t+BR, ..., t+7*BR.
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      float *Tg = T + (w * G + g) * kLDT + lane;
+      float v[kNW];
+#pragma unroll
+      for (int k = 0; k < kNW; ++k) v[k] = Tg[k * BR * kLDT];
+      fwht_regs<kNW>(v);
+#pragma unroll
+      for (int k = 0; k < kNW; ++k) Tg[k * BR * kLDT] = v[k];
+    }
+    __syncthreads();
+    if (jok) {
+      const int i = q >> cpb_log2;
+      if (i != cur_block) {
+        cur_block = i;
+        dtbit = (a.Dtbits[(int64_t)i * a.dt_words + (j >> 5)] >> (j & 31)) & 1u;
+      }
+      const uint32_t xhi = (uint32_t)q & ((1u << cpb_log2) - 1u);
+      const uint32_t par = (uint32_t)__popc(rhi & xhi) & 1u;
+      const float sgn = (par ^ dtbit) ? -1.f : 1.f;
+      const float4 *row = reinterpret_cast<const float4 *>(T + pos * kLDT);
+#pragma unroll
+      for (int c4 = 0; c4 < kCT / 4; ++c4) {
+        const float4 v = row[c4];
+        acc[4 * c4 + 0] = fmaf(sgn, v.x, acc[4 * c4 + 0]);
+        acc[4 * c4 + 1] = fmaf(sgn, v.y, acc[4 * c4 + 1]);
+        acc[4 * c4 + 2] = fmaf(sgn, v.z, acc[4 * c4 + 2]);
+        acc[4 * c4 + 3] = fmaf(sgn, v.w, acc[4 * c4 + 3]);
+      }
+    }
+    __syncthreads();
+  }
+};
+
+template <int BR>
+__global__ __launch_bounds__(kNW * 64) void fused_fp32_kernel(FusedArgs a) {
+  using Cta = FusedCta<BR>;
+  __shared__ __attribute__((aligned(16))) float T[Cta::B * kLDT];
+  Cta cta(T, a);
+  const int tid = threadIdx.x;
+  cta.lane = tid & 63;
+  cta.w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int c0 = blockIdx.x * kCT;
+  // Columns past m load a valid neighbour (column m-1); they never reach Y.
+  const int cc = min(c0 + cta.lane, a.m - 1) - c0;
+  cta.voff = cc * 4;
+  cta.row_bytes = (int)(a.lda * 4);
+  cta.wavebase = a.A + c0 + (int64_t)(cta.w * BR) * a.lda;
+  const int q0 = blockIdx.y * a.chunks_per_split;
+  const int q1 = min(q0 + a.chunks_per_split, a.total_chunks);
+  cta.j = blockIdx.z * (kNW * 64) + tid;
+  cta.jok = cta.j < a.l;
+  const int rj = cta.jok ? a.R[cta.j] : 0;
+  cta.pos = rj & (Cta::B - 1);
+  cta.rhi = (uint32_t)rj >> Cta::LOG2B;
+  cta.cpb_log2 = a.log2r - Cta::LOG2B;
+  cta.cur_block = -1;
+  cta.dtbit = 0;
+#pragma unroll
+  for (int k = 0; k < kCT; ++k) cta.acc[k] = 0.f;
+
+  float bufA[BR], bufB[BR];
+  if (q0 < q1) load_rows<BR>(bufA, cta.chunk_base(q0), cta.voff, cta.row_bytes);
+  for (int q = q0; q < q1; q += 2) {
+    cta.step(q, q1, bufA, bufB);
+    if (q + 1 < q1) cta.step(q + 1, q1, bufB, bufA);
+  }
+
+  if (cta.jok) {
+    float *o = a.out + (int64_t)blockIdx.y * a.split_stride + (int64_t)cta.j * a.ldo + c0;
+    const int ncol = min(kCT, a.m - c0);
+#pragma unroll
+    for (int k = 0; k < kCT; ++k)
+      if (k < ncol) o[k] = cta.acc[k] * a.scale;
+  }
+}
+
+// Y[j, c] = scale * sum_s part[s][j][c], splits summed in ascending order.
+__global__ void reduce_splits_kernel(const float *__restrict__ part, int splits,
+                                     int64_t split_stride, int l, int m,
+                                     float *__restrict__ Y, int64_t ldy, float scale) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)l * m) return;
+  const int j = (int)(idx / m);
+  const int c = (int)(idx - (int64_t)j * m);
+  const float *p = part + (int64_t)j * m + c;
+  float s = 0.f;
+  for (int sp = 0; sp < splits; ++sp) s += p[(int64_t)sp * split_stride];
+  Y[(int64_t)j * ldy + c] = s * scale;
+}
+
+// Direct evaluation of eq. (2.3) for blocks shorter than the smallest fused
+// chunk (r < 64): one thread per output entry, O(n) work each.
+__global__ void direct_kernel(const float *__restrict__ A, int64_t lda, int m,
+                              const int32_t *__restrict__ R, const uint32_t *__restrict__ Dbits,
+                              const uint32_t *__restrict__ Dtbits, int64_t dt_words, int l,
+                              int64_t p, int log2r, float *__restrict__ Y, int64_t ldy,
+                              float scale) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)l * m) return;
+  const int j = (int)(idx / m);
+  const int c = (int)(idx - (int64_t)j * m);
+  const int64_t r = int64_t(1) << log2r;
+  const uint32_t rj = (uint32_t)R[j];
+  float acc = 0.f;
+  for (int64_t i = 0; i < p; ++i) {
+    float s = 0.f;
+    for (int64_t x = 0; x < r; ++x) {
+      const int64_t g = i * r + x;
+      const uint32_t d = (Dbits[g >> 5] >> (g & 31)) & 1u;
+      const uint32_t h = (uint32_t)__popc(rj & (uint32_t)x) & 1u;
+      const float v = A[g * lda + c];
+      s += (d ^ h) ? -v : v;
+    }
+    const uint32_t dt = (Dtbits[i * dt_words + (j >> 5)] >> (j & 31)) & 1u;
+    acc += dt ? -s : s;
+  }
+  Y[(int64_t)j * ldy + c] = acc * scale;
+}
+
+struct Launch {
+  bool direct = false;
+  int br = 0, b = 0;
+  int ctiles = 0, groups = 0, splits = 1, cps = 0, total_chunks = 0;
+  size_t ws = 0;
+};
+
+Launch choose_launch(const bsrht_plan_s *pl, int64_t m, int64_t lda) {
+  Launch L;
+  // Largest chunk b = 8*BR <= r with 8 <= BR <= 64.
+  (void)lda;
+  int br = 64;
+  while (br >= 8 && (int64_t)br * kNW > pl->r) br >>= 1;
+  if (br < 8) {
+    L.direct = true;
+    return L;
+  }
+  L.br = br;
+  L.b = br * kNW;
+  const int lds_bytes = L.b * kLDT * 4;
+  const int per_cu = lds_bytes > 80 * 1024 ? 1 : 2;
+  L.total_chunks = (int)(pl->n / L.b);
+  L.ctiles = (int)((m + kCT - 1) / kCT);
+  const int spp = kNW * 64;
+  L.groups = (int)((pl->l + spp - 1) / spp);
+  const int64_t target = (int64_t)device_cu_count() * per_cu;
+  int64_t splits = target / ((int64_t)L.ctiles * L.groups);
+  if (splits < 1) splits = 1;
+  if (splits > L.total_chunks) splits = L.total_chunks;
+  L.cps = (int)((L.total_chunks + splits - 1) / splits);
+  L.splits = (L.total_chunks + L.cps - 1) / L.cps;
+  L.ws = L.splits > 1 ? (size_t)L.splits * (size_t)pl->l * (size_t)m * sizeof(float) : 0;
+  return L;
+}
+
+template <int BR>
+int launch_fused(const Launch &L, FusedArgs &a, hipStream_t s) {
+  dim3 grid((unsigned)L.ctiles, (unsigned)L.splits, (unsigned)L.groups);
+  hipEvent_t ev = timing_begin(BSRHT_TIMING_APPLY_FP32, s);
+  fused_fp32_kernel<BR><<<grid, kNW * 64, 0, s>>>(a);
+  timing_end(ev, s);
+  BSRHT_LAUNCH_CHECK();
+  return BSRHT_OK;
+}
+
+}  // namespace
+
+size_t apply_ws_bytes(const bsrht_plan_s *plan, int64_t m) {
+  if (!plan || m <= 0) return 0;
+  if (plan->precision == BSRHT_SPLIT_BF16) return apply_split_bf16_ws_bytes(plan, m);
+  return choose_launch(plan, m, m).ws;
+}
+
+int apply_fp32(const bsrht_plan_s *pl, const float *A, int64_t m, int64_t lda, float *Y,
+               int64_t ldy, void *ws, size_t ws_bytes, hipStream_t s) {
+  const float scale = 1.0f / sqrtf((float)pl->l);
+  const Launch L = choose_launch(pl, m, lda);
+  if (L.direct) {
+    const int64_t total = pl->l * m;
+    const int tb = 256;
+    direct_kernel<<<(unsigned)((total + tb - 1) / tb), tb, 0, s>>>(
+        A, lda, (int)m, pl->R, pl->Dbits, pl->Dtbits, pl->dt_words, (int)pl->l, pl->p,
+        pl->log2r, Y, ldy, scale);
+    BSRHT_LAUNCH_CHECK();
+    return BSRHT_OK;
+  }
+  if (L.groups > 65535 || L.ctiles <= 0) return BSRHT_EUNSUPPORTED;
+  // Row offsets inside one wave's BR rows are 32-bit buffer offsets.
+  if ((int64_t)L.br * lda * 4 >= (int64_t(1) << 31)) return BSRHT_EUNSUPPORTED;
+  if (ws_bytes < L.ws || (L.ws && !ws)) return BSRHT_ENOMEM;
+  FusedArgs a;
+  a.A = A;
+  a.lda = lda;
+  a.m = (int)m;
+  a.R = pl->R;
+  a.Dbits = pl->Dbits;
+  a.Dtbits = pl->Dtbits;
+  a.dt_words = (int)pl->dt_words;
+  a.l = (int)pl->l;
+  a.log2r = pl->log2r;
+  a.chunks_per_split = L.cps;
+  a.total_chunks = L.total_chunks;
+  if (L.splits > 1) {
+    a.out = static_cast<float *>(ws);
+    a.ldo = m;
+    a.split_stride = pl->l * m;
+    a.scale = 1.0f;
+  } else {
+    a.out = Y;
+    a.ldo = ldy;
+    a.split_stride = 0;
+    a.scale = scale;
+  }
+  int st;
+  switch (L.br) {
+    case 64: st = launch_fused<64>(L, a, s); break;
+    case 32: st = launch_fused<32>(L, a, s); break;
+    case 16: st = launch_fused<16>(L, a, s); break;
+    default: st = launch_fused<8>(L, a, s); break;
+  }
+  if (st != BSRHT_OK) return st;
+  if (L.splits > 1) {
+    const int64_t total = pl->l * m;
+    const int tb = 256;
+    reduce_splits_kernel<<<(unsigned)((total + tb - 1) / tb), tb, 0, s>>>(
+        static_cast<const float *>(ws), L.splits, pl->l * m, (int)pl->l, (int)m, Y, ldy, scale);
+    BSRHT_LAUNCH_CHECK();
+  }
+  return BSRHT_OK;
+}
+
+}  // namespace bsrht
+
+using namespace bsrht;
+
+extern "C" {
+
+size_t bsrht_apply_workspace(bsrht_plan_t plan, int64_t m) { return apply_ws_bytes(plan, m); }
+
+int bsrht_apply(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, float *Y,
+                int64_t ldy, void *ws, size_t ws_bytes, void *stream) {
+  if (!plan || m < 0) return BSRHT_EINVAL;
+  if (m == 0) return BSRHT_OK;
+  if (!A || !Y || lda < m || ldy < m || m > INT_MAX) return BSRHT_EINVAL;
+  if ((int64_t)plan->l * m > ((int64_t)1 << 40)) return BSRHT_EUNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  if (plan->precision == BSRHT_SPLIT_BF16)
+    return apply_split_bf16(plan, A, m, lda, Y, ldy, ws, ws_bytes, s);
+  return apply_fp32(plan, A, m, lda, Y, ldy, ws, ws_bytes, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/bsrht.h"
+
+struct bsrht_plan_s {
+  int64_t n, p, l, r;
+  int log2r;
+  uint64_t seed;
+  int sampling, precision;
+  int32_t *R;         // device, l entries in [0, r), draw order
+  uint32_t *Dbits;    // device, ceil(n/32) words; bit g = sign of D at global row g
+  uint32_t *Dtbits;   // device, p * dt_words words; block i at i*dt_words
+  int64_t d_words, dt_words;
+  hipStream_t stream; // stream the tables were written on
+  int device;
+};
+
+namespace bsrht {
+
+#define BSRHT_HIP_CHECK(expr)                   \
+  do {                                          \
+    if ((expr) != hipSuccess) return BSRHT_EDEVICE; \
+  } while (0)
+
+#define BSRHT_LAUNCH_CHECK()                          \
+  do {                                                \
+    if (hipGetLastError() != hipSuccess) return BSRHT_EDEVICE; \
+  } while (0)
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+inline bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+inline int ilog2_i64(int64_t x) {
+  int k = 0;
+  while ((int64_t(1) << k) < x) ++k;
+  return k;
+}
+
+// Number of compute units of the current device (256 on MI355X).
+int device_cu_count();
+
+// Workspace carving: successive 256-byte aligned regions of a caller buffer.
+struct Carve {
+  char *base;
+  size_t size;
+  size_t used = 0;
+  bool overflow = false;
+  Carve(void *b, size_t s) : base(static_cast<char *>(b)), size(s) {}
+  template <class T>
+  T *take(size_t count) {
+    size_t off = align256(used);
+    size_t bytes = count * sizeof(T);
+    used = off + bytes;
+    if (used > size || (base == nullptr && bytes > 0)) {
+      overflow = true;
+      return nullptr;
+    }
+    return reinterpret_cast<T *>(base + off);
+  }
+};
+
+// Workspace sizing mirrors Carve exactly.
+struct Sizer {
+  size_t used = 0;
+  template <class T>
+  void take(size_t count) { used = align256(used) + count * sizeof(T); }
+};
+
+// The sketch Y = Omega A for row-major A (n x m, lda) into Y (l x m, ldy).
+// ws must hold apply_ws_bytes(plan, m).  Used by bsrht_apply and by the
+// RSVD / Nystrom drivers.
+size_t apply_ws_bytes(const bsrht_plan_s *plan, int64_t m);
+int apply_fp32(const bsrht_plan_s *plan, const float *A, int64_t m, int64_t lda,
+               float *Y, int64_t ldy, void *ws, size_t ws_bytes, hipStream_t s);
+int apply_split_bf16(const bsrht_plan_s *plan, const float *A, int64_t m,
+                     int64_t lda, float *Y, int64_t ldy, void *ws,
+                     size_t ws_bytes, hipStream_t s);
+size_t apply_split_bf16_ws_bytes(const bsrht_plan_s *plan, int64_t m);
+
+// Instrumentation hooks around the launch of the kernel selected by
+// bsrht_timing_enable (no-ops otherwise).
+hipEvent_t timing_begin(int which, hipStream_t s);
+void timing_end(hipEvent_t began, hipStream_t s);
+
+}  // namespace bsrht
