@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--skip-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain device copy of A (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -126,6 +128,15 @@ def main():
     achieved = alg_bytes / (kern_avg_ms * 1e-3) / 1e9
     log(f"bench: {value:.1f} GB/s whole call; fused kernel {kern_avg_ms * 1e3:.1f} us avg over "
         f"{launches} launches -> {achieved:.1f} GB/s")
+
+    if args.copy_calibration:
+        # one plain copy of A: reads and writes exactly n*m*4 bytes, the
+        # reference against which the HBM byte counters are scaled
+        log("bench: copy calibration")
+        B = torch.empty_like(A)
+        B.copy_(A)
+        torch.cuda.synchronize()
+        del B
 
     # read-only ceiling on the same buffer (torch reduction, measurement only)
     torch.cuda.synchronize()

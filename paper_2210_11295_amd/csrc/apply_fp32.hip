@@ -6,8 +6,8 @@
 // owns 64 columns (lane = column) and streams chunks of b = 8*BR consecutive
 // rows (one chunk = one x_hi of one block i); wave w holds chunk rows
 // x_lo = w*BR + t, t in [0, BR), in registers.  For each chunk:
-//   1. load  : buffer loads, one 256-byte row segment per wave instruction;
-//              the next chunk is already in flight;
+//   1. load  : non-temporal buffer loads, one 256-byte row segment per
+//              wave instruction; the next chunk is already in flight;
 //   2. D^(i) : sign flips, wave-uniform per row (sign-bit xor);
 //   3. H_BR  : log2(BR) radix-2 stages over t, in registers;
 //   4. H_8   : one LDS exchange, 3 stages over w (rows t + BR*k);
@@ -33,6 +33,7 @@ constexpr int kNW = 8;          // waves per workgroup
 constexpr int kCT = 64;         // columns per workgroup (one per lane)
 constexpr int kLDT = kCT + 4;   // LDS row stride in floats (272 B, float4 aligned)
 constexpr int kBufDword3 = 0x00020000;  // raw buffer resource word 3 (gfx9 family)
+constexpr int kAuxNT = 2;       // buffer cache policy: non-temporal (A is read once)
 
 constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x >> 1); }
 
@@ -82,7 +83,7 @@ __device__ __forceinline__ void load_rows(float (&v)[BR], const float *base, int
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(base);
 #pragma unroll
   for (int t = T0; t < T1; ++t)
-    v[t] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, voff, t * row_bytes, 0));
+    v[t] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, voff, t * row_bytes, kAuxNT));
 }
 
 // D^(i) for global rows g0 .. g0+BR-1 (g0 a multiple of BR, wave-uniform):
