@@ -22,14 +22,34 @@ struct bsrht_plan_s {
 
 namespace bsrht {
 
-#define BSRHT_HIP_CHECK(expr)                   \
-  do {                                          \
-    if ((expr) != hipSuccess) return BSRHT_EDEVICE; \
+// With BSRHT_DEBUG set in the environment, failures print where they
+// happened (stderr); otherwise they only return the status.
+void debug_report(const char *file, int line, const char *what, int status);
+
+#define BSRHT_HIP_CHECK(expr)                                        \
+  do {                                                               \
+    if ((expr) != hipSuccess) {                                      \
+      ::bsrht::debug_report(__FILE__, __LINE__, #expr, BSRHT_EDEVICE); \
+      return BSRHT_EDEVICE;                                          \
+    }                                                                \
   } while (0)
 
-#define BSRHT_LAUNCH_CHECK()                          \
-  do {                                                \
-    if (hipGetLastError() != hipSuccess) return BSRHT_EDEVICE; \
+#define BSRHT_LAUNCH_CHECK()                                                     \
+  do {                                                                           \
+    if (hipGetLastError() != hipSuccess) {                                       \
+      ::bsrht::debug_report(__FILE__, __LINE__, "kernel launch", BSRHT_EDEVICE); \
+      return BSRHT_EDEVICE;                                                      \
+    }                                                                            \
+  } while (0)
+
+// Propagate a non-OK status from a library call, with the debug trace.
+#define BSRHT_TRY(expr)                                          \
+  do {                                                           \
+    const int st_ = (expr);                                      \
+    if (st_ != BSRHT_OK) {                                       \
+      ::bsrht::debug_report(__FILE__, __LINE__, #expr, st_);     \
+      return st_;                                                \
+    }                                                            \
   } while (0)
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }

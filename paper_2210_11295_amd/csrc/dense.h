@@ -1,0 +1,77 @@
+// Internal dense linear-algebra kernels (see dense.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace bsrht {
+
+// C = alpha * A B + beta * C with A[i][k] = A[i*sai + k*sak] (M x K),
+// B[k][j] = B[k*sbk + j*sbj] (K x N), C row-major with leading dimension ldc.
+// splits > 1 writes FP64 partial products at C + s*split_stride (beta = 0).
+struct GemmDesc {
+  int64_t M = 0, N = 0, K = 0;
+  int64_t sai = 0, sak = 0, sbk = 0, sbj = 0;
+  int64_t ldc = 0;
+  double alpha = 1.0, beta = 0.0;
+  int splits = 1;
+  int64_t split_stride = 0;
+};
+
+int gemm_f32(const GemmDesc &d, const float *A, const float *B, float *C, hipStream_t s);
+int gemm_f64(const GemmDesc &d, const double *A, const double *B, double *C, hipStream_t s);
+int gemm_f32f64_f64(const GemmDesc &d, const float *A, const double *B, double *C,
+                    hipStream_t s);
+int gemm_f64f64_f32(const GemmDesc &d, const double *A, const double *B, float *C,
+                    hipStream_t s);
+int gemm_f32f32_f64(const GemmDesc &d, const float *A, const float *B, double *C,
+                    hipStream_t s);
+
+// G = X^T X (K x K FP64) for X[r][c] = X[r*sr + c*sc], r < n, c < K; the row
+// range is split into `splits` FP64 partials (K*K each, in `partials`)
+// summed in split order.
+int gram_f32(const float *X, int64_t n, int64_t K, int64_t sr, int64_t sc, double *G,
+             int64_t ldg, double *partials, int splits, hipStream_t s);
+int gram_f64(const double *X, int64_t n, int64_t K, int64_t sr, int64_t sc, double *G,
+             int64_t ldg, double *partials, int splits, hipStream_t s);
+int gram_splits(int64_t n, int64_t K);
+// FP64 elements of split-K partials any Gram call with rows <= n (n fixed)
+// and K <= Kmax may need.
+int64_t gram_partial_elems(int64_t n, int64_t Kmax);
+
+// In-place FP64 Cholesky of the symmetric G (upper triangle read): G = C^T C,
+// C upper.  *info (device) = 0 on success, else the 1-based index of the first
+// pivot <= tol * max(diag(G)).
+int cholesky_upper(double *G, int64_t n, int64_t ldg, double tol, int32_t *info, hipStream_t s);
+int trinv_upper(const double *C, int64_t n, int64_t ldc, double *Ci, int64_t ldi, hipStream_t s);
+int eye(double *M, int64_t n, int64_t ld, hipStream_t s);
+int fill_f64(double *p, int64_t count, double value, hipStream_t s);
+
+// One-sided Jacobi SVD of X (nr x nc, column-major, ldx), nc even, nc <= 4096.
+// X is overwritten by U Sigma; S (nc, descending) and Vs (row-major nc x nc,
+// right singular vectors as columns, same order) are written; V is scratch
+// (nc x nc, column-major), perm scratch (nc int32), flags scratch (2 uint,
+// flags[1] = sweeps taken).
+int jacobi_svd(double *X, int64_t nr, int64_t nc, int64_t ldx, double *V, int64_t ldv,
+               double *S, double *Vs, int64_t ldvs, int32_t *perm, unsigned int *flags,
+               int max_sweeps, hipStream_t s);
+
+int transpose_f32_f64(const float *src, int64_t rows, int64_t cols, int64_t lds, double *dst,
+                      int64_t ldd, hipStream_t s);
+int transpose_f32(const float *src, int64_t rows, int64_t cols, int64_t lds, float *dst,
+                  int64_t ldd, hipStream_t s);
+int transpose_f64(const double *src, int64_t rows, int64_t cols, int64_t lds, double *dst,
+                  int64_t ldd, hipStream_t s);
+
+// dst[i][j] = src[i][j] * scale[j] for j < keep (scale NULL: 1), 0 for
+// keep <= j < out.
+int scale_cols_f64_f32(const double *src, int64_t rows, int64_t keep, int64_t out, int64_t lds,
+                       const double *scale, float *dst, int64_t ldd, hipStream_t s);
+int scale_cols_f64(const double *src, int64_t rows, int64_t keep, int64_t out, int64_t lds,
+                   const double *scale, double *dst, int64_t ldd, hipStream_t s);
+int scale_cols_f32(const float *src, int64_t rows, int64_t keep, int64_t out, int64_t lds,
+                   const double *scale, float *dst, int64_t ldd, hipStream_t s);
+
+}  // namespace bsrht

@@ -1,0 +1,603 @@
+// Dense linear-algebra kernels behind the randomized SVD (section 3.1,
+// Algorithm 1) and the Nystrom approximation (section 3.2, Algorithm 2):
+//   - matrix-core GEMM, C = alpha * A B (+ beta C) with strided operands,
+//     FP32 (v_mfma_f32_16x16x4f32) or FP64 (v_mfma_f64_16x16x4f64), split-K;
+//   - FP64 Cholesky C^T C = G (upper C), the factorisation behind
+//     Cholesky-QR (used where the paper's Algorithms ask for QR / TSQR);
+//   - inverse of an upper-triangular matrix;
+//   - one-sided (Hestenes) Jacobi SVD, the "SVD of R" step of both
+//     Algorithms, as one cooperative kernel with a grid barrier per round;
+//   - small helpers (identity, transpose/convert, column scaling, sort).
+#include <hip/hip_cooperative_groups.h>
+
+#include <algorithm>
+
+#include "common.h"
+#include "dense.h"
+
+namespace bsrht {
+namespace {
+
+constexpr int kTM = 64, kTN = 64, kTK = 16;  // GEMM workgroup tile
+constexpr int kGemmThreads = 256;            // 4 waves, each a 32 x 32 sub-tile
+
+template <typename T>
+__device__ __forceinline__ double to_d(T v) { return (double)v; }
+
+// One workgroup computes a kTM x kTN tile of C over the K range of its split.
+// A[i][k] = A[i*sai + k*sak], B[k][j] = B[k*sbk + j*sbj].
+template <typename TA, typename TB, typename TC, bool F64>
+__global__ __launch_bounds__(kGemmThreads) void gemm_kernel(GemmDesc d, const TA *__restrict__ A,
+                                                            const TB *__restrict__ B,
+                                                            TC *__restrict__ C) {
+  using TS = typename std::conditional<F64, double, float>::type;
+  __shared__ TS As[kTK][kTM + 1];
+  __shared__ TS Bs[kTK][kTN + 1];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * kTM, j0 = (int64_t)blockIdx.y * kTN;
+  const int64_t kchunk = (d.K + gridDim.z - 1) / gridDim.z;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t ke = min(d.K, kb + kchunk);
+  const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;  // wave sub-tile origin
+  using Acc = typename std::conditional<F64, double __attribute__((ext_vector_type(4))),
+                                        float __attribute__((ext_vector_type(4)))>::type;
+  Acc acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+
+  const bool a_icontig = d.sai == 1;
+  const bool b_jcontig = d.sbj == 1;
+  for (int64_t k0 = kb; k0 < ke; k0 += kTK) {
+    // stage A (kTM x kTK) and B (kTK x kTN), zero-filled outside the matrix
+#pragma unroll
+    for (int r = 0; r < (kTM * kTK) / kGemmThreads; ++r) {
+      const int e = tid + r * kGemmThreads;
+      int ii, kk;
+      if (a_icontig) {
+        ii = e % kTM;
+        kk = e / kTM;
+      } else {
+        ii = e / kTK;
+        kk = e % kTK;
+      }
+      const int64_t gi = i0 + ii, gk = k0 + kk;
+      TS v = 0;
+      if (gi < d.M && gk < ke) v = (TS)A[gi * d.sai + gk * d.sak];
+      As[kk][ii] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < (kTN * kTK) / kGemmThreads; ++r) {
+      const int e = tid + r * kGemmThreads;
+      int jj, kk;
+      if (b_jcontig) {
+        jj = e % kTN;
+        kk = e / kTN;
+      } else {
+        jj = e / kTK;
+        kk = e % kTK;
+      }
+      const int64_t gj = j0 + jj, gk = k0 + kk;
+      TS v = 0;
+      if (gj < d.N && gk < ke) v = (TS)B[gk * d.sbk + gj * d.sbj];
+      Bs[kk][jj] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kTK; ks += 4) {
+      const int kk = ks + (lane >> 4);
+      TS a0 = As[kk][wi + (lane & 15)], a1 = As[kk][wi + 16 + (lane & 15)];
+      TS b0 = Bs[kk][wj + (lane & 15)], b1 = Bs[kk][wj + 16 + (lane & 15)];
+      if constexpr (F64) {
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      } else {
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // D layout of the 16x16 blocks, lane l, item v, column l%16: row
+  // 4*(l/16)+v for the FP32 instruction and l/16 + 4v for the FP64 one.
+  TC *Cz = C + (int64_t)blockIdx.z * d.split_stride;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gi = i0 + wi + 16 * a + (F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
+        const int64_t gj = j0 + wj + 16 * b + (lane & 15);
+        if (gi < d.M && gj < d.N) {
+          const double val = d.alpha * (double)acc[a][b][v];
+          TC *dst = Cz + gi * d.ldc + gj;
+          if (d.beta != 0.0)
+            *dst = (TC)(val + d.beta * (double)*dst);
+          else
+            *dst = (TC)val;
+        }
+      }
+}
+
+// Sum of split-K partials in split order: C[i][j] = sum_s P[s][i][j].
+template <typename TC>
+__global__ void reduce_partials_kernel(const double *__restrict__ P, int splits, int64_t M,
+                                       int64_t N, TC *__restrict__ C, int64_t ldc) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M * N) return;
+  const int64_t i = idx / N, j = idx - i * N;
+  double s = 0.0;
+  for (int sp = 0; sp < splits; ++sp) s += P[(int64_t)sp * M * N + idx];
+  C[i * ldc + j] = (TC)s;
+}
+
+}  // namespace
+
+template <typename TA, typename TB, typename TC, bool F64>
+static int gemm_launch(const GemmDesc &d, const TA *A, const TB *B, TC *C, hipStream_t s) {
+  if (d.M <= 0 || d.N <= 0) return BSRHT_OK;
+  dim3 grid((unsigned)((d.M + kTM - 1) / kTM), (unsigned)((d.N + kTN - 1) / kTN),
+            (unsigned)d.splits);
+  gemm_kernel<TA, TB, TC, F64><<<grid, kGemmThreads, 0, s>>>(d, A, B, C);
+  BSRHT_LAUNCH_CHECK();
+  return BSRHT_OK;
+}
+
+int gemm_f32(const GemmDesc &d, const float *A, const float *B, float *C, hipStream_t s) {
+  return gemm_launch<float, float, float, false>(d, A, B, C, s);
+}
+int gemm_f64(const GemmDesc &d, const double *A, const double *B, double *C, hipStream_t s) {
+  return gemm_launch<double, double, double, true>(d, A, B, C, s);
+}
+int gemm_f32f64_f64(const GemmDesc &d, const float *A, const double *B, double *C,
+                    hipStream_t s) {
+  return gemm_launch<float, double, double, true>(d, A, B, C, s);
+}
+int gemm_f64f64_f32(const GemmDesc &d, const double *A, const double *B, float *C,
+                    hipStream_t s) {
+  return gemm_launch<double, double, float, true>(d, A, B, C, s);
+}
+int gemm_f32f32_f64(const GemmDesc &d, const float *A, const float *B, double *C,
+                    hipStream_t s) {
+  return gemm_launch<float, float, double, true>(d, A, B, C, s);
+}
+
+// G = X^T X (K x K, FP64) for X with rows r < n, X[r][c] = X[r*sr + c*sc],
+// split over rows into `splits` FP64 partials summed in order.
+template <typename TX>
+static int gram_impl(const TX *X, int64_t n, int64_t K, int64_t sr, int64_t sc, double *G,
+                     int64_t ldg, double *partials, int splits, hipStream_t s) {
+  GemmDesc d;
+  d.M = K;
+  d.N = K;
+  d.K = n;
+  d.sai = sc;  // A = X^T: A[i][k] = X[k][i]
+  d.sak = sr;
+  d.sbk = sr;  // B = X
+  d.sbj = sc;
+  d.alpha = 1.0;
+  d.beta = 0.0;
+  if (splits <= 1) {
+    d.splits = 1;
+    d.ldc = ldg;
+    d.split_stride = 0;
+    return gemm_launch<TX, TX, double, true>(d, X, X, G, s);
+  }
+  d.splits = splits;
+  d.ldc = K;
+  d.split_stride = K * K;
+  int st = gemm_launch<TX, TX, double, true>(d, X, X, partials, s);
+  if (st != BSRHT_OK) return st;
+  const int64_t total = K * K;
+  reduce_partials_kernel<double><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(
+      partials, splits, K, K, G, ldg);
+  BSRHT_LAUNCH_CHECK();
+  return BSRHT_OK;
+}
+
+int gram_f32(const float *X, int64_t n, int64_t K, int64_t sr, int64_t sc, double *G,
+             int64_t ldg, double *partials, int splits, hipStream_t s) {
+  return gram_impl<float>(X, n, K, sr, sc, G, ldg, partials, splits, s);
+}
+int gram_f64(const double *X, int64_t n, int64_t K, int64_t sr, int64_t sc, double *G,
+             int64_t ldg, double *partials, int splits, hipStream_t s) {
+  return gram_impl<double>(X, n, K, sr, sc, G, ldg, partials, splits, s);
+}
+
+int64_t gram_partial_elems(int64_t n, int64_t Kmax) {
+  int64_t best = 0;
+  for (int64_t K = 1; K <= Kmax; ++K) {
+    const int64_t sp = gram_splits(n, K);
+    if (sp > 1) best = std::max(best, sp * K * K);
+  }
+  return best;
+}
+
+int gram_splits(int64_t n, int64_t K) {
+  // enough workgroups to fill the chip; each split spans at least 1024 rows
+  const int64_t tiles = ((K + kTM - 1) / kTM) * ((K + kTN - 1) / kTN);
+  int64_t want = (2 * (int64_t)device_cu_count() + tiles - 1) / tiles;
+  int64_t maxs = (n + 1023) / 1024;
+  if (want > maxs) want = maxs;
+  if (want < 1) want = 1;
+  if (want > 256) want = 256;
+  return (int)want;
+}
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// FP64 Cholesky G = C^T C with C upper triangular, in place (one workgroup).
+// Right-looking: row k of C is G[k][k:] / sqrt(pivot); the trailing block is
+// updated by the outer product of that row.  A pivot <= tol * max(diag(G))
+// stops the factorisation and reports its 1-based index in *info (the
+// Remark 3.1 break-down); the lower triangle is zeroed on success.
+__global__ __launch_bounds__(1024) void cholesky_kernel(double *G, int64_t n, int64_t ldg,
+                                                        double tol, int32_t *info) {
+  __shared__ double s_piv;
+  __shared__ double s_thresh;
+  __shared__ int s_fail;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid == 0) {
+    double mx = 0.0;
+    for (int64_t i = 0; i < n; ++i) mx = fmax(mx, G[i * ldg + i]);
+    s_thresh = tol * mx;
+    s_fail = 0;
+  }
+  __syncthreads();
+  for (int64_t k = 0; k < n; ++k) {
+    if (tid == 0) {
+      const double p = G[k * ldg + k];
+      if (!(p > s_thresh)) {
+        s_fail = (int)(k + 1);
+      } else {
+        s_piv = sqrt(p);
+        G[k * ldg + k] = s_piv;
+      }
+    }
+    __syncthreads();
+    if (s_fail) break;
+    const double inv = 1.0 / s_piv;
+    for (int64_t j = k + 1 + tid; j < n; j += nt) G[k * ldg + j] *= inv;
+    __syncthreads();
+    // trailing update of the upper triangle: G[i][j] -= C[k][i] C[k][j], k < i <= j
+    const int64_t rem = n - k - 1;
+    for (int64_t e = tid; e < rem * rem; e += nt) {
+      const int64_t i = k + 1 + e / rem, j = k + 1 + e % rem;
+      if (j >= i) G[i * ldg + j] -= G[k * ldg + i] * G[k * ldg + j];
+    }
+    __syncthreads();
+  }
+  if (s_fail) {
+    if (tid == 0) *info = s_fail;
+    return;
+  }
+  for (int64_t e = tid; e < n * n; e += nt) {
+    const int64_t i = e / n, j = e % n;
+    if (j < i) G[i * ldg + j] = 0.0;
+  }
+  if (tid == 0) *info = 0;
+}
+
+// Inverse of an upper-triangular n x n matrix C (row-major): Ci = C^{-1},
+// also upper triangular.  Column j of Ci solves C x = e_j by back
+// substitution; one thread per column, columns independent.
+__global__ void trinv_upper_kernel(const double *__restrict__ C, int64_t n, int64_t ldc,
+                                   double *__restrict__ Ci, int64_t ldi) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  for (int64_t i = n - 1; i >= 0; --i) {
+    double v;
+    if (i > j) {
+      v = 0.0;
+    } else {
+      double s = (i == j) ? 1.0 : 0.0;
+      for (int64_t t = i + 1; t <= j; ++t) s -= C[i * ldc + t] * Ci[t * ldi + j];
+      v = s / C[i * ldc + i];
+    }
+    Ci[i * ldi + j] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One-sided Jacobi SVD of X (nr x nc, column-major, columns of length nr at
+// stride ldx), nc even after padding: X V = U Sigma.  Columns are rotated in
+// pairs until all are mutually orthogonal; V accumulates the rotations.
+// Round-robin ordering: nc-1 rounds per sweep, nc/2 disjoint pairs per round,
+// one wave per pair, a grid barrier between rounds.
+struct JacobiArgs {
+  double *X;
+  double *V;
+  int64_t nr, nc, ldx, ldv;
+  double tol;
+  int max_sweeps;
+  unsigned int *flags;  // [0]: rotations in this sweep (cleared per sweep), [1]: sweeps done
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Pair p of round r among nc players (round-robin, player nc-1 fixed).
+__device__ __forceinline__ void rr_pair(int64_t nc, int64_t r, int64_t p, int64_t &a,
+                                        int64_t &b) {
+  const int64_t m = nc - 1;
+  if (p == 0) {
+    a = r % m;
+    b = m;
+  } else {
+    a = (r + p) % m;
+    b = (r + m - p) % m;
+  }
+  if (a > b) {
+    const int64_t t = a;
+    a = b;
+    b = t;
+  }
+}
+
+__global__ __launch_bounds__(256) void jacobi_kernel(JacobiArgs ja) {
+  namespace cg = cooperative_groups;
+  cg::grid_group grid = cg::this_grid();
+  const int lane = threadIdx.x & 63;
+  const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t npairs = ja.nc / 2;
+  int sweep = 0;
+  for (; sweep < ja.max_sweeps; ++sweep) {
+    for (int64_t r = 0; r < ja.nc - 1; ++r) {
+      for (int64_t p = gw; p < npairs; p += nwaves) {
+        int64_t ca, cb;
+        rr_pair(ja.nc, r, p, ca, cb);
+        double *xa = ja.X + ca * ja.ldx, *xb = ja.X + cb * ja.ldx;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int64_t i = lane; i < ja.nr; i += 64) {
+          const double u = xa[i], v = xb[i];
+          al += u * u;
+          be += v * v;
+          ga += u * v;
+        }
+        al = wave_sum(al);
+        be = wave_sum(be);
+        ga = wave_sum(ga);
+        if (fabs(ga) > ja.tol * sqrt(al * be) && ga != 0.0) {
+          // rotation zeroing the (a, b) entry of the 2x2 Gram [al ga; ga be]
+          const double zeta = (be - al) / (2.0 * ga);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+          for (int64_t i = lane; i < ja.nr; i += 64) {
+            const double u = xa[i], v = xb[i];
+            xa[i] = c * u - sn * v;
+            xb[i] = sn * u + c * v;
+          }
+          double *va = ja.V + ca * ja.ldv, *vb = ja.V + cb * ja.ldv;
+          for (int64_t i = lane; i < ja.nc; i += 64) {
+            const double u = va[i], v = vb[i];
+            va[i] = c * u - sn * v;
+            vb[i] = sn * u + c * v;
+          }
+          if (lane == 0) atomicAdd(&ja.flags[0], 1u);
+        }
+      }
+      grid.sync();
+    }
+    const unsigned rot = __hip_atomic_load(&ja.flags[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    grid.sync();
+    if (blockIdx.x == 0 && threadIdx.x == 0) ja.flags[0] = 0u;
+    grid.sync();
+    if (rot == 0u) {
+      ++sweep;
+      break;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) ja.flags[1] = (unsigned)sweep;
+}
+
+// sigma_j = ||x_j||, then order (sigma, column of V) by decreasing sigma
+// (ties by index) into S and Vs (Vs[i][j] = V[j][i] of the sorted order,
+// i.e. row-major nc x nc with the singular vectors as columns).  One
+// workgroup; nc <= 4096.
+__global__ __launch_bounds__(1024) void jacobi_finish_kernel(const double *__restrict__ X,
+                                                             const double *__restrict__ V,
+                                                             int64_t nr, int64_t nc, int64_t ldx,
+                                                             int64_t ldv, double *__restrict__ S,
+                                                             double *__restrict__ Vs,
+                                                             int64_t ldvs, int32_t *__restrict__ perm) {
+  extern __shared__ double s_sig[];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int64_t j = tid; j < nc; j += nt) {
+    double s = 0.0;
+    for (int64_t i = 0; i < nr; ++i) {
+      const double u = X[j * ldx + i];
+      s += u * u;
+    }
+    s_sig[j] = sqrt(s);
+  }
+  __syncthreads();
+  // rank of each column: number of columns with larger sigma (ties by index)
+  for (int64_t j = tid; j < nc; j += nt) {
+    const double sj = s_sig[j];
+    int64_t rank = 0;
+    for (int64_t t = 0; t < nc; ++t) {
+      const double st = s_sig[t];
+      rank += (st > sj) || (st == sj && t < j);
+    }
+    perm[rank] = (int32_t)j;
+    S[rank] = sj;
+  }
+  __syncthreads();
+  for (int64_t e = tid; e < nc * nc; e += nt) {
+    const int64_t i = e / nc, rnk = e % nc;
+    Vs[i * ldvs + rnk] = V[(int64_t)perm[rnk] * ldv + i];
+  }
+}
+
+__global__ void zero_u32_kernel(unsigned int *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+__global__ void fill_f64_kernel(double *p, int64_t count, double value) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = value;
+}
+
+__global__ void eye_kernel(double *M, int64_t n, int64_t ld) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int64_t i = idx / n, j = idx % n;
+  M[i * ld + j] = (i == j) ? 1.0 : 0.0;
+}
+
+// dst[j][i] = src[i][j] converted, for src rows x cols.
+template <typename TS, typename TD>
+__global__ void transpose_kernel(const TS *__restrict__ src, int64_t rows, int64_t cols,
+                                 int64_t lds, TD *__restrict__ dst, int64_t ldd) {
+  __shared__ TS tile[32][33];
+  const int64_t bi = (int64_t)blockIdx.y * 32, bj = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = bi + r, j = bj + tx;
+    if (i < rows && j < cols) tile[r][tx] = src[i * lds + j];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t j = bj + r, i = bi + tx;
+    if (i < rows && j < cols) dst[j * ldd + i] = (TD)tile[tx][r];
+  }
+}
+
+// dst[i][j] = src[i][j] * scale[j] (scale may be NULL: plain copy/convert),
+// for j < cols_keep, and 0 for cols_keep <= j < cols_out.
+template <typename TS, typename TD>
+__global__ void scale_cols_kernel(const TS *__restrict__ src, int64_t rows, int64_t cols_keep,
+                                  int64_t cols_out, int64_t lds, const double *__restrict__ scale,
+                                  TD *__restrict__ dst, int64_t ldd) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols_out) return;
+  const int64_t i = idx / cols_out, j = idx % cols_out;
+  double v = 0.0;
+  if (j < cols_keep) {
+    v = (double)src[i * lds + j];
+    if (scale) v *= scale[j];
+  }
+  dst[i * ldd + j] = (TD)v;
+}
+
+}  // namespace
+
+int cholesky_upper(double *G, int64_t n, int64_t ldg, double tol, int32_t *info, hipStream_t s) {
+  cholesky_kernel<<<1, 1024, 0, s>>>(G, n, ldg, tol, info);
+  BSRHT_LAUNCH_CHECK();
+  return BSRHT_OK;
+}
+
+int fill_f64(double *p, int64_t count, double value, hipStream_t s) {
+  if (count <= 0) return BSRHT_OK;
+  fill_f64_kernel<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(p, count, value);
+  BSRHT_LAUNCH_CHECK();
+  return BSRHT_OK;
+}
+
+int trinv_upper(const double *C, int64_t n, int64_t ldc, double *Ci, int64_t ldi, hipStream_t s) {
+  trinv_upper_kernel<<<(unsigned)((n + 63) / 64), 64, 0, s>>>(C, n, ldc, Ci, ldi);
+  BSRHT_LAUNCH_CHECK();
+  return BSRHT_OK;
+}
+
+int eye(double *M, int64_t n, int64_t ld, hipStream_t s) {
+  eye_kernel<<<(unsigned)((n * n + 255) / 256), 256, 0, s>>>(M, n, ld);
+  BSRHT_LAUNCH_CHECK();
+  return BSRHT_OK;
+}
+
+int jacobi_svd(double *X, int64_t nr, int64_t nc, int64_t ldx, double *V, int64_t ldv,
+               double *S, double *Vs, int64_t ldvs, int32_t *perm, unsigned int *flags,
+               int max_sweeps, hipStream_t s) {
+  if (nc <= 0) return BSRHT_OK;
+  if (nc > 4096 || (nc & 1)) return BSRHT_EUNSUPPORTED;
+  int st = eye(V, nc, ldv, s);
+  if (st != BSRHT_OK) return st;
+  zero_u32_kernel<<<1, 64, 0, s>>>(flags, 2);
+  BSRHT_LAUNCH_CHECK();
+  JacobiArgs ja;
+  ja.X = X;
+  ja.V = V;
+  ja.nr = nr;
+  ja.nc = nc;
+  ja.ldx = ldx;
+  ja.ldv = ldv;
+  ja.tol = 1e-15 * (double)(nr > 16 ? nr : 16);
+  ja.max_sweeps = max_sweeps;
+  ja.flags = flags;
+  // one wave per pair, at most one workgroup of 4 waves per CU
+  const int64_t npairs = nc / 2;
+  int64_t blocks = (npairs + 3) / 4;
+  const int64_t maxb = device_cu_count();
+  if (blocks > maxb) blocks = maxb;
+  if (blocks < 1) blocks = 1;
+  void *args[] = {&ja};
+  if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&jacobi_kernel),
+                                 dim3((unsigned)blocks), dim3(256), args, 0, s) != hipSuccess)
+    return BSRHT_EDEVICE;
+  jacobi_finish_kernel<<<1, 1024, (size_t)nc * sizeof(double), s>>>(X, V, nr, nc, ldx, ldv, S,
+                                                                     Vs, ldvs, perm);
+  BSRHT_LAUNCH_CHECK();
+  return BSRHT_OK;
+}
+
+int transpose_f32_f64(const float *src, int64_t rows, int64_t cols, int64_t lds, double *dst,
+                      int64_t ldd, hipStream_t s) {
+  dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32));
+  transpose_kernel<float, double><<<grid, 256, 0, s>>>(src, rows, cols, lds, dst, ldd);
+  BSRHT_LAUNCH_CHECK();
+  return BSRHT_OK;
+}
+int transpose_f32(const float *src, int64_t rows, int64_t cols, int64_t lds, float *dst,
+                  int64_t ldd, hipStream_t s) {
+  dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32));
+  transpose_kernel<float, float><<<grid, 256, 0, s>>>(src, rows, cols, lds, dst, ldd);
+  BSRHT_LAUNCH_CHECK();
+  return BSRHT_OK;
+}
+int transpose_f64(const double *src, int64_t rows, int64_t cols, int64_t lds, double *dst,
+                  int64_t ldd, hipStream_t s) {
+  dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32));
+  transpose_kernel<double, double><<<grid, 256, 0, s>>>(src, rows, cols, lds, dst, ldd);
+  BSRHT_LAUNCH_CHECK();
+  return BSRHT_OK;
+}
+
+template <typename TS, typename TD>
+static int scale_cols_impl(const TS *src, int64_t rows, int64_t keep, int64_t out, int64_t lds,
+                           const double *scale, TD *dst, int64_t ldd, hipStream_t s) {
+  const int64_t total = rows * out;
+  if (total <= 0) return BSRHT_OK;
+  scale_cols_kernel<TS, TD><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(
+      src, rows, keep, out, lds, scale, dst, ldd);
+  BSRHT_LAUNCH_CHECK();
+  return BSRHT_OK;
+}
+int scale_cols_f64_f32(const double *src, int64_t rows, int64_t keep, int64_t out, int64_t lds,
+                       const double *scale, float *dst, int64_t ldd, hipStream_t s) {
+  return scale_cols_impl<double, float>(src, rows, keep, out, lds, scale, dst, ldd, s);
+}
+int scale_cols_f64(const double *src, int64_t rows, int64_t keep, int64_t out, int64_t lds,
+                   const double *scale, double *dst, int64_t ldd, hipStream_t s) {
+  return scale_cols_impl<double, double>(src, rows, keep, out, lds, scale, dst, ldd, s);
+}
+int scale_cols_f32(const float *src, int64_t rows, int64_t keep, int64_t out, int64_t lds,
+                   const double *scale, float *dst, int64_t ldd, hipStream_t s) {
+  return scale_cols_impl<float, float>(src, rows, keep, out, lds, scale, dst, ldd, s);
+}
+
+}  // namespace bsrht

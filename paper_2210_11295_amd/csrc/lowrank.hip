@@ -1,22 +1,516 @@
-// Randomized SVD (Algorithm 1) and Nystrom (Algorithm 2) drivers.
-// Placeholder entry points: report BSRHT_EUNSUPPORTED until the FP64 dense
-// kernels are in place.
+// Randomized SVD (section 3.1, Algorithm 1) and Nystrom approximation
+// (section 3.2, Algorithm 2) on top of the block SRHT sketch.
+//
+// Where the paper asks for a QR factorisation (TSQR on a distributed
+// machine), one GPU uses Cholesky-QR in FP64: the Gram matrix X^T X of the
+// tall factor on the matrix cores, then a Cholesky factor R with
+// R^T R = X^T X; orthonormal bases are X R^{-1} (twice, "Cholesky-QR2", for
+// the range basis Q).  The small SVDs are one-sided Jacobi in FP64.
+//
+// Both entry points synchronise their stream to read back a Cholesky flag:
+// Remark 3.1's fallback (a square root from an eigendecomposition, keeping
+// eigenvalues above tau * lambda_max) changes the sizes of the later steps,
+// so the path is chosen on the host.
+#include <algorithm>
+#include <vector>
+
 #include "common.h"
+#include "dense.h"
+
+namespace bsrht {
+namespace {
+
+constexpr double kU32 = 5.9604644775390625e-08;  // 2^-24, unit roundoff of FP32 data
+constexpr double kU64 = 2.220446049250313e-16;   // 2^-52, FP64 machine epsilon
+constexpr int kMaxSweeps = 40;
+
+__global__ void eye_f32_kernel(float *M, int64_t n, int64_t ld) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int64_t i = idx / n, j = idx % n;
+  M[i * ld + j] = (i == j) ? 1.f : 0.f;
+}
+
+// Bs = (B + B^T) / 2 in FP64 (Omega Y is symmetric in exact arithmetic).
+__global__ void sym_f64_kernel(const float *__restrict__ B, int64_t n, int64_t ldb,
+                               double *__restrict__ Bs, int64_t lds) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int64_t i = idx / n, j = idx % n;
+  Bs[i * lds + j] = 0.5 * ((double)B[i * ldb + j] + (double)B[j * ldb + i]);
+}
+
+// inv[j] = 1/sigma_j for j < keep with sigma_j > rel * sigma_0, else 0; the
+// outputs S (FP64, count k) get sigma_j^pw for kept j, else 0.  When a
+// requested j < k has no kept value the info word gets RANK_CLAMPED.
+__global__ void finish_sigma_kernel(const double *__restrict__ sigma, int64_t avail, int64_t k,
+                                    double rel, int pw, double *__restrict__ inv,
+                                    double *__restrict__ S, int32_t *__restrict__ info) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  const double s0 = sigma[0];
+  const bool keep = j < avail && sigma[j] > rel * s0 && sigma[j] > 0.0;
+  inv[j] = keep ? 1.0 / sigma[j] : 0.0;
+  S[j] = keep ? (pw == 2 ? sigma[j] * sigma[j] : sigma[j]) : 0.0;
+  if (!keep) atomicOr(info, BSRHT_INFO_RANK_CLAMPED);
+}
+
+// lam[j] = v_j^T B v_j for the columns of V (row-major n x n): the signed
+// eigenvalues behind the Jacobi singular values of a symmetric B.
+__global__ void rayleigh_kernel(const double *__restrict__ B, const double *__restrict__ V,
+                                int64_t n, int64_t ldb, int64_t ldv, double *__restrict__ lam) {
+  const int64_t j = (int64_t)blockIdx.x;
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    double bv = 0.0;
+    for (int64_t t = 0; t < n; ++t) bv += B[i * ldb + t] * V[t * ldv + j];
+    acc += V[i * ldv + j] * bv;
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) lam[j] = red[0];
+}
+
+__global__ void or_info_kernel(int32_t *info, int32_t bits) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *info |= bits;
+}
+
+__global__ void zero_i32_kernel(int32_t *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+inline int64_t even_up(int64_t x) { return (x + 1) & ~int64_t(1); }
+
+inline int read_i32(const int32_t *dev, hipStream_t s, int32_t *out) {
+  if (hipStreamSynchronize(s) != hipSuccess) return BSRHT_EDEVICE;
+  if (hipMemcpy(out, dev, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+    return BSRHT_EDEVICE;
+  return BSRHT_OK;
+}
+
+// Workspace of the small SVD stage for an nc x nc problem (nc even).
+template <class A>
+struct SvdBufs {
+  double *X, *V, *S, *Vs, *inv;
+  int32_t *perm;
+  unsigned int *flags;
+  void take(A &a, int64_t nc, int64_t k) {
+    X = a.template take<double>((size_t)(nc * nc));
+    V = a.template take<double>((size_t)(nc * nc));
+    S = a.template take<double>((size_t)nc);
+    Vs = a.template take<double>((size_t)(nc * nc));
+    inv = a.template take<double>((size_t)std::max<int64_t>(k, nc));
+    perm = a.template take<int32_t>((size_t)nc);
+    flags = a.template take<unsigned int>(4);
+  }
+};
+
+// Allocator that only counts (Sizer) or also hands out pointers (Carve).
+struct SizeOnly {
+  Sizer sz;
+  template <class T>
+  T *take(size_t n) {
+    sz.take<T>(n);
+    return nullptr;
+  }
+};
+
+// ----------------------------------------------------------------------------
+// Randomized SVD workspace layout.
+template <class A>
+struct RsvdWs {
+  float *W;
+  void *apply_ws;
+  size_t apply_bytes;
+  double *G, *Ginv, *Q1, *G2, *C2inv;
+  float *Q32, *Z, *M, *Vk;
+  double *gram_part, *Gz;
+  int32_t *flag;
+  SvdBufs<A> qb, sv;
+  void layout(A &a, const bsrht_plan_s *pl, int64_t m, int64_t k) {
+    const int64_t l = pl->l, n = pl->n, lq = std::min(l, m);
+    W = a.template take<float>((size_t)(l * m));
+    apply_bytes = apply_ws_bytes(pl, m);
+    apply_ws = a.template take<char>(apply_bytes);
+    G = a.template take<double>((size_t)(l * l));
+    Ginv = a.template take<double>((size_t)(l * l));
+    Q1 = a.template take<double>((size_t)(m * l));
+    G2 = a.template take<double>((size_t)(l * l));
+    C2inv = a.template take<double>((size_t)(l * l));
+    Q32 = a.template take<float>((size_t)(m * lq));
+    Z = a.template take<float>((size_t)(n * lq));
+    gram_part = a.template take<double>((size_t)std::max(
+        {gram_partial_elems(m, l), gram_partial_elems(n, lq), (int64_t)1}));
+    Gz = a.template take<double>((size_t)(lq * lq));
+    M = a.template take<float>((size_t)(lq * k));
+    Vk = a.template take<float>((size_t)(lq * k));
+    flag = a.template take<int32_t>(4);
+    qb.take(a, even_up(l), l);
+    sv.take(a, even_up(lq), k);
+  }
+};
+
+// ----------------------------------------------------------------------------
+// Nystrom workspace layout.
+template <class A>
+struct NysWs {
+  float *W, *Y, *B;
+  void *apply_ws;
+  size_t apply_bytes;
+  double *Bs, *Cinv, *Mf, *lam, *Z, *gram_part, *Gz, *Mk;
+  int32_t *flag;
+  SvdBufs<A> fb, sv;
+  void layout(A &a, const bsrht_plan_s *pl, int64_t k) {
+    const int64_t l = pl->l, n = pl->n;
+    W = a.template take<float>((size_t)(l * n));
+    Y = a.template take<float>((size_t)(n * l));
+    B = a.template take<float>((size_t)(l * l));
+    apply_bytes = std::max(apply_ws_bytes(pl, n), apply_ws_bytes(pl, l));
+    apply_ws = a.template take<char>(apply_bytes);
+    Bs = a.template take<double>((size_t)(l * l));
+    Cinv = a.template take<double>((size_t)(l * l));
+    Mf = a.template take<double>((size_t)(l * l));
+    lam = a.template take<double>((size_t)l);
+    Z = a.template take<double>((size_t)(n * l));
+    gram_part = a.template take<double>((size_t)std::max(gram_partial_elems(n, l), (int64_t)1));
+    Gz = a.template take<double>((size_t)(l * l));
+    Mk = a.template take<double>((size_t)(l * std::max<int64_t>(k, 1)));
+    flag = a.template take<int32_t>(4);
+    fb.take(a, even_up(l), l);
+    sv.take(a, even_up(l), k);
+  }
+};
+
+// SVD of the nc0 x nc0 matrix given row-major at R (ldr): copies it
+// column-major into the (even-sized, zero-padded) Jacobi buffers and runs
+// the one-sided Jacobi.  Sorted singular values in b.S, right singular
+// vectors as columns of b.Vs (row-major, leading dimension nc).
+template <class A>
+int small_svd(SvdBufs<A> &b, const double *R, int64_t nc0, int64_t ldr, hipStream_t s) {
+  const int64_t nc = even_up(nc0);
+  int st = fill_f64(b.X, nc * nc, 0.0, s);  // zero padding: a zero column sorts last
+  if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); return st; }
+  // column-major X: X[j*nc + i] = R[i][j]
+  st = transpose_f64(R, nc0, nc0, ldr, b.X, nc, s);
+  if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); return st; }
+  return jacobi_svd(b.X, nc, nc, nc, b.V, nc, b.S, b.Vs, nc, b.perm, b.flags, kMaxSweeps, s);
+}
+
+}  // namespace
+}  // namespace bsrht
+
+using namespace bsrht;
 
 extern "C" {
 
-size_t rsvd_workspace(bsrht_plan_t, int64_t, int64_t) { return 0; }
-
-int rsvd(bsrht_plan_t, const float *, int64_t, int64_t, int64_t, float *, double *, float *,
-         int32_t *, void *, size_t, void *) {
-  return BSRHT_EUNSUPPORTED;
+size_t rsvd_workspace(bsrht_plan_t plan, int64_t m, int64_t k) {
+  if (!plan || m < 1 || k < 1) return 0;
+  SizeOnly so;
+  RsvdWs<SizeOnly> w;
+  w.layout(so, plan, m, k);
+  return align256(so.sz.used);
 }
 
-size_t nystrom_workspace(bsrht_plan_t, int64_t) { return 0; }
+int rsvd(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, int64_t k, float *U,
+         double *S, float *V, int32_t *info, void *ws, size_t ws_bytes, void *stream) {
+  if (!plan || !A || !U || !S || !V || !info || m < 1 || k < 1 || lda < m) return BSRHT_EINVAL;
+  if (ws_bytes < rsvd_workspace(plan, m, k) || !ws) return BSRHT_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = plan->n, l = plan->l;
+  int64_t lq = std::min(l, m);
+  if (even_up(std::max(l, lq)) > 4096) return BSRHT_EUNSUPPORTED;
+  Carve cv(ws, ws_bytes);
+  RsvdWs<Carve> w;
+  w.layout(cv, plan, m, k);
+  if (cv.overflow) return BSRHT_ENOMEM;
+  int st;
+  zero_i32_kernel<<<1, 64, 0, s>>>(info, 1);
+  BSRHT_LAUNCH_CHECK();
 
-int nystrom(bsrht_plan_t, const float *, int64_t, int64_t, float *, double *, int32_t *, void *,
-            size_t, void *) {
-  return BSRHT_EUNSUPPORTED;
+  // 1. W = Omega A  (l x m): the paper's Y = A_p Omega^T for A_p = A^T.
+  if (plan->precision == BSRHT_SPLIT_BF16)
+    st = apply_split_bf16(plan, A, m, lda, w.W, m, w.apply_ws, w.apply_bytes, s);
+  else
+    st = apply_fp32(plan, A, m, lda, w.W, m, w.apply_ws, w.apply_bytes, s);
+  if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); return st; }
+
+  // 2. Q = orth(W^T) (m x lq).  l >= m: range(W^T) is all of R^m, Q = I.
+  if (l >= m) {
+    lq = m;
+    eye_f32_kernel<<<(unsigned)((m * m + 255) / 256), 256, 0, s>>>(w.Q32, m, m);
+    BSRHT_LAUNCH_CHECK();
+  } else {
+    // Cholesky-QR2 of W^T: G = W W^T, G = C^T C, Q1 = W^T C^{-1}; then again.
+    const int gs = gram_splits(m, l);
+    st = gram_f32(w.W, m, l, 1, m, w.G, l, w.gram_part, gs, s);  // X = W^T: X[r][c] = W[c][r]
+    if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); return st; }
+    BSRHT_TRY(cholesky_upper(w.G, l, l, (double)l * kU64, w.flag, s));
+    int32_t hf = 0;
+    BSRHT_TRY(read_i32(w.flag, s, &hf));
+    int64_t lk = l;  // columns of Q1
+    if (hf == 0) {
+      BSRHT_TRY(trinv_upper(w.G, l, l, w.Ginv, l, s));
+      GemmDesc d;
+      d.M = m; d.N = l; d.K = l;
+      d.sai = 1; d.sak = m;       // A = W^T
+      d.sbk = l; d.sbj = 1;       // B = C^{-1}
+      d.ldc = l;
+      BSRHT_TRY(gemm_f32f64_f64(d, w.W, w.Ginv, w.Q1, s));
+    } else {
+      // W^T is rank deficient (e.g. rank(A) < l): an eigen split of
+      // G = W W^T keeps the eigenvalues above l u lambda_max and
+      // Q1 = W^T V_+ Lam_+^{-1/2}.
+      st = gram_f32(w.W, m, l, 1, m, w.G, l, w.gram_part, gs, s);
+      if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); return st; }
+      BSRHT_TRY(small_svd(w.qb, w.G, l, l, s));
+      std::vector<double> ev((size_t)l);
+      if (hipStreamSynchronize(s) != hipSuccess ||
+          hipMemcpy(ev.data(), w.qb.S, sizeof(double) * (size_t)l, hipMemcpyDeviceToHost) !=
+              hipSuccess)
+        return BSRHT_EDEVICE;
+      int64_t keep = 0;
+      for (int64_t i = 0; i < l; ++i)
+        if (ev[(size_t)i] > (double)l * kU64 * ev[0] && ev[(size_t)i] > 0.0) ++keep;
+      if (keep < 1) keep = 1;
+      std::vector<double> sc((size_t)keep);
+      for (int64_t i = 0; i < keep; ++i) sc[(size_t)i] = 1.0 / sqrt(ev[(size_t)i]);
+      if (hipMemcpy(w.qb.inv, sc.data(), sizeof(double) * (size_t)keep, hipMemcpyHostToDevice) !=
+          hipSuccess)
+        return BSRHT_EDEVICE;
+      const int64_t nce = even_up(l);
+      BSRHT_TRY(scale_cols_f64(w.qb.Vs, l, keep, keep, nce, w.qb.inv, w.Ginv, keep, s));
+      GemmDesc d;
+      d.M = m; d.N = keep; d.K = l;
+      d.sai = 1; d.sak = m;
+      d.sbk = keep; d.sbj = 1;
+      d.ldc = keep;
+      BSRHT_TRY(gemm_f32f64_f64(d, w.W, w.Ginv, w.Q1, s));
+      lk = keep;
+      or_info_kernel<<<1, 1, 0, s>>>(info, BSRHT_INFO_QB_FALLBACK);
+      BSRHT_LAUNCH_CHECK();
+    }
+    // second pass: G2 = Q1^T Q1, C2, Q = Q1 C2^{-1}
+    const int gs2 = gram_splits(m, lk);
+    BSRHT_TRY(gram_f64(w.Q1, m, lk, lk, 1, w.G2, lk, w.gram_part, gs2, s));
+    BSRHT_TRY(cholesky_upper(w.G2, lk, lk, 1e-14, w.flag + 1, s));
+    int32_t hf2 = 0;
+    BSRHT_TRY(read_i32(w.flag + 1, s, &hf2));
+    if (hf2 != 0) {  // Q1 has orthonormal columns to O(eps*kappa^2): should not happen
+      debug_report(__FILE__, __LINE__, "second Cholesky-QR pass", BSRHT_EDEVICE);
+      return BSRHT_EDEVICE;
+    }
+    BSRHT_TRY(trinv_upper(w.G2, lk, lk, w.C2inv, lk, s));
+    GemmDesc d;
+    d.M = m; d.N = lk; d.K = lk;
+    d.sai = lk; d.sak = 1;
+    d.sbk = lk; d.sbj = 1;
+    d.ldc = lk;
+    BSRHT_TRY(gemm_f64f64_f32(d, w.Q1, w.C2inv, w.Q32, s));
+    lq = lk;
+  }
+
+  // 3. Z = A Q  (n x lq): the paper's Z = Q^T A_p, transposed; matrix cores.
+  {
+    GemmDesc d;
+    d.M = n; d.N = lq; d.K = m;
+    d.sai = lda; d.sak = 1;
+    d.sbk = lq; d.sbj = 1;
+    d.ldc = lq;
+    hipEvent_t ev = timing_begin(BSRHT_TIMING_GEMM_AQ, s);
+    st = gemm_f32(d, A, w.Q32, w.Z, s);
+    timing_end(ev, s);
+    if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); return st; }
+  }
+  // 4. R-factor of Z: Gz = Z^T Z (FP64), Gz = R^T R.
+  const int gsz = gram_splits(n, lq);
+  BSRHT_TRY(gram_f32(w.Z, n, lq, lq, 1, w.Gz, lq, w.gram_part, gsz, s));
+  BSRHT_TRY(cholesky_upper(w.Gz, lq, lq, (double)lq * kU32 * kU32, w.flag + 2, s));
+  int32_t hz = 0;
+  BSRHT_TRY(read_i32(w.flag + 2, s, &hz));
+  int pw;
+  if (hz == 0) {
+    // 5. SVD of R: R = Ut St Vt^T
+    BSRHT_TRY(small_svd(w.sv, w.Gz, lq, lq, s));
+    pw = 1;
+  } else {
+    // rank(Z) < lq: Z^T Z = Vt St^2 Vt^T from its eigen decomposition
+    BSRHT_TRY(gram_f32(w.Z, n, lq, lq, 1, w.Gz, lq, w.gram_part, gsz, s));
+    BSRHT_TRY(small_svd(w.sv, w.Gz, lq, lq, s));
+    // the Jacobi values are St^2: take square roots through the scale step
+    pw = 0;
+  }
+  const int64_t nce = even_up(lq);
+  // singular values of Z (sqrt of the Gram eigenvalues on the fallback path)
+  if (pw == 0) {
+    std::vector<double> ev((size_t)lq);
+    if (hipStreamSynchronize(s) != hipSuccess ||
+        hipMemcpy(ev.data(), w.sv.S, sizeof(double) * (size_t)lq, hipMemcpyDeviceToHost) !=
+            hipSuccess)
+      return BSRHT_EDEVICE;
+    for (auto &x : ev) x = x > 0.0 ? sqrt(x) : 0.0;
+    if (hipMemcpy(w.sv.S, ev.data(), sizeof(double) * (size_t)lq, hipMemcpyHostToDevice) !=
+        hipSuccess)
+      return BSRHT_EDEVICE;
+  }
+  // 6. U = Z Vt_k St_k^{-1}, S = St_k, V = Q Vt_k
+  finish_sigma_kernel<<<(unsigned)((k + 255) / 256), 256, 0, s>>>(
+      w.sv.S, lq, k, (double)lq * kU32, 1, w.sv.inv, S, info);
+  BSRHT_LAUNCH_CHECK();
+  const int64_t keep = std::min(k, lq);
+  BSRHT_TRY(scale_cols_f64_f32(w.sv.Vs, lq, keep, k, nce, w.sv.inv, w.M, k, s));
+  {
+    GemmDesc d;
+    d.M = n; d.N = k; d.K = lq;
+    d.sai = lq; d.sak = 1;
+    d.sbk = k; d.sbj = 1;
+    d.ldc = k;
+    BSRHT_TRY(gemm_f32(d, w.Z, w.M, U, s));
+  }
+  BSRHT_TRY(scale_cols_f64_f32(w.sv.Vs, lq, keep, k, nce, nullptr, w.Vk, k, s));
+  {
+    GemmDesc d;
+    d.M = m; d.N = k; d.K = lq;
+    d.sai = lq; d.sak = 1;
+    d.sbk = k; d.sbj = 1;
+    d.ldc = k;
+    BSRHT_TRY(gemm_f32(d, w.Q32, w.Vk, V, s));
+  }
+  return BSRHT_OK;
+}
+
+size_t nystrom_workspace(bsrht_plan_t plan, int64_t k) {
+  if (!plan || k < 1) return 0;
+  SizeOnly so;
+  NysWs<SizeOnly> w;
+  w.layout(so, plan, k);
+  return align256(so.sz.used);
+}
+
+int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U, double *lambda,
+            int32_t *info, void *ws, size_t ws_bytes, void *stream) {
+  if (!plan || !A || !U || !lambda || !info || k < 1 || lda < plan->n) return BSRHT_EINVAL;
+  if (ws_bytes < nystrom_workspace(plan, k) || !ws) return BSRHT_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = plan->n, l = plan->l;
+  if (even_up(l) > 4096) return BSRHT_EUNSUPPORTED;
+  Carve cv(ws, ws_bytes);
+  NysWs<Carve> w;
+  w.layout(cv, plan, k);
+  if (cv.overflow) return BSRHT_ENOMEM;
+  int st;
+  zero_i32_kernel<<<1, 64, 0, s>>>(info, 1);
+  BSRHT_LAUNCH_CHECK();
+  auto sketch = [&](const float *X, int64_t mm, int64_t ldx, float *Yo) {
+    if (plan->precision == BSRHT_SPLIT_BF16)
+      return apply_split_bf16(plan, X, mm, ldx, Yo, mm, w.apply_ws, w.apply_bytes, s);
+    return apply_fp32(plan, X, mm, ldx, Yo, mm, w.apply_ws, w.apply_bytes, s);
+  };
+  // 1. Y = A Omega^T = (Omega A)^T (A symmetric)
+  BSRHT_TRY(sketch(A, n, lda, w.W));
+  BSRHT_TRY(transpose_f32(w.W, l, n, n, w.Y, l, s));
+  // 2. Cholesky factor of Omega Y (symmetrised)
+  BSRHT_TRY(sketch(w.Y, l, l, w.B));
+  sym_f64_kernel<<<(unsigned)((l * l + 255) / 256), 256, 0, s>>>(w.B, l, l, w.Bs, l);
+  BSRHT_LAUNCH_CHECK();
+  BSRHT_TRY(scale_cols_f64(w.Bs, l, l, l, l, nullptr, w.Mf, l, s));
+  BSRHT_TRY(cholesky_upper(w.Mf, l, l, (double)l * kU32, w.flag, s));
+  int32_t hf = 0;
+  BSRHT_TRY(read_i32(w.flag, s, &hf));
+  int64_t lz = l;
+  if (hf == 0) {
+    // 3. Z = Y C^{-1}
+    BSRHT_TRY(trinv_upper(w.Mf, l, l, w.Cinv, l, s));
+    GemmDesc d;
+    d.M = n; d.N = l; d.K = l;
+    d.sai = l; d.sak = 1;
+    d.sbk = l; d.sbj = 1;
+    d.ldc = l;
+    BSRHT_TRY(gemm_f32f64_f64(d, w.Y, w.Cinv, w.Z, s));
+  } else {
+    // Remark 3.1: B = V Lam V^T, keep Lam_i > l u Lam_max, Z = Y V_+ Lam_+^{-1/2}
+    BSRHT_TRY(small_svd(w.fb, w.Bs, l, l, s));
+    const int64_t nce = even_up(l);
+    rayleigh_kernel<<<(unsigned)l, 256, 0, s>>>(w.Bs, w.fb.Vs, l, l, nce, w.lam);
+    BSRHT_LAUNCH_CHECK();
+    std::vector<double> lam((size_t)l);
+    if (hipStreamSynchronize(s) != hipSuccess ||
+        hipMemcpy(lam.data(), w.lam, sizeof(double) * (size_t)l, hipMemcpyDeviceToHost) !=
+            hipSuccess)
+      return BSRHT_EDEVICE;
+    double lmax = 0.0;
+    for (double x : lam) lmax = std::max(lmax, x);
+    // kept columns in Jacobi order (descending |lambda|)
+    std::vector<int> idx;
+    std::vector<double> sc;
+    for (int64_t i = 0; i < l; ++i)
+      if (lam[(size_t)i] > (double)l * kU32 * lmax && lam[(size_t)i] > 0.0) {
+        idx.push_back((int)i);
+        sc.push_back(1.0 / sqrt(lam[(size_t)i]));
+      }
+    if (idx.empty()) return BSRHT_EDEVICE;
+    lz = (int64_t)idx.size();
+    // Mf = V_+ Lam_+^{-1/2} (l x lz): gather the kept columns on the host side
+    // of the index list, scale on the device.
+    std::vector<double> Vh((size_t)(l * nce));
+    if (hipMemcpy(Vh.data(), w.fb.Vs, sizeof(double) * Vh.size(), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+      return BSRHT_EDEVICE;
+    std::vector<double> Mh((size_t)(l * lz));
+    for (int64_t i = 0; i < l; ++i)
+      for (int64_t c = 0; c < lz; ++c)
+        Mh[(size_t)(i * lz + c)] = Vh[(size_t)(i * nce + idx[(size_t)c])] * sc[(size_t)c];
+    if (hipMemcpy(w.Mf, Mh.data(), sizeof(double) * Mh.size(), hipMemcpyHostToDevice) !=
+        hipSuccess)
+      return BSRHT_EDEVICE;
+    GemmDesc d;
+    d.M = n; d.N = lz; d.K = l;
+    d.sai = l; d.sak = 1;
+    d.sbk = lz; d.sbj = 1;
+    d.ldc = lz;
+    BSRHT_TRY(gemm_f32f64_f64(d, w.Y, w.Mf, w.Z, s));
+    or_info_kernel<<<1, 1, 0, s>>>(info, BSRHT_INFO_CHOL_FALLBACK);
+    BSRHT_LAUNCH_CHECK();
+  }
+  // 4. R-factor of Z: Gz = Z^T Z = R^T R
+  const int gsz = gram_splits(n, lz);
+  BSRHT_TRY(gram_f64(w.Z, n, lz, lz, 1, w.Gz, lz, w.gram_part, gsz, s));
+  BSRHT_TRY(scale_cols_f64(w.Gz, lz, lz, lz, lz, nullptr, w.Bs, lz, s));
+  BSRHT_TRY(cholesky_upper(w.Gz, lz, lz, 1e-15 * (double)lz, w.flag + 1, s));
+  int32_t hz = 0;
+  BSRHT_TRY(read_i32(w.flag + 1, s, &hz));
+  // 5. SVD of R (or the eigen decomposition of Z^T Z when R is singular)
+  const double *Rsrc = hz == 0 ? w.Gz : w.Bs;
+  BSRHT_TRY(small_svd(w.sv, Rsrc, lz, lz, s));
+  if (hz != 0) {
+    std::vector<double> ev((size_t)lz);
+    if (hipStreamSynchronize(s) != hipSuccess ||
+        hipMemcpy(ev.data(), w.sv.S, sizeof(double) * (size_t)lz, hipMemcpyDeviceToHost) !=
+            hipSuccess)
+      return BSRHT_EDEVICE;
+    for (auto &x : ev) x = x > 0.0 ? sqrt(x) : 0.0;
+    if (hipMemcpy(w.sv.S, ev.data(), sizeof(double) * (size_t)lz, hipMemcpyHostToDevice) !=
+        hipSuccess)
+      return BSRHT_EDEVICE;
+  }
+  // 6. U = Z Vt_k St_k^{-1}; lambda = St_k^2
+  finish_sigma_kernel<<<(unsigned)((k + 255) / 256), 256, 0, s>>>(
+      w.sv.S, lz, k, (double)lz * kU32, 2, w.sv.inv, lambda, info);
+  BSRHT_LAUNCH_CHECK();
+  const int64_t keep = std::min(k, lz);
+  const int64_t nce = even_up(lz);
+  BSRHT_TRY(scale_cols_f64(w.sv.Vs, lz, keep, k, nce, w.sv.inv, w.Mk, k, s));
+  GemmDesc d;
+  d.M = n; d.N = k; d.K = lz;
+  d.sai = lz; d.sak = 1;
+  d.sbk = k; d.sbj = 1;
+  d.ldc = k;
+  return gemm_f64f64_f32(d, w.Z, w.Mk, U, s);
 }
 
 }  // extern "C"

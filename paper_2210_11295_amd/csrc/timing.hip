@@ -1,6 +1,9 @@
 // Instrumentation: HIP events recorded around the launches of one chosen
 // kernel, on the stream that kernel runs on, so a benchmark can report that
 // kernel's own duration next to the whole call's.
+#include <stdio.h>
+#include <stdlib.h>
+
 #include <vector>
 
 #include "common.h"
@@ -17,6 +20,13 @@ struct TimingState {
 TimingState g_timing;
 
 }  // namespace
+
+void debug_report(const char *file, int line, const char *what, int status) {
+  static const bool on = getenv("BSRHT_DEBUG") != nullptr;
+  if (!on) return;
+  fprintf(stderr, "[bsrht] %s:%d: %s -> status %d (%s)\n", file, line, what, status,
+          bsrht_strerror(status));
+}
 
 hipEvent_t timing_begin(int which, hipStream_t s) {
   if (g_timing.which != which) return nullptr;
