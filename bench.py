@@ -73,6 +73,82 @@ def cpu_baseline(A, cfg):
                       f"(l={cfg['l']}); numpy FP64 FWHT, single thread; {dt:.2f} s"}
 
 
+def _fro_error(A, U, S, V, chunk=1 << 16):
+    """||A - U diag(S) V^T||_F / ||A||_F in FP64 on the device (measurement)."""
+    import torch
+    SVt = (S.double()[:, None] * V.double().T)
+    num = 0.0
+    den = 0.0
+    for r0 in range(0, A.shape[0], chunk):
+        Ab = A[r0:r0 + chunk].double()
+        E = Ab - U[r0:r0 + chunk].double() @ SVt
+        num += float((E * E).sum())
+        den += float((Ab * Ab).sum())
+    return (num / den) ** 0.5
+
+
+def bench_rsvd(bs, A, plan, cfg, reps):
+    """Algorithm 1 at full size: rank k, l = 512, FP64 Cholesky-QR2 on the GPU."""
+    import torch
+    n, m, k = cfg["n"], cfg["m"], cfg["k"]
+    ws = torch.empty(max(1, bs.rsvd_workspace(plan, m, k)), dtype=torch.uint8, device=A.device)
+    log(f"bench: rsvd rank {k} (workspace {ws.numel() / 2**30:.2f} GiB)")
+    U, S, V, info = bs.rsvd(plan, A, k, ws)
+    torch.cuda.synchronize()
+    bs.timing_enable(bs.TIMING_GEMM_AQ)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        U, S, V, info = bs.rsvd(plan, A, k, ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    gms, gl = bs.timing_read()
+    bs.timing_enable(bs.TIMING_OFF)
+    lq = min(cfg["l"], m)
+    gemm_ms = gms / max(gl, 1)
+    err = _fro_error(A, U, S, V)
+    return {"ms": round(dt * 1e3, 2), "k": k, "l": cfg["l"],
+            "gemm_AQ_ms": round(gemm_ms, 3),
+            "gemm_AQ_TFLOPs": round(2.0 * n * m * lq / (gemm_ms * 1e-3) / 1e12, 2),
+            "gemm_AQ_frac_fp32_mfma_peak": round(2.0 * n * m * lq / (gemm_ms * 1e-3) / 157.3e12, 4),
+            "rel_fro_error": err, "info": int(info.item())}
+
+
+def bench_nystrom(bs, reps):
+    """Algorithm 2 on the 65536 x 65536 SPD matrix (s_j = j^-3, p = 64, l = 1024,
+    rank 512), FP64 factorisations on the GPU."""
+    import torch
+    import workloads
+    c = workloads.CONFIGS["c5_nystrom"]
+    n, l, k, p = c["n"], c["l"], c["k"], c["p"]
+    dev = torch.device("cuda:0")
+    log(f"bench: nystrom, generating SPD {n}x{n}")
+    A, X, s = workloads.spd(n, c["d"], c["spectrum"], c["seed"], device=dev, return_factors=True)
+    plan = bs.Plan(n, p, l, c["seed"], device=dev)
+    ws = torch.empty(max(1, bs.nystrom_workspace(plan, k)), dtype=torch.uint8, device=dev)
+    U, lam, info = bs.nystrom(plan, A, k, ws)
+    torch.cuda.synchronize()
+    bs.timing_enable(bs.TIMING_APPLY_FP32)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        U, lam, info = bs.nystrom(plan, A, k, ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    kms, kl = bs.timing_read()
+    bs.timing_enable(bs.TIMING_OFF)
+    # trace error via the structure: A - U diag(lam) U^T lies in span[X, U]
+    B, _ = torch.linalg.qr(torch.cat([X, U.double()], dim=1))
+    XtB = X.T @ B
+    UtB = U.double().T @ B
+    E = (XtB.T * s[None, :]) @ XtB - (UtB.T * lam[None, :]) @ UtB
+    ev = torch.linalg.eigvalsh(0.5 * (E + E.T))
+    err = float(ev.abs().sum() / s.sum())
+    opt = float(s[k:].sum() / s.sum())
+    return {"ms": round(dt * 1e3, 2), "n": n, "l": l, "k": k, "p": p,
+            "sketch_kernel_ms_per_call": round(kms / max(reps, 1), 3),
+            "trace_rel_error": err, "optimal_trace_rel_error": opt,
+            "info": int(info.item())}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +157,12 @@ def main():
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of A (HBM counter calibration)")
+    ap.add_argument("--skip-lowrank", action="store_true",
+                    help="skip the randomized SVD and Nystrom measurements")
+    ap.add_argument("--lowrank-reps", type=int, default=3)
+    ap.add_argument("--only", choices=["all", "sketch", "rsvd", "nystrom"], default="all",
+                    help="profiling aid: run one part (the JSON line is printed for 'all' "
+                         "and 'sketch' only)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -92,6 +174,9 @@ def main():
     import paper_2210_11295_amd as bs
     import workloads
 
+    if args.only == "nystrom":
+        log(json.dumps(bench_nystrom(bs, args.lowrank_reps)))
+        return
     cfg = dict(workloads.CONFIGS["c2_fp32_apply"])
     n, m, p, l, seed = cfg["n"], cfg["m"], cfg["p"], cfg["l"], cfg["seed"]
     dev = torch.device("cuda:0")
@@ -100,6 +185,9 @@ def main():
     A = workloads.lowrank_tall(n, m, cfg["spectrum"], seed, device=dev)
     torch.cuda.synchronize()
     plan = bs.Plan(n, p, l, seed, device=dev)
+    if args.only == "rsvd":
+        log(json.dumps(bench_rsvd(bs, A, plan, cfg, args.lowrank_reps)))
+        return
     Y = torch.empty(l, m, dtype=torch.float32, device=dev)
     ws = torch.empty(max(1, bs.bsrht_apply_workspace(plan, m)), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
@@ -172,9 +260,17 @@ def main():
                      "kernel_avg_us": round(kern_avg_ms * 1e3, 2),
                      "alg_bytes_per_launch": alg_bytes},
     }
+    if args.only == "sketch":
+        args.skip_lowrank = True
+    if not args.skip_lowrank:
+        out["rsvd"] = bench_rsvd(bs, A, plan, cfg, args.lowrank_reps)
     if not args.skip_cpu_baseline:
         log("bench: timing the CPU oracle on one block")
         out["cpu_baseline"] = cpu_baseline(A, cfg)
+    if not args.skip_lowrank:
+        del A, Y, ws
+        torch.cuda.empty_cache()
+        out["nystrom"] = bench_nystrom(bs, args.lowrank_reps)
     print(json.dumps(out), flush=True)
 
 

@@ -184,9 +184,11 @@ size_t nystrom_workspace(bsrht_plan_t plan, int64_t k);
  *   Cholesky, C upper); Z = Y C^{-1}; Z = Q~ R (FP64 Gram + Cholesky);
  *   R = Ut St Vt^T (FP64 one-sided Jacobi); U = Z Vt_k St_k^{-1} (= Q~ Ut_k);
  *   lambda = St_k^2;  A ~= U diag(lambda) U^T.
- * Remark 3.1: when a Cholesky pivot of B is <= l * 2^-24 * max(diag(B)),
- * B = V Lam V^T is used instead, keeping Lam_i > l * 2^-24 * Lam_max and
- * Z = Y V_+ Lam_+^{-1/2}; BSRHT_INFO_CHOL_FALLBACK is set.
+ * Remark 3.1: when a Cholesky pivot of B is <= l * 2^-53 * max(diag(B)) (the
+ * factorisation is FP64), B = V Lam V^T is used instead, keeping
+ * Lam_i > l * 2^-53 * Lam_max and Z = Y V_+ Lam_+^{-1/2};
+ * BSRHT_INFO_CHOL_FALLBACK is set.  rsvd and nystrom synchronise the stream
+ * (to read this flag back) before returning.
  *
  * A      : device float32 n x n, lda >= n (only read through Omega).
  * U      : device float32 n x k (leading dimension k).

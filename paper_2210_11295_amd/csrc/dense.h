@@ -44,7 +44,11 @@ int64_t gram_partial_elems(int64_t n, int64_t Kmax);
 // In-place FP64 Cholesky of the symmetric G (upper triangle read): G = C^T C,
 // C upper.  *info (device) = 0 on success, else the 1-based index of the first
 // pivot <= tol * max(diag(G)).
-int cholesky_upper(double *G, int64_t n, int64_t ldg, double tol, int32_t *info, hipStream_t s);
+// `state` is device scratch of cholesky_state_bytes() bytes.
+int cholesky_upper(double *G, int64_t n, int64_t ldg, double tol, int32_t *info, void *state,
+                   hipStream_t s);
+size_t cholesky_state_bytes();
+// n <= 2048.
 int trinv_upper(const double *C, int64_t n, int64_t ldc, double *Ci, int64_t ldi, hipStream_t s);
 int eye(double *M, int64_t n, int64_t ld, hipStream_t s);
 int fill_f64(double *p, int64_t count, double value, hipStream_t s);

@@ -234,76 +234,133 @@ int gram_splits(int64_t n, int64_t K) {
 namespace {
 
 // ---------------------------------------------------------------------------
-// FP64 Cholesky G = C^T C with C upper triangular, in place (one workgroup).
-// Right-looking: row k of C is G[k][k:] / sqrt(pivot); the trailing block is
-// updated by the outer product of that row.  A pivot <= tol * max(diag(G))
-// stops the factorisation and reports its 1-based index in *info (the
-// Remark 3.1 break-down); the lower triangle is zeroed on success.
-__global__ __launch_bounds__(1024) void cholesky_kernel(double *G, int64_t n, int64_t ldg,
-                                                        double tol, int32_t *info) {
-  __shared__ double s_piv;
-  __shared__ double s_thresh;
-  __shared__ int s_fail;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  if (tid == 0) {
-    double mx = 0.0;
-    for (int64_t i = 0; i < n; ++i) mx = fmax(mx, G[i * ldg + i]);
-    s_thresh = tol * mx;
-    s_fail = 0;
-  }
+// FP64 Cholesky G = C^T C with C upper triangular, in place, blocked
+// right-looking with nb x nb diagonal blocks: factor the diagonal block in
+// LDS, solve the block row C12 = C11^{-T} G12, update the trailing block
+// G22 -= C12^T C12 on the matrix cores.  A pivot <= tol * max(diag(G)) of the
+// original G stops the factorisation: its 1-based index goes to *info and the
+// later steps do nothing (the Remark 3.1 break-down).
+constexpr int kCholNB = 32;
+
+struct CholState {
+  double thresh;
+  int32_t stop;
+};
+
+__global__ __launch_bounds__(256) void chol_init_kernel(const double *__restrict__ G, int64_t n,
+                                                        int64_t ldg, double tol,
+                                                        CholState *st, int32_t *info) {
+  __shared__ double red[256];
+  double mx = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) mx = fmax(mx, G[i * ldg + i]);
+  red[threadIdx.x] = mx;
   __syncthreads();
-  for (int64_t k = 0; k < n; ++k) {
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    st->thresh = tol * red[0];
+    st->stop = 0;
+    *info = 0;
+  }
+}
+
+// Factor the nb x nb diagonal block at (kb, kb) in LDS.
+__global__ __launch_bounds__(1024) void chol_diag_kernel(double *G, int64_t ldg, int64_t kb,
+                                                         int nb, CholState *st, int32_t *info) {
+  __shared__ double T[kCholNB][kCholNB + 1];
+  __shared__ int s_fail;
+  if (st->stop) return;
+  const int tid = threadIdx.x;
+  const int r = tid / kCholNB, c = tid % kCholNB;
+  if (r < nb && c < nb) T[r][c] = G[(kb + r) * ldg + kb + c];
+  if (tid == 0) s_fail = 0;
+  __syncthreads();
+  const double thresh = st->thresh;
+  for (int k = 0; k < nb; ++k) {
     if (tid == 0) {
-      const double p = G[k * ldg + k];
-      if (!(p > s_thresh)) {
-        s_fail = (int)(k + 1);
-      } else {
-        s_piv = sqrt(p);
-        G[k * ldg + k] = s_piv;
-      }
+      const double p = T[k][k];
+      if (!(p > thresh))
+        s_fail = (int)(kb + k + 1);
+      else
+        T[k][k] = sqrt(p);
     }
     __syncthreads();
     if (s_fail) break;
-    const double inv = 1.0 / s_piv;
-    for (int64_t j = k + 1 + tid; j < n; j += nt) G[k * ldg + j] *= inv;
+    if (r == k && c > k && c < nb) T[k][c] /= T[k][k];
     __syncthreads();
-    // trailing update of the upper triangle: G[i][j] -= C[k][i] C[k][j], k < i <= j
-    const int64_t rem = n - k - 1;
-    for (int64_t e = tid; e < rem * rem; e += nt) {
-      const int64_t i = k + 1 + e / rem, j = k + 1 + e % rem;
-      if (j >= i) G[i * ldg + j] -= G[k * ldg + i] * G[k * ldg + j];
-    }
+    if (r > k && r < nb && c >= r && c < nb) T[r][c] -= T[k][r] * T[k][c];
     __syncthreads();
   }
   if (s_fail) {
-    if (tid == 0) *info = s_fail;
+    if (tid == 0) {
+      st->stop = 1;
+      *info = s_fail;
+    }
     return;
   }
-  for (int64_t e = tid; e < n * n; e += nt) {
-    const int64_t i = e / n, j = e % n;
-    if (j < i) G[i * ldg + j] = 0.0;
-  }
-  if (tid == 0) *info = 0;
+  if (r < nb && c < nb) G[(kb + r) * ldg + kb + c] = (c >= r) ? T[r][c] : 0.0;
 }
 
-// Inverse of an upper-triangular n x n matrix C (row-major): Ci = C^{-1},
-// also upper triangular.  Column j of Ci solves C x = e_j by back
-// substitution; one thread per column, columns independent.
-__global__ void trinv_upper_kernel(const double *__restrict__ C, int64_t n, int64_t ldc,
-                                   double *__restrict__ Ci, int64_t ldi) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Block row: C12[:, j] = C11^{-T} G12[:, j] for the columns j right of the
+// diagonal block (forward substitution with the lower-triangular C11^T).
+__global__ __launch_bounds__(256) void chol_trsm_kernel(double *G, int64_t n, int64_t ldg,
+                                                        int64_t kb, int nb, const CholState *st) {
+  __shared__ double C11[kCholNB][kCholNB + 1];
+  if (st->stop) return;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nb * nb; e += blockDim.x) C11[e / nb][e % nb] = G[(kb + e / nb) * ldg + kb + e % nb];
+  __syncthreads();
+  const int64_t j = kb + nb + (int64_t)blockIdx.x * blockDim.x + tid;
   if (j >= n) return;
-  for (int64_t i = n - 1; i >= 0; --i) {
-    double v;
-    if (i > j) {
-      v = 0.0;
-    } else {
-      double s = (i == j) ? 1.0 : 0.0;
-      for (int64_t t = i + 1; t <= j; ++t) s -= C[i * ldc + t] * Ci[t * ldi + j];
-      v = s / C[i * ldc + i];
+  double x[kCholNB];
+#pragma unroll
+  for (int i = 0; i < kCholNB; ++i) {
+    if (i < nb) {
+      double s = G[(kb + i) * ldg + j];
+#pragma unroll
+      for (int t = 0; t < kCholNB; ++t)
+        if (t < i) s -= C11[t][i] * x[t];
+      x[i] = s / C11[i][i];
+      G[(kb + i) * ldg + j] = x[i];
     }
-    Ci[i * ldi + j] = v;
   }
+}
+
+// zero the strict lower triangle after a successful factorisation
+__global__ void chol_finish_kernel(double *G, int64_t n, int64_t ldg, const CholState *st) {
+  if (st->stop) return;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int64_t i = idx / n, j = idx % n;
+  if (j < i) G[i * ldg + j] = 0.0;
+}
+
+// Inverse of an upper-triangular n x n matrix C (row-major): column j of
+// Ci = C^{-1} solves C x = e_j by back substitution; one wave per column, the
+// dot product of each step split across the lanes, x kept in LDS.
+constexpr int kTrinvWaves = 4;
+
+__global__ __launch_bounds__(64 * kTrinvWaves) void trinv_upper_kernel(
+    const double *__restrict__ C, int64_t n, int64_t ldc, double *__restrict__ Ci, int64_t ldi) {
+  extern __shared__ double s_x[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * kTrinvWaves + wv;
+  double *x = s_x + (int64_t)wv * n;
+  if (j >= n) return;
+  for (int64_t i = lane; i < n; i += 64) x[i] = 0.0;
+  for (int64_t i = j; i >= 0; --i) {
+    double s = 0.0;
+    for (int64_t t = i + 1 + lane; t <= j; t += 64) s += C[i * ldc + t] * x[t];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    const double xi = (((i == j) ? 1.0 : 0.0) - s) / C[i * ldc + i];
+    if (lane == 0) x[i] = xi;
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): x[i] is in LDS before the next step
+    __builtin_amdgcn_wave_barrier();
+  }
+  for (int64_t i = lane; i < n; i += 64) Ci[i * ldi + j] = x[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -495,11 +552,42 @@ __global__ void scale_cols_kernel(const TS *__restrict__ src, int64_t rows, int6
 
 }  // namespace
 
-int cholesky_upper(double *G, int64_t n, int64_t ldg, double tol, int32_t *info, hipStream_t s) {
-  cholesky_kernel<<<1, 1024, 0, s>>>(G, n, ldg, tol, info);
+int cholesky_upper(double *G, int64_t n, int64_t ldg, double tol, int32_t *info,
+                   void *state, hipStream_t s) {
+  if (n <= 0) return BSRHT_OK;
+  CholState *st = static_cast<CholState *>(state);
+  chol_init_kernel<<<1, 256, 0, s>>>(G, n, ldg, tol, st, info);
+  BSRHT_LAUNCH_CHECK();
+  for (int64_t kb = 0; kb < n; kb += kCholNB) {
+    const int nb = (int)std::min<int64_t>(kCholNB, n - kb);
+    chol_diag_kernel<<<1, 1024, 0, s>>>(G, ldg, kb, nb, st, info);
+    BSRHT_LAUNCH_CHECK();
+    const int64_t rest = n - kb - nb;
+    if (rest <= 0) break;
+    chol_trsm_kernel<<<(unsigned)((rest + 255) / 256), 256, 0, s>>>(G, n, ldg, kb, nb, st);
+    BSRHT_LAUNCH_CHECK();
+    GemmDesc d;  // G22 -= C12^T C12 (full trailing block; only its upper part is used)
+    d.M = rest;
+    d.N = rest;
+    d.K = nb;
+    d.sai = 1;
+    d.sak = ldg;
+    d.sbk = ldg;
+    d.sbj = 1;
+    d.ldc = ldg;
+    d.alpha = -1.0;
+    d.beta = 1.0;
+    const double *C12 = G + kb * ldg + kb + nb;
+    double *G22 = G + (kb + nb) * ldg + kb + nb;
+    int rc = gemm_launch<double, double, double, true>(d, C12, C12, G22, s);
+    if (rc != BSRHT_OK) return rc;
+  }
+  chol_finish_kernel<<<(unsigned)((n * n + 255) / 256), 256, 0, s>>>(G, n, ldg, st);
   BSRHT_LAUNCH_CHECK();
   return BSRHT_OK;
 }
+
+size_t cholesky_state_bytes() { return sizeof(CholState); }
 
 int fill_f64(double *p, int64_t count, double value, hipStream_t s) {
   if (count <= 0) return BSRHT_OK;
@@ -509,7 +597,10 @@ int fill_f64(double *p, int64_t count, double value, hipStream_t s) {
 }
 
 int trinv_upper(const double *C, int64_t n, int64_t ldc, double *Ci, int64_t ldi, hipStream_t s) {
-  trinv_upper_kernel<<<(unsigned)((n + 63) / 64), 64, 0, s>>>(C, n, ldc, Ci, ldi);
+  if (n <= 0) return BSRHT_OK;
+  if (n * kTrinvWaves * sizeof(double) > 64 * 1024) return BSRHT_EUNSUPPORTED;
+  trinv_upper_kernel<<<(unsigned)((n + kTrinvWaves - 1) / kTrinvWaves), 64 * kTrinvWaves,
+                       (size_t)n * kTrinvWaves * sizeof(double), s>>>(C, n, ldc, Ci, ldi);
   BSRHT_LAUNCH_CHECK();
   return BSRHT_OK;
 }

@@ -21,7 +21,7 @@ namespace bsrht {
 namespace {
 
 constexpr double kU32 = 5.9604644775390625e-08;  // 2^-24, unit roundoff of FP32 data
-constexpr double kU64 = 2.220446049250313e-16;   // 2^-52, FP64 machine epsilon
+constexpr double kU64 = 1.1102230246251565e-16;  // 2^-53, FP64 unit roundoff
 constexpr int kMaxSweeps = 40;
 
 __global__ void eye_f32_kernel(float *M, int64_t n, int64_t ld) {
@@ -132,6 +132,7 @@ struct RsvdWs {
   float *Q32, *Z, *M, *Vk;
   double *gram_part, *Gz;
   int32_t *flag;
+  void *chol_state;
   SvdBufs<A> qb, sv;
   void layout(A &a, const bsrht_plan_s *pl, int64_t m, int64_t k) {
     const int64_t l = pl->l, n = pl->n, lq = std::min(l, m);
@@ -151,6 +152,7 @@ struct RsvdWs {
     M = a.template take<float>((size_t)(lq * k));
     Vk = a.template take<float>((size_t)(lq * k));
     flag = a.template take<int32_t>(4);
+    chol_state = a.template take<char>(cholesky_state_bytes());
     qb.take(a, even_up(l), l);
     sv.take(a, even_up(lq), k);
   }
@@ -165,6 +167,7 @@ struct NysWs {
   size_t apply_bytes;
   double *Bs, *Cinv, *Mf, *lam, *Z, *gram_part, *Gz, *Mk;
   int32_t *flag;
+  void *chol_state;
   SvdBufs<A> fb, sv;
   void layout(A &a, const bsrht_plan_s *pl, int64_t k) {
     const int64_t l = pl->l, n = pl->n;
@@ -182,6 +185,7 @@ struct NysWs {
     Gz = a.template take<double>((size_t)(l * l));
     Mk = a.template take<double>((size_t)(l * std::max<int64_t>(k, 1)));
     flag = a.template take<int32_t>(4);
+    chol_state = a.template take<char>(cholesky_state_bytes());
     fb.take(a, even_up(l), l);
     sv.take(a, even_up(l), k);
   }
@@ -250,7 +254,7 @@ int rsvd(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, int64_t k, f
     const int gs = gram_splits(m, l);
     st = gram_f32(w.W, m, l, 1, m, w.G, l, w.gram_part, gs, s);  // X = W^T: X[r][c] = W[c][r]
     if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); return st; }
-    BSRHT_TRY(cholesky_upper(w.G, l, l, (double)l * kU64, w.flag, s));
+    BSRHT_TRY(cholesky_upper(w.G, l, l, (double)l * kU64, w.flag, w.chol_state, s));
     int32_t hf = 0;
     BSRHT_TRY(read_i32(w.flag, s, &hf));
     int64_t lk = l;  // columns of Q1
@@ -298,7 +302,7 @@ int rsvd(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, int64_t k, f
     // second pass: G2 = Q1^T Q1, C2, Q = Q1 C2^{-1}
     const int gs2 = gram_splits(m, lk);
     BSRHT_TRY(gram_f64(w.Q1, m, lk, lk, 1, w.G2, lk, w.gram_part, gs2, s));
-    BSRHT_TRY(cholesky_upper(w.G2, lk, lk, 1e-14, w.flag + 1, s));
+    BSRHT_TRY(cholesky_upper(w.G2, lk, lk, 1e-14, w.flag + 1, w.chol_state, s));
     int32_t hf2 = 0;
     BSRHT_TRY(read_i32(w.flag + 1, s, &hf2));
     if (hf2 != 0) {  // Q1 has orthonormal columns to O(eps*kappa^2): should not happen
@@ -330,7 +334,7 @@ int rsvd(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, int64_t k, f
   // 4. R-factor of Z: Gz = Z^T Z (FP64), Gz = R^T R.
   const int gsz = gram_splits(n, lq);
   BSRHT_TRY(gram_f32(w.Z, n, lq, lq, 1, w.Gz, lq, w.gram_part, gsz, s));
-  BSRHT_TRY(cholesky_upper(w.Gz, lq, lq, (double)lq * kU32 * kU32, w.flag + 2, s));
+  BSRHT_TRY(cholesky_upper(w.Gz, lq, lq, (double)lq * kU32 * kU32, w.flag + 2, w.chol_state, s));
   int32_t hz = 0;
   BSRHT_TRY(read_i32(w.flag + 2, s, &hz));
   int pw;
@@ -360,7 +364,7 @@ int rsvd(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, int64_t k, f
   }
   // 6. U = Z Vt_k St_k^{-1}, S = St_k, V = Q Vt_k
   finish_sigma_kernel<<<(unsigned)((k + 255) / 256), 256, 0, s>>>(
-      w.sv.S, lq, k, (double)lq * kU32, 1, w.sv.inv, S, info);
+      w.sv.S, lq, k, sqrt((double)lq * kU64), 1, w.sv.inv, S, info);
   BSRHT_LAUNCH_CHECK();
   const int64_t keep = std::min(k, lq);
   BSRHT_TRY(scale_cols_f64_f32(w.sv.Vs, lq, keep, k, nce, w.sv.inv, w.M, k, s));
@@ -419,7 +423,7 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
   sym_f64_kernel<<<(unsigned)((l * l + 255) / 256), 256, 0, s>>>(w.B, l, l, w.Bs, l);
   BSRHT_LAUNCH_CHECK();
   BSRHT_TRY(scale_cols_f64(w.Bs, l, l, l, l, nullptr, w.Mf, l, s));
-  BSRHT_TRY(cholesky_upper(w.Mf, l, l, (double)l * kU32, w.flag, s));
+  BSRHT_TRY(cholesky_upper(w.Mf, l, l, (double)l * kU64, w.flag, w.chol_state, s));
   int32_t hf = 0;
   BSRHT_TRY(read_i32(w.flag, s, &hf));
   int64_t lz = l;
@@ -449,7 +453,7 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
     std::vector<int> idx;
     std::vector<double> sc;
     for (int64_t i = 0; i < l; ++i)
-      if (lam[(size_t)i] > (double)l * kU32 * lmax && lam[(size_t)i] > 0.0) {
+      if (lam[(size_t)i] > (double)l * kU64 * lmax && lam[(size_t)i] > 0.0) {
         idx.push_back((int)i);
         sc.push_back(1.0 / sqrt(lam[(size_t)i]));
       }
@@ -481,7 +485,7 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
   const int gsz = gram_splits(n, lz);
   BSRHT_TRY(gram_f64(w.Z, n, lz, lz, 1, w.Gz, lz, w.gram_part, gsz, s));
   BSRHT_TRY(scale_cols_f64(w.Gz, lz, lz, lz, lz, nullptr, w.Bs, lz, s));
-  BSRHT_TRY(cholesky_upper(w.Gz, lz, lz, 1e-15 * (double)lz, w.flag + 1, s));
+  BSRHT_TRY(cholesky_upper(w.Gz, lz, lz, 1e-15 * (double)lz, w.flag + 1, w.chol_state, s));
   int32_t hz = 0;
   BSRHT_TRY(read_i32(w.flag + 1, s, &hz));
   // 5. SVD of R (or the eigen decomposition of Z^T Z when R is singular)
@@ -500,7 +504,7 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
   }
   // 6. U = Z Vt_k St_k^{-1}; lambda = St_k^2
   finish_sigma_kernel<<<(unsigned)((k + 255) / 256), 256, 0, s>>>(
-      w.sv.S, lz, k, (double)lz * kU32, 2, w.sv.inv, lambda, info);
+      w.sv.S, lz, k, sqrt((double)lz * kU64), 2, w.sv.inv, lambda, info);
   BSRHT_LAUNCH_CHECK();
   const int64_t keep = std::min(k, lz);
   const int64_t nce = even_up(lz);
