@@ -364,15 +364,25 @@ __global__ __launch_bounds__(64 * kTrinvWaves) void trinv_upper_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// One-sided Jacobi SVD of X (nr x nc, column-major, columns of length nr at
-// stride ldx), nc even after padding: X V = U Sigma.  Columns are rotated in
-// pairs until all are mutually orthogonal; V accumulates the rotations.
+// One-sided Jacobi (Hestenes) on the columns of X (nr x nc, column-major,
+// columns of length nr at stride ldx), nc even: columns are rotated in pairs
+// until all are mutually orthogonal, X V = U Sigma.  The singular values are
+// the final column norms.  Without accumulation the returned vectors are the
+// normalised columns (U); a column with small sigma_j then carries an error
+// of order u sigma_1 / sigma_j, which is harmless where the caller weights
+// column j by sigma_j (the SVD of an R factor, passed as X = R^T: the
+// row-major buffer of R already is R^T in column-major order).  With
+// accumulation (V != NULL) the rotations are also applied to V = I and its
+// columns are returned: V stays orthogonal to working precision, so for a
+// symmetric X the pairs (v_j, v_j^T X v_j) are a backward-stable eigen
+// decomposition, which callers that scale by 1/sqrt(lambda_j) need.
 // Round-robin ordering: nc-1 rounds per sweep, nc/2 disjoint pairs per round,
 // one wave per pair, a grid barrier between rounds.
 struct JacobiArgs {
   double *X;
-  double *V;
-  int64_t nr, nc, ldx, ldv;
+  int64_t nr, nc, ldx;
+  double *V;  // NULL, or nc x nc column-major (ldv) accumulating the rotations
+  int64_t ldv;
   double tol;
   int max_sweeps;
   unsigned int *flags;  // [0]: rotations in this sweep (cleared per sweep), [1]: sweeps done
@@ -436,11 +446,13 @@ __global__ __launch_bounds__(256) void jacobi_kernel(JacobiArgs ja) {
             xa[i] = c * u - sn * v;
             xb[i] = sn * u + c * v;
           }
-          double *va = ja.V + ca * ja.ldv, *vb = ja.V + cb * ja.ldv;
-          for (int64_t i = lane; i < ja.nc; i += 64) {
-            const double u = va[i], v = vb[i];
-            va[i] = c * u - sn * v;
-            vb[i] = sn * u + c * v;
+          if (ja.V) {
+            double *va = ja.V + ca * ja.ldv, *vb = ja.V + cb * ja.ldv;
+            for (int64_t i = lane; i < ja.nc; i += 64) {
+              const double u = va[i], v = vb[i];
+              va[i] = c * u - sn * v;
+              vb[i] = sn * u + c * v;
+            }
           }
           if (lane == 0) atomicAdd(&ja.flags[0], 1u);
         }
@@ -459,16 +471,17 @@ __global__ __launch_bounds__(256) void jacobi_kernel(JacobiArgs ja) {
   if (blockIdx.x == 0 && threadIdx.x == 0) ja.flags[1] = (unsigned)sweep;
 }
 
-// sigma_j = ||x_j||, then order (sigma, column of V) by decreasing sigma
-// (ties by index) into S and Vs (Vs[i][j] = V[j][i] of the sorted order,
-// i.e. row-major nc x nc with the singular vectors as columns).  One
-// workgroup; nc <= 4096.
+// sigma_j = ||x_j||; order by decreasing sigma (ties by index) into S, and
+// write in that order as the columns of Us either the normalised columns of X
+// (row-major nr x nc, zero where sigma = 0) or, when V is given, the columns
+// of V (row-major nc x nc).  One workgroup; nc <= 4096.
 __global__ __launch_bounds__(1024) void jacobi_finish_kernel(const double *__restrict__ X,
-                                                             const double *__restrict__ V,
                                                              int64_t nr, int64_t nc, int64_t ldx,
-                                                             int64_t ldv, double *__restrict__ S,
-                                                             double *__restrict__ Vs,
-                                                             int64_t ldvs, int32_t *__restrict__ perm) {
+                                                             const double *__restrict__ V,
+                                                             int64_t ldv,
+                                                             double *__restrict__ S,
+                                                             double *__restrict__ Us,
+                                                             int64_t ldu, int32_t *__restrict__ perm) {
   extern __shared__ double s_sig[];
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int64_t j = tid; j < nc; j += nt) {
@@ -480,7 +493,6 @@ __global__ __launch_bounds__(1024) void jacobi_finish_kernel(const double *__res
     s_sig[j] = sqrt(s);
   }
   __syncthreads();
-  // rank of each column: number of columns with larger sigma (ties by index)
   for (int64_t j = tid; j < nc; j += nt) {
     const double sj = s_sig[j];
     int64_t rank = 0;
@@ -492,9 +504,18 @@ __global__ __launch_bounds__(1024) void jacobi_finish_kernel(const double *__res
     S[rank] = sj;
   }
   __syncthreads();
-  for (int64_t e = tid; e < nc * nc; e += nt) {
+  if (V) {
+    for (int64_t e = tid; e < nc * nc; e += nt) {
+      const int64_t i = e / nc, rnk = e % nc;
+      Us[i * ldu + rnk] = V[(int64_t)perm[rnk] * ldv + i];
+    }
+    return;
+  }
+  for (int64_t e = tid; e < nr * nc; e += nt) {
     const int64_t i = e / nc, rnk = e % nc;
-    Vs[i * ldvs + rnk] = V[(int64_t)perm[rnk] * ldv + i];
+    const int64_t col = perm[rnk];
+    const double sg = s_sig[col];
+    Us[i * ldu + rnk] = sg > 0.0 ? X[col * ldx + i] / sg : 0.0;
   }
 }
 
@@ -611,22 +632,24 @@ int eye(double *M, int64_t n, int64_t ld, hipStream_t s) {
   return BSRHT_OK;
 }
 
-int jacobi_svd(double *X, int64_t nr, int64_t nc, int64_t ldx, double *V, int64_t ldv,
-               double *S, double *Vs, int64_t ldvs, int32_t *perm, unsigned int *flags,
-               int max_sweeps, hipStream_t s) {
+int jacobi_svd(double *X, int64_t nr, int64_t nc, int64_t ldx, double *V, double *S,
+               double *Us, int64_t ldu, int32_t *perm, unsigned int *flags, int max_sweeps,
+               hipStream_t s) {
   if (nc <= 0) return BSRHT_OK;
   if (nc > 4096 || (nc & 1)) return BSRHT_EUNSUPPORTED;
-  int st = eye(V, nc, ldv, s);
-  if (st != BSRHT_OK) return st;
   zero_u32_kernel<<<1, 64, 0, s>>>(flags, 2);
   BSRHT_LAUNCH_CHECK();
+  if (V) {
+    eye_kernel<<<(unsigned)((nc * nc + 255) / 256), 256, 0, s>>>(V, nc, nc);
+    BSRHT_LAUNCH_CHECK();
+  }
   JacobiArgs ja;
   ja.X = X;
-  ja.V = V;
   ja.nr = nr;
   ja.nc = nc;
   ja.ldx = ldx;
-  ja.ldv = ldv;
+  ja.V = V;
+  ja.ldv = nc;
   ja.tol = 1e-15 * (double)(nr > 16 ? nr : 16);
   ja.max_sweeps = max_sweeps;
   ja.flags = flags;
@@ -640,8 +663,8 @@ int jacobi_svd(double *X, int64_t nr, int64_t nc, int64_t ldx, double *V, int64_
   if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&jacobi_kernel),
                                  dim3((unsigned)blocks), dim3(256), args, 0, s) != hipSuccess)
     return BSRHT_EDEVICE;
-  jacobi_finish_kernel<<<1, 1024, (size_t)nc * sizeof(double), s>>>(X, V, nr, nc, ldx, ldv, S,
-                                                                     Vs, ldvs, perm);
+  jacobi_finish_kernel<<<1, 1024, (size_t)nc * sizeof(double), s>>>(X, nr, nc, ldx, V, nc, S,
+                                                                     Us, ldu, perm);
   BSRHT_LAUNCH_CHECK();
   return BSRHT_OK;
 }

@@ -191,19 +191,26 @@ struct NysWs {
   }
 };
 
-// SVD of the nc0 x nc0 matrix given row-major at R (ldr): copies it
-// column-major into the (even-sized, zero-padded) Jacobi buffers and runs
-// the one-sided Jacobi.  Sorted singular values in b.S, right singular
-// vectors as columns of b.Vs (row-major, leading dimension nc).
+// Right singular vectors of the nc0 x nc0 matrix M given row-major at R
+// (ldr).  Factor mode (eigen = false, M an R factor): the row-major buffer of
+// M is M^T in column-major order, so the one-sided Jacobi on its columns
+// yields the left singular vectors of M^T, i.e. the right singular vectors of
+// M, as normalised columns.  Eigen mode (eigen = true, M symmetric): the
+// rotations are accumulated and returned, so that the eigenvectors stay
+// orthogonal to working precision even for tiny |lambda|, where the callers
+// scale by 1/sqrt(lambda).  The problem is zero padded to an even size; an
+// extra zero column sorts last.  Sorted singular values in b.S, vectors as
+// columns of b.Vs (row-major, leading dimension nc).
 template <class A>
-int small_svd(SvdBufs<A> &b, const double *R, int64_t nc0, int64_t ldr, hipStream_t s) {
+int small_svd(SvdBufs<A> &b, const double *R, int64_t nc0, int64_t ldr, bool eigen,
+              hipStream_t s) {
   const int64_t nc = even_up(nc0);
-  int st = fill_f64(b.X, nc * nc, 0.0, s);  // zero padding: a zero column sorts last
-  if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); return st; }
-  // column-major X: X[j*nc + i] = R[i][j]
-  st = transpose_f64(R, nc0, nc0, ldr, b.X, nc, s);
-  if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); return st; }
-  return jacobi_svd(b.X, nc, nc, nc, b.V, nc, b.S, b.Vs, nc, b.perm, b.flags, kMaxSweeps, s);
+  int st = fill_f64(b.X, nc * nc, 0.0, s);
+  if (st != BSRHT_OK) return st;
+  st = scale_cols_f64(R, nc0, nc0, nc0, ldr, nullptr, b.X, nc, s);  // copy, ld ldr -> nc
+  if (st != BSRHT_OK) return st;
+  return jacobi_svd(b.X, nc, nc, nc, eigen ? b.V : nullptr, b.S, b.Vs, nc, b.perm, b.flags,
+                    kMaxSweeps, s);
 }
 
 }  // namespace
@@ -272,7 +279,7 @@ int rsvd(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, int64_t k, f
       // Q1 = W^T V_+ Lam_+^{-1/2}.
       st = gram_f32(w.W, m, l, 1, m, w.G, l, w.gram_part, gs, s);
       if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); return st; }
-      BSRHT_TRY(small_svd(w.qb, w.G, l, l, s));
+      BSRHT_TRY(small_svd(w.qb, w.G, l, l, true, s));
       std::vector<double> ev((size_t)l);
       if (hipStreamSynchronize(s) != hipSuccess ||
           hipMemcpy(ev.data(), w.qb.S, sizeof(double) * (size_t)l, hipMemcpyDeviceToHost) !=
@@ -340,12 +347,12 @@ int rsvd(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, int64_t k, f
   int pw;
   if (hz == 0) {
     // 5. SVD of R: R = Ut St Vt^T
-    BSRHT_TRY(small_svd(w.sv, w.Gz, lq, lq, s));
+    BSRHT_TRY(small_svd(w.sv, w.Gz, lq, lq, false, s));
     pw = 1;
   } else {
     // rank(Z) < lq: Z^T Z = Vt St^2 Vt^T from its eigen decomposition
     BSRHT_TRY(gram_f32(w.Z, n, lq, lq, 1, w.Gz, lq, w.gram_part, gsz, s));
-    BSRHT_TRY(small_svd(w.sv, w.Gz, lq, lq, s));
+    BSRHT_TRY(small_svd(w.sv, w.Gz, lq, lq, true, s));
     // the Jacobi values are St^2: take square roots through the scale step
     pw = 0;
   }
@@ -438,7 +445,7 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
     BSRHT_TRY(gemm_f32f64_f64(d, w.Y, w.Cinv, w.Z, s));
   } else {
     // Remark 3.1: B = V Lam V^T, keep Lam_i > l u Lam_max, Z = Y V_+ Lam_+^{-1/2}
-    BSRHT_TRY(small_svd(w.fb, w.Bs, l, l, s));
+    BSRHT_TRY(small_svd(w.fb, w.Bs, l, l, true, s));
     const int64_t nce = even_up(l);
     rayleigh_kernel<<<(unsigned)l, 256, 0, s>>>(w.Bs, w.fb.Vs, l, l, nce, w.lam);
     BSRHT_LAUNCH_CHECK();
@@ -490,7 +497,7 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
   BSRHT_TRY(read_i32(w.flag + 1, s, &hz));
   // 5. SVD of R (or the eigen decomposition of Z^T Z when R is singular)
   const double *Rsrc = hz == 0 ? w.Gz : w.Bs;
-  BSRHT_TRY(small_svd(w.sv, Rsrc, lz, lz, s));
+  BSRHT_TRY(small_svd(w.sv, Rsrc, lz, lz, hz != 0, s));
   if (hz != 0) {
     std::vector<double> ev((size_t)lz);
     if (hipStreamSynchronize(s) != hipSuccess ||
