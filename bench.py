@@ -54,23 +54,28 @@ def _traffic(profile_name, src_files, bytes_per_launch_alg):
     return doc.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(A, cfg):
-    """The FP64 oracle sketch timed on host cores: the first block of A
-    (2^16 rows x 1024 columns) as a p = 1 plan with the same r, l, seed."""
+def cpu_baseline(A, cfg, blocks=8):
+    """The FP64 oracle sketch timed on host cores, on a bounded sample of the
+    same workload: the first `blocks` row blocks of A (blocks * 2^16 rows x
+    1024 columns) as a plan with p = blocks and the same r, l, seed.  The
+    tables of block i depend only on (seed, i), so this is exactly the partial
+    sum of the first `blocks` terms of (2.4)."""
     import numpy as np
     from oracle import rng, sketch
 
     r = cfg["n"] // cfg["p"]
-    sample = A[:r].cpu().numpy()
-    op = rng.Plan(r, 1, cfg["l"], cfg["seed"])
+    blocks = min(blocks, cfg["p"])
+    sample = A[:blocks * r].cpu().numpy()
+    op = rng.Plan(blocks * r, blocks, cfg["l"], cfg["seed"])
     t0 = time.perf_counter()
     Y = sketch.sketch(op, sample)
     dt = time.perf_counter() - t0
     assert np.isfinite(Y).all()
     gbs = sample.size * 4 / dt / 1e9
     return {"value": round(gbs, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"first block: {r} x {cfg['m']} float32 rows of A as a p=1 plan "
-                      f"(l={cfg['l']}); numpy FP64 FWHT, single thread; {dt:.2f} s"}
+            "sample": f"first {blocks} of {cfg['p']} row blocks: {blocks * r} x {cfg['m']} "
+                      f"float32 rows of A as a p={blocks} plan (r={r}, l={cfg['l']}, same "
+                      f"seed); numpy FP64 FWHT, single thread; {dt:.2f} s"}
 
 
 def _fro_error(A, U, S, V, chunk=1 << 16):
@@ -161,8 +166,8 @@ def main():
                     help="skip the randomized SVD and Nystrom measurements")
     ap.add_argument("--lowrank-reps", type=int, default=3)
     ap.add_argument("--only", choices=["all", "sketch", "rsvd", "nystrom"], default="all",
-                    help="profiling aid: run one part (the JSON line is printed for 'all' "
-                         "and 'sketch' only)")
+                    help="profiling aid: run one part ('rsvd' and 'nystrom' print only "
+                         "that part's JSON object)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -175,7 +180,7 @@ def main():
     import workloads
 
     if args.only == "nystrom":
-        log(json.dumps(bench_nystrom(bs, args.lowrank_reps)))
+        print(json.dumps({"nystrom": bench_nystrom(bs, args.lowrank_reps)}), flush=True)
         return
     cfg = dict(workloads.CONFIGS["c2_fp32_apply"])
     n, m, p, l, seed = cfg["n"], cfg["m"], cfg["p"], cfg["l"], cfg["seed"]
@@ -186,7 +191,7 @@ def main():
     torch.cuda.synchronize()
     plan = bs.Plan(n, p, l, seed, device=dev)
     if args.only == "rsvd":
-        log(json.dumps(bench_rsvd(bs, A, plan, cfg, args.lowrank_reps)))
+        print(json.dumps({"rsvd": bench_rsvd(bs, A, plan, cfg, args.lowrank_reps)}), flush=True)
         return
     Y = torch.empty(l, m, dtype=torch.float32, device=dev)
     ws = torch.empty(max(1, bs.bsrht_apply_workspace(plan, m)), dtype=torch.uint8, device=dev)
@@ -226,15 +231,6 @@ def main():
         torch.cuda.synchronize()
         del B
 
-    # read-only ceiling on the same buffer (torch reduction, measurement only)
-    torch.cuda.synchronize()
-    tr0 = time.perf_counter()
-    for _ in range(10):
-        s = A.sum()
-    torch.cuda.synchronize()
-    read_gbs = bytes_a * 10 / (time.perf_counter() - tr0) / 1e9
-    del s
-
     traffic = _traffic("traffic_fused_fp32_sketch_2p20x1024.json", ["apply_fp32.hip"], alg_bytes)
     out = {
         "metric": "block-SRHT sketch GB/s of A (FP32 fused apply)",
@@ -253,7 +249,6 @@ def main():
                                "l=512, seed 0", "n": n, "m": m, "p": p, "l": l,
                    "parallelism": "single GPU"},
         "frac_hbm_peak": round(value / HBM_PEAK_GBS, 4),
-        "read_ceiling_GBs": round(read_gbs, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "fused_fp32_kernel<64>",
