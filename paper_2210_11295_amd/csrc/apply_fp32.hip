@@ -317,10 +317,25 @@ int launch_fused(const Launch &L, FusedArgs &a, hipStream_t s) {
 
 }  // namespace
 
+size_t apply_fp32_ws_bytes(const bsrht_plan_s *plan, int64_t m) {
+  if (!plan || m <= 0) return 0;
+  return choose_launch(plan, m, m).ws;
+}
+
 size_t apply_ws_bytes(const bsrht_plan_s *plan, int64_t m) {
   if (!plan || m <= 0) return 0;
   if (plan->precision == BSRHT_SPLIT_BF16) return apply_split_bf16_ws_bytes(plan, m);
-  return choose_launch(plan, m, m).ws;
+  return apply_fp32_ws_bytes(plan, m);
+}
+
+int reduce_splits(const float *part, int splits, int64_t split_stride, int64_t l, int64_t m,
+                  float *Y, int64_t ldy, float scale, hipStream_t s) {
+  const int64_t total = l * m;
+  const int tb = 256;
+  reduce_splits_kernel<<<(unsigned)((total + tb - 1) / tb), tb, 0, s>>>(
+      part, splits, split_stride, (int)l, (int)m, Y, ldy, scale);
+  BSRHT_LAUNCH_CHECK();
+  return BSRHT_OK;
 }
 
 int apply_fp32(const bsrht_plan_s *pl, const float *A, int64_t m, int64_t lda, float *Y,
@@ -371,13 +386,9 @@ int apply_fp32(const bsrht_plan_s *pl, const float *A, int64_t m, int64_t lda, f
     default: st = launch_fused<8>(L, a, s); break;
   }
   if (st != BSRHT_OK) return st;
-  if (L.splits > 1) {
-    const int64_t total = pl->l * m;
-    const int tb = 256;
-    reduce_splits_kernel<<<(unsigned)((total + tb - 1) / tb), tb, 0, s>>>(
-        static_cast<const float *>(ws), L.splits, pl->l * m, (int)pl->l, (int)m, Y, ldy, scale);
-    BSRHT_LAUNCH_CHECK();
-  }
+  if (L.splits > 1)
+    return reduce_splits(static_cast<const float *>(ws), L.splits, pl->l * m, pl->l, m, Y, ldy,
+                         scale, s);
   return BSRHT_OK;
 }
 

@@ -102,6 +102,10 @@ int apply_split_bf16(const bsrht_plan_s *plan, const float *A, int64_t m,
                      int64_t lda, float *Y, int64_t ldy, void *ws,
                      size_t ws_bytes, hipStream_t s);
 size_t apply_split_bf16_ws_bytes(const bsrht_plan_s *plan, int64_t m);
+size_t apply_fp32_ws_bytes(const bsrht_plan_s *plan, int64_t m);
+// Y[j][c] = scale * sum_s part[s][j][c] over the splits in ascending order.
+int reduce_splits(const float *part, int splits, int64_t split_stride, int64_t l, int64_t m,
+                  float *Y, int64_t ldy, float scale, hipStream_t s);
 
 // Instrumentation hooks around the launch of the kernel selected by
 // bsrht_timing_enable (no-ops otherwise).
