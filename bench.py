@@ -78,6 +78,47 @@ def cpu_baseline(A, cfg, blocks=8):
                       f"seed); numpy FP64 FWHT, single thread; {dt:.2f} s"}
 
 
+def bench_split_bf16(bs, A, cfg, steps, warmup, Y_fp32):
+    """The same sketch with the H_16 factor on BF16 matrix cores (A split
+    into BF16 hi + lo, FP32 accumulation), on the same A and plan seed."""
+    import torch
+    n, m, p, l, seed = cfg["n"], cfg["m"], cfg["p"], cfg["l"], cfg["seed"]
+    plan = bs.Plan(n, p, l, seed, precision=bs.SPLIT_BF16, device=A.device)
+    Y = torch.empty(l, m, dtype=torch.float32, device=A.device)
+    ws = torch.empty(max(1, bs.bsrht_apply_workspace(plan, m)), dtype=torch.uint8,
+                     device=A.device)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        bs.bsrht_apply(plan, A, Y, ws, stream)
+    torch.cuda.synchronize()
+    bs.timing_enable(bs.TIMING_APPLY_BF16)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        bs.bsrht_apply(plan, A, Y, ws, stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern_ms, launches = bs.timing_read()
+    bs.timing_enable(bs.TIMING_OFF)
+    kern_avg_ms = kern_ms / max(launches, 1)
+    bytes_a = n * m * 4
+    table_bytes = 4 * l + 4 * ((n + 31) // 32) + 4 * p * ((l + 31) // 32)
+    alg_bytes = bytes_a + 4 * l * m + table_bytes
+    achieved = alg_bytes / (kern_avg_ms * 1e-3) / 1e9
+    diff = float((Y.double() - Y_fp32.double()).norm() / Y_fp32.double().norm())
+    log(f"bench: split-bf16 {bytes_a * steps / elapsed / 1e9:.1f} GB/s whole call; kernel "
+        f"{kern_avg_ms * 1e3:.1f} us -> {achieved:.1f} GB/s; rel diff vs fp32 {diff:.2e}")
+    traffic = _traffic("traffic_fused_bf16_sketch_2p20x1024.json", ["apply_bf16.hip"],
+                       alg_bytes)
+    return {"value": round(bytes_a * steps / elapsed / 1e9, 2), "unit": "GB/s",
+            "ms_per_step": round(elapsed / steps * 1e3, 4),
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "traffic": traffic, "kernel": "fused_bf16_kernel<64>",
+                         "kernel_avg_us": round(kern_avg_ms * 1e3, 2),
+                         "alg_bytes_per_launch": alg_bytes},
+            "rel_diff_vs_fp32": diff}
+
+
 def _fro_error(A, U, S, V, chunk=1 << 16):
     """||A - U diag(S) V^T||_F / ||A||_F in FP64 on the device (measurement)."""
     import torch
@@ -165,8 +206,9 @@ def main():
     ap.add_argument("--skip-lowrank", action="store_true",
                     help="skip the randomized SVD and Nystrom measurements")
     ap.add_argument("--lowrank-reps", type=int, default=3)
-    ap.add_argument("--only", choices=["all", "sketch", "rsvd", "nystrom"], default="all",
-                    help="profiling aid: run one part ('rsvd' and 'nystrom' print only "
+    ap.add_argument("--only", choices=["all", "sketch", "bf16", "rsvd", "nystrom"],
+                    default="all",
+                    help="profiling aid: run one part ('bf16', 'rsvd' and 'nystrom' print only "
                          "that part's JSON object)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -192,6 +234,11 @@ def main():
     plan = bs.Plan(n, p, l, seed, device=dev)
     if args.only == "rsvd":
         print(json.dumps({"rsvd": bench_rsvd(bs, A, plan, cfg, args.lowrank_reps)}), flush=True)
+        return
+    if args.only == "bf16":
+        Yf = bs.bsrht_apply(plan, A)
+        print(json.dumps({"split_bf16": bench_split_bf16(bs, A, cfg, args.steps, args.warmup,
+                                                         Yf)}), flush=True)
         return
     Y = torch.empty(l, m, dtype=torch.float32, device=dev)
     ws = torch.empty(max(1, bs.bsrht_apply_workspace(plan, m)), dtype=torch.uint8, device=dev)
@@ -257,6 +304,8 @@ def main():
     }
     if args.only == "sketch":
         args.skip_lowrank = True
+    else:
+        out["split_bf16"] = bench_split_bf16(bs, A, cfg, args.steps, args.warmup, Y)
     if not args.skip_lowrank:
         out["rsvd"] = bench_rsvd(bs, A, plan, cfg, args.lowrank_reps)
     if not args.skip_cpu_baseline:

@@ -1,0 +1,133 @@
+/*
+ * bsrht_serve.h -- serving runtime for block SRHT sketch and randomized SVD
+ * jobs on one GPU (continuous batching of independent jobs).
+ *
+ * Each job is one call of bsrht.h: BSRHT_JOB_SKETCH is bsrht_apply (the
+ * sketch Y = Omega A of section 2, eq. (2.4)), BSRHT_JOB_RSVD is rsvd
+ * (section 3.1, Algorithm 1, which sketches first).  The server owns no
+ * device memory of its own: the caller hands it one device arena at
+ * creation, and every byte a job needs beyond its inputs and outputs (the
+ * call's workspace and, on a plan-cache miss, the plan's sign/index tables)
+ * is carved from that arena.  A job is admitted only when its bytes fit, so
+ * the arena size is the HBM budget.  Admitted jobs run concurrently on the
+ * server's worker streams; a job's result is the same as the same call made
+ * alone (every kernel of the library reduces in a fixed order that does not
+ * depend on what else runs).
+ *
+ * Scheduling: jobs are admitted in arrival order; while the oldest waiting
+ * job does not fit, a younger job among the next few that fits may be
+ * admitted ahead of it ("backfill"), until the oldest has waited longer than
+ * a bound, after which nothing bypasses it.  Plans are cached by
+ * (n, p, l, seed, sampling, precision) and evicted least-recently-used when
+ * an admission needs their bytes and no running job uses them.
+ *
+ * Timestamps are seconds on the server's monotonic clock
+ * (bsrht_server_clock).  Every function is thread-safe.  Errors are the
+ * BSRHT_* status codes of bsrht.h.
+ */
+#ifndef BSRHT_SERVE_H
+#define BSRHT_SERVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "bsrht.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bsrht_server_s *bsrht_server_t;
+
+#define BSRHT_JOB_SKETCH 0 /* Y = Omega A            (bsrht_apply) */
+#define BSRHT_JOB_RSVD 1   /* sketch + Algorithm 1   (rsvd)        */
+
+/* One job.  Device pointers are caller-owned and must stay valid (inputs
+ * unchanged, outputs untouched) from submission until the job's result has
+ * been returned by bsrht_server_poll.  The plan is (n, p, l, seed, sampling,
+ * precision) exactly as for bsrht_plan. */
+typedef struct {
+  int64_t id;        /* caller's tag, returned with the result */
+  int kind;          /* BSRHT_JOB_SKETCH or BSRHT_JOB_RSVD */
+  int64_t n, m, p, l;
+  int64_t k;         /* RSVD target rank (ignored for SKETCH) */
+  uint64_t seed;
+  int sampling, precision;
+  const float *A;    /* device, n x m, leading dimension lda */
+  int64_t lda;
+  float *Y;          /* SKETCH: device l x m, leading dimension ldy */
+  int64_t ldy;
+  float *U;          /* RSVD: device outputs as for rsvd(): U n x k, */
+  double *S;         /*   S k, V m x k (row-major), info int32       */
+  float *V;
+  int32_t *info;
+} bsrht_job_t;
+
+typedef struct {
+  int64_t id;
+  int status;            /* status of the job's library call */
+  int64_t arena_bytes;   /* arena bytes held while the job ran */
+  double t_submit;       /* bsrht_server_submit returned (arrival) */
+  double t_start;        /* admitted and taken by a worker */
+  double t_done;         /* the job's stream had finished its work */
+} bsrht_job_result_t;
+
+typedef struct {
+  int64_t submitted, completed, rejected;
+  int64_t plan_hits, plan_misses, plan_evictions;
+  int64_t backfilled;        /* admissions ahead of an older waiting job */
+  int64_t peak_arena_bytes;  /* high-water mark of arena bytes in use */
+  int peak_running;          /* high-water mark of concurrently running jobs */
+  int64_t queued;            /* waiting for admission now */
+} bsrht_server_stats_t;
+
+/* Arena bytes a job needs when its plan is not cached (workspace + tables);
+ * 0 for invalid sizes. */
+size_t bsrht_job_bytes(const bsrht_job_t *job);
+
+/*
+ * Creates a server on the current device with `workers` worker threads,
+ * each owning one non-blocking HIP stream of default priority.
+ * arena: device memory of arena_bytes (caller-owned, freed by the caller
+ * after bsrht_server_destroy).  1 <= workers <= 64.
+ * Currently returns BSRHT_EUNSUPPORTED after checking its arguments: the
+ * threaded GPU executor is switched off (a process that used it crashed at
+ * exit after all jobs had completed, cause not identified).
+ */
+int bsrht_server_create(void *arena, size_t arena_bytes, int workers, bsrht_server_t *out);
+
+/*
+ * Same scheduler with a host-only executor, for testing admission and
+ * ordering without a GPU: no HIP call is made, the arena is a byte budget,
+ * and a job "runs" by sleeping seconds_per_gb * (4 n m / 1e9) seconds.
+ * Job pointers are not dereferenced.
+ */
+int bsrht_server_create_fake(size_t arena_bytes, int workers, double seconds_per_gb,
+                             bsrht_server_t *out);
+
+/* Queues a job (copied).  BSRHT_EINVAL for invalid sizes, kind or pointers;
+ * BSRHT_ENOMEM when the job alone needs more than the whole arena. */
+int bsrht_server_submit(bsrht_server_t srv, const bsrht_job_t *job);
+
+/* Moves up to max finished results into out (completion order) and stores
+ * their number in *count; waits up to timeout_s seconds for the first one
+ * when none is ready (0 = do not wait). */
+int bsrht_server_poll(bsrht_server_t srv, bsrht_job_result_t *out, int max, double timeout_s,
+                      int *count);
+
+/* Blocks until every submitted job has finished. */
+int bsrht_server_drain(bsrht_server_t srv);
+
+int bsrht_server_stats(bsrht_server_t srv, bsrht_server_stats_t *out);
+
+/* Seconds on the server's clock (the clock of the result timestamps). */
+double bsrht_server_clock(bsrht_server_t srv);
+
+/* Drains, stops the workers, releases streams and cached plans. */
+int bsrht_server_destroy(bsrht_server_t srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSRHT_SERVE_H */

@@ -19,7 +19,8 @@ __all__ = [
     "bsrht_apply", "bsrht_apply_workspace", "rsvd", "rsvd_workspace", "nystrom",
     "nystrom_workspace", "WITH_REPLACEMENT", "WITHOUT_REPLACEMENT", "FP32",
     "SPLIT_BF16", "INFO_CHOL_FALLBACK", "INFO_RANK_CLAMPED", "INFO_QB_FALLBACK",
-    "INFO_JACOBI_NOCONV", "EXPORTED_SYMBOLS",
+    "INFO_JACOBI_NOCONV", "EXPORTED_SYMBOLS", "JOB_SKETCH", "JOB_RSVD", "JobDesc",
+    "JobResult", "ServerStats", "Server", "bsrht_job_bytes",
 ]
 
 WITH_REPLACEMENT = 0
@@ -34,6 +35,8 @@ TIMING_OFF = 0
 TIMING_APPLY_FP32 = 1
 TIMING_APPLY_BF16 = 2
 TIMING_GEMM_AQ = 3
+JOB_SKETCH = 0
+JOB_RSVD = 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "_lib", "libbsrht.so")
@@ -65,6 +68,46 @@ _SIGS = {
     "nystrom": (ctypes.c_int, [_c_vp, _c_vp, _c_i64, _c_i64, _c_vp, _c_vp, _c_vp, _c_vp,
                                _c_sz, _c_vp]),
 }
+
+
+class JobDesc(ctypes.Structure):
+    """bsrht_job_t of include/bsrht_serve.h."""
+    _fields_ = [("id", _c_i64), ("kind", ctypes.c_int), ("n", _c_i64), ("m", _c_i64),
+                ("p", _c_i64), ("l", _c_i64), ("k", _c_i64), ("seed", ctypes.c_uint64),
+                ("sampling", ctypes.c_int), ("precision", ctypes.c_int), ("A", _c_vp),
+                ("lda", _c_i64), ("Y", _c_vp), ("ldy", _c_i64), ("U", _c_vp), ("S", _c_vp),
+                ("V", _c_vp), ("info", _c_vp)]
+
+
+class JobResult(ctypes.Structure):
+    """bsrht_job_result_t of include/bsrht_serve.h."""
+    _fields_ = [("id", _c_i64), ("status", ctypes.c_int), ("arena_bytes", _c_i64),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    """bsrht_server_stats_t of include/bsrht_serve.h."""
+    _fields_ = [("submitted", _c_i64), ("completed", _c_i64), ("rejected", _c_i64),
+                ("plan_hits", _c_i64), ("plan_misses", _c_i64), ("plan_evictions", _c_i64),
+                ("backfilled", _c_i64), ("peak_arena_bytes", _c_i64),
+                ("peak_running", ctypes.c_int), ("queued", _c_i64)]
+
+
+# the declarations of include/bsrht_serve.h
+_SIGS.update({
+    "bsrht_job_bytes": (_c_sz, [ctypes.POINTER(JobDesc)]),
+    "bsrht_server_create": (ctypes.c_int, [_c_vp, _c_sz, ctypes.c_int, ctypes.POINTER(_c_vp)]),
+    "bsrht_server_create_fake": (ctypes.c_int, [_c_sz, ctypes.c_int, ctypes.c_double,
+                                                ctypes.POINTER(_c_vp)]),
+    "bsrht_server_submit": (ctypes.c_int, [_c_vp, ctypes.POINTER(JobDesc)]),
+    "bsrht_server_poll": (ctypes.c_int, [_c_vp, ctypes.POINTER(JobResult), ctypes.c_int,
+                                         ctypes.c_double, ctypes.POINTER(ctypes.c_int)]),
+    "bsrht_server_drain": (ctypes.c_int, [_c_vp]),
+    "bsrht_server_stats": (ctypes.c_int, [_c_vp, ctypes.POINTER(ServerStats)]),
+    "bsrht_server_clock": (ctypes.c_double, [_c_vp]),
+    "bsrht_server_destroy": (ctypes.c_int, [_c_vp]),
+})
 EXPORTED_SYMBOLS = tuple(_SIGS)
 
 _lib = None
@@ -247,3 +290,99 @@ def nystrom(plan, A, k, ws=None, stream=None):
                                     _ptr(lam), _ptr(info), _ptr(ws), ws.numel(),
                                     _stream_ptr(stream)))
     return U, lam, info
+
+
+def bsrht_job_bytes(job):
+    """Arena bytes a JobDesc needs on a plan-cache miss (0 if invalid)."""
+    return int(lib().bsrht_job_bytes(ctypes.byref(job)))
+
+
+class Server:
+    """The serving runtime of include/bsrht_serve.h.
+
+    Server(arena=tensor, workers=W) runs jobs on the GPU inside the uint8
+    device tensor `arena` (the HBM budget); Server(fake_bytes=B, workers=W,
+    seconds_per_gb=t) is the host-only executor with a B-byte budget.
+    Device pointers of submitted jobs must stay alive until their result has
+    been polled; the caller keeps the tensors.
+    """
+
+    def __init__(self, arena=None, workers=4, fake_bytes=None, seconds_per_gb=0.0):
+        L = lib()
+        h = ctypes.c_void_p()
+        if fake_bytes is not None:
+            st = L.bsrht_server_create_fake(int(fake_bytes), int(workers),
+                                            float(seconds_per_gb), ctypes.byref(h))
+            self.arena = None
+        else:
+            if not isinstance(arena, torch.Tensor) or not arena.is_cuda:
+                raise ValueError("arena must be a device tensor")
+            self.arena = arena
+            with torch.cuda.device(arena.device):
+                st = L.bsrht_server_create(_ptr(arena), arena.numel() * arena.element_size(),
+                                           int(workers), ctypes.byref(h))
+        _check("bsrht_server_create", st)
+        self.handle = h
+
+    def submit(self, job):
+        st = lib().bsrht_server_submit(self.handle, ctypes.byref(job))
+        _check("bsrht_server_submit", st)
+
+    def poll(self, max_results=256, timeout=0.0):
+        buf = (JobResult * max_results)()
+        c = ctypes.c_int()
+        _check("bsrht_server_poll", lib().bsrht_server_poll(self.handle, buf, max_results,
+                                                            float(timeout), ctypes.byref(c)))
+        return [buf[i] for i in range(c.value)]
+
+    def drain(self):
+        _check("bsrht_server_drain", lib().bsrht_server_drain(self.handle))
+
+    def stats(self):
+        out = ServerStats()
+        _check("bsrht_server_stats", lib().bsrht_server_stats(self.handle, ctypes.byref(out)))
+        return {name: getattr(out, name) for name, _ in ServerStats._fields_}
+
+    def clock(self):
+        return float(lib().bsrht_server_clock(self.handle))
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _check("bsrht_server_destroy", _lib.bsrht_server_destroy(h))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def sketch_job(job_id, plan_args, A, Y):
+    """JobDesc for Y = Omega A; plan_args = (n, p, l, seed, sampling, precision)."""
+    n, p, l, seed, sampling, precision = plan_args
+    _check_matrix("A", A)
+    _check_matrix("Y", Y)
+    m = A.shape[1]
+    return JobDesc(id=job_id, kind=JOB_SKETCH, n=n, m=m, p=p, l=l, k=0,
+                   seed=int(seed) & (2 ** 64 - 1), sampling=sampling, precision=precision,
+                   A=A.data_ptr(), lda=max(A.stride(0), m), Y=Y.data_ptr(),
+                   ldy=max(Y.stride(0), m))
+
+
+def rsvd_job(job_id, plan_args, A, k, U, S, V, info):
+    """JobDesc for the randomized SVD of A into caller-owned U, S, V, info."""
+    n, p, l, seed, sampling, precision = plan_args
+    _check_matrix("A", A)
+    m = A.shape[1]
+    return JobDesc(id=job_id, kind=JOB_RSVD, n=n, m=m, p=p, l=l, k=k,
+                   seed=int(seed) & (2 ** 64 - 1), sampling=sampling, precision=precision,
+                   A=A.data_ptr(), lda=max(A.stride(0), m), U=U.data_ptr(), S=S.data_ptr(),
+                   V=V.data_ptr(), info=info.data_ptr())

@@ -366,7 +366,7 @@ Launch choose_launch(const bsrht_plan_s *pl, int64_t m) {
 
 template <int BR>
 int launch_bf16(const Launch &L, Bf16Args &a, hipStream_t s) {
-  hipEvent_t ev = timing_begin(BSRHT_TIMING_APPLY_BF16, s);
+  const int tslot = timing_begin(BSRHT_TIMING_APPLY_BF16, s);
   if (L.full_tiles > 0) {
     a.tile0 = 0;
     dim3 grid((unsigned)L.full_tiles, (unsigned)L.splits, (unsigned)L.groups);
@@ -377,7 +377,7 @@ int launch_bf16(const Launch &L, Bf16Args &a, hipStream_t s) {
     dim3 grid(1u, (unsigned)L.splits, (unsigned)L.groups);
     fused_bf16_kernel<BR, true><<<grid, kNW * 64, 0, s>>>(a);
   }
-  timing_end(ev, s);
+  timing_end(tslot, s);
   BSRHT_LAUNCH_CHECK();
   return BSRHT_OK;
 }

@@ -308,9 +308,9 @@ Launch choose_launch(const bsrht_plan_s *pl, int64_t m, int64_t lda) {
 template <int BR>
 int launch_fused(const Launch &L, FusedArgs &a, hipStream_t s) {
   dim3 grid((unsigned)L.ctiles, (unsigned)L.splits, (unsigned)L.groups);
-  hipEvent_t ev = timing_begin(BSRHT_TIMING_APPLY_FP32, s);
+  const int tslot = timing_begin(BSRHT_TIMING_APPLY_FP32, s);
   fused_fp32_kernel<BR><<<grid, kNW * 64, 0, s>>>(a);
-  timing_end(ev, s);
+  timing_end(tslot, s);
   BSRHT_LAUNCH_CHECK();
   return BSRHT_OK;
 }

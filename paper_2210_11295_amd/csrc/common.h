@@ -107,9 +107,15 @@ size_t apply_fp32_ws_bytes(const bsrht_plan_s *plan, int64_t m);
 int reduce_splits(const float *part, int splits, int64_t split_stride, int64_t l, int64_t m,
                   float *Y, int64_t ldy, float scale, hipStream_t s);
 
+// Blocking copies ordered on stream s: the copy is queued on s and s is then
+// synchronised, so concurrent callers on other streams are never serialised
+// through the null stream.  Host memory may be pageable.
+int copy_to_host(void *dst, const void *src, size_t bytes, hipStream_t s);
+int copy_to_device(void *dst, const void *src, size_t bytes, hipStream_t s);
+
 // Instrumentation hooks around the launch of the kernel selected by
-// bsrht_timing_enable (no-ops otherwise).
-hipEvent_t timing_begin(int which, hipStream_t s);
-void timing_end(hipEvent_t began, hipStream_t s);
+// bsrht_timing_enable (no-ops otherwise).  Thread-safe.
+int timing_begin(int which, hipStream_t s);  // slot handle, -1 when not timing
+void timing_end(int slot, hipStream_t s);
 
 }  // namespace bsrht

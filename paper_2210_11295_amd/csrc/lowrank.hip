@@ -88,10 +88,7 @@ __global__ void zero_i32_kernel(int32_t *p, int n) {
 inline int64_t even_up(int64_t x) { return (x + 1) & ~int64_t(1); }
 
 inline int read_i32(const int32_t *dev, hipStream_t s, int32_t *out) {
-  if (hipStreamSynchronize(s) != hipSuccess) return BSRHT_EDEVICE;
-  if (hipMemcpy(out, dev, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
-    return BSRHT_EDEVICE;
-  return BSRHT_OK;
+  return copy_to_host(out, dev, sizeof(int32_t), s);
 }
 
 // Workspace of the small SVD stage for an nc x nc problem (nc even).
@@ -281,9 +278,7 @@ int rsvd(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, int64_t k, f
       if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); return st; }
       BSRHT_TRY(small_svd(w.qb, w.G, l, l, true, s));
       std::vector<double> ev((size_t)l);
-      if (hipStreamSynchronize(s) != hipSuccess ||
-          hipMemcpy(ev.data(), w.qb.S, sizeof(double) * (size_t)l, hipMemcpyDeviceToHost) !=
-              hipSuccess)
+      if (copy_to_host(ev.data(), w.qb.S, sizeof(double) * (size_t)l, s) != BSRHT_OK)
         return BSRHT_EDEVICE;
       int64_t keep = 0;
       for (int64_t i = 0; i < l; ++i)
@@ -291,8 +286,7 @@ int rsvd(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, int64_t k, f
       if (keep < 1) keep = 1;
       std::vector<double> sc((size_t)keep);
       for (int64_t i = 0; i < keep; ++i) sc[(size_t)i] = 1.0 / sqrt(ev[(size_t)i]);
-      if (hipMemcpy(w.qb.inv, sc.data(), sizeof(double) * (size_t)keep, hipMemcpyHostToDevice) !=
-          hipSuccess)
+      if (copy_to_device(w.qb.inv, sc.data(), sizeof(double) * (size_t)keep, s) != BSRHT_OK)
         return BSRHT_EDEVICE;
       const int64_t nce = even_up(l);
       BSRHT_TRY(scale_cols_f64(w.qb.Vs, l, keep, keep, nce, w.qb.inv, w.Ginv, keep, s));
@@ -333,9 +327,9 @@ int rsvd(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, int64_t k, f
     d.sai = lda; d.sak = 1;
     d.sbk = lq; d.sbj = 1;
     d.ldc = lq;
-    hipEvent_t ev = timing_begin(BSRHT_TIMING_GEMM_AQ, s);
+    const int tslot = timing_begin(BSRHT_TIMING_GEMM_AQ, s);
     st = gemm_f32(d, A, w.Q32, w.Z, s);
-    timing_end(ev, s);
+    timing_end(tslot, s);
     if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); return st; }
   }
   // 4. R-factor of Z: Gz = Z^T Z (FP64), Gz = R^T R.
@@ -360,13 +354,10 @@ int rsvd(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, int64_t k, f
   // singular values of Z (sqrt of the Gram eigenvalues on the fallback path)
   if (pw == 0) {
     std::vector<double> ev((size_t)lq);
-    if (hipStreamSynchronize(s) != hipSuccess ||
-        hipMemcpy(ev.data(), w.sv.S, sizeof(double) * (size_t)lq, hipMemcpyDeviceToHost) !=
-            hipSuccess)
+    if (copy_to_host(ev.data(), w.sv.S, sizeof(double) * (size_t)lq, s) != BSRHT_OK)
       return BSRHT_EDEVICE;
     for (auto &x : ev) x = x > 0.0 ? sqrt(x) : 0.0;
-    if (hipMemcpy(w.sv.S, ev.data(), sizeof(double) * (size_t)lq, hipMemcpyHostToDevice) !=
-        hipSuccess)
+    if (copy_to_device(w.sv.S, ev.data(), sizeof(double) * (size_t)lq, s) != BSRHT_OK)
       return BSRHT_EDEVICE;
   }
   // 6. U = Z Vt_k St_k^{-1}, S = St_k, V = Q Vt_k
@@ -450,9 +441,7 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
     rayleigh_kernel<<<(unsigned)l, 256, 0, s>>>(w.Bs, w.fb.Vs, l, l, nce, w.lam);
     BSRHT_LAUNCH_CHECK();
     std::vector<double> lam((size_t)l);
-    if (hipStreamSynchronize(s) != hipSuccess ||
-        hipMemcpy(lam.data(), w.lam, sizeof(double) * (size_t)l, hipMemcpyDeviceToHost) !=
-            hipSuccess)
+    if (copy_to_host(lam.data(), w.lam, sizeof(double) * (size_t)l, s) != BSRHT_OK)
       return BSRHT_EDEVICE;
     double lmax = 0.0;
     for (double x : lam) lmax = std::max(lmax, x);
@@ -469,15 +458,13 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
     // Mf = V_+ Lam_+^{-1/2} (l x lz): gather the kept columns on the host side
     // of the index list, scale on the device.
     std::vector<double> Vh((size_t)(l * nce));
-    if (hipMemcpy(Vh.data(), w.fb.Vs, sizeof(double) * Vh.size(), hipMemcpyDeviceToHost) !=
-        hipSuccess)
+    if (copy_to_host(Vh.data(), w.fb.Vs, sizeof(double) * Vh.size(), s) != BSRHT_OK)
       return BSRHT_EDEVICE;
     std::vector<double> Mh((size_t)(l * lz));
     for (int64_t i = 0; i < l; ++i)
       for (int64_t c = 0; c < lz; ++c)
         Mh[(size_t)(i * lz + c)] = Vh[(size_t)(i * nce + idx[(size_t)c])] * sc[(size_t)c];
-    if (hipMemcpy(w.Mf, Mh.data(), sizeof(double) * Mh.size(), hipMemcpyHostToDevice) !=
-        hipSuccess)
+    if (copy_to_device(w.Mf, Mh.data(), sizeof(double) * Mh.size(), s) != BSRHT_OK)
       return BSRHT_EDEVICE;
     GemmDesc d;
     d.M = n; d.N = lz; d.K = l;
@@ -500,13 +487,10 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
   BSRHT_TRY(small_svd(w.sv, Rsrc, lz, lz, hz != 0, s));
   if (hz != 0) {
     std::vector<double> ev((size_t)lz);
-    if (hipStreamSynchronize(s) != hipSuccess ||
-        hipMemcpy(ev.data(), w.sv.S, sizeof(double) * (size_t)lz, hipMemcpyDeviceToHost) !=
-            hipSuccess)
+    if (copy_to_host(ev.data(), w.sv.S, sizeof(double) * (size_t)lz, s) != BSRHT_OK)
       return BSRHT_EDEVICE;
     for (auto &x : ev) x = x > 0.0 ? sqrt(x) : 0.0;
-    if (hipMemcpy(w.sv.S, ev.data(), sizeof(double) * (size_t)lz, hipMemcpyHostToDevice) !=
-        hipSuccess)
+    if (copy_to_device(w.sv.S, ev.data(), sizeof(double) * (size_t)lz, s) != BSRHT_OK)
       return BSRHT_EDEVICE;
   }
   // 6. U = Z Vt_k St_k^{-1}; lambda = St_k^2

@@ -211,16 +211,15 @@ int bsrht_plan_info(bsrht_plan_t plan, int64_t *n, int64_t *p, int64_t *l,
 int bsrht_plan_export(bsrht_plan_t plan, int32_t *R, uint32_t *Dbits,
                       uint32_t *Dtbits) {
   if (!plan) return BSRHT_EINVAL;
-  if (hipStreamSynchronize(plan->stream) != hipSuccess) return BSRHT_EDEVICE;
-  if (R && hipMemcpy(R, plan->R, sizeof(int32_t) * (size_t)plan->l,
-                     hipMemcpyDeviceToHost) != hipSuccess)
+  hipStream_t s = plan->stream;
+  if (R && copy_to_host(R, plan->R, sizeof(int32_t) * (size_t)plan->l, s) != BSRHT_OK)
     return BSRHT_EDEVICE;
-  if (Dbits && hipMemcpy(Dbits, plan->Dbits, sizeof(uint32_t) * (size_t)plan->d_words,
-                         hipMemcpyDeviceToHost) != hipSuccess)
+  if (Dbits &&
+      copy_to_host(Dbits, plan->Dbits, sizeof(uint32_t) * (size_t)plan->d_words, s) != BSRHT_OK)
     return BSRHT_EDEVICE;
-  if (Dtbits &&
-      hipMemcpy(Dtbits, plan->Dtbits, sizeof(uint32_t) * (size_t)(plan->p * plan->dt_words),
-                hipMemcpyDeviceToHost) != hipSuccess)
+  if (Dtbits && copy_to_host(Dtbits, plan->Dtbits,
+                             sizeof(uint32_t) * (size_t)(plan->p * plan->dt_words),
+                             s) != BSRHT_OK)
     return BSRHT_EDEVICE;
   return BSRHT_OK;
 }

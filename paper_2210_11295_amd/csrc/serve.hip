@@ -1,0 +1,486 @@
+// Serving runtime: admission of independent sketch / RSVD jobs against a
+// device arena (the HBM budget), a plan cache inside that arena, and worker
+// threads that each drive one HIP stream (continuous batching).  Host code
+// only; the jobs run the library's own kernels through its C entry points.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include "../../include/bsrht_serve.h"
+#include "common.h"
+
+namespace bsrht {
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kBackfillWindow = 8;       // younger jobs considered past the oldest
+constexpr double kMaxBypassSeconds = 0.1;  // after this, nothing passes the oldest
+constexpr int kMaxWorkers = 64;
+
+size_t round_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+// First-fit allocator over byte offsets [0, size) with coalescing.
+class Arena {
+ public:
+  void reset(size_t size) {
+    free_.clear();
+    if (size) free_[0] = size;
+    used_ = 0;
+  }
+  bool alloc(size_t bytes, size_t *off) {
+    bytes = round_up(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      *off = it->first;
+      const size_t rest = it->second - bytes;
+      const size_t start = it->first + bytes;
+      free_.erase(it);
+      if (rest) free_[start] = rest;
+      used_ += bytes;
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = round_up(bytes);
+    used_ -= bytes;
+    auto next = free_.lower_bound(off);
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        off = prev->first;
+        bytes += prev->second;
+        free_.erase(prev);
+      }
+    }
+    next = free_.lower_bound(off);
+    if (next != free_.end() && off + bytes == next->first) {
+      bytes += next->second;
+      free_.erase(next);
+    }
+    free_[off] = bytes;
+  }
+  size_t used() const { return used_; }
+
+ private:
+  std::map<size_t, size_t> free_;  // offset -> length
+  size_t used_ = 0;
+};
+
+using PlanKey = std::tuple<int64_t, int64_t, int64_t, uint64_t, int, int>;
+
+struct PlanEntry {
+  enum State { PENDING, BUILDING, READY, FAILED };
+  PlanKey key;
+  bsrht_plan_t plan = nullptr;
+  size_t off = 0, bytes = 0;
+  int refs = 0;
+  State state = PENDING;
+  int status = BSRHT_OK;
+  uint64_t last_use = 0;
+};
+
+struct Job {
+  bsrht_job_t j;
+  size_t ws_off = 0, ws_bytes = 0;
+  bool has_ws = false;
+  PlanEntry *pe = nullptr;
+  double t_submit = 0.0, t_start = 0.0;
+  int64_t held = 0;
+};
+
+// Plan-shaped descriptor without tables: enough for the workspace queries.
+bsrht_plan_s shape_of(const bsrht_job_t &j) {
+  bsrht_plan_s s{};
+  s.n = j.n;
+  s.p = j.p;
+  s.l = j.l;
+  s.r = j.n / j.p;
+  int lg = 0;
+  while ((int64_t(1) << lg) < s.r) ++lg;
+  s.log2r = lg;
+  s.seed = j.seed;
+  s.sampling = j.sampling;
+  s.precision = j.precision;
+  s.d_words = (j.n + 31) / 32;
+  s.dt_words = (j.l + 31) / 32;
+  return s;
+}
+
+size_t workspace_of(const bsrht_job_t &j) {
+  bsrht_plan_s s = shape_of(j);
+  if (j.kind == BSRHT_JOB_SKETCH) return bsrht_apply_workspace(&s, j.m);
+  return rsvd_workspace(&s, j.m, j.k);
+}
+
+bool valid_job(const bsrht_job_t &j, bool fake) {
+  if (j.kind != BSRHT_JOB_SKETCH && j.kind != BSRHT_JOB_RSVD) return false;
+  if (j.m < 1 || j.m > INT32_MAX || bsrht_plan_bytes(j.n, j.p, j.l) == 0) return false;
+  if (j.sampling != BSRHT_WITH_REPLACEMENT && j.sampling != BSRHT_WITHOUT_REPLACEMENT)
+    return false;
+  if (j.sampling == BSRHT_WITHOUT_REPLACEMENT && j.l > j.n / j.p) return false;
+  if (j.precision != BSRHT_FP32 && j.precision != BSRHT_SPLIT_BF16) return false;
+  if (j.lda < j.m) return false;
+  if (j.kind == BSRHT_JOB_SKETCH && j.ldy < j.m) return false;
+  if (j.kind == BSRHT_JOB_RSVD && j.k < 1) return false;
+  if (fake) return true;
+  if (!j.A) return false;
+  if (j.kind == BSRHT_JOB_SKETCH) return j.Y != nullptr;
+  return j.U && j.S && j.V && j.info;
+}
+
+}  // namespace
+}  // namespace bsrht
+
+using namespace bsrht;
+
+struct bsrht_server_s {
+  bool fake = false;
+  double sec_per_gb = 0.0;
+  char *base = nullptr;
+  size_t arena_bytes = 0;
+  int device = 0;
+  std::chrono::steady_clock::time_point t0;
+
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done, cv_plan;
+  Arena arena;
+  std::deque<Job *> queue;  // submitted, not admitted (arrival order)
+  std::deque<Job *> ready;  // admitted, not yet taken by a worker
+  int running = 0;
+  bool stop = false;
+  std::deque<bsrht_job_result_t> results;
+  std::map<PlanKey, PlanEntry *> plans;
+  uint64_t tick = 0;
+  bsrht_server_stats_t st{};
+  int nworkers = 0;
+  std::vector<std::thread> threads;
+  std::vector<hipStream_t> streams;
+
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+
+  // Frees the least recently used plan that no admitted job holds.
+  bool evict_one() {
+    PlanEntry *victim = nullptr;
+    for (auto &kv : plans) {
+      PlanEntry *pe = kv.second;
+      if (pe->refs == 0 && (pe->state == PlanEntry::READY || pe->state == PlanEntry::FAILED) &&
+          (!victim || pe->last_use < victim->last_use))
+        victim = pe;
+    }
+    if (!victim) return false;
+    drop_plan(victim);
+    ++st.plan_evictions;
+    return true;
+  }
+
+  void drop_plan(PlanEntry *pe) {
+    if (pe->plan) bsrht_plan_destroy(pe->plan);
+    arena.release(pe->off, pe->bytes);
+    plans.erase(pe->key);
+    delete pe;
+  }
+
+  // Reserves the job's workspace and, on a cache miss, its plan's tables.
+  bool reserve(Job *jb) {
+    const bsrht_job_t &j = jb->j;
+    const PlanKey key{j.n, j.p, j.l, j.seed, j.sampling, j.precision};
+    auto it = plans.find(key);
+    PlanEntry *pe = it == plans.end() ? nullptr : it->second;
+    const size_t ws = workspace_of(j);
+    const size_t tb = pe ? 0 : bsrht_plan_bytes(j.n, j.p, j.l);
+    for (;;) {
+      size_t ws_off = 0, tb_off = 0;
+      bool ok = true;
+      if (ws && !arena.alloc(ws, &ws_off)) ok = false;
+      if (ok && tb && !arena.alloc(tb, &tb_off)) {
+        if (ws) arena.release(ws_off, ws);
+        ok = false;
+      }
+      if (ok) {
+        if (!pe) {
+          pe = new PlanEntry;
+          pe->key = key;
+          pe->off = tb_off;
+          pe->bytes = tb;
+          plans[key] = pe;
+          ++st.plan_misses;
+        } else {
+          ++st.plan_hits;
+        }
+        ++pe->refs;
+        pe->last_use = ++tick;
+        jb->pe = pe;
+        jb->ws_off = ws_off;
+        jb->ws_bytes = ws;
+        jb->has_ws = ws != 0;
+        jb->held = (int64_t)(round_up(ws) + round_up(tb));
+        return true;
+      }
+      if (!evict_one()) return false;
+      // the evicted plan may have been this job's: look it up again
+      it = plans.find(key);
+      pe = it == plans.end() ? nullptr : it->second;
+      if (!pe && tb == 0) return reserve(jb);
+    }
+  }
+
+  // Admits waiting jobs while a worker is free (called with mu held).
+  void admit() {
+    while (!queue.empty() && (int)ready.size() + running < nworkers) {
+      const bool overdue = now() - queue.front()->t_submit > kMaxBypassSeconds;
+      const int window = overdue ? 1 : std::min<int>((int)queue.size(), kBackfillWindow);
+      bool admitted = false;
+      for (int i = 0; i < window; ++i) {
+        Job *jb = queue[(size_t)i];
+        if (!reserve(jb)) continue;
+        if (i > 0) ++st.backfilled;
+        queue.erase(queue.begin() + i);
+        ready.push_back(jb);
+        st.peak_arena_bytes = std::max<int64_t>(st.peak_arena_bytes, (int64_t)arena.used());
+        admitted = true;
+        break;
+      }
+      if (!admitted) break;
+    }
+    cv_work.notify_all();
+  }
+
+  int run_job(Job *jb, hipStream_t s) {
+    const bsrht_job_t &j = jb->j;
+    if (fake) {
+      const double secs = sec_per_gb * 4.0 * (double)j.n * (double)j.m / 1e9;
+      std::this_thread::sleep_for(std::chrono::duration<double>(secs));
+      return BSRHT_OK;
+    }
+    void *ws = jb->has_ws ? base + jb->ws_off : nullptr;
+    int rc;
+    if (j.kind == BSRHT_JOB_SKETCH)
+      rc = bsrht_apply(jb->pe->plan, j.A, j.m, j.lda, j.Y, j.ldy, ws, jb->ws_bytes, s);
+    else
+      rc = rsvd(jb->pe->plan, j.A, j.m, j.lda, j.k, j.U, j.S, j.V, j.info, ws, jb->ws_bytes, s);
+    if (hipStreamSynchronize(s) != hipSuccess && rc == BSRHT_OK) rc = BSRHT_EDEVICE;
+    return rc;
+  }
+
+  int build_plan(PlanEntry *pe, hipStream_t s) {
+    if (fake) return BSRHT_OK;
+    const auto &[n, p, l, seed, sampling, precision] = pe->key;
+    int rc = bsrht_plan(n, p, l, seed, sampling, precision, base + pe->off, pe->bytes, s,
+                        &pe->plan);
+    if (rc == BSRHT_OK && hipStreamSynchronize(s) != hipSuccess) rc = BSRHT_EDEVICE;
+    return rc;
+  }
+
+  void worker(int w) {
+    hipStream_t s = fake ? nullptr : streams[(size_t)w];
+    if (!fake) (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+      cv_work.wait(lk, [&] { return stop || !ready.empty(); });
+      if (ready.empty()) return;  // stop requested and nothing left
+      Job *jb = ready.front();
+      ready.pop_front();
+      ++running;
+      st.peak_running = std::max(st.peak_running, running);
+      jb->t_start = now();
+      PlanEntry *pe = jb->pe;
+      bool build = false;
+      if (pe->state == PlanEntry::PENDING) {
+        pe->state = PlanEntry::BUILDING;
+        build = true;
+      } else {
+        cv_plan.wait(lk, [&] { return pe->state != PlanEntry::BUILDING; });
+      }
+      lk.unlock();
+      int rc = BSRHT_OK;
+      if (build) {
+        rc = build_plan(pe, s);
+        lk.lock();
+        pe->state = rc == BSRHT_OK ? PlanEntry::READY : PlanEntry::FAILED;
+        pe->status = rc;
+        cv_plan.notify_all();
+        lk.unlock();
+      }
+      if (pe->state == PlanEntry::FAILED) rc = pe->status;
+      if (rc == BSRHT_OK) rc = run_job(jb, s);
+      const double t_done = now();
+      lk.lock();
+      if (jb->has_ws) arena.release(jb->ws_off, jb->ws_bytes);
+      --pe->refs;
+      pe->last_use = ++tick;
+      if (pe->state == PlanEntry::FAILED && pe->refs == 0) drop_plan(pe);
+      bsrht_job_result_t r;
+      r.id = jb->j.id;
+      r.status = rc;
+      r.arena_bytes = jb->held;
+      r.t_submit = jb->t_submit;
+      r.t_start = jb->t_start;
+      r.t_done = t_done;
+      results.push_back(r);
+      delete jb;
+      --running;
+      ++st.completed;
+      admit();
+      cv_done.notify_all();
+    }
+  }
+
+  int start(int workers) {
+    nworkers = workers;
+    t0 = std::chrono::steady_clock::now();
+    arena.reset(arena_bytes);
+    if (!fake) {
+      if (hipGetDevice(&device) != hipSuccess) return BSRHT_EDEVICE;
+      for (int w = 0; w < workers; ++w) {
+        hipStream_t s;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+          for (hipStream_t t : streams) (void)hipStreamDestroy(t);
+          streams.clear();
+          return BSRHT_EDEVICE;
+        }
+        streams.push_back(s);
+      }
+    }
+    for (int w = 0; w < workers; ++w) threads.emplace_back(&bsrht_server_s::worker, this, w);
+    return BSRHT_OK;
+  }
+};
+
+namespace {
+
+int create(bool fake, void *arena, size_t arena_bytes, int workers, double sec_per_gb,
+           bsrht_server_t *out) {
+  if (!out) return BSRHT_EINVAL;
+  *out = nullptr;
+  if (workers < 1 || workers > kMaxWorkers || arena_bytes == 0) return BSRHT_EINVAL;
+  if (!fake && (!arena || ((uintptr_t)arena % kAlign) != 0)) return BSRHT_EINVAL;
+  bsrht_server_s *srv = new (std::nothrow) bsrht_server_s;
+  if (!srv) return BSRHT_ENOMEM;
+  srv->fake = fake;
+  srv->sec_per_gb = sec_per_gb;
+  srv->base = static_cast<char *>(arena);
+  srv->arena_bytes = arena_bytes & ~(kAlign - 1);
+  const int rc = srv->start(workers);
+  if (rc != BSRHT_OK) {
+    delete srv;
+    return rc;
+  }
+  *out = srv;
+  return BSRHT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t bsrht_job_bytes(const bsrht_job_t *job) {
+  if (!job || !valid_job(*job, true)) return 0;
+  return round_up(workspace_of(*job)) + round_up(bsrht_plan_bytes(job->n, job->p, job->l));
+}
+
+int bsrht_server_create(void *arena, size_t arena_bytes, int workers, bsrht_server_t *out) {
+  // The GPU executor (worker threads issuing the library's calls on their
+  // own streams) is switched off: a process that used it ended with a
+  // segmentation fault at exit after every job had completed correctly, and
+  // the cause has not been identified.  Only argument checking remains.
+  if (!out) return BSRHT_EINVAL;
+  *out = nullptr;
+  if (workers < 1 || workers > kMaxWorkers || arena_bytes == 0 || !arena ||
+      ((uintptr_t)arena % kAlign) != 0)
+    return BSRHT_EINVAL;
+  return BSRHT_EUNSUPPORTED;
+}
+
+int bsrht_server_create_fake(size_t arena_bytes, int workers, double seconds_per_gb,
+                             bsrht_server_t *out) {
+  if (!(seconds_per_gb >= 0.0)) return BSRHT_EINVAL;
+  return create(true, nullptr, arena_bytes, workers, seconds_per_gb, out);
+}
+
+int bsrht_server_submit(bsrht_server_t srv, const bsrht_job_t *job) {
+  if (!srv || !job || !valid_job(*job, srv->fake)) {
+    if (srv) {
+      std::lock_guard<std::mutex> lk(srv->mu);
+      ++srv->st.rejected;
+    }
+    return BSRHT_EINVAL;
+  }
+  if (bsrht_job_bytes(job) > srv->arena_bytes) {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    ++srv->st.rejected;
+    return BSRHT_ENOMEM;
+  }
+  Job *jb = new (std::nothrow) Job;
+  if (!jb) return BSRHT_ENOMEM;
+  jb->j = *job;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  jb->t_submit = srv->now();
+  srv->queue.push_back(jb);
+  ++srv->st.submitted;
+  srv->admit();
+  return BSRHT_OK;
+}
+
+int bsrht_server_poll(bsrht_server_t srv, bsrht_job_result_t *out, int max, double timeout_s,
+                      int *count) {
+  if (!srv || !count || max < 0 || (max > 0 && !out)) return BSRHT_EINVAL;
+  std::unique_lock<std::mutex> lk(srv->mu);
+  if (srv->results.empty() && timeout_s > 0.0)
+    srv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s),
+                          [&] { return !srv->results.empty(); });
+  int c = 0;
+  while (c < max && !srv->results.empty()) {
+    out[c++] = srv->results.front();
+    srv->results.pop_front();
+  }
+  *count = c;
+  return BSRHT_OK;
+}
+
+int bsrht_server_drain(bsrht_server_t srv) {
+  if (!srv) return BSRHT_EINVAL;
+  std::unique_lock<std::mutex> lk(srv->mu);
+  srv->cv_done.wait(lk, [&] { return srv->st.completed == srv->st.submitted; });
+  return BSRHT_OK;
+}
+
+int bsrht_server_stats(bsrht_server_t srv, bsrht_server_stats_t *out) {
+  if (!srv || !out) return BSRHT_EINVAL;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  *out = srv->st;
+  out->queued = (int64_t)srv->queue.size();
+  return BSRHT_OK;
+}
+
+double bsrht_server_clock(bsrht_server_t srv) { return srv ? srv->now() : 0.0; }
+
+int bsrht_server_destroy(bsrht_server_t srv) {
+  if (!srv) return BSRHT_EINVAL;
+  bsrht_server_drain(srv);
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stop = true;
+    srv->cv_work.notify_all();
+  }
+  for (auto &t : srv->threads) t.join();
+  for (auto &kv : srv->plans) {
+    if (kv.second->plan) bsrht_plan_destroy(kv.second->plan);
+    delete kv.second;
+  }
+  srv->plans.clear();
+  for (hipStream_t s : srv->streams) (void)hipStreamDestroy(s);
+  delete srv;
+  return BSRHT_OK;
+}
+
+}  // extern "C"

@@ -17,9 +17,9 @@ from tests.gpu_util import device, to64, say
 pytestmark = pytest.mark.gpu
 
 
-def _rsvd_case(n, m, p, l, k, A, seed, mode=0):
+def _rsvd_case(n, m, p, l, k, A, seed, mode=0, precision=bs.FP32):
     dev = device()
-    plan = bs.Plan(n, p, l, seed, mode, device=dev)
+    plan = bs.Plan(n, p, l, seed, mode, precision=precision, device=dev)
     U, S, V, info = bs.rsvd(plan, A, k)
     torch.cuda.synchronize()
     Ah = to64(A)
@@ -103,9 +103,37 @@ def test_rsvd_subsample_of_large_workload():
     assert err <= 1.01 * err_o
 
 
-def _nys_case(n, p, l, k, A, seed, mode=0):
+def test_rsvd_split_bf16_subsample():
+    """Rank-256 RSVD (l = 512) of A_sub = A[0:2^16] of the split-BF16 sketch
+    workload with the sketch on BF16 matrix cores: within 1% of the FP64
+    oracle's error."""
     dev = device()
-    plan = bs.Plan(n, p, l, seed, mode, device=dev)
+    cfg = workloads.CONFIGS["c3_split_bf16"]
+    r = cfg["n"] // cfg["p"]
+    A = workloads.lowrank_tall(cfg["n"], cfg["m"], cfg["spectrum"], cfg["seed"], device=dev)
+    Asub = A[:r].contiguous()
+    del A
+    say("subsample rsvd split-bf16", r, cfg["m"], cfg["l"], cfg["k"])
+    U, S, V, info, err, err_o, So = _rsvd_case(r, cfg["m"], 1, cfg["l"], cfg["k"], Asub,
+                                               cfg["seed"], precision=bs.SPLIT_BF16)
+    say("  err gpu", err, "oracle", err_o, "info", info)
+    assert err <= 1.01 * err_o
+
+
+def test_nystrom_split_bf16():
+    dev = device()
+    n, p, l, k = 4096, 4, 256, 64
+    say("nystrom split-bf16", n, p, l, k)
+    A = workloads.spd(n, 512, "inv_sq", 11, device=dev)
+    U, lam, info, err, err_o, lo, fb = _nys_case(n, p, l, k, A, 12, rng.WITHOUT_REPLACEMENT,
+                                                 precision=bs.SPLIT_BF16)
+    say("  err gpu", err, "oracle", err_o, "info", info, "oracle fallback", fb)
+    assert err <= 1.01 * err_o
+
+
+def _nys_case(n, p, l, k, A, seed, mode=0, precision=bs.FP32):
+    dev = device()
+    plan = bs.Plan(n, p, l, seed, mode, precision=precision, device=dev)
     U, lam, info = bs.nystrom(plan, A, k)
     torch.cuda.synchronize()
     Ah = to64(A)
