@@ -53,17 +53,21 @@ int trinv_upper(const double *C, int64_t n, int64_t ldc, double *Ci, int64_t ldi
 int eye(double *M, int64_t n, int64_t ld, hipStream_t s);
 int fill_f64(double *p, int64_t count, double value, hipStream_t s);
 
-// One-sided Jacobi on the columns of X (nr x nc, column-major, ldx), nc even,
-// nc <= 4096: X is overwritten by X V = U Sigma; S (nc, descending) is
-// written, and Us (row-major, ldu) receives in the same order either the
-// normalised columns U (V == NULL: nr x nc, the left singular vectors of X)
-// or, when V (nc * nc doubles, scratch) is given, the accumulated rotations
-// (nc x nc: the right singular vectors; for symmetric X, eigenvectors that
-// stay orthogonal to working precision).  perm (nc int32) and flags (2 uint,
-// flags[1] = sweeps taken) are scratch.
+// One-sided block Jacobi on the columns of X (nr x nc, column-major, ldx),
+// nc a multiple of 32, nc <= 4096, nr <= 4096: X is overwritten by
+// X V = U Sigma; S (nc, descending) is written, and Us (row-major, ldu)
+// receives in the same order either the normalised columns U (V == NULL:
+// nr x nc, the left singular vectors of X) or, when V (nc * nc doubles,
+// scratch) is given, the accumulated rotations (nc x nc: the right singular
+// vectors; for symmetric X, eigenvectors that stay orthogonal to working
+// precision).  perm (nc int32) and flags (4 uint, 8-byte aligned) are
+// scratch.  Pairs with a column norm at or below u ||X||_F (u = 2^-53) count
+// as orthogonal, so rank-deficient inputs converge.  When
+// max_sweeps sweeps still rotate, BSRHT_INFO_JACOBI_NOCONV is or-ed into
+// *info (device, may be NULL).  Synchronises the stream once per sweep.
 int jacobi_svd(double *X, int64_t nr, int64_t nc, int64_t ldx, double *V, double *S,
                double *Us, int64_t ldu, int32_t *perm, unsigned int *flags, int max_sweeps,
-               hipStream_t s);
+               int32_t *info, hipStream_t s);
 
 int transpose_f32_f64(const float *src, int64_t rows, int64_t cols, int64_t lds, double *dst,
                       int64_t ldd, hipStream_t s);

@@ -5,11 +5,9 @@
 //   - FP64 Cholesky C^T C = G (upper C), the factorisation behind
 //     Cholesky-QR (used where the paper's Algorithms ask for QR / TSQR);
 //   - inverse of an upper-triangular matrix;
-//   - one-sided (Hestenes) Jacobi SVD, the "SVD of R" step of both
-//     Algorithms, as one cooperative kernel with a grid barrier per round;
+//   - one-sided (Hestenes) block Jacobi SVD, the "SVD of R" step of both
+//     Algorithms: block pairs swept in LDS, one launch per round;
 //   - small helpers (identity, transpose/convert, column scaling, sort).
-#include <hip/hip_cooperative_groups.h>
-
 #include <algorithm>
 
 #include "common.h"
@@ -364,28 +362,35 @@ __global__ __launch_bounds__(64 * kTrinvWaves) void trinv_upper_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// One-sided Jacobi (Hestenes) on the columns of X (nr x nc, column-major,
-// columns of length nr at stride ldx), nc even: columns are rotated in pairs
-// until all are mutually orthogonal, X V = U Sigma.  The singular values are
-// the final column norms.  Without accumulation the returned vectors are the
-// normalised columns (U); a column with small sigma_j then carries an error
-// of order u sigma_1 / sigma_j, which is harmless where the caller weights
-// column j by sigma_j (the SVD of an R factor, passed as X = R^T: the
-// row-major buffer of R already is R^T in column-major order).  With
-// accumulation (V != NULL) the rotations are also applied to V = I and its
-// columns are returned: V stays orthogonal to working precision, so for a
-// symmetric X the pairs (v_j, v_j^T X v_j) are a backward-stable eigen
+// One-sided block Jacobi (Hestenes) on the columns of X (nr x nc,
+// column-major, columns of length nr at stride ldx): columns are rotated in
+// pairs until all are mutually orthogonal, X V = U Sigma.  The singular
+// values are the final column norms.  Without accumulation the returned
+// vectors are the normalised columns (U); a column with small sigma_j then
+// carries an error of order u sigma_1 / sigma_j, which is harmless where the
+// caller weights column j by sigma_j (the SVD of an R factor, passed as
+// X = R^T: the row-major buffer of R already is R^T in column-major order).
+// With accumulation (V != NULL) the rotations are also applied to V = I and
+// its columns are returned: V stays orthogonal to working precision, so for
+// a symmetric X the pairs (v_j, v_j^T X v_j) are a backward-stable eigen
 // decomposition, which callers that scale by 1/sqrt(lambda_j) need.
-// Round-robin ordering: nc-1 rounds per sweep, nc/2 disjoint pairs per round,
-// one wave per pair, a grid barrier between rounds.
-struct JacobiArgs {
+//
+// Blocking: the columns form nc/W blocks of W.  One launch is one round of a
+// round-robin over block pairs; a workgroup copies its pair (2W columns) into
+// LDS and runs one full cyclic sweep over the 2W(2W-1)/2 column pairs there
+// (W disjoint pairs at a time, 256/W threads per pair), recording the
+// rotations in a 2W x 2W matrix J; it then writes the columns back and, when
+// accumulating, updates V's 2W columns as V J.  A sweep is nc/W - 1 launches;
+// sweeps repeat until one performs no rotation.
+struct JacobiBlockArgs {
   double *X;
-  int64_t nr, nc, ldx;
-  double *V;  // NULL, or nc x nc column-major (ldv) accumulating the rotations
-  int64_t ldv;
+  int nr;
+  int64_t ldx;
+  double *V;  // NULL, or nc x nc column-major (leading dimension nc)
+  int nc, nblocks, round;
   double tol;
-  int max_sweeps;
-  unsigned int *flags;  // [0]: rotations in this sweep (cleared per sweep), [1]: sweeps done
+  const double *floor2;  // (u ||X||_F)^2: columns at or below it are rounding noise
+  unsigned int *rot;     // workgroups that rotated in this sweep
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -395,9 +400,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Pair p of round r among nc players (round-robin, player nc-1 fixed).
-__device__ __forceinline__ void rr_pair(int64_t nc, int64_t r, int64_t p, int64_t &a,
-                                        int64_t &b) {
-  const int64_t m = nc - 1;
+__device__ __forceinline__ void rr_pair(int nc, int r, int p, int &a, int &b) {
+  const int m = nc - 1;
   if (p == 0) {
     a = r % m;
     b = m;
@@ -406,69 +410,125 @@ __device__ __forceinline__ void rr_pair(int64_t nc, int64_t r, int64_t p, int64_
     b = (r + m - p) % m;
   }
   if (a > b) {
-    const int64_t t = a;
+    const int t = a;
     a = b;
     b = t;
   }
 }
 
-__global__ __launch_bounds__(256) void jacobi_kernel(JacobiArgs ja) {
-  namespace cg = cooperative_groups;
-  cg::grid_group grid = cg::this_grid();
-  const int lane = threadIdx.x & 63;
-  const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  const int64_t npairs = ja.nc / 2;
-  int sweep = 0;
-  for (; sweep < ja.max_sweeps; ++sweep) {
-    for (int64_t r = 0; r < ja.nc - 1; ++r) {
-      for (int64_t p = gw; p < npairs; p += nwaves) {
-        int64_t ca, cb;
-        rr_pair(ja.nc, r, p, ca, cb);
-        double *xa = ja.X + ca * ja.ldx, *xb = ja.X + cb * ja.ldx;
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int64_t i = lane; i < ja.nr; i += 64) {
-          const double u = xa[i], v = xb[i];
-          al += u * u;
-          be += v * v;
-          ga += u * v;
-        }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        ga = wave_sum(ga);
-        if (fabs(ga) > ja.tol * sqrt(al * be) && ga != 0.0) {
-          // rotation zeroing the (a, b) entry of the 2x2 Gram [al ga; ga be]
-          const double zeta = (be - al) / (2.0 * ga);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-          for (int64_t i = lane; i < ja.nr; i += 64) {
-            const double u = xa[i], v = xb[i];
-            xa[i] = c * u - sn * v;
-            xb[i] = sn * u + c * v;
-          }
-          if (ja.V) {
-            double *va = ja.V + ca * ja.ldv, *vb = ja.V + cb * ja.ldv;
-            for (int64_t i = lane; i < ja.nc; i += 64) {
-              const double u = va[i], v = vb[i];
-              va[i] = c * u - sn * v;
-              vb[i] = sn * u + c * v;
-            }
-          }
-          if (lane == 0) atomicAdd(&ja.flags[0], 1u);
-        }
-      }
-      grid.sync();
+// Sums of (x, y, z) over the T consecutive threads of a pair team.
+template <int T>
+__device__ __forceinline__ void team_sum3(double &x, double &y, double &z, double (*red)[3]) {
+  constexpr int kW = T < 64 ? T : 64;
+#pragma unroll
+  for (int off = kW / 2; off > 0; off >>= 1) {
+    x += __shfl_xor(x, off, 64);
+    y += __shfl_xor(y, off, 64);
+    z += __shfl_xor(z, off, 64);
+  }
+  if constexpr (T > 64) {
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+      red[wv][0] = x;
+      red[wv][1] = y;
+      red[wv][2] = z;
     }
-    const unsigned rot = __hip_atomic_load(&ja.flags[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    grid.sync();
-    if (blockIdx.x == 0 && threadIdx.x == 0) ja.flags[0] = 0u;
-    grid.sync();
-    if (rot == 0u) {
-      ++sweep;
-      break;
+    __syncthreads();
+    const int w0 = wv & ~(T / 64 - 1);
+    x = y = z = 0.0;
+    for (int k = 0; k < T / 64; ++k) {
+      x += red[w0 + k][0];
+      y += red[w0 + k][1];
+      z += red[w0 + k][2];
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) ja.flags[1] = (unsigned)sweep;
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void jacobi_block_kernel(JacobiBlockArgs ja) {
+  constexpr int C = 2 * W;            // columns of a block pair
+  constexpr int NRMAX = 8192 / W;     // 2W * NRMAX doubles = 128 KiB
+  constexpr int LDL = NRMAX + 2;      // LDS column stride (breaks bank aliasing)
+  constexpr int T = 256 / W;          // threads per column pair
+  __shared__ double L[C * LDL];
+  __shared__ double J[C * C];         // column-major: J[c * C + k]
+  __shared__ double red[4][3];
+  const int tid = threadIdx.x;
+  const int nr = ja.nr;
+  int ba, bb;
+  rr_pair(ja.nblocks, ja.round, (int)blockIdx.x, ba, bb);
+  auto gcol = [&](int c) -> int64_t { return c < W ? (int64_t)ba * W + c : (int64_t)bb * W + (c - W); };
+  for (int c = 0; c < C; ++c) {
+    const double *src = ja.X + gcol(c) * ja.ldx;
+    for (int i = tid; i < nr; i += 256) L[c * LDL + i] = src[i];
+  }
+  if (ja.V)
+    for (int e = tid; e < C * C; e += 256) J[e] = (e / C == e % C) ? 1.0 : 0.0;
+  __syncthreads();
+  const int team = tid / T, lt = tid % T;
+  const double floor2 = *ja.floor2;
+  bool any = false;
+  for (int ir = 0; ir < C - 1; ++ir) {
+    int ca, cb;
+    rr_pair(C, ir, team, ca, cb);
+    double *xa = L + ca * LDL, *xb = L + cb * LDL;
+    double al = 0.0, be = 0.0, ga = 0.0;
+    for (int i = lt; i < nr; i += T) {
+      const double u = xa[i], v = xb[i];
+      al += u * u;
+      be += v * v;
+      ga += u * v;
+    }
+    team_sum3<T>(al, be, ga, red);
+    // A column whose norm is at the rounding level of the whole matrix has no
+    // relative accuracy left, so its orthogonality cannot improve: such pairs
+    // count as converged (otherwise a rank-deficient input never converges).
+    if (fabs(ga) > ja.tol * sqrt(al * be) && ga != 0.0 && fmin(al, be) > floor2) {
+      // rotation zeroing the (a, b) entry of the 2x2 Gram [al ga; ga be]
+      const double zeta = (be - al) / (2.0 * ga);
+      const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+      const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+      for (int i = lt; i < nr; i += T) {
+        const double u = xa[i], v = xb[i];
+        xa[i] = c * u - sn * v;
+        xb[i] = sn * u + c * v;
+      }
+      if (ja.V) {
+        double *Ja = J + ca * C, *Jb = J + cb * C;
+        for (int i = lt; i < C; i += T) {
+          const double u = Ja[i], v = Jb[i];
+          Ja[i] = c * u - sn * v;
+          Jb[i] = sn * u + c * v;
+        }
+      }
+      any = true;
+    }
+    __syncthreads();
+  }
+  for (int c = 0; c < C; ++c) {
+    double *dst = ja.X + gcol(c) * ja.ldx;
+    for (int i = tid; i < nr; i += 256) dst[i] = L[c * LDL + i];
+  }
+  const bool rotated = __syncthreads_or(any);
+  if (ja.V && rotated) {
+    // V's block-pair columns <- (those columns) J, staged through LDS
+    // (nc <= NRMAX is guaranteed by the host's choice of W)
+    for (int c = 0; c < C; ++c) {
+      const double *src = ja.V + gcol(c) * ja.nc;
+      for (int i = tid; i < ja.nc; i += 256) L[c * LDL + i] = src[i];
+    }
+    __syncthreads();
+    for (int c = 0; c < C; ++c) {
+      const double *Jc = J + c * C;
+      double *dst = ja.V + gcol(c) * ja.nc;
+      for (int i = tid; i < ja.nc; i += 256) {
+        double acc = 0.0;
+        for (int k = 0; k < C; ++k) acc += L[k * LDL + i] * Jc[k];
+        dst[i] = acc;
+      }
+    }
+  }
+  if (rotated && tid == 0) atomicAdd(ja.rot, 1u);
 }
 
 // sigma_j = ||x_j||; order by decreasing sigma (ties by index) into S, and
@@ -517,6 +577,32 @@ __global__ __launch_bounds__(1024) void jacobi_finish_kernel(const double *__res
     const double sg = s_sig[col];
     Us[i * ldu + rnk] = sg > 0.0 ? X[col * ldx + i] / sg : 0.0;
   }
+}
+
+// out = (u ||X||_F)^2, u = 2^-53, for X (nr x nc, column-major, ldx).  One
+// workgroup of 1024 threads; fixed summation order.
+__global__ __launch_bounds__(1024) void noise_floor_kernel(const double *__restrict__ X,
+                                                            int64_t nr, int64_t nc, int64_t ldx,
+                                                            double *__restrict__ out) {
+  __shared__ double part[16];
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < nr * nc; e += 1024) {
+    const double v = X[(e / nr) * ldx + e % nr];
+    acc += v * v;
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += part[w];
+    const double u = 0x1p-53;
+    *out = u * u * t;
+  }
+}
+
+__global__ void or_bits_kernel(int32_t *p, int32_t bits) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p |= bits;
 }
 
 __global__ void zero_u32_kernel(unsigned int *p, int n) {
@@ -632,37 +718,70 @@ int eye(double *M, int64_t n, int64_t ld, hipStream_t s) {
   return BSRHT_OK;
 }
 
+template <int W>
+static int jacobi_sweeps(JacobiBlockArgs &ja, int max_sweeps, int *sweeps, hipStream_t s) {
+  *sweeps = max_sweeps + 1;  // not converged unless a sweep without rotations is seen
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    zero_u32_kernel<<<1, 64, 0, s>>>(ja.rot, 1);
+    BSRHT_LAUNCH_CHECK();
+    for (int r = 0; r < ja.nblocks - 1; ++r) {
+      ja.round = r;
+      jacobi_block_kernel<W><<<(unsigned)(ja.nblocks / 2), 256, 0, s>>>(ja);
+      BSRHT_LAUNCH_CHECK();
+    }
+    unsigned int rot = 0;
+    if (copy_to_host(&rot, ja.rot, sizeof(rot), s) != BSRHT_OK) return BSRHT_EDEVICE;
+    if (rot == 0) {
+      *sweeps = sw + 1;
+      break;
+    }
+  }
+  return BSRHT_OK;
+}
+
 int jacobi_svd(double *X, int64_t nr, int64_t nc, int64_t ldx, double *V, double *S,
                double *Us, int64_t ldu, int32_t *perm, unsigned int *flags, int max_sweeps,
-               hipStream_t s) {
+               int32_t *info, hipStream_t s) {
   if (nc <= 0) return BSRHT_OK;
-  if (nc > 4096 || (nc & 1)) return BSRHT_EUNSUPPORTED;
-  zero_u32_kernel<<<1, 64, 0, s>>>(flags, 2);
-  BSRHT_LAUNCH_CHECK();
+  if (nc > 4096 || nr > 4096 || (nc % 32) != 0) return BSRHT_EUNSUPPORTED;
   if (V) {
     eye_kernel<<<(unsigned)((nc * nc + 255) / 256), 256, 0, s>>>(V, nc, nc);
     BSRHT_LAUNCH_CHECK();
   }
-  JacobiArgs ja;
+  JacobiBlockArgs ja;
   ja.X = X;
-  ja.nr = nr;
-  ja.nc = nc;
+  ja.nr = (int)nr;
   ja.ldx = ldx;
   ja.V = V;
-  ja.ldv = nc;
+  ja.nc = (int)nc;
+  ja.round = 0;
   ja.tol = 1e-15 * (double)(nr > 16 ? nr : 16);
-  ja.max_sweeps = max_sweeps;
-  ja.flags = flags;
-  // one wave per pair, at most one workgroup of 4 waves per CU
-  const int64_t npairs = nc / 2;
-  int64_t blocks = (npairs + 3) / 4;
-  const int64_t maxb = device_cu_count();
-  if (blocks > maxb) blocks = maxb;
-  if (blocks < 1) blocks = 1;
-  void *args[] = {&ja};
-  if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&jacobi_kernel),
-                                 dim3((unsigned)blocks), dim3(256), args, 0, s) != hipSuccess)
-    return BSRHT_EDEVICE;
+  ja.rot = flags;
+  double *floor2 = reinterpret_cast<double *>(flags + 2);
+  ja.floor2 = floor2;
+  noise_floor_kernel<<<1, 1024, 0, s>>>(X, nr, nc, ldx, floor2);
+  BSRHT_LAUNCH_CHECK();
+  int sweeps = 0, st;
+  // LDS holds 2W columns of max(nr, nc when accumulating) rows
+  const int64_t rows = V ? std::max(nr, nc) : nr;
+  if (rows <= 512) {
+    ja.nblocks = (int)(nc / 16);
+    st = jacobi_sweeps<16>(ja, max_sweeps, &sweeps, s);
+  } else if (rows <= 1024) {
+    ja.nblocks = (int)(nc / 8);
+    st = jacobi_sweeps<8>(ja, max_sweeps, &sweeps, s);
+  } else if (rows <= 2048) {
+    ja.nblocks = (int)(nc / 4);
+    st = jacobi_sweeps<4>(ja, max_sweeps, &sweeps, s);
+  } else {
+    ja.nblocks = (int)(nc / 2);
+    st = jacobi_sweeps<2>(ja, max_sweeps, &sweeps, s);
+  }
+  if (st != BSRHT_OK) return st;
+  if (sweeps > max_sweeps && info) {
+    or_bits_kernel<<<1, 1, 0, s>>>(info, BSRHT_INFO_JACOBI_NOCONV);
+    BSRHT_LAUNCH_CHECK();
+  }
   jacobi_finish_kernel<<<1, 1024, (size_t)nc * sizeof(double), s>>>(X, nr, nc, ldx, V, nc, S,
                                                                      Us, ldu, perm);
   BSRHT_LAUNCH_CHECK();

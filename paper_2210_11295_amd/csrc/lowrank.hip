@@ -85,7 +85,9 @@ __global__ void zero_i32_kernel(int32_t *p, int n) {
   if (i < n) p[i] = 0;
 }
 
-inline int64_t even_up(int64_t x) { return (x + 1) & ~int64_t(1); }
+// Size of the small SVD problems: a multiple of 32 (the block Jacobi pairs
+// column blocks of up to 16); the padding is zero rows and columns.
+inline int64_t svd_pad(int64_t x) { return (x + 31) & ~int64_t(31); }
 
 inline int read_i32(const int32_t *dev, hipStream_t s, int32_t *out) {
   return copy_to_host(out, dev, sizeof(int32_t), s);
@@ -150,8 +152,8 @@ struct RsvdWs {
     Vk = a.template take<float>((size_t)(lq * k));
     flag = a.template take<int32_t>(4);
     chol_state = a.template take<char>(cholesky_state_bytes());
-    qb.take(a, even_up(l), l);
-    sv.take(a, even_up(lq), k);
+    qb.take(a, svd_pad(l), l);
+    sv.take(a, svd_pad(lq), k);
   }
 };
 
@@ -183,8 +185,8 @@ struct NysWs {
     Mk = a.template take<double>((size_t)(l * std::max<int64_t>(k, 1)));
     flag = a.template take<int32_t>(4);
     chol_state = a.template take<char>(cholesky_state_bytes());
-    fb.take(a, even_up(l), l);
-    sv.take(a, even_up(l), k);
+    fb.take(a, svd_pad(l), l);
+    sv.take(a, svd_pad(l), k);
   }
 };
 
@@ -195,19 +197,19 @@ struct NysWs {
 // M, as normalised columns.  Eigen mode (eigen = true, M symmetric): the
 // rotations are accumulated and returned, so that the eigenvectors stay
 // orthogonal to working precision even for tiny |lambda|, where the callers
-// scale by 1/sqrt(lambda).  The problem is zero padded to an even size; an
-// extra zero column sorts last.  Sorted singular values in b.S, vectors as
-// columns of b.Vs (row-major, leading dimension nc).
+// scale by 1/sqrt(lambda).  The problem is zero padded to a multiple of 32;
+// the extra zero columns sort last.  Sorted singular values in b.S, vectors
+// as columns of b.Vs (row-major, leading dimension nc).
 template <class A>
 int small_svd(SvdBufs<A> &b, const double *R, int64_t nc0, int64_t ldr, bool eigen,
-              hipStream_t s) {
-  const int64_t nc = even_up(nc0);
+              int32_t *info, hipStream_t s) {
+  const int64_t nc = svd_pad(nc0);
   int st = fill_f64(b.X, nc * nc, 0.0, s);
   if (st != BSRHT_OK) return st;
   st = scale_cols_f64(R, nc0, nc0, nc0, ldr, nullptr, b.X, nc, s);  // copy, ld ldr -> nc
   if (st != BSRHT_OK) return st;
   return jacobi_svd(b.X, nc, nc, nc, eigen ? b.V : nullptr, b.S, b.Vs, nc, b.perm, b.flags,
-                    kMaxSweeps, s);
+                    kMaxSweeps, info, s);
 }
 
 }  // namespace
@@ -232,7 +234,7 @@ int rsvd(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, int64_t k, f
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = plan->n, l = plan->l;
   int64_t lq = std::min(l, m);
-  if (even_up(std::max(l, lq)) > 4096) return BSRHT_EUNSUPPORTED;
+  if (svd_pad(std::max(l, lq)) > 4096) return BSRHT_EUNSUPPORTED;
   Carve cv(ws, ws_bytes);
   RsvdWs<Carve> w;
   w.layout(cv, plan, m, k);
@@ -276,7 +278,7 @@ int rsvd(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, int64_t k, f
       // Q1 = W^T V_+ Lam_+^{-1/2}.
       st = gram_f32(w.W, m, l, 1, m, w.G, l, w.gram_part, gs, s);
       if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); return st; }
-      BSRHT_TRY(small_svd(w.qb, w.G, l, l, true, s));
+      BSRHT_TRY(small_svd(w.qb, w.G, l, l, true, info, s));
       std::vector<double> ev((size_t)l);
       if (copy_to_host(ev.data(), w.qb.S, sizeof(double) * (size_t)l, s) != BSRHT_OK)
         return BSRHT_EDEVICE;
@@ -288,7 +290,7 @@ int rsvd(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, int64_t k, f
       for (int64_t i = 0; i < keep; ++i) sc[(size_t)i] = 1.0 / sqrt(ev[(size_t)i]);
       if (copy_to_device(w.qb.inv, sc.data(), sizeof(double) * (size_t)keep, s) != BSRHT_OK)
         return BSRHT_EDEVICE;
-      const int64_t nce = even_up(l);
+      const int64_t nce = svd_pad(l);
       BSRHT_TRY(scale_cols_f64(w.qb.Vs, l, keep, keep, nce, w.qb.inv, w.Ginv, keep, s));
       GemmDesc d;
       d.M = m; d.N = keep; d.K = l;
@@ -341,16 +343,16 @@ int rsvd(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, int64_t k, f
   int pw;
   if (hz == 0) {
     // 5. SVD of R: R = Ut St Vt^T
-    BSRHT_TRY(small_svd(w.sv, w.Gz, lq, lq, false, s));
+    BSRHT_TRY(small_svd(w.sv, w.Gz, lq, lq, false, info, s));
     pw = 1;
   } else {
     // rank(Z) < lq: Z^T Z = Vt St^2 Vt^T from its eigen decomposition
     BSRHT_TRY(gram_f32(w.Z, n, lq, lq, 1, w.Gz, lq, w.gram_part, gsz, s));
-    BSRHT_TRY(small_svd(w.sv, w.Gz, lq, lq, true, s));
+    BSRHT_TRY(small_svd(w.sv, w.Gz, lq, lq, true, info, s));
     // the Jacobi values are St^2: take square roots through the scale step
     pw = 0;
   }
-  const int64_t nce = even_up(lq);
+  const int64_t nce = svd_pad(lq);
   // singular values of Z (sqrt of the Gram eigenvalues on the fallback path)
   if (pw == 0) {
     std::vector<double> ev((size_t)lq);
@@ -400,7 +402,7 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
   if (ws_bytes < nystrom_workspace(plan, k) || !ws) return BSRHT_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = plan->n, l = plan->l;
-  if (even_up(l) > 4096) return BSRHT_EUNSUPPORTED;
+  if (svd_pad(l) > 4096) return BSRHT_EUNSUPPORTED;
   Carve cv(ws, ws_bytes);
   NysWs<Carve> w;
   w.layout(cv, plan, k);
@@ -436,8 +438,8 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
     BSRHT_TRY(gemm_f32f64_f64(d, w.Y, w.Cinv, w.Z, s));
   } else {
     // Remark 3.1: B = V Lam V^T, keep Lam_i > l u Lam_max, Z = Y V_+ Lam_+^{-1/2}
-    BSRHT_TRY(small_svd(w.fb, w.Bs, l, l, true, s));
-    const int64_t nce = even_up(l);
+    BSRHT_TRY(small_svd(w.fb, w.Bs, l, l, true, info, s));
+    const int64_t nce = svd_pad(l);
     rayleigh_kernel<<<(unsigned)l, 256, 0, s>>>(w.Bs, w.fb.Vs, l, l, nce, w.lam);
     BSRHT_LAUNCH_CHECK();
     std::vector<double> lam((size_t)l);
@@ -484,7 +486,7 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
   BSRHT_TRY(read_i32(w.flag + 1, s, &hz));
   // 5. SVD of R (or the eigen decomposition of Z^T Z when R is singular)
   const double *Rsrc = hz == 0 ? w.Gz : w.Bs;
-  BSRHT_TRY(small_svd(w.sv, Rsrc, lz, lz, hz != 0, s));
+  BSRHT_TRY(small_svd(w.sv, Rsrc, lz, lz, hz != 0, info, s));
   if (hz != 0) {
     std::vector<double> ev((size_t)lz);
     if (copy_to_host(ev.data(), w.sv.S, sizeof(double) * (size_t)lz, s) != BSRHT_OK)
@@ -498,7 +500,7 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
       w.sv.S, lz, k, sqrt((double)lz * kU64), 2, w.sv.inv, lambda, info);
   BSRHT_LAUNCH_CHECK();
   const int64_t keep = std::min(k, lz);
-  const int64_t nce = even_up(lz);
+  const int64_t nce = svd_pad(lz);
   BSRHT_TRY(scale_cols_f64(w.sv.Vs, lz, keep, k, nce, w.sv.inv, w.Mk, k, s));
   GemmDesc d;
   d.M = n; d.N = k; d.K = lz;

@@ -51,6 +51,22 @@ def test_rsvd_matches_oracle(n, m, p, l, k):
     assert np.all(np.diff(Sh) <= 0)
 
 
+@pytest.mark.parametrize("n,m,p,l,k", [
+    (8192, 1500, 2, 1100, 50),    # SVD of R on 1120 columns: blocks of 4
+    (8192, 2600, 1, 2200, 40),    # 2208 columns: blocks of 2
+    (4096, 900, 4, 700, 30),      # 704 columns: blocks of 8
+])
+def test_rsvd_large_sketch_sizes(n, m, p, l, k):
+    """Sketch sizes that take every column-block width of the Jacobi SVD."""
+    dev = device()
+    say("rsvd large l", n, m, p, l, k)
+    A = workloads.gaussian_cols(n, m, "pow1.5", n + m + l, device=dev)
+    U, S, V, info, err, err_o, So = _rsvd_case(n, m, p, l, k, A, 17)
+    say("  err gpu", err, "oracle", err_o, "info", info)
+    assert info & bs.INFO_JACOBI_NOCONV == 0
+    assert err <= 1.01 * err_o
+
+
 def test_rsvd_full_range_is_truncated_svd():
     dev = device()
     n, m, p, l, k = 2048, 64, 4, 128, 16
