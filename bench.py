@@ -78,6 +78,17 @@ def cpu_baseline(A, cfg, blocks=8):
                       f"seed); numpy FP64 FWHT, single thread; {dt:.2f} s"}
 
 
+def _copy_calibration(A):
+    """One plain device copy of A: reads and writes exactly A's bytes, the
+    reference against which the HBM byte counters are scaled."""
+    import torch
+    log("bench: copy calibration")
+    B = torch.empty_like(A)
+    B.copy_(A)
+    torch.cuda.synchronize()
+    del B
+
+
 def bench_split_bf16(bs, A, cfg, steps, warmup, Y_fp32):
     """The same sketch with the H_16 factor on BF16 matrix cores (A split
     into BF16 hi + lo, FP32 accumulation), on the same A and plan seed."""
@@ -237,8 +248,10 @@ def main():
         return
     if args.only == "bf16":
         Yf = bs.bsrht_apply(plan, A)
-        print(json.dumps({"split_bf16": bench_split_bf16(bs, A, cfg, args.steps, args.warmup,
-                                                         Yf)}), flush=True)
+        out_b = bench_split_bf16(bs, A, cfg, args.steps, args.warmup, Yf)
+        if args.copy_calibration:
+            _copy_calibration(A)
+        print(json.dumps({"split_bf16": out_b}), flush=True)
         return
     Y = torch.empty(l, m, dtype=torch.float32, device=dev)
     ws = torch.empty(max(1, bs.bsrht_apply_workspace(plan, m)), dtype=torch.uint8, device=dev)
@@ -270,13 +283,7 @@ def main():
         f"{launches} launches -> {achieved:.1f} GB/s")
 
     if args.copy_calibration:
-        # one plain copy of A: reads and writes exactly n*m*4 bytes, the
-        # reference against which the HBM byte counters are scaled
-        log("bench: copy calibration")
-        B = torch.empty_like(A)
-        B.copy_(A)
-        torch.cuda.synchronize()
-        del B
+        _copy_calibration(A)
 
     traffic = _traffic("traffic_fused_fp32_sketch_2p20x1024.json", ["apply_fp32.hip"], alg_bytes)
     out = {

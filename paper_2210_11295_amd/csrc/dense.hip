@@ -378,7 +378,7 @@ __global__ __launch_bounds__(64 * kTrinvWaves) void trinv_upper_kernel(
 // Blocking: the columns form nc/W blocks of W.  One launch is one round of a
 // round-robin over block pairs; a workgroup copies its pair (2W columns) into
 // LDS and runs one full cyclic sweep over the 2W(2W-1)/2 column pairs there
-// (W disjoint pairs at a time, 256/W threads per pair), recording the
+// (W disjoint pairs at a time, one wave per pair), recording the
 // rotations in a 2W x 2W matrix J; it then writes the columns back and, when
 // accumulating, updates V's 2W columns as V J.  A sweep is nc/W - 1 launches;
 // sweeps repeat until one performs no rotation.
@@ -399,6 +399,32 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// One 32-bit DPP lane permutation applied to both halves of a double.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF,
+                                                            true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL,
+                                                            0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Wave-wide sum, identical in every lane: each level adds a value and its
+// partner's with the operands swapped between the two lanes, which IEEE
+// addition makes bitwise equal.  The first four levels stay inside a row of
+// 16 lanes (DPP: quad permutations, half-row and row mirrors); the last two
+// cross rows.
+__device__ __forceinline__ double wave_sum_fast(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
 // Pair p of round r among nc players (round-robin, player nc-1 fixed).
 __device__ __forceinline__ void rr_pair(int nc, int r, int p, int &a, int &b) {
   const int m = nc - 1;
@@ -416,70 +442,77 @@ __device__ __forceinline__ void rr_pair(int nc, int r, int p, int &a, int &b) {
   }
 }
 
-// Sums of (x, y, z) over the T consecutive threads of a pair team.
-template <int T>
-__device__ __forceinline__ void team_sum3(double &x, double &y, double &z, double (*red)[3]) {
-  constexpr int kW = T < 64 ? T : 64;
+// L[c * ldl + i] = src[gcol(c) * lds + i] for the flattened index
+// e = c * rows + i < total; eight loads per thread are in flight at once.
+template <int NT, class GCol>
+__device__ __forceinline__ void copy_in(double *L, int ldl, const double *__restrict__ src,
+                                        int64_t lds, int rows, int total, const GCol &gcol) {
+  for (int e0 = threadIdx.x; e0 < total; e0 += 8 * NT) {
+    double v[8];
 #pragma unroll
-  for (int off = kW / 2; off > 0; off >>= 1) {
-    x += __shfl_xor(x, off, 64);
-    y += __shfl_xor(y, off, 64);
-    z += __shfl_xor(z, off, 64);
-  }
-  if constexpr (T > 64) {
-    const int wv = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-      red[wv][0] = x;
-      red[wv][1] = y;
-      red[wv][2] = z;
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * NT;
+      if (e < total) {
+        const int c = e / rows, i = e - c * rows;
+        v[u] = src[gcol(c) * lds + i];
+      }
     }
-    __syncthreads();
-    const int w0 = wv & ~(T / 64 - 1);
-    x = y = z = 0.0;
-    for (int k = 0; k < T / 64; ++k) {
-      x += red[w0 + k][0];
-      y += red[w0 + k][1];
-      z += red[w0 + k][2];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * NT;
+      if (e < total) {
+        const int c = e / rows, i = e - c * rows;
+        L[c * ldl + i] = v[u];
+      }
     }
   }
 }
 
-template <int W>
-__global__ __launch_bounds__(256) void jacobi_block_kernel(JacobiBlockArgs ja) {
+template <int W, int KR>
+__global__ __launch_bounds__(64 * W) void jacobi_block_kernel(JacobiBlockArgs ja) {
   constexpr int C = 2 * W;            // columns of a block pair
-  constexpr int NRMAX = 8192 / W;     // 2W * NRMAX doubles = 128 KiB
+  constexpr int NRMAX = 64 * KR;      // rows held (KR per lane)
   constexpr int LDL = NRMAX + 2;      // LDS column stride (breaks bank aliasing)
-  constexpr int T = 256 / W;          // threads per column pair
+  constexpr int NT = 64 * W;          // one wave per column pair of a round
   __shared__ double L[C * LDL];
   __shared__ double J[C * C];         // column-major: J[c * C + k]
-  __shared__ double red[4][3];
   const int tid = threadIdx.x;
   const int nr = ja.nr;
   int ba, bb;
   rr_pair(ja.nblocks, ja.round, (int)blockIdx.x, ba, bb);
   auto gcol = [&](int c) -> int64_t { return c < W ? (int64_t)ba * W + c : (int64_t)bb * W + (c - W); };
-  for (int c = 0; c < C; ++c) {
-    const double *src = ja.X + gcol(c) * ja.ldx;
-    for (int i = tid; i < nr; i += 256) L[c * LDL + i] = src[i];
-  }
+  // Copies run over the flattened (column, row) index in batches of 8 loads
+  // per thread, issued before any of them is waited for.
+  const int total = C * nr;
+  copy_in<NT>(L, LDL, ja.X, ja.ldx, nr, total, gcol);
   if (ja.V)
-    for (int e = tid; e < C * C; e += 256) J[e] = (e / C == e % C) ? 1.0 : 0.0;
+    for (int e = tid; e < C * C; e += NT) J[e] = (e / C == e % C) ? 1.0 : 0.0;
   __syncthreads();
-  const int team = tid / T, lt = tid % T;
+  const int team = tid >> 6, lt = tid & 63;
   const double floor2 = *ja.floor2;
   bool any = false;
   for (int ir = 0; ir < C - 1; ++ir) {
     int ca, cb;
     rr_pair(C, ir, team, ca, cb);
     double *xa = L + ca * LDL, *xb = L + cb * LDL;
-    double al = 0.0, be = 0.0, ga = 0.0;
-    for (int i = lt; i < nr; i += T) {
-      const double u = xa[i], v = xb[i];
-      al += u * u;
-      be += v * v;
-      ga += u * v;
+    // the pair's rows of this lane, read once and kept for the rotation
+    double u[KR], v[KR];
+#pragma unroll
+    for (int q = 0; q < KR; ++q) {
+      const int i = lt + 64 * q;
+      u[q] = i < nr ? xa[i] : 0.0;
+      v[q] = i < nr ? xb[i] : 0.0;
     }
-    team_sum3<T>(al, be, ga, red);
+    double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+    for (int q = 0; q < KR; ++q) {
+      al += u[q] * u[q];
+      be += v[q] * v[q];
+      ga += u[q] * v[q];
+    }
+    al = wave_sum_fast(al);
+    be = wave_sum_fast(be);
+    ga = wave_sum_fast(ga);
     // A column whose norm is at the rounding level of the whole matrix has no
     // relative accuracy left, so its orthogonality cannot improve: such pairs
     // count as converged (otherwise a rank-deficient input never converges).
@@ -488,14 +521,17 @@ __global__ __launch_bounds__(256) void jacobi_block_kernel(JacobiBlockArgs ja) {
       const double zeta = (be - al) / (2.0 * ga);
       const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
       const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-      for (int i = lt; i < nr; i += T) {
-        const double u = xa[i], v = xb[i];
-        xa[i] = c * u - sn * v;
-        xb[i] = sn * u + c * v;
+#pragma unroll
+      for (int q = 0; q < KR; ++q) {
+        const int i = lt + 64 * q;
+        if (i < nr) {
+          xa[i] = c * u[q] - sn * v[q];
+          xb[i] = sn * u[q] + c * v[q];
+        }
       }
       if (ja.V) {
         double *Ja = J + ca * C, *Jb = J + cb * C;
-        for (int i = lt; i < C; i += T) {
+        for (int i = lt; i < C; i += 64) {
           const double u = Ja[i], v = Jb[i];
           Ja[i] = c * u - sn * v;
           Jb[i] = sn * u + c * v;
@@ -505,23 +541,20 @@ __global__ __launch_bounds__(256) void jacobi_block_kernel(JacobiBlockArgs ja) {
     }
     __syncthreads();
   }
-  for (int c = 0; c < C; ++c) {
-    double *dst = ja.X + gcol(c) * ja.ldx;
-    for (int i = tid; i < nr; i += 256) dst[i] = L[c * LDL + i];
+  for (int e = tid; e < total; e += NT) {
+    const int c = e / nr, i = e - c * nr;
+    ja.X[gcol(c) * ja.ldx + i] = L[c * LDL + i];
   }
   const bool rotated = __syncthreads_or(any);
   if (ja.V && rotated) {
     // V's block-pair columns <- (those columns) J, staged through LDS
     // (nc <= NRMAX is guaranteed by the host's choice of W)
-    for (int c = 0; c < C; ++c) {
-      const double *src = ja.V + gcol(c) * ja.nc;
-      for (int i = tid; i < ja.nc; i += 256) L[c * LDL + i] = src[i];
-    }
+    copy_in<NT>(L, LDL, ja.V, ja.nc, ja.nc, C * ja.nc, gcol);
     __syncthreads();
     for (int c = 0; c < C; ++c) {
       const double *Jc = J + c * C;
       double *dst = ja.V + gcol(c) * ja.nc;
-      for (int i = tid; i < ja.nc; i += 256) {
+      for (int i = tid; i < ja.nc; i += NT) {
         double acc = 0.0;
         for (int k = 0; k < C; ++k) acc += L[k * LDL + i] * Jc[k];
         dst[i] = acc;
@@ -718,15 +751,16 @@ int eye(double *M, int64_t n, int64_t ld, hipStream_t s) {
   return BSRHT_OK;
 }
 
-template <int W>
+template <int W, int KR>
 static int jacobi_sweeps(JacobiBlockArgs &ja, int max_sweeps, int *sweeps, hipStream_t s) {
+  ja.nblocks = ja.nc / W;
   *sweeps = max_sweeps + 1;  // not converged unless a sweep without rotations is seen
   for (int sw = 0; sw < max_sweeps; ++sw) {
     zero_u32_kernel<<<1, 64, 0, s>>>(ja.rot, 1);
     BSRHT_LAUNCH_CHECK();
     for (int r = 0; r < ja.nblocks - 1; ++r) {
       ja.round = r;
-      jacobi_block_kernel<W><<<(unsigned)(ja.nblocks / 2), 256, 0, s>>>(ja);
+      jacobi_block_kernel<W, KR><<<(unsigned)(ja.nblocks / 2), 64 * W, 0, s>>>(ja);
       BSRHT_LAUNCH_CHECK();
     }
     unsigned int rot = 0;
@@ -739,11 +773,32 @@ static int jacobi_sweeps(JacobiBlockArgs &ja, int max_sweeps, int *sweeps, hipSt
   return BSRHT_OK;
 }
 
-int jacobi_svd(double *X, int64_t nr, int64_t nc, int64_t ldx, double *V, double *S,
-               double *Us, int64_t ldu, int32_t *perm, unsigned int *flags, int max_sweeps,
-               int32_t *info, hipStream_t s) {
+// Block width W and rows per lane KR (64 KR >= rows) for a problem whose
+// LDS copy holds `rows` rows.  Measured on MI355X (graded 320..1024-column
+// problems): narrower blocks give more workgroups per round and win up to
+// 512 rows; beyond that the LDS capacity decides.
+static void jacobi_shape(int64_t rows, int *W, int *KR) {
+  if (rows <= 512) {
+    *W = 8;
+    *KR = 8;
+  } else if (rows <= 1024) {
+    *W = 8;
+    *KR = 16;
+  } else if (rows <= 2048) {
+    *W = 4;
+    *KR = 32;
+  } else {
+    *W = 2;
+    *KR = 64;
+  }
+}
+
+int jacobi_svd_shape(double *X, int64_t nr, int64_t nc, int64_t ldx, double *V, double *S,
+                     double *Us, int64_t ldu, int32_t *perm, unsigned int *flags, int max_sweeps,
+                     int32_t *info, int W, int KR, hipStream_t s) {
   if (nc <= 0) return BSRHT_OK;
-  if (nc > 4096 || nr > 4096 || (nc % 32) != 0) return BSRHT_EUNSUPPORTED;
+  const int64_t rows = V ? std::max(nr, nc) : nr;
+  if (nc > 4096 || nr > 4096 || (nc % 32) != 0 || rows > 64 * (int64_t)KR) return BSRHT_EUNSUPPORTED;
   if (V) {
     eye_kernel<<<(unsigned)((nc * nc + 255) / 256), 256, 0, s>>>(V, nc, nc);
     BSRHT_LAUNCH_CHECK();
@@ -762,20 +817,16 @@ int jacobi_svd(double *X, int64_t nr, int64_t nc, int64_t ldx, double *V, double
   noise_floor_kernel<<<1, 1024, 0, s>>>(X, nr, nc, ldx, floor2);
   BSRHT_LAUNCH_CHECK();
   int sweeps = 0, st;
-  // LDS holds 2W columns of max(nr, nc when accumulating) rows
-  const int64_t rows = V ? std::max(nr, nc) : nr;
-  if (rows <= 512) {
-    ja.nblocks = (int)(nc / 16);
-    st = jacobi_sweeps<16>(ja, max_sweeps, &sweeps, s);
-  } else if (rows <= 1024) {
-    ja.nblocks = (int)(nc / 8);
-    st = jacobi_sweeps<8>(ja, max_sweeps, &sweeps, s);
-  } else if (rows <= 2048) {
-    ja.nblocks = (int)(nc / 4);
-    st = jacobi_sweeps<4>(ja, max_sweeps, &sweeps, s);
-  } else {
-    ja.nblocks = (int)(nc / 2);
-    st = jacobi_sweeps<2>(ja, max_sweeps, &sweeps, s);
+  const int key = W * 1000 + KR;
+  switch (key) {
+    case 16008: st = jacobi_sweeps<16, 8>(ja, max_sweeps, &sweeps, s); break;
+    case 8008: st = jacobi_sweeps<8, 8>(ja, max_sweeps, &sweeps, s); break;
+    case 8016: st = jacobi_sweeps<8, 16>(ja, max_sweeps, &sweeps, s); break;
+    case 4008: st = jacobi_sweeps<4, 8>(ja, max_sweeps, &sweeps, s); break;
+    case 4016: st = jacobi_sweeps<4, 16>(ja, max_sweeps, &sweeps, s); break;
+    case 4032: st = jacobi_sweeps<4, 32>(ja, max_sweeps, &sweeps, s); break;
+    case 2064: st = jacobi_sweeps<2, 64>(ja, max_sweeps, &sweeps, s); break;
+    default: return BSRHT_EUNSUPPORTED;
   }
   if (st != BSRHT_OK) return st;
   if (sweeps > max_sweeps && info) {
@@ -786,6 +837,15 @@ int jacobi_svd(double *X, int64_t nr, int64_t nc, int64_t ldx, double *V, double
                                                                      Us, ldu, perm);
   BSRHT_LAUNCH_CHECK();
   return BSRHT_OK;
+}
+
+int jacobi_svd(double *X, int64_t nr, int64_t nc, int64_t ldx, double *V, double *S,
+               double *Us, int64_t ldu, int32_t *perm, unsigned int *flags, int max_sweeps,
+               int32_t *info, hipStream_t s) {
+  int W, KR;
+  jacobi_shape(V ? std::max(nr, nc) : nr, &W, &KR);
+  return jacobi_svd_shape(X, nr, nc, ldx, V, S, Us, ldu, perm, flags, max_sweeps, info, W, KR,
+                          s);
 }
 
 int transpose_f32_f64(const float *src, int64_t rows, int64_t cols, int64_t lds, double *dst,
