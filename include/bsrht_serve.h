@@ -9,21 +9,30 @@
  * creation, and every byte a job needs beyond its inputs and outputs (the
  * call's workspace and, on a plan-cache miss, the plan's sign/index tables)
  * is carved from that arena.  A job is admitted only when its bytes fit, so
- * the arena size is the HBM budget.  Admitted jobs run concurrently on the
- * server's worker streams; a job's result is the same as the same call made
- * alone (every kernel of the library reduces in a fixed order that does not
- * depend on what else runs).
+ * the arena size is the HBM budget.  A job's result is the same as the same
+ * call made alone (every kernel of the library reduces in a fixed order that
+ * does not depend on what else runs).
+ *
+ * Execution: admitted jobs run concurrently, one per stream slot.  A job is a
+ * coroutine that queues its kernels on its slot's stream and suspends where
+ * the algorithm needs a value from the device (a Cholesky flag, a Jacobi
+ * sweep count); the server resumes it once the event recorded there has
+ * completed.  There are no worker threads: jobs advance inside
+ * bsrht_server_submit, bsrht_server_poll and bsrht_server_drain, which make
+ * every HIP call of the server, so a client keeps polling while jobs run.
  *
  * Scheduling: jobs are admitted in arrival order; while the oldest waiting
- * job does not fit, a younger job among the next few that fits may be
- * admitted ahead of it ("backfill"), until the oldest has waited longer than
- * a bound, after which nothing bypasses it.  Plans are cached by
- * (n, p, l, seed, sampling, precision) and evicted least-recently-used when
- * an admission needs their bytes and no running job uses them.
+ * job does not fit, a younger job among the next 8 that fits may be admitted
+ * ahead of it ("backfill"), until the oldest has waited 100 ms, after which
+ * nothing bypasses it.  Plans are cached by (n, p, l, seed, sampling,
+ * precision) and evicted least-recently-used when an admission needs their
+ * bytes and no admitted job uses them.
  *
  * Timestamps are seconds on the server's monotonic clock
- * (bsrht_server_clock).  Every function is thread-safe.  Errors are the
- * BSRHT_* status codes of bsrht.h.
+ * (bsrht_server_clock); t_done is taken when the server observes the job's
+ * completion event, so its resolution is the client's polling interval.
+ * Every function is thread-safe (one lock).  Errors are the BSRHT_* status
+ * codes of bsrht.h.
  */
 #ifndef BSRHT_SERVE_H
 #define BSRHT_SERVE_H
@@ -86,21 +95,19 @@ typedef struct {
 size_t bsrht_job_bytes(const bsrht_job_t *job);
 
 /*
- * Creates a server on the current device with `workers` worker threads,
- * each owning one non-blocking HIP stream of default priority.
- * arena: device memory of arena_bytes (caller-owned, freed by the caller
- * after bsrht_server_destroy).  1 <= workers <= 64.
- * Currently returns BSRHT_EUNSUPPORTED after checking its arguments: the
- * threaded GPU executor is switched off (a process that used it crashed at
- * exit after all jobs had completed, cause not identified).
+ * Creates a server on the current device with `streams` concurrent job slots
+ * (1..64), each a non-blocking HIP stream of default priority with an event
+ * and 128 KiB of pinned staging.  arena: device memory of arena_bytes
+ * (caller-owned, 256-byte aligned, freed by the caller after
+ * bsrht_server_destroy).
  */
-int bsrht_server_create(void *arena, size_t arena_bytes, int workers, bsrht_server_t *out);
+int bsrht_server_create(void *arena, size_t arena_bytes, int streams, bsrht_server_t *out);
 
 /*
  * Same scheduler with a host-only executor, for testing admission and
  * ordering without a GPU: no HIP call is made, the arena is a byte budget,
- * and a job "runs" by sleeping seconds_per_gb * (4 n m / 1e9) seconds.
- * Job pointers are not dereferenced.
+ * and a job "runs" by sleeping seconds_per_gb * (4 n m / 1e9) seconds on one
+ * of `workers` threads.  Job pointers are not dereferenced.
  */
 int bsrht_server_create_fake(size_t arena_bytes, int workers, double seconds_per_gb,
                              bsrht_server_t *out);
@@ -109,13 +116,13 @@ int bsrht_server_create_fake(size_t arena_bytes, int workers, double seconds_per
  * BSRHT_ENOMEM when the job alone needs more than the whole arena. */
 int bsrht_server_submit(bsrht_server_t srv, const bsrht_job_t *job);
 
-/* Moves up to max finished results into out (completion order) and stores
- * their number in *count; waits up to timeout_s seconds for the first one
- * when none is ready (0 = do not wait). */
+/* Advances running jobs, then moves up to max finished results into out
+ * (completion order) and stores their number in *count; waits up to
+ * timeout_s seconds for the first one when none is ready (0 = do not wait). */
 int bsrht_server_poll(bsrht_server_t srv, bsrht_job_result_t *out, int max, double timeout_s,
                       int *count);
 
-/* Blocks until every submitted job has finished. */
+/* Runs / waits until every submitted job has finished. */
 int bsrht_server_drain(bsrht_server_t srv);
 
 int bsrht_server_stats(bsrht_server_t srv, bsrht_server_stats_t *out);
@@ -123,7 +130,7 @@ int bsrht_server_stats(bsrht_server_t srv, bsrht_server_stats_t *out);
 /* Seconds on the server's clock (the clock of the result timestamps). */
 double bsrht_server_clock(bsrht_server_t srv);
 
-/* Drains, stops the workers, releases streams and cached plans. */
+/* Drains, then releases the streams, events, staging and cached plans. */
 int bsrht_server_destroy(bsrht_server_t srv);
 
 #ifdef __cplusplus

@@ -300,11 +300,13 @@ def bsrht_job_bytes(job):
 class Server:
     """The serving runtime of include/bsrht_serve.h.
 
-    Server(arena=tensor, workers=W) runs jobs on the GPU inside the uint8
-    device tensor `arena` (the HBM budget); Server(fake_bytes=B, workers=W,
-    seconds_per_gb=t) is the host-only executor with a B-byte budget.
-    Device pointers of submitted jobs must stay alive until their result has
-    been polled; the caller keeps the tensors.
+    Server(arena=tensor, workers=W) runs up to W jobs at a time on the GPU,
+    one per stream slot, inside the uint8 device tensor `arena` (the HBM
+    budget); jobs advance while submit / poll / drain are called.
+    Server(fake_bytes=B, workers=W, seconds_per_gb=t) is the host-only
+    executor with a B-byte budget.  Device pointers of submitted jobs must
+    stay alive until their result has been polled; the caller keeps the
+    tensors.
     """
 
     def __init__(self, arena=None, workers=4, fake_bytes=None, seconds_per_gb=0.0):

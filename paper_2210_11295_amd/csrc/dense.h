@@ -70,7 +70,8 @@ int jacobi_svd(double *X, int64_t nr, int64_t nc, int64_t ldx, double *V, double
                int32_t *info, hipStream_t s);
 // The same with the block width W and rows per lane KR forced (64 KR must
 // cover the rows held in LDS); (W, KR) in {(16,8), (8,8), (8,16), (4,8),
-// (4,16), (4,32), (2,64)}.  jacobi_svd picks them from the row count.
+// (4,16), (4,32), (2,64)}, or W = 0 to pick them from the row count as
+// jacobi_svd does.
 int jacobi_svd_shape(double *X, int64_t nr, int64_t nc, int64_t ldx, double *V, double *S,
                      double *Us, int64_t ldu, int32_t *perm, unsigned int *flags, int max_sweeps,
                      int32_t *info, int W, int KR, hipStream_t s);

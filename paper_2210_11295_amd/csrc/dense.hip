@@ -12,6 +12,7 @@
 
 #include "common.h"
 #include "dense.h"
+#include "task.h"
 
 namespace bsrht {
 namespace {
@@ -751,26 +752,29 @@ int eye(double *M, int64_t n, int64_t ld, hipStream_t s) {
   return BSRHT_OK;
 }
 
+// One launch per round, nblocks - 1 rounds per sweep; after each sweep the
+// rotation counter is read back and the sweeps stop at the first one without
+// rotations.  *sweeps = max_sweeps + 1 when that never happens.
 template <int W, int KR>
-static int jacobi_sweeps(JacobiBlockArgs &ja, int max_sweeps, int *sweeps, hipStream_t s) {
+static Task jacobi_sweeps_task(DevCtx &ctx, JacobiBlockArgs ja, int max_sweeps, int *sweeps) {
   ja.nblocks = ja.nc / W;
-  *sweeps = max_sweeps + 1;  // not converged unless a sweep without rotations is seen
+  *sweeps = max_sweeps + 1;
   for (int sw = 0; sw < max_sweeps; ++sw) {
-    zero_u32_kernel<<<1, 64, 0, s>>>(ja.rot, 1);
-    BSRHT_LAUNCH_CHECK();
+    zero_u32_kernel<<<1, 64, 0, ctx.s>>>(ja.rot, 1);
+    if (hipGetLastError() != hipSuccess) co_return BSRHT_EDEVICE;
     for (int r = 0; r < ja.nblocks - 1; ++r) {
       ja.round = r;
-      jacobi_block_kernel<W, KR><<<(unsigned)(ja.nblocks / 2), 64 * W, 0, s>>>(ja);
-      BSRHT_LAUNCH_CHECK();
+      jacobi_block_kernel<W, KR><<<(unsigned)(ja.nblocks / 2), 64 * W, 0, ctx.s>>>(ja);
+      if (hipGetLastError() != hipSuccess) co_return BSRHT_EDEVICE;
     }
     unsigned int rot = 0;
-    if (copy_to_host(&rot, ja.rot, sizeof(rot), s) != BSRHT_OK) return BSRHT_EDEVICE;
+    BSRHT_CO_TRY(co_await readback(ctx, &rot, ja.rot, sizeof(rot)));
     if (rot == 0) {
       *sweeps = sw + 1;
       break;
     }
   }
-  return BSRHT_OK;
+  co_return BSRHT_OK;
 }
 
 // Block width W and rows per lane KR (64 KR >= rows) for a problem whose
@@ -793,15 +797,18 @@ static void jacobi_shape(int64_t rows, int *W, int *KR) {
   }
 }
 
-int jacobi_svd_shape(double *X, int64_t nr, int64_t nc, int64_t ldx, double *V, double *S,
-                     double *Us, int64_t ldu, int32_t *perm, unsigned int *flags, int max_sweeps,
-                     int32_t *info, int W, int KR, hipStream_t s) {
-  if (nc <= 0) return BSRHT_OK;
+Task jacobi_svd_task(DevCtx &ctx, double *X, int64_t nr, int64_t nc, int64_t ldx, double *V,
+                     double *S, double *Us, int64_t ldu, int32_t *perm, unsigned int *flags,
+                     int max_sweeps, int32_t *info, int W, int KR) {
+  if (nc <= 0) co_return BSRHT_OK;
   const int64_t rows = V ? std::max(nr, nc) : nr;
-  if (nc > 4096 || nr > 4096 || (nc % 32) != 0 || rows > 64 * (int64_t)KR) return BSRHT_EUNSUPPORTED;
+  if (W == 0) jacobi_shape(rows, &W, &KR);
+  if (nc > 4096 || nr > 4096 || (nc % 32) != 0 || rows > 64 * (int64_t)KR)
+    co_return BSRHT_EUNSUPPORTED;
+  hipStream_t s = ctx.s;
   if (V) {
     eye_kernel<<<(unsigned)((nc * nc + 255) / 256), 256, 0, s>>>(V, nc, nc);
-    BSRHT_LAUNCH_CHECK();
+    if (hipGetLastError() != hipSuccess) co_return BSRHT_EDEVICE;
   }
   JacobiBlockArgs ja;
   ja.X = X;
@@ -809,43 +816,49 @@ int jacobi_svd_shape(double *X, int64_t nr, int64_t nc, int64_t ldx, double *V, 
   ja.ldx = ldx;
   ja.V = V;
   ja.nc = (int)nc;
+  ja.nblocks = 0;
   ja.round = 0;
   ja.tol = 1e-15 * (double)(nr > 16 ? nr : 16);
   ja.rot = flags;
   double *floor2 = reinterpret_cast<double *>(flags + 2);
   ja.floor2 = floor2;
   noise_floor_kernel<<<1, 1024, 0, s>>>(X, nr, nc, ldx, floor2);
-  BSRHT_LAUNCH_CHECK();
+  if (hipGetLastError() != hipSuccess) co_return BSRHT_EDEVICE;
   int sweeps = 0, st;
-  const int key = W * 1000 + KR;
-  switch (key) {
-    case 16008: st = jacobi_sweeps<16, 8>(ja, max_sweeps, &sweeps, s); break;
-    case 8008: st = jacobi_sweeps<8, 8>(ja, max_sweeps, &sweeps, s); break;
-    case 8016: st = jacobi_sweeps<8, 16>(ja, max_sweeps, &sweeps, s); break;
-    case 4008: st = jacobi_sweeps<4, 8>(ja, max_sweeps, &sweeps, s); break;
-    case 4016: st = jacobi_sweeps<4, 16>(ja, max_sweeps, &sweeps, s); break;
-    case 4032: st = jacobi_sweeps<4, 32>(ja, max_sweeps, &sweeps, s); break;
-    case 2064: st = jacobi_sweeps<2, 64>(ja, max_sweeps, &sweeps, s); break;
-    default: return BSRHT_EUNSUPPORTED;
+  switch (W * 1000 + KR) {
+    case 16008: st = co_await jacobi_sweeps_task<16, 8>(ctx, ja, max_sweeps, &sweeps); break;
+    case 8008: st = co_await jacobi_sweeps_task<8, 8>(ctx, ja, max_sweeps, &sweeps); break;
+    case 8016: st = co_await jacobi_sweeps_task<8, 16>(ctx, ja, max_sweeps, &sweeps); break;
+    case 4008: st = co_await jacobi_sweeps_task<4, 8>(ctx, ja, max_sweeps, &sweeps); break;
+    case 4016: st = co_await jacobi_sweeps_task<4, 16>(ctx, ja, max_sweeps, &sweeps); break;
+    case 4032: st = co_await jacobi_sweeps_task<4, 32>(ctx, ja, max_sweeps, &sweeps); break;
+    case 2064: st = co_await jacobi_sweeps_task<2, 64>(ctx, ja, max_sweeps, &sweeps); break;
+    default: co_return BSRHT_EUNSUPPORTED;
   }
-  if (st != BSRHT_OK) return st;
+  if (st != BSRHT_OK) co_return st;
   if (sweeps > max_sweeps && info) {
     or_bits_kernel<<<1, 1, 0, s>>>(info, BSRHT_INFO_JACOBI_NOCONV);
-    BSRHT_LAUNCH_CHECK();
+    if (hipGetLastError() != hipSuccess) co_return BSRHT_EDEVICE;
   }
   jacobi_finish_kernel<<<1, 1024, (size_t)nc * sizeof(double), s>>>(X, nr, nc, ldx, V, nc, S,
                                                                      Us, ldu, perm);
-  BSRHT_LAUNCH_CHECK();
-  return BSRHT_OK;
+  if (hipGetLastError() != hipSuccess) co_return BSRHT_EDEVICE;
+  co_return BSRHT_OK;
+}
+
+int jacobi_svd_shape(double *X, int64_t nr, int64_t nc, int64_t ldx, double *V, double *S,
+                     double *Us, int64_t ldu, int32_t *perm, unsigned int *flags, int max_sweeps,
+                     int32_t *info, int W, int KR, hipStream_t s) {
+  DevCtx ctx;
+  ctx.s = s;
+  return run_blocking(jacobi_svd_task(ctx, X, nr, nc, ldx, V, S, Us, ldu, perm, flags,
+                                      max_sweeps, info, W, KR));
 }
 
 int jacobi_svd(double *X, int64_t nr, int64_t nc, int64_t ldx, double *V, double *S,
                double *Us, int64_t ldu, int32_t *perm, unsigned int *flags, int max_sweeps,
                int32_t *info, hipStream_t s) {
-  int W, KR;
-  jacobi_shape(V ? std::max(nr, nc) : nr, &W, &KR);
-  return jacobi_svd_shape(X, nr, nc, ldx, V, S, Us, ldu, perm, flags, max_sweeps, info, W, KR,
-                          s);
+  return jacobi_svd_shape(X, nr, nc, ldx, V, S, Us, ldu, perm, flags, max_sweeps, info, 0, 0, s);
 }
 
 int transpose_f32_f64(const float *src, int64_t rows, int64_t cols, int64_t lds, double *dst,

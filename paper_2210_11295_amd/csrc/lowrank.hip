@@ -16,6 +16,7 @@
 
 #include "common.h"
 #include "dense.h"
+#include "task.h"
 
 namespace bsrht {
 namespace {
@@ -201,18 +202,188 @@ struct NysWs {
 // the extra zero columns sort last.  Sorted singular values in b.S, vectors
 // as columns of b.Vs (row-major, leading dimension nc).
 template <class A>
+Task small_svd_task(DevCtx &ctx, SvdBufs<A> &b, const double *R, int64_t nc0, int64_t ldr,
+                    bool eigen, int32_t *info) {
+  const int64_t nc = svd_pad(nc0);
+  BSRHT_CO_TRY(fill_f64(b.X, nc * nc, 0.0, ctx.s));
+  BSRHT_CO_TRY(scale_cols_f64(R, nc0, nc0, nc0, ldr, nullptr, b.X, nc, ctx.s));  // ld ldr -> nc
+  co_return co_await jacobi_svd_task(ctx, b.X, nc, nc, nc, eigen ? b.V : nullptr, b.S, b.Vs, nc,
+                                     b.perm, b.flags, kMaxSweeps, info, 0, 0);
+}
+
+template <class A>
 int small_svd(SvdBufs<A> &b, const double *R, int64_t nc0, int64_t ldr, bool eigen,
               int32_t *info, hipStream_t s) {
-  const int64_t nc = svd_pad(nc0);
-  int st = fill_f64(b.X, nc * nc, 0.0, s);
-  if (st != BSRHT_OK) return st;
-  st = scale_cols_f64(R, nc0, nc0, nc0, ldr, nullptr, b.X, nc, s);  // copy, ld ldr -> nc
-  if (st != BSRHT_OK) return st;
-  return jacobi_svd(b.X, nc, nc, nc, eigen ? b.V : nullptr, b.S, b.Vs, nc, b.perm, b.flags,
-                    kMaxSweeps, info, s);
+  DevCtx ctx;
+  ctx.s = s;
+  return run_blocking(small_svd_task(ctx, b, R, nc0, ldr, eigen, info));
 }
 
 }  // namespace
+}  // namespace bsrht
+
+namespace bsrht {
+
+Task rsvd_task(DevCtx &ctx, const bsrht_plan_s *plan, const float *A, int64_t m, int64_t lda,
+               int64_t k, float *U, double *S, float *V, int32_t *info, void *ws,
+               size_t ws_bytes) {
+  hipStream_t s = ctx.s;
+  const int64_t n = plan->n, l = plan->l;
+  int64_t lq = std::min(l, m);
+  if (svd_pad(std::max(l, lq)) > 4096) co_return BSRHT_EUNSUPPORTED;
+  Carve cv(ws, ws_bytes);
+  RsvdWs<Carve> w;
+  w.layout(cv, plan, m, k);
+  if (cv.overflow) co_return BSRHT_ENOMEM;
+  int st;
+  zero_i32_kernel<<<1, 64, 0, s>>>(info, 1);
+  BSRHT_CO_LAUNCH_CHECK();
+
+  // 1. W = Omega A  (l x m): the paper's Y = A_p Omega^T for A_p = A^T.
+  if (plan->precision == BSRHT_SPLIT_BF16)
+    st = apply_split_bf16(plan, A, m, lda, w.W, m, w.apply_ws, w.apply_bytes, s);
+  else
+    st = apply_fp32(plan, A, m, lda, w.W, m, w.apply_ws, w.apply_bytes, s);
+  if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); co_return st; }
+
+  // 2. Q = orth(W^T) (m x lq).  l >= m: range(W^T) is all of R^m, Q = I.
+  if (l >= m) {
+    lq = m;
+    eye_f32_kernel<<<(unsigned)((m * m + 255) / 256), 256, 0, s>>>(w.Q32, m, m);
+    BSRHT_CO_LAUNCH_CHECK();
+  } else {
+    // Cholesky-QR2 of W^T: G = W W^T, G = C^T C, Q1 = W^T C^{-1}; then again.
+    const int gs = gram_splits(m, l);
+    st = gram_f32(w.W, m, l, 1, m, w.G, l, w.gram_part, gs, s);  // X = W^T: X[r][c] = W[c][r]
+    if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); co_return st; }
+    BSRHT_CO_TRY(cholesky_upper(w.G, l, l, (double)l * kU64, w.flag, w.chol_state, s));
+    int32_t hf = 0;
+    BSRHT_CO_TRY(co_await readback(ctx, &hf, w.flag, sizeof(hf)));
+    int64_t lk = l;  // columns of Q1
+    if (hf == 0) {
+      BSRHT_CO_TRY(trinv_upper(w.G, l, l, w.Ginv, l, s));
+      GemmDesc d;
+      d.M = m; d.N = l; d.K = l;
+      d.sai = 1; d.sak = m;       // A = W^T
+      d.sbk = l; d.sbj = 1;       // B = C^{-1}
+      d.ldc = l;
+      BSRHT_CO_TRY(gemm_f32f64_f64(d, w.W, w.Ginv, w.Q1, s));
+    } else {
+      // W^T is rank deficient (e.g. rank(A) < l): an eigen split of
+      // G = W W^T keeps the eigenvalues above l u lambda_max and
+      // Q1 = W^T V_+ Lam_+^{-1/2}.
+      st = gram_f32(w.W, m, l, 1, m, w.G, l, w.gram_part, gs, s);
+      if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); co_return st; }
+      BSRHT_CO_TRY(co_await small_svd_task(ctx, w.qb, w.G, l, l, true, info));
+      std::vector<double> ev((size_t)l);
+      if (co_await readback(ctx, ev.data(), w.qb.S, sizeof(double) * (size_t)l) != BSRHT_OK)
+        co_return BSRHT_EDEVICE;
+      int64_t keep = 0;
+      for (int64_t i = 0; i < l; ++i)
+        if (ev[(size_t)i] > (double)l * kU64 * ev[0] && ev[(size_t)i] > 0.0) ++keep;
+      if (keep < 1) keep = 1;
+      std::vector<double> sc((size_t)keep);
+      for (int64_t i = 0; i < keep; ++i) sc[(size_t)i] = 1.0 / sqrt(ev[(size_t)i]);
+      if (co_await upload(ctx, w.qb.inv, sc.data(), sizeof(double) * (size_t)keep) != BSRHT_OK)
+        co_return BSRHT_EDEVICE;
+      const int64_t nce = svd_pad(l);
+      BSRHT_CO_TRY(scale_cols_f64(w.qb.Vs, l, keep, keep, nce, w.qb.inv, w.Ginv, keep, s));
+      GemmDesc d;
+      d.M = m; d.N = keep; d.K = l;
+      d.sai = 1; d.sak = m;
+      d.sbk = keep; d.sbj = 1;
+      d.ldc = keep;
+      BSRHT_CO_TRY(gemm_f32f64_f64(d, w.W, w.Ginv, w.Q1, s));
+      lk = keep;
+      or_info_kernel<<<1, 1, 0, s>>>(info, BSRHT_INFO_QB_FALLBACK);
+      BSRHT_CO_LAUNCH_CHECK();
+    }
+    // second pass: G2 = Q1^T Q1, C2, Q = Q1 C2^{-1}
+    const int gs2 = gram_splits(m, lk);
+    BSRHT_CO_TRY(gram_f64(w.Q1, m, lk, lk, 1, w.G2, lk, w.gram_part, gs2, s));
+    BSRHT_CO_TRY(cholesky_upper(w.G2, lk, lk, 1e-14, w.flag + 1, w.chol_state, s));
+    int32_t hf2 = 0;
+    BSRHT_CO_TRY(co_await readback(ctx, &hf2, w.flag + 1, sizeof(hf2)));
+    if (hf2 != 0) {  // Q1 has orthonormal columns to O(eps*kappa^2): should not happen
+      debug_report(__FILE__, __LINE__, "second Cholesky-QR pass", BSRHT_EDEVICE);
+      co_return BSRHT_EDEVICE;
+    }
+    BSRHT_CO_TRY(trinv_upper(w.G2, lk, lk, w.C2inv, lk, s));
+    GemmDesc d;
+    d.M = m; d.N = lk; d.K = lk;
+    d.sai = lk; d.sak = 1;
+    d.sbk = lk; d.sbj = 1;
+    d.ldc = lk;
+    BSRHT_CO_TRY(gemm_f64f64_f32(d, w.Q1, w.C2inv, w.Q32, s));
+    lq = lk;
+  }
+
+  // 3. Z = A Q  (n x lq): the paper's Z = Q^T A_p, transposed; matrix cores.
+  {
+    GemmDesc d;
+    d.M = n; d.N = lq; d.K = m;
+    d.sai = lda; d.sak = 1;
+    d.sbk = lq; d.sbj = 1;
+    d.ldc = lq;
+    const int tslot = timing_begin(BSRHT_TIMING_GEMM_AQ, s);
+    st = gemm_f32(d, A, w.Q32, w.Z, s);
+    timing_end(tslot, s);
+    if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); co_return st; }
+  }
+  // 4. R-factor of Z: Gz = Z^T Z (FP64), Gz = R^T R.
+  const int gsz = gram_splits(n, lq);
+  BSRHT_CO_TRY(gram_f32(w.Z, n, lq, lq, 1, w.Gz, lq, w.gram_part, gsz, s));
+  BSRHT_CO_TRY(cholesky_upper(w.Gz, lq, lq, (double)lq * kU32 * kU32, w.flag + 2, w.chol_state, s));
+  int32_t hz = 0;
+  BSRHT_CO_TRY(co_await readback(ctx, &hz, w.flag + 2, sizeof(hz)));
+  int pw;
+  if (hz == 0) {
+    // 5. SVD of R: R = Ut St Vt^T
+    BSRHT_CO_TRY(co_await small_svd_task(ctx, w.sv, w.Gz, lq, lq, false, info));
+    pw = 1;
+  } else {
+    // rank(Z) < lq: Z^T Z = Vt St^2 Vt^T from its eigen decomposition
+    BSRHT_CO_TRY(gram_f32(w.Z, n, lq, lq, 1, w.Gz, lq, w.gram_part, gsz, s));
+    BSRHT_CO_TRY(co_await small_svd_task(ctx, w.sv, w.Gz, lq, lq, true, info));
+    // the Jacobi values are St^2: take square roots through the scale step
+    pw = 0;
+  }
+  const int64_t nce = svd_pad(lq);
+  // singular values of Z (sqrt of the Gram eigenvalues on the fallback path)
+  if (pw == 0) {
+    std::vector<double> ev((size_t)lq);
+    if (co_await readback(ctx, ev.data(), w.sv.S, sizeof(double) * (size_t)lq) != BSRHT_OK)
+      co_return BSRHT_EDEVICE;
+    for (auto &x : ev) x = x > 0.0 ? sqrt(x) : 0.0;
+    if (co_await upload(ctx, w.sv.S, ev.data(), sizeof(double) * (size_t)lq) != BSRHT_OK)
+      co_return BSRHT_EDEVICE;
+  }
+  // 6. U = Z Vt_k St_k^{-1}, S = St_k, V = Q Vt_k
+  finish_sigma_kernel<<<(unsigned)((k + 255) / 256), 256, 0, s>>>(
+      w.sv.S, lq, k, sqrt((double)lq * kU64), 1, w.sv.inv, S, info);
+  BSRHT_CO_LAUNCH_CHECK();
+  const int64_t keep = std::min(k, lq);
+  BSRHT_CO_TRY(scale_cols_f64_f32(w.sv.Vs, lq, keep, k, nce, w.sv.inv, w.M, k, s));
+  {
+    GemmDesc d;
+    d.M = n; d.N = k; d.K = lq;
+    d.sai = lq; d.sak = 1;
+    d.sbk = k; d.sbj = 1;
+    d.ldc = k;
+    BSRHT_CO_TRY(gemm_f32(d, w.Z, w.M, U, s));
+  }
+  BSRHT_CO_TRY(scale_cols_f64_f32(w.sv.Vs, lq, keep, k, nce, nullptr, w.Vk, k, s));
+  {
+    GemmDesc d;
+    d.M = m; d.N = k; d.K = lq;
+    d.sai = lq; d.sak = 1;
+    d.sbk = k; d.sbj = 1;
+    d.ldc = k;
+    BSRHT_CO_TRY(gemm_f32(d, w.Q32, w.Vk, V, s));
+  }
+  co_return BSRHT_OK;
+}
+
 }  // namespace bsrht
 
 using namespace bsrht;
@@ -231,161 +402,9 @@ int rsvd(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, int64_t k, f
          double *S, float *V, int32_t *info, void *ws, size_t ws_bytes, void *stream) {
   if (!plan || !A || !U || !S || !V || !info || m < 1 || k < 1 || lda < m) return BSRHT_EINVAL;
   if (ws_bytes < rsvd_workspace(plan, m, k) || !ws) return BSRHT_ENOMEM;
-  hipStream_t s = (hipStream_t)stream;
-  const int64_t n = plan->n, l = plan->l;
-  int64_t lq = std::min(l, m);
-  if (svd_pad(std::max(l, lq)) > 4096) return BSRHT_EUNSUPPORTED;
-  Carve cv(ws, ws_bytes);
-  RsvdWs<Carve> w;
-  w.layout(cv, plan, m, k);
-  if (cv.overflow) return BSRHT_ENOMEM;
-  int st;
-  zero_i32_kernel<<<1, 64, 0, s>>>(info, 1);
-  BSRHT_LAUNCH_CHECK();
-
-  // 1. W = Omega A  (l x m): the paper's Y = A_p Omega^T for A_p = A^T.
-  if (plan->precision == BSRHT_SPLIT_BF16)
-    st = apply_split_bf16(plan, A, m, lda, w.W, m, w.apply_ws, w.apply_bytes, s);
-  else
-    st = apply_fp32(plan, A, m, lda, w.W, m, w.apply_ws, w.apply_bytes, s);
-  if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); return st; }
-
-  // 2. Q = orth(W^T) (m x lq).  l >= m: range(W^T) is all of R^m, Q = I.
-  if (l >= m) {
-    lq = m;
-    eye_f32_kernel<<<(unsigned)((m * m + 255) / 256), 256, 0, s>>>(w.Q32, m, m);
-    BSRHT_LAUNCH_CHECK();
-  } else {
-    // Cholesky-QR2 of W^T: G = W W^T, G = C^T C, Q1 = W^T C^{-1}; then again.
-    const int gs = gram_splits(m, l);
-    st = gram_f32(w.W, m, l, 1, m, w.G, l, w.gram_part, gs, s);  // X = W^T: X[r][c] = W[c][r]
-    if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); return st; }
-    BSRHT_TRY(cholesky_upper(w.G, l, l, (double)l * kU64, w.flag, w.chol_state, s));
-    int32_t hf = 0;
-    BSRHT_TRY(read_i32(w.flag, s, &hf));
-    int64_t lk = l;  // columns of Q1
-    if (hf == 0) {
-      BSRHT_TRY(trinv_upper(w.G, l, l, w.Ginv, l, s));
-      GemmDesc d;
-      d.M = m; d.N = l; d.K = l;
-      d.sai = 1; d.sak = m;       // A = W^T
-      d.sbk = l; d.sbj = 1;       // B = C^{-1}
-      d.ldc = l;
-      BSRHT_TRY(gemm_f32f64_f64(d, w.W, w.Ginv, w.Q1, s));
-    } else {
-      // W^T is rank deficient (e.g. rank(A) < l): an eigen split of
-      // G = W W^T keeps the eigenvalues above l u lambda_max and
-      // Q1 = W^T V_+ Lam_+^{-1/2}.
-      st = gram_f32(w.W, m, l, 1, m, w.G, l, w.gram_part, gs, s);
-      if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); return st; }
-      BSRHT_TRY(small_svd(w.qb, w.G, l, l, true, info, s));
-      std::vector<double> ev((size_t)l);
-      if (copy_to_host(ev.data(), w.qb.S, sizeof(double) * (size_t)l, s) != BSRHT_OK)
-        return BSRHT_EDEVICE;
-      int64_t keep = 0;
-      for (int64_t i = 0; i < l; ++i)
-        if (ev[(size_t)i] > (double)l * kU64 * ev[0] && ev[(size_t)i] > 0.0) ++keep;
-      if (keep < 1) keep = 1;
-      std::vector<double> sc((size_t)keep);
-      for (int64_t i = 0; i < keep; ++i) sc[(size_t)i] = 1.0 / sqrt(ev[(size_t)i]);
-      if (copy_to_device(w.qb.inv, sc.data(), sizeof(double) * (size_t)keep, s) != BSRHT_OK)
-        return BSRHT_EDEVICE;
-      const int64_t nce = svd_pad(l);
-      BSRHT_TRY(scale_cols_f64(w.qb.Vs, l, keep, keep, nce, w.qb.inv, w.Ginv, keep, s));
-      GemmDesc d;
-      d.M = m; d.N = keep; d.K = l;
-      d.sai = 1; d.sak = m;
-      d.sbk = keep; d.sbj = 1;
-      d.ldc = keep;
-      BSRHT_TRY(gemm_f32f64_f64(d, w.W, w.Ginv, w.Q1, s));
-      lk = keep;
-      or_info_kernel<<<1, 1, 0, s>>>(info, BSRHT_INFO_QB_FALLBACK);
-      BSRHT_LAUNCH_CHECK();
-    }
-    // second pass: G2 = Q1^T Q1, C2, Q = Q1 C2^{-1}
-    const int gs2 = gram_splits(m, lk);
-    BSRHT_TRY(gram_f64(w.Q1, m, lk, lk, 1, w.G2, lk, w.gram_part, gs2, s));
-    BSRHT_TRY(cholesky_upper(w.G2, lk, lk, 1e-14, w.flag + 1, w.chol_state, s));
-    int32_t hf2 = 0;
-    BSRHT_TRY(read_i32(w.flag + 1, s, &hf2));
-    if (hf2 != 0) {  // Q1 has orthonormal columns to O(eps*kappa^2): should not happen
-      debug_report(__FILE__, __LINE__, "second Cholesky-QR pass", BSRHT_EDEVICE);
-      return BSRHT_EDEVICE;
-    }
-    BSRHT_TRY(trinv_upper(w.G2, lk, lk, w.C2inv, lk, s));
-    GemmDesc d;
-    d.M = m; d.N = lk; d.K = lk;
-    d.sai = lk; d.sak = 1;
-    d.sbk = lk; d.sbj = 1;
-    d.ldc = lk;
-    BSRHT_TRY(gemm_f64f64_f32(d, w.Q1, w.C2inv, w.Q32, s));
-    lq = lk;
-  }
-
-  // 3. Z = A Q  (n x lq): the paper's Z = Q^T A_p, transposed; matrix cores.
-  {
-    GemmDesc d;
-    d.M = n; d.N = lq; d.K = m;
-    d.sai = lda; d.sak = 1;
-    d.sbk = lq; d.sbj = 1;
-    d.ldc = lq;
-    const int tslot = timing_begin(BSRHT_TIMING_GEMM_AQ, s);
-    st = gemm_f32(d, A, w.Q32, w.Z, s);
-    timing_end(tslot, s);
-    if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); return st; }
-  }
-  // 4. R-factor of Z: Gz = Z^T Z (FP64), Gz = R^T R.
-  const int gsz = gram_splits(n, lq);
-  BSRHT_TRY(gram_f32(w.Z, n, lq, lq, 1, w.Gz, lq, w.gram_part, gsz, s));
-  BSRHT_TRY(cholesky_upper(w.Gz, lq, lq, (double)lq * kU32 * kU32, w.flag + 2, w.chol_state, s));
-  int32_t hz = 0;
-  BSRHT_TRY(read_i32(w.flag + 2, s, &hz));
-  int pw;
-  if (hz == 0) {
-    // 5. SVD of R: R = Ut St Vt^T
-    BSRHT_TRY(small_svd(w.sv, w.Gz, lq, lq, false, info, s));
-    pw = 1;
-  } else {
-    // rank(Z) < lq: Z^T Z = Vt St^2 Vt^T from its eigen decomposition
-    BSRHT_TRY(gram_f32(w.Z, n, lq, lq, 1, w.Gz, lq, w.gram_part, gsz, s));
-    BSRHT_TRY(small_svd(w.sv, w.Gz, lq, lq, true, info, s));
-    // the Jacobi values are St^2: take square roots through the scale step
-    pw = 0;
-  }
-  const int64_t nce = svd_pad(lq);
-  // singular values of Z (sqrt of the Gram eigenvalues on the fallback path)
-  if (pw == 0) {
-    std::vector<double> ev((size_t)lq);
-    if (copy_to_host(ev.data(), w.sv.S, sizeof(double) * (size_t)lq, s) != BSRHT_OK)
-      return BSRHT_EDEVICE;
-    for (auto &x : ev) x = x > 0.0 ? sqrt(x) : 0.0;
-    if (copy_to_device(w.sv.S, ev.data(), sizeof(double) * (size_t)lq, s) != BSRHT_OK)
-      return BSRHT_EDEVICE;
-  }
-  // 6. U = Z Vt_k St_k^{-1}, S = St_k, V = Q Vt_k
-  finish_sigma_kernel<<<(unsigned)((k + 255) / 256), 256, 0, s>>>(
-      w.sv.S, lq, k, sqrt((double)lq * kU64), 1, w.sv.inv, S, info);
-  BSRHT_LAUNCH_CHECK();
-  const int64_t keep = std::min(k, lq);
-  BSRHT_TRY(scale_cols_f64_f32(w.sv.Vs, lq, keep, k, nce, w.sv.inv, w.M, k, s));
-  {
-    GemmDesc d;
-    d.M = n; d.N = k; d.K = lq;
-    d.sai = lq; d.sak = 1;
-    d.sbk = k; d.sbj = 1;
-    d.ldc = k;
-    BSRHT_TRY(gemm_f32(d, w.Z, w.M, U, s));
-  }
-  BSRHT_TRY(scale_cols_f64_f32(w.sv.Vs, lq, keep, k, nce, nullptr, w.Vk, k, s));
-  {
-    GemmDesc d;
-    d.M = m; d.N = k; d.K = lq;
-    d.sai = lq; d.sak = 1;
-    d.sbk = k; d.sbj = 1;
-    d.ldc = k;
-    BSRHT_TRY(gemm_f32(d, w.Q32, w.Vk, V, s));
-  }
-  return BSRHT_OK;
+  DevCtx ctx;
+  ctx.s = (hipStream_t)stream;
+  return run_blocking(rsvd_task(ctx, plan, A, m, lda, k, U, S, V, info, ws, ws_bytes));
 }
 
 size_t nystrom_workspace(bsrht_plan_t plan, int64_t k) {

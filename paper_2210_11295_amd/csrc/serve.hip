@@ -1,7 +1,9 @@
 // Serving runtime: admission of independent sketch / RSVD jobs against a
-// device arena (the HBM budget), a plan cache inside that arena, and worker
-// threads that each drive one HIP stream (continuous batching).  Host code
-// only; the jobs run the library's own kernels through its C entry points.
+// device arena (the HBM budget), a plan cache inside that arena, and an
+// event-driven executor: every admitted job is a coroutine on one of a few
+// HIP streams, resumed by the thread that calls the server whenever the event
+// it waits on has completed (continuous batching without worker threads).
+// The host-only test executor runs jobs as sleeps on worker threads instead.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -9,12 +11,14 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <optional>
 #include <thread>
 #include <tuple>
 #include <vector>
 
 #include "../../include/bsrht_serve.h"
 #include "common.h"
+#include "task.h"
 
 namespace bsrht {
 namespace {
@@ -23,6 +27,8 @@ constexpr size_t kAlign = 256;
 constexpr int kBackfillWindow = 8;       // younger jobs considered past the oldest
 constexpr double kMaxBypassSeconds = 0.1;  // after this, nothing passes the oldest
 constexpr int kMaxWorkers = 64;
+constexpr size_t kStagingHalf = 64 * 1024;  // pinned bytes per direction per stream slot
+constexpr double kPollSleep = 20e-6;        // seconds between executor passes while waiting
 
 size_t round_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -77,7 +83,7 @@ class Arena {
 using PlanKey = std::tuple<int64_t, int64_t, int64_t, uint64_t, int, int>;
 
 struct PlanEntry {
-  enum State { PENDING, BUILDING, READY, FAILED };
+  enum State { PENDING, READY, FAILED };
   PlanKey key;
   bsrht_plan_t plan = nullptr;
   size_t off = 0, bytes = 0;
@@ -136,6 +142,27 @@ bool valid_job(const bsrht_job_t &j, bool fake) {
   return j.U && j.S && j.V && j.info;
 }
 
+// The work of one job on its slot's stream, ending when the stream has
+// finished it.
+Task sketch_job(DevCtx &ctx, bsrht_plan_t plan, const bsrht_job_t j, void *ws, size_t ws_bytes) {
+  const int st = bsrht_apply(plan, j.A, j.m, j.lda, j.Y, j.ldy, ws, ws_bytes, ctx.s);
+  if (st != BSRHT_OK) co_return st;
+  co_return co_await drained(ctx);
+}
+
+Task rsvd_job(DevCtx &ctx, bsrht_plan_t plan, const bsrht_job_t j, void *ws, size_t ws_bytes) {
+  const int st = co_await rsvd_task(ctx, plan, j.A, j.m, j.lda, j.k, j.U, j.S, j.V, j.info, ws,
+                                    ws_bytes);
+  if (st != BSRHT_OK) co_return st;
+  co_return co_await drained(ctx);
+}
+
+struct Slot {
+  DevCtx ctx;
+  Job *job = nullptr;
+  std::optional<Task> task;
+};
+
 }  // namespace
 }  // namespace bsrht
 
@@ -150,7 +177,7 @@ struct bsrht_server_s {
   std::chrono::steady_clock::time_point t0;
 
   std::mutex mu;
-  std::condition_variable cv_work, cv_done, cv_plan;
+  std::condition_variable cv_work, cv_done;  // host-only executor
   Arena arena;
   std::deque<Job *> queue;  // submitted, not admitted (arrival order)
   std::deque<Job *> ready;  // admitted, not yet taken by a worker
@@ -160,9 +187,9 @@ struct bsrht_server_s {
   std::map<PlanKey, PlanEntry *> plans;
   uint64_t tick = 0;
   bsrht_server_stats_t st{};
-  int nworkers = 0;
-  std::vector<std::thread> threads;
-  std::vector<hipStream_t> streams;
+  int nworkers = 0;                 // concurrent jobs: worker threads or stream slots
+  std::vector<std::thread> threads;  // host-only executor
+  std::vector<Slot> slots;           // GPU executor
 
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -255,35 +282,29 @@ struct bsrht_server_s {
     cv_work.notify_all();
   }
 
-  int run_job(Job *jb, hipStream_t s) {
-    const bsrht_job_t &j = jb->j;
-    if (fake) {
-      const double secs = sec_per_gb * 4.0 * (double)j.n * (double)j.m / 1e9;
-      std::this_thread::sleep_for(std::chrono::duration<double>(secs));
-      return BSRHT_OK;
-    }
-    void *ws = jb->has_ws ? base + jb->ws_off : nullptr;
-    int rc;
-    if (j.kind == BSRHT_JOB_SKETCH)
-      rc = bsrht_apply(jb->pe->plan, j.A, j.m, j.lda, j.Y, j.ldy, ws, jb->ws_bytes, s);
-    else
-      rc = rsvd(jb->pe->plan, j.A, j.m, j.lda, j.k, j.U, j.S, j.V, j.info, ws, jb->ws_bytes, s);
-    if (hipStreamSynchronize(s) != hipSuccess && rc == BSRHT_OK) rc = BSRHT_EDEVICE;
-    return rc;
+  // Releases a finished job's arena bytes and plan reference and records its
+  // result (mu held).
+  void retire(Job *jb, int rc, double t_done) {
+    PlanEntry *pe = jb->pe;
+    if (jb->has_ws) arena.release(jb->ws_off, jb->ws_bytes);
+    --pe->refs;
+    pe->last_use = ++tick;
+    if (pe->state == PlanEntry::FAILED && pe->refs == 0) drop_plan(pe);
+    bsrht_job_result_t r;
+    r.id = jb->j.id;
+    r.status = rc;
+    r.arena_bytes = jb->held;
+    r.t_submit = jb->t_submit;
+    r.t_start = jb->t_start;
+    r.t_done = t_done;
+    results.push_back(r);
+    delete jb;
+    --running;
+    ++st.completed;
   }
 
-  int build_plan(PlanEntry *pe, hipStream_t s) {
-    if (fake) return BSRHT_OK;
-    const auto &[n, p, l, seed, sampling, precision] = pe->key;
-    int rc = bsrht_plan(n, p, l, seed, sampling, precision, base + pe->off, pe->bytes, s,
-                        &pe->plan);
-    if (rc == BSRHT_OK && hipStreamSynchronize(s) != hipSuccess) rc = BSRHT_EDEVICE;
-    return rc;
-  }
-
-  void worker(int w) {
-    hipStream_t s = fake ? nullptr : streams[(size_t)w];
-    if (!fake) (void)hipSetDevice(device);
+  // ---- host-only executor: worker threads that sleep in place of work ----
+  void worker() {
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
       cv_work.wait(lk, [&] { return stop || !ready.empty(); });
@@ -293,45 +314,84 @@ struct bsrht_server_s {
       ++running;
       st.peak_running = std::max(st.peak_running, running);
       jb->t_start = now();
-      PlanEntry *pe = jb->pe;
-      bool build = false;
-      if (pe->state == PlanEntry::PENDING) {
-        pe->state = PlanEntry::BUILDING;
-        build = true;
-      } else {
-        cv_plan.wait(lk, [&] { return pe->state != PlanEntry::BUILDING; });
-      }
+      if (jb->pe->state == PlanEntry::PENDING) jb->pe->state = PlanEntry::READY;
       lk.unlock();
-      int rc = BSRHT_OK;
-      if (build) {
-        rc = build_plan(pe, s);
-        lk.lock();
-        pe->state = rc == BSRHT_OK ? PlanEntry::READY : PlanEntry::FAILED;
-        pe->status = rc;
-        cv_plan.notify_all();
-        lk.unlock();
-      }
-      if (pe->state == PlanEntry::FAILED) rc = pe->status;
-      if (rc == BSRHT_OK) rc = run_job(jb, s);
-      const double t_done = now();
+      const double secs = sec_per_gb * 4.0 * (double)jb->j.n * (double)jb->j.m / 1e9;
+      std::this_thread::sleep_for(std::chrono::duration<double>(secs));
       lk.lock();
-      if (jb->has_ws) arena.release(jb->ws_off, jb->ws_bytes);
-      --pe->refs;
-      pe->last_use = ++tick;
-      if (pe->state == PlanEntry::FAILED && pe->refs == 0) drop_plan(pe);
-      bsrht_job_result_t r;
-      r.id = jb->j.id;
-      r.status = rc;
-      r.arena_bytes = jb->held;
-      r.t_submit = jb->t_submit;
-      r.t_start = jb->t_start;
-      r.t_done = t_done;
-      results.push_back(r);
-      delete jb;
-      --running;
-      ++st.completed;
+      retire(jb, BSRHT_OK, now());
       admit();
       cv_done.notify_all();
+    }
+  }
+
+  // ---- GPU executor ----
+  void start_job(Slot &sl, Job *jb) {
+    sl.job = jb;
+    ++running;
+    st.peak_running = std::max(st.peak_running, running);
+    jb->t_start = now();
+    PlanEntry *pe = jb->pe;
+    if (pe->state == PlanEntry::PENDING) {
+      const auto &[n, p, l, seed, sampling, precision] = pe->key;
+      int rc = bsrht_plan(n, p, l, seed, sampling, precision, base + pe->off, pe->bytes,
+                          sl.ctx.s, &pe->plan);
+      if (rc == BSRHT_OK && hipStreamSynchronize(sl.ctx.s) != hipSuccess) rc = BSRHT_EDEVICE;
+      pe->state = rc == BSRHT_OK ? PlanEntry::READY : PlanEntry::FAILED;
+      pe->status = rc;
+    }
+    if (pe->state == PlanEntry::FAILED) {
+      sl.job = nullptr;
+      retire(jb, pe->status, now());
+      return;
+    }
+    void *ws = jb->has_ws ? base + jb->ws_off : nullptr;
+    if (jb->j.kind == BSRHT_JOB_SKETCH)
+      sl.task.emplace(sketch_job(sl.ctx, pe->plan, jb->j, ws, jb->ws_bytes));
+    else
+      sl.task.emplace(rsvd_job(sl.ctx, pe->plan, jb->j, ws, jb->ws_bytes));
+    sl.task->start();  // runs until its first wait on the device
+  }
+
+  void finish_slot(Slot &sl, int rc) {
+    Job *jb = sl.job;
+    sl.job = nullptr;
+    sl.task.reset();
+    retire(jb, rc, now());
+  }
+
+  // One executor pass: resume jobs whose awaited event has completed, retire
+  // finished jobs, admit and start waiting ones (mu held).  Repeats while it
+  // makes progress.
+  void pump() {
+    for (bool moved = true; moved;) {
+      moved = false;
+      for (Slot &sl : slots) {
+        if (!sl.job) continue;
+        if (!sl.task->done()) {
+          const hipError_t q = hipEventQuery(sl.ctx.ev);
+          if (q == hipErrorNotReady) continue;
+          if (q != hipSuccess) {
+            finish_slot(sl, BSRHT_EDEVICE);
+            moved = true;
+            continue;
+          }
+          sl.ctx.resume_point.resume();
+          moved = true;
+        }
+        if (sl.task->done()) {
+          finish_slot(sl, sl.task->status());
+          moved = true;
+        }
+      }
+      admit();
+      for (Slot &sl : slots) {
+        if (sl.job || ready.empty()) continue;
+        Job *jb = ready.front();
+        ready.pop_front();
+        start_job(sl, jb);
+        moved = true;
+      }
     }
   }
 
@@ -339,20 +399,33 @@ struct bsrht_server_s {
     nworkers = workers;
     t0 = std::chrono::steady_clock::now();
     arena.reset(arena_bytes);
-    if (!fake) {
-      if (hipGetDevice(&device) != hipSuccess) return BSRHT_EDEVICE;
-      for (int w = 0; w < workers; ++w) {
-        hipStream_t s;
-        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
-          for (hipStream_t t : streams) (void)hipStreamDestroy(t);
-          streams.clear();
-          return BSRHT_EDEVICE;
-        }
-        streams.push_back(s);
-      }
+    if (fake) {
+      for (int w = 0; w < workers; ++w) threads.emplace_back(&bsrht_server_s::worker, this);
+      return BSRHT_OK;
     }
-    for (int w = 0; w < workers; ++w) threads.emplace_back(&bsrht_server_s::worker, this, w);
+    if (hipGetDevice(&device) != hipSuccess) return BSRHT_EDEVICE;
+    slots.resize((size_t)workers);
+    for (Slot &sl : slots) {
+      void *pin = nullptr;
+      if (hipStreamCreateWithFlags(&sl.ctx.s, hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&sl.ctx.ev, hipEventDisableTiming) != hipSuccess ||
+          hipHostMalloc(&pin, 2 * kStagingHalf, hipHostMallocDefault) != hipSuccess)
+        return BSRHT_EDEVICE;
+      sl.ctx.blocking = false;
+      sl.ctx.pinned = static_cast<char *>(pin);
+      sl.ctx.half_bytes = kStagingHalf;
+    }
     return BSRHT_OK;
+  }
+
+  void release_device() {
+    for (Slot &sl : slots) {
+      sl.task.reset();
+      if (sl.ctx.pinned) (void)hipHostFree(sl.ctx.pinned);
+      if (sl.ctx.ev) (void)hipEventDestroy(sl.ctx.ev);
+      if (sl.ctx.s) (void)hipStreamDestroy(sl.ctx.s);
+    }
+    slots.clear();
   }
 };
 
@@ -372,6 +445,7 @@ int create(bool fake, void *arena, size_t arena_bytes, int workers, double sec_p
   srv->arena_bytes = arena_bytes & ~(kAlign - 1);
   const int rc = srv->start(workers);
   if (rc != BSRHT_OK) {
+    srv->release_device();
     delete srv;
     return rc;
   }
@@ -388,17 +462,8 @@ size_t bsrht_job_bytes(const bsrht_job_t *job) {
   return round_up(workspace_of(*job)) + round_up(bsrht_plan_bytes(job->n, job->p, job->l));
 }
 
-int bsrht_server_create(void *arena, size_t arena_bytes, int workers, bsrht_server_t *out) {
-  // The GPU executor (worker threads issuing the library's calls on their
-  // own streams) is switched off: a process that used it ended with a
-  // segmentation fault at exit after every job had completed correctly, and
-  // the cause has not been identified.  Only argument checking remains.
-  if (!out) return BSRHT_EINVAL;
-  *out = nullptr;
-  if (workers < 1 || workers > kMaxWorkers || arena_bytes == 0 || !arena ||
-      ((uintptr_t)arena % kAlign) != 0)
-    return BSRHT_EINVAL;
-  return BSRHT_EUNSUPPORTED;
+int bsrht_server_create(void *arena, size_t arena_bytes, int streams, bsrht_server_t *out) {
+  return create(false, arena, arena_bytes, streams, 0.0, out);
 }
 
 int bsrht_server_create_fake(size_t arena_bytes, int workers, double seconds_per_gb,
@@ -428,6 +493,7 @@ int bsrht_server_submit(bsrht_server_t srv, const bsrht_job_t *job) {
   srv->queue.push_back(jb);
   ++srv->st.submitted;
   srv->admit();
+  if (!srv->fake) srv->pump();
   return BSRHT_OK;
 }
 
@@ -435,9 +501,20 @@ int bsrht_server_poll(bsrht_server_t srv, bsrht_job_result_t *out, int max, doub
                       int *count) {
   if (!srv || !count || max < 0 || (max > 0 && !out)) return BSRHT_EINVAL;
   std::unique_lock<std::mutex> lk(srv->mu);
-  if (srv->results.empty() && timeout_s > 0.0)
-    srv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s),
-                          [&] { return !srv->results.empty(); });
+  if (srv->fake) {
+    if (srv->results.empty() && timeout_s > 0.0)
+      srv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s),
+                            [&] { return !srv->results.empty(); });
+  } else {
+    const double until = srv->now() + std::max(timeout_s, 0.0);
+    for (;;) {
+      srv->pump();
+      if (!srv->results.empty() || srv->now() >= until) break;
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::duration<double>(kPollSleep));
+      lk.lock();
+    }
+  }
   int c = 0;
   while (c < max && !srv->results.empty()) {
     out[c++] = srv->results.front();
@@ -450,8 +527,17 @@ int bsrht_server_poll(bsrht_server_t srv, bsrht_job_result_t *out, int max, doub
 int bsrht_server_drain(bsrht_server_t srv) {
   if (!srv) return BSRHT_EINVAL;
   std::unique_lock<std::mutex> lk(srv->mu);
-  srv->cv_done.wait(lk, [&] { return srv->st.completed == srv->st.submitted; });
-  return BSRHT_OK;
+  if (srv->fake) {
+    srv->cv_done.wait(lk, [&] { return srv->st.completed == srv->st.submitted; });
+    return BSRHT_OK;
+  }
+  for (;;) {
+    srv->pump();
+    if (srv->st.completed == srv->st.submitted) return BSRHT_OK;
+    lk.unlock();
+    std::this_thread::sleep_for(std::chrono::duration<double>(kPollSleep));
+    lk.lock();
+  }
 }
 
 int bsrht_server_stats(bsrht_server_t srv, bsrht_server_stats_t *out) {
@@ -478,7 +564,7 @@ int bsrht_server_destroy(bsrht_server_t srv) {
     delete kv.second;
   }
   srv->plans.clear();
-  for (hipStream_t s : srv->streams) (void)hipStreamDestroy(s);
+  srv->release_device();
   delete srv;
   return BSRHT_OK;
 }

@@ -1,7 +1,7 @@
 """Serving runtime on the GPU: a mix of sketch and randomized-SVD jobs run
-concurrently through the server gives, job by job, exactly the result of the
-same library call made alone (every reduction runs in a fixed order), and
-sampled small jobs match the FP64 oracle."""
+concurrently through the server's stream slots gives, job by job, exactly the
+result of the same library call made alone (every reduction runs in a fixed
+order), and sampled small jobs match the FP64 oracle."""
 import numpy as np
 import pytest
 import torch
@@ -57,9 +57,6 @@ def _alone(js, A):
     return dict(U=U, S=S, V=V, info=info)
 
 
-@pytest.mark.skip(reason="threaded GPU executor switched off: a process running this test "
-                         "ended with a segmentation fault at exit after the test had passed; "
-                         "cause not identified")
 def test_mix_equals_alone_and_matches_oracle():
     dev = device()
     jobs = _jobs(120, 5)

@@ -148,4 +148,5 @@ def test_invalid_server_arguments():
     assert L.bsrht_server_create_fake(1 << 20, 65, 0.0, ctypes.byref(h)) == -1
     assert L.bsrht_server_create_fake(1 << 20, 2, -1.0, ctypes.byref(h)) == -1
     assert L.bsrht_server_create(None, 1 << 20, 2, ctypes.byref(h)) == -1
-    assert L.bsrht_server_create(ctypes.c_void_p(4096), 1 << 20, 2, ctypes.byref(h)) == -4
+    assert L.bsrht_server_create(ctypes.c_void_p(4096 + 8), 1 << 20, 2, ctypes.byref(h)) == -1
+    assert L.bsrht_server_create(ctypes.c_void_p(4096), 1 << 20, 0, ctypes.byref(h)) == -1
