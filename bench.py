@@ -9,8 +9,9 @@ output signs and the sum over blocks), with A resident in HBM.
 
 Prints one JSON line: GB/s of A streamed, the dominant kernel's roofline
 (achieved vs the 8 TB/s HBM peak, from HIP events around that kernel), and the
-FP64 CPU oracle timed on a sample of the same workload.  Progress goes to
-stderr.
+FP64 CPU oracle timed on a sample of the same workload; then the split-BF16
+sketch, the randomized SVD and Nystrom at full size, and the serving workload
+(Poisson arrivals of sketch + RSVD jobs).  Progress goes to stderr.
 """
 import argparse
 import hashlib
@@ -23,6 +24,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+
+# The serving leg keeps up to 16 jobs in flight on 16 streams; HIP maps
+# streams onto this many hardware queues (its default of 4 would serialise
+# them).  Must be set before the HIP runtime starts.
+os.environ["GPU_MAX_HW_QUEUES"] = "16"
+SERVE_STREAMS = 16
 
 HBM_PEAK_GBS = 8000.0
 
@@ -170,6 +177,115 @@ def bench_rsvd(bs, A, plan, cfg, reps):
             "rel_fro_error": err, "info": int(info.item())}
 
 
+def bench_serving(bs, njobs, streams, rate=200.0, arena_gib=32, ahead=16, live_gib=64):
+    """Serving workload: Poisson arrivals at `rate` jobs/s of sketch + RSVD
+    jobs with seeded random shapes (n = 2^a, a in 14..20; m log-uniform in
+    [64, 2048]; p in {1, 4, 16, 64}; k in 16..256; l = 2k + 32), payload
+    A = X diag(j^-1.5) with Gaussian X generated on the device up to `ahead`
+    jobs before its arrival (the client never blocks on it: a payload is
+    submitted once its event has completed).  Latency runs from the
+    scheduled arrival to the server observing the job's completion event, so
+    client-side delays (a payload not ready, more than `live_gib` GiB of
+    payloads in flight) count against it."""
+    import collections
+
+    import numpy as np
+    import torch
+    import workloads
+
+    dev = torch.device("cuda:0")
+    jobs = workloads.serving_jobs(njobs, rate, seed=0)
+    arena = torch.empty(arena_gib << 30, dtype=torch.uint8, device=dev)
+    gen_stream = torch.cuda.Stream(device=dev)
+    log(f"bench: serving {njobs} jobs at {rate:.0f}/s on {streams} stream slots, "
+        f"arena {arena_gib} GiB")
+    lat, done_at = {}, {}
+    live = {}          # submitted, not finished: id -> tensors
+    prepared = collections.deque()  # (job, tensors, ready event), arrival order
+    a_bytes = 0
+    live_bytes = 0
+    lag = 0.0
+    nxt = 0            # next job to prepare
+
+    def prepare(js):
+        n, m, k = js["n"], js["m"], js["k"]
+        g = torch.Generator(device=dev)
+        g.manual_seed(js["seed"] & (2 ** 63 - 1))
+        with torch.cuda.stream(gen_stream):
+            scale = torch.arange(1, m + 1, device=dev, dtype=torch.float32) ** -1.5
+            A = torch.randn(n, m, generator=g, device=dev) * scale
+            out = (A, torch.empty(n, k, device=dev),
+                   torch.empty(k, dtype=torch.float64, device=dev),
+                   torch.empty(m, k, device=dev), torch.zeros(1, dtype=torch.int32, device=dev))
+            ev = torch.cuda.Event()
+            ev.record(gen_stream)
+        return out, ev
+
+    with bs.Server(arena=arena, workers=streams) as srv:
+        def collect(res):
+            nonlocal live_bytes
+            for r in res:
+                if r.status != 0:
+                    raise RuntimeError(f"serving job {r.id} failed with status {r.status}")
+                lat[r.id] = r.t_done - (t0 + jobs[r.id]["arrival"])
+                done_at[r.id] = r.t_done
+                t = live.pop(r.id)
+                live_bytes -= t[0].numel() * 4
+
+        t0 = srv.clock() + 0.05
+        for i, js in enumerate(jobs):
+            # keep up to `ahead` payloads prepared, within the live-bytes cap
+            while nxt < njobs and nxt < i + ahead and live_bytes < (live_gib << 30):
+                out, ev = prepare(jobs[nxt])
+                prepared.append((jobs[nxt], out, ev))
+                live_bytes += out[0].numel() * 4
+                nxt += 1
+            if not prepared:  # cap reached with nothing prepared: wait for completions
+                while not prepared:
+                    collect(srv.poll(256, timeout=5e-4))
+                    if live_bytes < (live_gib << 30) and nxt < njobs:
+                        out, ev = prepare(jobs[nxt])
+                        prepared.append((jobs[nxt], out, ev))
+                        live_bytes += out[0].numel() * 4
+                        nxt += 1
+            js_p, out, ev = prepared[0]
+            assert js_p["id"] == js["id"]
+            while srv.clock() < t0 + js["arrival"] or not ev.query():
+                collect(srv.poll(256, timeout=min(5e-4, max(t0 + js["arrival"] - srv.clock(),
+                                                            5e-5))))
+            prepared.popleft()
+            lag = max(lag, srv.clock() - (t0 + js["arrival"]))
+            live[js["id"]] = out
+            A, U, S, V, info = out
+            srv.submit(bs.rsvd_job(js["id"], (js["n"], js["p"], js["l"], 0,
+                                              bs.WITH_REPLACEMENT, bs.FP32),
+                                   A, js["k"], U, S, V, info))
+            a_bytes += A.numel() * 4
+            collect(srv.poll(256))
+            if js["id"] % 500 == 499:
+                log(f"bench: serving {js['id'] + 1} submitted, {len(lat)} done, "
+                    f"{live_bytes / 2 ** 30:.1f} GiB of payloads live")
+        srv.drain()
+        collect(srv.poll(njobs))
+        st = srv.stats()
+    L = np.array([lat[i] for i in range(njobs)]) * 1e3
+    span = max(done_at.values()) - t0
+    out = {"jobs": njobs, "offered_jobs_per_s": rate, "stream_slots": streams,
+           "p50_ms": round(float(np.percentile(L, 50)), 3),
+           "p99_ms": round(float(np.percentile(L, 99)), 3),
+           "max_ms": round(float(L.max()), 3),
+           "jobs_per_s": round(njobs / span, 2), "GBs_of_A": round(a_bytes / span / 1e9, 2),
+           "max_submit_lag_ms": round(lag * 1e3, 3),
+           "peak_running": st["peak_running"], "peak_arena_GiB": round(
+               st["peak_arena_bytes"] / 2 ** 30, 3),
+           "plan_hits": st["plan_hits"], "plan_misses": st["plan_misses"],
+           "plan_evictions": st["plan_evictions"], "backfilled": st["backfilled"],
+           "rejected": st["rejected"]}
+    log(f"bench: serving p50 {out['p50_ms']} ms p99 {out['p99_ms']} ms, "
+        f"{out['jobs_per_s']} jobs/s, {out['GBs_of_A']} GB/s of A")
+    return out
+
+
 def bench_nystrom(bs, reps):
     """Algorithm 2 on the 65536 x 65536 SPD matrix (s_j = j^-3, p = 64, l = 1024,
     rank 512), FP64 factorisations on the GPU."""
@@ -217,9 +333,13 @@ def main():
     ap.add_argument("--skip-lowrank", action="store_true",
                     help="skip the randomized SVD and Nystrom measurements")
     ap.add_argument("--lowrank-reps", type=int, default=3)
-    ap.add_argument("--only", choices=["all", "sketch", "bf16", "rsvd", "nystrom"],
+    ap.add_argument("--serve-jobs", type=int, default=2000,
+                    help="jobs of the serving workload (0 skips it)")
+    ap.add_argument("--serve-streams", type=int, default=SERVE_STREAMS)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--only", choices=["all", "sketch", "bf16", "rsvd", "nystrom", "serve"],
                     default="all",
-                    help="profiling aid: run one part ('bf16', 'rsvd' and 'nystrom' print only "
+                    help="profiling aid: run one part ('bf16', 'rsvd', 'nystrom' and 'serve' print only "
                          "that part's JSON object)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -232,6 +352,10 @@ def main():
     import paper_2210_11295_amd as bs
     import workloads
 
+    if args.only == "serve":
+        print(json.dumps({"serving": bench_serving(bs, args.serve_jobs, args.serve_streams,
+                                                   rate=args.serve_rate)}), flush=True)
+        return
     if args.only == "nystrom":
         print(json.dumps({"nystrom": bench_nystrom(bs, args.lowrank_reps)}), flush=True)
         return
@@ -322,6 +446,10 @@ def main():
         del A, Y, ws
         torch.cuda.empty_cache()
         out["nystrom"] = bench_nystrom(bs, args.lowrank_reps)
+        torch.cuda.empty_cache()
+    if args.serve_jobs > 0 and args.only == "all":
+        out["serving"] = bench_serving(bs, args.serve_jobs, args.serve_streams,
+                                       rate=args.serve_rate)
     print(json.dumps(out), flush=True)
 
 
