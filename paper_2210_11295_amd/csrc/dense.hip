@@ -619,10 +619,11 @@ __global__ __launch_bounds__(1024) void noise_floor_kernel(const double *__restr
                                                             int64_t nr, int64_t nc, int64_t ldx,
                                                             double *__restrict__ out) {
   __shared__ double part[16];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double acc = 0.0;
-  for (int64_t e = threadIdx.x; e < nr * nc; e += 1024) {
-    const double v = X[(e / nr) * ldx + e % nr];
-    acc += v * v;
+  for (int64_t c = w; c < nc; c += 16) {  // wave w: columns w, w + 16, ...
+    const double *col = X + c * ldx;
+    for (int64_t i = lane; i < nr; i += 64) acc += col[i] * col[i];
   }
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
