@@ -125,6 +125,176 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(GemmDesc d, const TA
       }
 }
 
+// ---------------------------------------------------------------------------
+// Large-tile GEMM for the tall products (Z = A Q, the Gram Z^T Z, U = Z M):
+// a 128 x 128 workgroup tile, 4 waves of 64 x 64 (4 x 4 MFMA blocks each),
+// 16-wide k tiles double-buffered in LDS with one barrier per tile and the
+// next tile's 16-byte global loads in flight during the MFMAs.  Used when B
+// is j-contiguous and A is k-contiguous (AK) or i-contiguous (!AK), with
+// 16-byte aligned bases and strides that are multiples of 4 elements; the
+// split-K chunks are multiples of the k tile.  Other shapes take gemm_kernel.
+constexpr int kBM = 128, kBN = 128, kBK = 16, kBPad = 4;
+constexpr int kBThreads = 256;
+
+template <typename T>
+struct Vec4 {
+  T v[4];
+};
+
+// Four consecutive elements at p (16-byte aligned for float, 32 for double).
+template <typename T>
+__device__ __forceinline__ Vec4<T> load4(const T *p) {
+  Vec4<T> r;
+  if constexpr (sizeof(T) == 4) {
+    const float4 f = *reinterpret_cast<const float4 *>(p);
+    r.v[0] = f.x;
+    r.v[1] = f.y;
+    r.v[2] = f.z;
+    r.v[3] = f.w;
+  } else {
+    const double2 a = *reinterpret_cast<const double2 *>(p);
+    const double2 b = *reinterpret_cast<const double2 *>(p + 2);
+    r.v[0] = a.x;
+    r.v[1] = a.y;
+    r.v[2] = b.x;
+    r.v[3] = b.y;
+  }
+  return r;
+}
+
+template <typename TA, typename TB, typename TC, bool F64, bool AK>
+__global__ __launch_bounds__(kBThreads) void gemm_big_kernel(GemmDesc d, const TA *__restrict__ A,
+                                                             const TB *__restrict__ B,
+                                                             TC *__restrict__ C) {
+  using TS = typename std::conditional<F64, double, float>::type;
+  __shared__ __attribute__((aligned(16))) TS As[2][kBK][kBM + kBPad];
+  __shared__ __attribute__((aligned(16))) TS Bs[2][kBK][kBN + kBPad];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * kBM, j0 = (int64_t)blockIdx.y * kBN;
+  int64_t kchunk = (d.K + gridDim.z - 1) / gridDim.z;
+  kchunk = (kchunk + kBK - 1) / kBK * kBK;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t ke = min(d.K, kb + kchunk);
+  const int wi = (wave >> 1) * 64, wj = (wave & 1) * 64;
+  using Acc = typename std::conditional<F64, double __attribute__((ext_vector_type(4))),
+                                        float __attribute__((ext_vector_type(4)))>::type;
+  Acc acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+
+  // Each thread moves two 4-element vectors of A and two of B per k tile.
+  Vec4<TS> ra[2], rb[2];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int v = tid + h * kBThreads;  // 0..511
+      int64_t gi, gk;
+      if constexpr (AK) {  // 128 rows x 4 vectors of k
+        gi = i0 + (v >> 2);
+        gk = k0 + 4 * (v & 3);
+      } else {             // 16 k rows x 32 vectors of i
+        gk = k0 + (v >> 5);
+        gi = i0 + 4 * (v & 31);
+      }
+      const TA *src = A + gi * d.sai + gk * d.sak;
+      const bool full = AK ? (gi < d.M && gk + 3 < ke) : (gk < ke && gi + 3 < d.M);
+      if (full) {
+        const Vec4<TA> t = load4<TA>(src);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ra[h].v[e] = (TS)t.v[e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const bool in = AK ? (gi < d.M && gk + e < ke) : (gk < ke && gi + e < d.M);
+          ra[h].v[e] = in ? (TS)src[AK ? e : e * d.sai] : (TS)0;
+        }
+      }
+      // B: 16 k rows x 32 vectors of j
+      const int64_t bk = k0 + (v >> 5), bj = j0 + 4 * (v & 31);
+      const TB *bsrc = B + bk * d.sbk + bj;
+      if (bk < ke && bj + 3 < d.N) {
+        const Vec4<TB> t = load4<TB>(bsrc);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rb[h].v[e] = (TS)t.v[e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rb[h].v[e] = (bk < ke && bj + e < d.N) ? (TS)bsrc[e] : (TS)0;
+      }
+    }
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int v = tid + h * kBThreads;
+      if constexpr (AK) {
+        const int ii = v >> 2, kk = 4 * (v & 3);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) As[buf][kk + e][ii] = ra[h].v[e];
+      } else {
+        const int kk = v >> 5, ii = 4 * (v & 31);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) As[buf][kk][ii + e] = ra[h].v[e];
+      }
+      const int kk = v >> 5, jj = 4 * (v & 31);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) Bs[buf][kk][jj + e] = rb[h].v[e];
+    }
+  };
+
+  const int64_t ntiles = (ke - kb + kBK - 1) / kBK;
+  if (ntiles > 0) {
+    fetch(kb);
+    stage(0);
+  }
+  __syncthreads();
+  for (int64_t t = 0; t < ntiles; ++t) {
+    const int cur = (int)(t & 1);
+    const bool more = t + 1 < ntiles;
+    if (more) fetch(kb + (t + 1) * kBK);
+#pragma unroll
+    for (int ks = 0; ks < kBK; ks += 4) {
+      const int kk = ks + (lane >> 4);
+      TS av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[cur][kk][wi + 16 * a + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Bs[cur][kk][wj + 16 * b + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          if constexpr (F64)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+          else
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
+    }
+    if (more) stage(cur ^ 1);
+    __syncthreads();
+  }
+  TC *Cz = C + (int64_t)blockIdx.z * d.split_stride;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gi = i0 + wi + 16 * a + (F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
+        const int64_t gj = j0 + wj + 16 * b + (lane & 15);
+        if (gi < d.M && gj < d.N) {
+          const double val = d.alpha * (double)acc[a][b][v];
+          TC *dst = Cz + gi * d.ldc + gj;
+          if (d.beta != 0.0)
+            *dst = (TC)(val + d.beta * (double)*dst);
+          else
+            *dst = (TC)val;
+        }
+      }
+}
+
 // Sum of split-K partials in split order: C[i][j] = sum_s P[s][i][j].
 template <typename TC>
 __global__ void reduce_partials_kernel(const double *__restrict__ P, int splits, int64_t M,
@@ -139,9 +309,24 @@ __global__ void reduce_partials_kernel(const double *__restrict__ P, int splits,
 
 }  // namespace
 
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
 template <typename TA, typename TB, typename TC, bool F64>
 static int gemm_launch(const GemmDesc &d, const TA *A, const TB *B, TC *C, hipStream_t s) {
   if (d.M <= 0 || d.N <= 0) return BSRHT_OK;
+  const bool b_ok = d.sbj == 1 && d.sbk % 4 == 0 && aligned16(B);
+  const bool a_k = d.sak == 1 && d.sai % 4 == 0;
+  const bool a_i = d.sai == 1 && d.sak % 4 == 0;
+  if (b_ok && (a_k || a_i) && aligned16(A) && d.M >= 64 && d.N >= 64) {
+    dim3 grid((unsigned)((d.M + kBM - 1) / kBM), (unsigned)((d.N + kBN - 1) / kBN),
+              (unsigned)d.splits);
+    if (a_k)
+      gemm_big_kernel<TA, TB, TC, F64, true><<<grid, kBThreads, 0, s>>>(d, A, B, C);
+    else
+      gemm_big_kernel<TA, TB, TC, F64, false><<<grid, kBThreads, 0, s>>>(d, A, B, C);
+    BSRHT_LAUNCH_CHECK();
+    return BSRHT_OK;
+  }
   dim3 grid((unsigned)((d.M + kTM - 1) / kTM), (unsigned)((d.N + kTN - 1) / kTN),
             (unsigned)d.splits);
   gemm_kernel<TA, TB, TC, F64><<<grid, kGemmThreads, 0, s>>>(d, A, B, C);
@@ -221,7 +406,7 @@ int64_t gram_partial_elems(int64_t n, int64_t Kmax) {
 
 int gram_splits(int64_t n, int64_t K) {
   // enough workgroups to fill the chip; each split spans at least 1024 rows
-  const int64_t tiles = ((K + kTM - 1) / kTM) * ((K + kTN - 1) / kTN);
+  const int64_t tiles = ((K + kBM - 1) / kBM) * ((K + kBN - 1) / kBN);
   int64_t want = (2 * (int64_t)device_cu_count() + tiles - 1) / tiles;
   int64_t maxs = (n + 1023) / 1024;
   if (want > maxs) want = maxs;
