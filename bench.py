@@ -221,6 +221,8 @@ def bench_serving(bs, njobs, streams, rate=200.0, arena_gib=32, ahead=16, live_g
             ev.record(gen_stream)
         return out, ev
 
+    import resource
+    ru0 = resource.getrusage(resource.RUSAGE_SELF)
     with bs.Server(arena=arena, workers=streams) as srv:
         def collect(res):
             nonlocal live_bytes
@@ -268,6 +270,8 @@ def bench_serving(bs, njobs, streams, rate=200.0, arena_gib=32, ahead=16, live_g
         srv.drain()
         collect(srv.poll(njobs))
         st = srv.stats()
+    ru1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu_s = (ru1.ru_utime - ru0.ru_utime) + (ru1.ru_stime - ru0.ru_stime)
     L = np.array([lat[i] for i in range(njobs)]) * 1e3
     span = max(done_at.values()) - t0
     out = {"jobs": njobs, "offered_jobs_per_s": rate, "stream_slots": streams,
@@ -276,6 +280,7 @@ def bench_serving(bs, njobs, streams, rate=200.0, arena_gib=32, ahead=16, live_g
            "max_ms": round(float(L.max()), 3),
            "jobs_per_s": round(njobs / span, 2), "GBs_of_A": round(a_bytes / span / 1e9, 2),
            "max_submit_lag_ms": round(lag * 1e3, 3),
+           "host_cpu_s_per_wall_s": round(cpu_s / span, 3),
            "peak_running": st["peak_running"], "peak_arena_GiB": round(
                st["peak_arena_bytes"] / 2 ** 30, 3),
            "plan_hits": st["plan_hits"], "plan_misses": st["plan_misses"],
