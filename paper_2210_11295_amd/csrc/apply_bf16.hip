@@ -2,9 +2,10 @@
 // ("split-BF16"): Y = Omega A (section 2, eq. (2.3)-(2.4)) for row-major A
 // (n x m), the same result as the FP32 butterfly kernel up to rounding.
 //
-// Kronecker form (section 2): for a chunk of b = 8*BR rows of one block,
-// H_b = H_8 (x) H_{BR/16} (x) H_16 over the bit fields of the chunk row
-// x = 64*w' + 16*t_hi + x_16 (w' = wave, BR = 64).  Per chunk:
+// Kronecker form (section 2): for a chunk of b = NW*BR rows of one block
+// (NW = 8 waves, or 16 when l > 512 so that one thread serves each sample),
+// H_b = H_NW (x) H_{BR/16} (x) H_16 over the bit fields of the chunk row
+// x = BR*w' + 16*t_hi + x_16 (w' = wave).  Per chunk:
 //   1. load  : lane (q, g) = (lane & 15, lane >> 4) fetches 16 bytes
 //              (columns 4q .. 4q+3) of rows 4t + g, t in [0, BR/4): one
 //              dwordx4 load per t covers 4 rows x 64 columns;
@@ -17,7 +18,7 @@
 //              |v - hi - lo| <= 2^-16 |v|;
 //   4. H_{BR/16} over t_hi in FP32 registers (applied before step 3: the
 //      factors act on disjoint bit fields and commute), then LDS stores;
-//   5. H_8 over the 8 waves through LDS and the output-pruned gather of the
+//   5. H_NW over the waves through LDS and the output-pruned gather of the
 //      l sampled rows, as in the FP32 kernel:
 //        (H_r v)[R_j] = sum_{x_hi} (-1)^popcount(R_j,hi & x_hi)
 //                       * (H_b v_{x_hi})[R_j,lo].
@@ -32,7 +33,6 @@
 namespace bsrht {
 namespace {
 
-constexpr int kNW = 8;          // waves per workgroup
 constexpr int kCT = 64;         // columns per workgroup
 constexpr int kLDT = kCT + 4;   // LDS row stride in floats
 constexpr int kBufDword3 = 0x00020000;  // raw buffer resource word 3 (gfx9 family)
@@ -99,13 +99,13 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const float *base) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), (short)0, -1, kBufDword3);
 }
 
-template <int BR, bool RAGGED>
+template <int NW, int BR, bool RAGGED>
 struct Bf16Cta {
-  static constexpr int B = BR * kNW;
+  static constexpr int B = BR * NW;
   static constexpr int LOG2B = ilog2c(B);
   static constexpr int NT = BR / 4;   // row quads per wave
   static constexpr int NH = NT / 4;   // values of t_hi
-  static constexpr int G = BR / kNW;  // H_8 groups per wave
+  static constexpr int G = BR / NW;  // H_NW groups per wave
   static_assert(BR >= 16 && BR <= 64, "BR in {16, 32, 64}");
 
   float *T;
@@ -237,12 +237,12 @@ struct Bf16Cta {
 #pragma unroll
     for (int gi = 0; gi < G; ++gi) {
       float *Tg = T + (w * G + gi) * kLDT + lane;
-      float u[kNW];
+      float u[NW];
 #pragma unroll
-      for (int k = 0; k < kNW; ++k) u[k] = Tg[k * BR * kLDT];
-      fwht_regs<kNW>(u);
+      for (int k = 0; k < NW; ++k) u[k] = Tg[k * BR * kLDT];
+      fwht_regs<NW>(u);
 #pragma unroll
-      for (int k = 0; k < kNW; ++k) Tg[k * BR * kLDT] = u[k];
+      for (int k = 0; k < NW; ++k) Tg[k * BR * kLDT] = u[k];
     }
     __syncthreads();
     if (jok) {
@@ -268,9 +268,9 @@ struct Bf16Cta {
   }
 };
 
-template <int BR, bool RAGGED>
-__global__ __launch_bounds__(kNW * 64) void fused_bf16_kernel(Bf16Args a) {
-  using Cta = Bf16Cta<BR, RAGGED>;
+template <int NW, int BR, bool RAGGED>
+__global__ __launch_bounds__(NW * 64) void fused_bf16_kernel(Bf16Args a) {
+  using Cta = Bf16Cta<NW, BR, RAGGED>;
   __shared__ __attribute__((aligned(16))) float T[Cta::B * kLDT];
   __shared__ u32x4_t Hop[64];
   Cta cta(T, a);
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(kNW * 64) void fused_bf16_kernel(Bf16Args a) {
   __syncthreads();
   const int q0 = blockIdx.y * a.chunks_per_split;
   const int q1 = min(q0 + a.chunks_per_split, a.total_chunks);
-  cta.j = blockIdx.z * (kNW * 64) + tid;
+  cta.j = blockIdx.z * (NW * 64) + tid;
   cta.jok = cta.j < a.l;
   const int rj = cta.jok ? a.R[cta.j] : 0;
   cta.pos = rj & (Cta::B - 1);
@@ -330,29 +330,38 @@ __global__ __launch_bounds__(kNW * 64) void fused_bf16_kernel(Bf16Args a) {
 
 struct Launch {
   bool fp32 = false;
-  int br = 0, b = 0;
+  int nw = 8, br = 0, b = 0;
   int full_tiles = 0, ragged = 0, groups = 0, splits = 1, cps = 0, total_chunks = 0;
   size_t ws = 0;
 };
 
 Launch choose_launch(const bsrht_plan_s *pl, int64_t m) {
   Launch L;
-  // Largest chunk b = 8*BR <= r with 16 <= BR <= 64.
-  int br = 64;
-  while (br >= 16 && (int64_t)br * kNW > pl->r) br >>= 1;
-  if (br < 16) {
-    L.fp32 = true;
-    return L;
+  int per_cu;
+  if (pl->l > 512 && pl->r >= 256) {
+    // 16 waves, one thread per sample for l <= 1024: A is read once per
+    // 1024 samples; chunks of b = 16*16 rows.
+    L.nw = 16;
+    L.br = 16;
+    per_cu = 1;
+  } else {
+    // Largest chunk b = 8*BR <= r with 16 <= BR <= 64.
+    int br = 64;
+    while (br >= 16 && (int64_t)br * 8 > pl->r) br >>= 1;
+    if (br < 16) {
+      L.fp32 = true;
+      return L;
+    }
+    L.nw = 8;
+    L.br = br;
+    per_cu = br * 8 * kLDT * 4 > 80 * 1024 ? 1 : 2;
   }
-  L.br = br;
-  L.b = br * kNW;
-  const int lds_bytes = L.b * kLDT * 4;
-  const int per_cu = lds_bytes > 80 * 1024 ? 1 : 2;
+  L.b = L.br * L.nw;
   L.total_chunks = (int)(pl->n / L.b);
   L.full_tiles = (int)(m / kCT);
   L.ragged = (m % kCT) != 0 ? 1 : 0;
   const int ctiles = L.full_tiles + L.ragged;
-  const int spp = kNW * 64;
+  const int spp = L.nw * 64;
   L.groups = (int)((pl->l + spp - 1) / spp);
   const int64_t target = (int64_t)device_cu_count() * per_cu;
   int64_t splits = target / ((int64_t)ctiles * L.groups);
@@ -364,18 +373,18 @@ Launch choose_launch(const bsrht_plan_s *pl, int64_t m) {
   return L;
 }
 
-template <int BR>
+template <int NW, int BR>
 int launch_bf16(const Launch &L, Bf16Args &a, hipStream_t s) {
   const int tslot = timing_begin(BSRHT_TIMING_APPLY_BF16, s);
   if (L.full_tiles > 0) {
     a.tile0 = 0;
     dim3 grid((unsigned)L.full_tiles, (unsigned)L.splits, (unsigned)L.groups);
-    fused_bf16_kernel<BR, false><<<grid, kNW * 64, 0, s>>>(a);
+    fused_bf16_kernel<NW, BR, false><<<grid, NW * 64, 0, s>>>(a);
   }
   if (L.ragged) {
     a.tile0 = L.full_tiles;
     dim3 grid(1u, (unsigned)L.splits, (unsigned)L.groups);
-    fused_bf16_kernel<BR, true><<<grid, kNW * 64, 0, s>>>(a);
+    fused_bf16_kernel<NW, BR, true><<<grid, NW * 64, 0, s>>>(a);
   }
   timing_end(tslot, s);
   BSRHT_LAUNCH_CHECK();
@@ -425,10 +434,14 @@ int apply_split_bf16(const bsrht_plan_s *pl, const float *A, int64_t m, int64_t 
     a.scale = scale;
   }
   int st;
-  switch (L.br) {
-    case 64: st = launch_bf16<64>(L, a, s); break;
-    case 32: st = launch_bf16<32>(L, a, s); break;
-    default: st = launch_bf16<16>(L, a, s); break;
+  if (L.nw == 16) {
+    st = launch_bf16<16, 16>(L, a, s);
+  } else {
+    switch (L.br) {
+      case 64: st = launch_bf16<8, 64>(L, a, s); break;
+      case 32: st = launch_bf16<8, 32>(L, a, s); break;
+      default: st = launch_bf16<8, 16>(L, a, s); break;
+    }
   }
   if (st != BSRHT_OK) return st;
   if (L.splits > 1)

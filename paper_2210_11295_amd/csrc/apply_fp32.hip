@@ -2,15 +2,16 @@
 // eq. (2.3)-(2.4)) for row-major A (n x m).
 //
 // Structure.  H_r factors as H_{r/b} (x) H_b for the index split
-// x = x_hi*b + x_lo (Kronecker form of H, section 2).  A workgroup of 8 waves
-// owns 64 columns (lane = column) and streams chunks of b = 8*BR consecutive
-// rows (one chunk = one x_hi of one block i); wave w holds chunk rows
+// x = x_hi*b + x_lo (Kronecker form of H, section 2).  A workgroup of NW waves
+// (8, or 16 when l > 512 so that one thread serves each sample) owns 64
+// columns (lane = column) and streams chunks of b = NW*BR consecutive rows
+// (one chunk = one x_hi of one block i); wave w holds chunk rows
 // x_lo = w*BR + t, t in [0, BR), in registers.  For each chunk:
 //   1. load  : non-temporal buffer loads, one 256-byte row segment per
 //              wave instruction; the next chunk is already in flight;
 //   2. D^(i) : sign flips, wave-uniform per row (sign-bit xor);
 //   3. H_BR  : log2(BR) radix-2 stages over t, in registers;
-//   4. H_8   : one LDS exchange, 3 stages over w (rows t + BR*k);
+//   4. H_NW  : one LDS exchange, log2(NW) stages over w (rows t + BR*k);
 //              the chunk now holds H_b applied to each column;
 //   5. gather: lane = sample j; only the l sampled outputs are needed,
 //              (H_r v)[R_j] = sum_{x_hi} (-1)^popcount(R_j,hi & x_hi)
@@ -29,7 +30,6 @@
 namespace bsrht {
 namespace {
 
-constexpr int kNW = 8;          // waves per workgroup
 constexpr int kCT = 64;         // columns per workgroup (one per lane)
 constexpr int kLDT = kCT + 4;   // LDS row stride in floats (272 B, float4 aligned)
 constexpr int kBufDword3 = 0x00020000;  // raw buffer resource word 3 (gfx9 family)
@@ -111,17 +111,20 @@ __device__ __forceinline__ void apply_dsigns(float (&v)[BR], const uint32_t *__r
   }
 }
 
-template <int BR>
+template <int NW, int BR>
 struct FusedCta {
-  static constexpr int B = BR * kNW;
+  static constexpr int B = BR * NW;
   static constexpr int LOG2B = ilog2c(B);
-  static constexpr int G = BR / kNW;  // radix-8 groups per wave
-  static_assert(G >= 1, "need BR >= 8");
+  static constexpr int G = BR / NW;  // radix-NW groups per wave
+  static_assert(G >= 1, "need BR >= NW");
 
   float *T;
   const FusedArgs &a;
   int lane, w, j, pos, cpb_log2, voff, row_bytes;
   bool jok;
+  // R_j's chunk-index bits, kept in LDS rather than a register: registers
+  // are tightest in the gather, and a spill reload there (a vector-memory
+  // access) would wait for the whole prefetch of the next chunk.
   uint32_t rhi;
   int cur_block;
   uint32_t dtbit;
@@ -153,12 +156,12 @@ struct FusedCta {
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       float *Tg = T + (w * G + g) * kLDT + lane;
-      float v[kNW];
+      float v[NW];
 #pragma unroll
-      for (int k = 0; k < kNW; ++k) v[k] = Tg[k * BR * kLDT];
-      fwht_regs<kNW>(v);
+      for (int k = 0; k < NW; ++k) v[k] = Tg[k * BR * kLDT];
+      fwht_regs<NW>(v);
 #pragma unroll
-      for (int k = 0; k < kNW; ++k) Tg[k * BR * kLDT] = v[k];
+      for (int k = 0; k < NW; ++k) Tg[k * BR * kLDT] = v[k];
     }
     __syncthreads();
     if (jok) {
@@ -184,10 +187,11 @@ struct FusedCta {
   }
 };
 
-template <int BR>
-__global__ __launch_bounds__(kNW * 64) void fused_fp32_kernel(FusedArgs a) {
-  using Cta = FusedCta<BR>;
+template <int NW, int BR>
+__global__ __launch_bounds__(NW * 64) void fused_fp32_kernel(FusedArgs a) {
+  using Cta = FusedCta<NW, BR>;
   __shared__ __attribute__((aligned(16))) float T[Cta::B * kLDT];
+  __shared__ uint32_t Rhi[NW * 64];
   Cta cta(T, a);
   const int tid = threadIdx.x;
   cta.lane = tid & 63;
@@ -200,7 +204,7 @@ __global__ __launch_bounds__(kNW * 64) void fused_fp32_kernel(FusedArgs a) {
   cta.wavebase = a.A + c0 + (int64_t)(cta.w * BR) * a.lda;
   const int q0 = blockIdx.y * a.chunks_per_split;
   const int q1 = min(q0 + a.chunks_per_split, a.total_chunks);
-  cta.j = blockIdx.z * (kNW * 64) + tid;
+  cta.j = blockIdx.z * (NW * 64) + tid;
   cta.jok = cta.j < a.l;
   const int rj = cta.jok ? a.R[cta.j] : 0;
   cta.pos = rj & (Cta::B - 1);
@@ -272,28 +276,37 @@ __global__ void direct_kernel(const float *__restrict__ A, int64_t lda, int m,
 
 struct Launch {
   bool direct = false;
-  int br = 0, b = 0;
+  int nw = 8, br = 0, b = 0;
   int ctiles = 0, groups = 0, splits = 1, cps = 0, total_chunks = 0;
   size_t ws = 0;
 };
 
 Launch choose_launch(const bsrht_plan_s *pl, int64_t m, int64_t lda) {
   Launch L;
-  // Largest chunk b = 8*BR <= r with 8 <= BR <= 64.
   (void)lda;
-  int br = 64;
-  while (br >= 8 && (int64_t)br * kNW > pl->r) br >>= 1;
-  if (br < 8) {
-    L.direct = true;
-    return L;
+  int per_cu;
+  if (pl->l > 512 && pl->r >= 256) {
+    // 16 waves, one thread per sample for l <= 1024: A is read once per
+    // 1024 samples instead of once per 512; chunks of b = 16*16 rows.
+    L.nw = 16;
+    L.br = 16;
+    per_cu = 1;  // 1024 threads at ~100 VGPRs fill the register file
+  } else {
+    // Largest chunk b = 8*BR <= r with 8 <= BR <= 64.
+    int br = 64;
+    while (br >= 8 && (int64_t)br * 8 > pl->r) br >>= 1;
+    if (br < 8) {
+      L.direct = true;
+      return L;
+    }
+    L.nw = 8;
+    L.br = br;
+    per_cu = br * 8 * kLDT * 4 > 80 * 1024 ? 1 : 2;
   }
-  L.br = br;
-  L.b = br * kNW;
-  const int lds_bytes = L.b * kLDT * 4;
-  const int per_cu = lds_bytes > 80 * 1024 ? 1 : 2;
+  L.b = L.br * L.nw;
   L.total_chunks = (int)(pl->n / L.b);
   L.ctiles = (int)((m + kCT - 1) / kCT);
-  const int spp = kNW * 64;
+  const int spp = L.nw * 64;
   L.groups = (int)((pl->l + spp - 1) / spp);
   const int64_t target = (int64_t)device_cu_count() * per_cu;
   int64_t splits = target / ((int64_t)L.ctiles * L.groups);
@@ -305,11 +318,11 @@ Launch choose_launch(const bsrht_plan_s *pl, int64_t m, int64_t lda) {
   return L;
 }
 
-template <int BR>
+template <int NW, int BR>
 int launch_fused(const Launch &L, FusedArgs &a, hipStream_t s) {
   dim3 grid((unsigned)L.ctiles, (unsigned)L.splits, (unsigned)L.groups);
   const int tslot = timing_begin(BSRHT_TIMING_APPLY_FP32, s);
-  fused_fp32_kernel<BR><<<grid, kNW * 64, 0, s>>>(a);
+  fused_fp32_kernel<NW, BR><<<grid, NW * 64, 0, s>>>(a);
   timing_end(tslot, s);
   BSRHT_LAUNCH_CHECK();
   return BSRHT_OK;
@@ -379,11 +392,15 @@ int apply_fp32(const bsrht_plan_s *pl, const float *A, int64_t m, int64_t lda, f
     a.scale = scale;
   }
   int st;
-  switch (L.br) {
-    case 64: st = launch_fused<64>(L, a, s); break;
-    case 32: st = launch_fused<32>(L, a, s); break;
-    case 16: st = launch_fused<16>(L, a, s); break;
-    default: st = launch_fused<8>(L, a, s); break;
+  if (L.nw == 16) {
+    st = launch_fused<16, 16>(L, a, s);
+  } else {
+    switch (L.br) {
+      case 64: st = launch_fused<8, 64>(L, a, s); break;
+      case 32: st = launch_fused<8, 32>(L, a, s); break;
+      case 16: st = launch_fused<8, 16>(L, a, s); break;
+      default: st = launch_fused<8, 8>(L, a, s); break;
+    }
   }
   if (st != BSRHT_OK) return st;
   if (L.splits > 1)

@@ -73,8 +73,8 @@ SKETCH_CASES = [
     (4096, 4, 128, 256, 0),       # the small RSVD workload's shape
     (4096, 4, 128, 100, 0),       # ragged column tile
     (8192, 8, 300, 65, 0),        # r = 1024, l not a multiple of 64
-    (16384, 1, 513, 33, 0),       # r = 2^14, two sample groups
-    (2048, 8, 1100, 7, 0),        # r = 256 < l: three sample groups
+    (16384, 1, 513, 33, 0),       # r = 2^14, l = 513: 16-wave kernel
+    (2048, 8, 1100, 7, 0),        # r = 256 < l: 16-wave kernel, two sample groups
     (1024, 8, 200, 64, 0),        # r = 128 (chunk 128)
     (1024, 16, 77, 130, 0),       # r = 64 (smallest fused chunk)
     (512, 16, 40, 5, 0),          # r = 32: direct kernel

@@ -38,8 +38,8 @@ CASES = [
     (4096, 4, 128, 256, 0),       # r = 1024, chunk 512
     (4096, 4, 128, 100, 0),       # ragged column tile (100 = 64 + 36)
     (8192, 8, 300, 65, 0),        # one column past a tile
-    (16384, 1, 513, 33, 0),       # r = 2^14, two sample groups, only a ragged tile
-    (2048, 8, 1100, 7, 0),        # r = 256 (chunk 256) < l: three sample groups
+    (16384, 1, 513, 33, 0),       # r = 2^14, l = 513: 16-wave kernel, only a ragged tile
+    (2048, 8, 1100, 7, 0),        # r = 256 < l: 16-wave kernel, two sample groups
     (1024, 8, 200, 64, 0),        # r = 128 (chunk 128)
     (1 << 16, 1, 512, 130, 0),    # r = 2^16 as one block, ragged
     (4096, 2, 1024, 31, 1),       # without replacement
