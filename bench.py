@@ -313,6 +313,23 @@ def bench_nystrom(bs, reps):
     dt = (time.perf_counter() - t0) / reps
     kms, kl = bs.timing_read()
     bs.timing_enable(bs.TIMING_OFF)
+    # the sketch of A alone (16 GiB) in both precisions: GB/s of A
+    apply = {}
+    for name, prec, hook in (("fp32", bs.FP32, bs.TIMING_APPLY_FP32),
+                             ("split_bf16", bs.SPLIT_BF16, bs.TIMING_APPLY_BF16)):
+        pl = bs.Plan(n, p, l, c["seed"], precision=prec, device=dev)
+        W = torch.empty(l, n, dtype=torch.float32, device=dev)
+        aws = torch.empty(max(1, bs.bsrht_apply_workspace(pl, n)), dtype=torch.uint8, device=dev)
+        bs.bsrht_apply(pl, A, W, aws)
+        torch.cuda.synchronize()
+        bs.timing_enable(hook)
+        for _ in range(3):
+            bs.bsrht_apply(pl, A, W, aws)
+        torch.cuda.synchronize()
+        ams, al = bs.timing_read()
+        bs.timing_enable(bs.TIMING_OFF)
+        apply[f"apply_{name}_GBs"] = round(n * n * 4 / (ams / al * 1e-3) / 1e9, 1)
+        del W, aws
     # trace error via the structure: A - U diag(lam) U^T lies in span[X, U]
     B, _ = torch.linalg.qr(torch.cat([X, U.double()], dim=1))
     XtB = X.T @ B
@@ -322,7 +339,7 @@ def bench_nystrom(bs, reps):
     err = float(ev.abs().sum() / s.sum())
     opt = float(s[k:].sum() / s.sum())
     return {"ms": round(dt * 1e3, 2), "n": n, "l": l, "k": k, "p": p,
-            "sketch_kernel_ms_per_call": round(kms / max(reps, 1), 3),
+            "sketch_kernel_ms_per_call": round(kms / max(reps, 1), 3), **apply,
             "trace_rel_error": err, "optimal_trace_rel_error": opt,
             "info": int(info.item())}
 

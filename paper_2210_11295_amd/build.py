@@ -26,10 +26,19 @@ COMMON_FLAGS = [
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 
+# Per-file device code generation options.  The dense kernels keep MFMA
+# accumulators in ordinary VGPRs: with AGPR accumulators the FP64 GEMM copies
+# all of them between the two register files on every k tile and needs more
+# than 256 registers, which leaves one wave per SIMD.
+FILE_FLAGS = {
+    "dense.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+}
+
 
 def _compile(src, obj_dir):
     obj = os.path.join(obj_dir, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + COMMON_FLAGS + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + COMMON_FLAGS + FILE_FLAGS.get(os.path.basename(src), []) + [
+        "-c", src, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{res.stdout}\n{res.stderr}")

@@ -18,6 +18,7 @@ struct GemmDesc {
   double alpha = 1.0, beta = 0.0;
   int splits = 1;
   int64_t split_stride = 0;
+  bool upper_tiles = false;  // compute only workgroup tiles on or above the diagonal
 };
 
 int gemm_f32(const GemmDesc &d, const float *A, const float *B, float *C, hipStream_t s);

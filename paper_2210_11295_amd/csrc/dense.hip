@@ -167,16 +167,20 @@ __global__ __launch_bounds__(kBThreads) void gemm_big_kernel(GemmDesc d, const T
                                                              const TB *__restrict__ B,
                                                              TC *__restrict__ C) {
   using TS = typename std::conditional<F64, double, float>::type;
-  __shared__ __attribute__((aligned(16))) TS As[2][kBK][kBM + kBPad];
-  __shared__ __attribute__((aligned(16))) TS Bs[2][kBK][kBN + kBPad];
+  constexpr int KT = kBK;
+  constexpr int NV = KT / 8;  // 4-element vectors per thread per operand and tile
+  __shared__ __attribute__((aligned(16))) TS As[2][KT][kBM + kBPad];
+  __shared__ __attribute__((aligned(16))) TS Bs[2][KT][kBN + kBPad];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
+  if (d.upper_tiles && blockIdx.x > blockIdx.y) return;  // mirrored by the caller
   const int64_t i0 = (int64_t)blockIdx.x * kBM, j0 = (int64_t)blockIdx.y * kBN;
   int64_t kchunk = (d.K + gridDim.z - 1) / gridDim.z;
-  kchunk = (kchunk + kBK - 1) / kBK * kBK;
+  kchunk = (kchunk + KT - 1) / KT * KT;
   const int64_t kb = (int64_t)blockIdx.z * kchunk;
   const int64_t ke = min(d.K, kb + kchunk);
   const int wi = (wave >> 1) * 64, wj = (wave & 1) * 64;
+  const bool ij_inside = i0 + kBM <= d.M && j0 + kBN <= d.N;
   using Acc = typename std::conditional<F64, double __attribute__((ext_vector_type(4))),
                                         float __attribute__((ext_vector_type(4)))>::type;
   Acc acc[4][4];
@@ -185,66 +189,70 @@ __global__ __launch_bounds__(kBThreads) void gemm_big_kernel(GemmDesc d, const T
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = Acc{0, 0, 0, 0};
 
-  // Each thread moves two 4-element vectors of A and two of B per k tile.
-  Vec4<TS> ra[2], rb[2];
+  // Each thread moves NV 4-element vectors of A and NV of B per k tile.  They
+  // stay in the storage type until staged: a conversion right after the load
+  // would make the load wait at once instead of overlapping the MFMAs.
+  Vec4<TA> ra[NV];
+  Vec4<TB> rb[NV];
+  auto a_pos = [&](int v, int64_t k0, int64_t &gi, int64_t &gk) {
+    if constexpr (AK) {  // 128 rows x KT/4 vectors of k
+      gi = i0 + v / (KT / 4);
+      gk = k0 + 4 * (v % (KT / 4));
+    } else {             // KT k rows x 32 vectors of i
+      gk = k0 + (v >> 5);
+      gi = i0 + 4 * (v & 31);
+    }
+  };
   auto fetch = [&](int64_t k0) {
+    if (ij_inside && k0 + KT <= ke) {  // whole tile in range (uniform branch)
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int v = tid + h * kBThreads;  // 0..511
+      for (int h = 0; h < NV; ++h) {
+        const int v = tid + h * kBThreads;
+        int64_t gi, gk;
+        a_pos(v, k0, gi, gk);
+        ra[h] = load4<TA>(A + gi * d.sai + gk * d.sak);
+        rb[h] = load4<TB>(B + (k0 + (v >> 5)) * d.sbk + j0 + 4 * (v & 31));
+      }
+      return;
+    }
+#pragma unroll
+    for (int h = 0; h < NV; ++h) {
+      const int v = tid + h * kBThreads;
       int64_t gi, gk;
-      if constexpr (AK) {  // 128 rows x 4 vectors of k
-        gi = i0 + (v >> 2);
-        gk = k0 + 4 * (v & 3);
-      } else {             // 16 k rows x 32 vectors of i
-        gk = k0 + (v >> 5);
-        gi = i0 + 4 * (v & 31);
-      }
+      a_pos(v, k0, gi, gk);
       const TA *src = A + gi * d.sai + gk * d.sak;
-      const bool full = AK ? (gi < d.M && gk + 3 < ke) : (gk < ke && gi + 3 < d.M);
-      if (full) {
-        const Vec4<TA> t = load4<TA>(src);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) ra[h].v[e] = (TS)t.v[e];
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const bool in = AK ? (gi < d.M && gk + e < ke) : (gk < ke && gi + e < d.M);
-          ra[h].v[e] = in ? (TS)src[AK ? e : e * d.sai] : (TS)0;
-        }
+      for (int e = 0; e < 4; ++e) {
+        const bool in = AK ? (gi < d.M && gk + e < ke) : (gk < ke && gi + e < d.M);
+        ra[h].v[e] = in ? src[AK ? e : e * d.sai] : (TA)0;
       }
-      // B: 16 k rows x 32 vectors of j
+      // B: KT k rows x 32 vectors of j
       const int64_t bk = k0 + (v >> 5), bj = j0 + 4 * (v & 31);
       const TB *bsrc = B + bk * d.sbk + bj;
-      if (bk < ke && bj + 3 < d.N) {
-        const Vec4<TB> t = load4<TB>(bsrc);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) rb[h].v[e] = (TS)t.v[e];
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) rb[h].v[e] = (bk < ke && bj + e < d.N) ? (TS)bsrc[e] : (TS)0;
-      }
+      for (int e = 0; e < 4; ++e) rb[h].v[e] = (bk < ke && bj + e < d.N) ? bsrc[e] : (TB)0;
     }
   };
   auto stage = [&](int buf) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NV; ++h) {
       const int v = tid + h * kBThreads;
       if constexpr (AK) {
-        const int ii = v >> 2, kk = 4 * (v & 3);
+        const int ii = v / (KT / 4), kk = 4 * (v % (KT / 4));
 #pragma unroll
-        for (int e = 0; e < 4; ++e) As[buf][kk + e][ii] = ra[h].v[e];
+        for (int e = 0; e < 4; ++e) As[buf][kk + e][ii] = (TS)ra[h].v[e];
       } else {
         const int kk = v >> 5, ii = 4 * (v & 31);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) As[buf][kk][ii + e] = ra[h].v[e];
+        for (int e = 0; e < 4; ++e) As[buf][kk][ii + e] = (TS)ra[h].v[e];
       }
       const int kk = v >> 5, jj = 4 * (v & 31);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) Bs[buf][kk][jj + e] = rb[h].v[e];
+      for (int e = 0; e < 4; ++e) Bs[buf][kk][jj + e] = (TS)rb[h].v[e];
     }
   };
 
-  const int64_t ntiles = (ke - kb + kBK - 1) / kBK;
+  const int64_t ntiles = (ke - kb + KT - 1) / KT;
   if (ntiles > 0) {
     fetch(kb);
     stage(0);
@@ -253,9 +261,9 @@ __global__ __launch_bounds__(kBThreads) void gemm_big_kernel(GemmDesc d, const T
   for (int64_t t = 0; t < ntiles; ++t) {
     const int cur = (int)(t & 1);
     const bool more = t + 1 < ntiles;
-    if (more) fetch(kb + (t + 1) * kBK);
+    if (more) fetch(kb + (t + 1) * KT);
 #pragma unroll
-    for (int ks = 0; ks < kBK; ks += 4) {
+    for (int ks = 0; ks < KT; ks += 4) {
       const int kk = ks + (lane >> 4);
       TS av[4], bv[4];
 #pragma unroll
@@ -295,29 +303,47 @@ __global__ __launch_bounds__(kBThreads) void gemm_big_kernel(GemmDesc d, const T
       }
 }
 
-// Sum of split-K partials in split order: C[i][j] = sum_s P[s][i][j].
+// Sum of split-K partials in split order: C[i][j] = sum_s P[s][i][j].  With
+// `mirror` (a symmetric product computed on upper tiles only) an element of a
+// skipped tile below the diagonal takes its transposed partner.
 template <typename TC>
 __global__ void reduce_partials_kernel(const double *__restrict__ P, int splits, int64_t M,
-                                       int64_t N, TC *__restrict__ C, int64_t ldc) {
+                                       int64_t N, TC *__restrict__ C, int64_t ldc, bool mirror) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= M * N) return;
   const int64_t i = idx / N, j = idx - i * N;
+  const int64_t src = (mirror && i / kBM > j / kBN) ? j * N + i : idx;
   double s = 0.0;
-  for (int sp = 0; sp < splits; ++sp) s += P[(int64_t)sp * M * N + idx];
+  for (int sp = 0; sp < splits; ++sp) s += P[(int64_t)sp * M * N + src];
   C[i * ldc + j] = (TC)s;
+}
+
+// C[i][j] = C[j][i] for the elements of tiles below the diagonal.
+__global__ void mirror_tiles_kernel(double *__restrict__ C, int64_t n, int64_t ldc) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int64_t i = idx / n, j = idx - i * n;
+  if (i / kBM > j / kBN) C[i * ldc + j] = C[j * ldc + i];
 }
 
 }  // namespace
 
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 
-template <typename TA, typename TB, typename TC, bool F64>
-static int gemm_launch(const GemmDesc &d, const TA *A, const TB *B, TC *C, hipStream_t s) {
-  if (d.M <= 0 || d.N <= 0) return BSRHT_OK;
+// Whether gemm_launch takes the large-tile kernel for these operands.
+template <typename TA, typename TB>
+static bool gemm_big_eligible(const GemmDesc &d, const TA *A, const TB *B) {
   const bool b_ok = d.sbj == 1 && d.sbk % 4 == 0 && aligned16(B);
   const bool a_k = d.sak == 1 && d.sai % 4 == 0;
   const bool a_i = d.sai == 1 && d.sak % 4 == 0;
-  if (b_ok && (a_k || a_i) && aligned16(A) && d.M >= 64 && d.N >= 64) {
+  return b_ok && (a_k || a_i) && aligned16(A) && d.M >= 64 && d.N >= 64;
+}
+
+template <typename TA, typename TB, typename TC, bool F64>
+static int gemm_launch(const GemmDesc &d, const TA *A, const TB *B, TC *C, hipStream_t s) {
+  if (d.M <= 0 || d.N <= 0) return BSRHT_OK;
+  const bool a_k = d.sak == 1 && d.sai % 4 == 0;
+  if (gemm_big_eligible(d, A, B)) {
     dim3 grid((unsigned)((d.M + kBM - 1) / kBM), (unsigned)((d.N + kBN - 1) / kBN),
               (unsigned)d.splits);
     if (a_k)
@@ -368,20 +394,27 @@ static int gram_impl(const TX *X, int64_t n, int64_t K, int64_t sr, int64_t sc, 
   d.sbj = sc;
   d.alpha = 1.0;
   d.beta = 0.0;
+  // G is symmetric: when the large-tile kernel runs, only its tiles on or
+  // above the diagonal are computed and the rest is mirrored.
+  d.upper_tiles = gemm_big_eligible(d, X, X);
+  const int64_t total = K * K;
   if (splits <= 1) {
     d.splits = 1;
     d.ldc = ldg;
     d.split_stride = 0;
-    return gemm_launch<TX, TX, double, true>(d, X, X, G, s);
+    int st = gemm_launch<TX, TX, double, true>(d, X, X, G, s);
+    if (st != BSRHT_OK || !d.upper_tiles) return st;
+    mirror_tiles_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(G, K, ldg);
+    BSRHT_LAUNCH_CHECK();
+    return BSRHT_OK;
   }
   d.splits = splits;
   d.ldc = K;
   d.split_stride = K * K;
   int st = gemm_launch<TX, TX, double, true>(d, X, X, partials, s);
   if (st != BSRHT_OK) return st;
-  const int64_t total = K * K;
   reduce_partials_kernel<double><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(
-      partials, splits, K, K, G, ldg);
+      partials, splits, K, K, G, ldg, d.upper_tiles);
   BSRHT_LAUNCH_CHECK();
   return BSRHT_OK;
 }
@@ -405,10 +438,13 @@ int64_t gram_partial_elems(int64_t n, int64_t Kmax) {
 }
 
 int gram_splits(int64_t n, int64_t K) {
-  // enough workgroups to fill the chip; each split spans at least 1024 rows
-  const int64_t tiles = ((K + kBM - 1) / kBM) * ((K + kBN - 1) / kBN);
-  int64_t want = (2 * (int64_t)device_cu_count() + tiles - 1) / tiles;
-  int64_t maxs = (n + 1023) / 1024;
+  // at most two workgroups per CU (the FP64 kernel's occupancy) over the tiles
+  // on or above the diagonal, so that all of them run in one round; each split
+  // spans at least 1024 rows
+  const int64_t nt = (K + kBM - 1) / kBM;
+  const int64_t tiles = nt * (nt + 1) / 2;
+  int64_t want = 2 * (int64_t)device_cu_count() / tiles;
+  const int64_t maxs = (n + 1023) / 1024;
   if (want > maxs) want = maxs;
   if (want < 1) want = 1;
   if (want > 256) want = 256;
