@@ -69,13 +69,13 @@ int fill_f64(double *p, int64_t count, double value, hipStream_t s);
 int jacobi_svd(double *X, int64_t nr, int64_t nc, int64_t ldx, double *V, double *S,
                double *Us, int64_t ldu, int32_t *perm, unsigned int *flags, int max_sweeps,
                int32_t *info, hipStream_t s);
-// The same with the block width W and rows per lane KR forced (64 KR must
-// cover the rows held in LDS); (W, KR) in {(16,8), (8,8), (8,16), (4,8),
-// (4,16), (4,32), (2,64)}, or W = 0 to pick them from the row count as
-// jacobi_svd does.
+// The same with the form of the block step forced: 1 = 16-column block pairs
+// staged in LDS (at most 1024 rows, and V of at most 1024 rows), 2 =
+// 32-column block pairs streamed from global memory (any row count), or 0 to
+// pick as jacobi_svd does (1 when it applies).
 int jacobi_svd_shape(double *X, int64_t nr, int64_t nc, int64_t ldx, double *V, double *S,
                      double *Us, int64_t ldu, int32_t *perm, unsigned int *flags, int max_sweeps,
-                     int32_t *info, int W, int KR, hipStream_t s);
+                     int32_t *info, int form, hipStream_t s);
 
 int transpose_f32_f64(const float *src, int64_t rows, int64_t cols, int64_t lds, double *dst,
                       int64_t ldd, hipStream_t s);

@@ -598,12 +598,12 @@ __global__ __launch_bounds__(64 * kTrinvWaves) void trinv_upper_kernel(
 // decomposition, which callers that scale by 1/sqrt(lambda_j) need.
 //
 // Blocking: the columns form nc/W blocks of W.  One launch is one round of a
-// round-robin over block pairs; a workgroup copies its pair (2W columns) into
-// LDS and runs one full cyclic sweep over the 2W(2W-1)/2 column pairs there
-// (W disjoint pairs at a time, one wave per pair), recording the
-// rotations in a 2W x 2W matrix J; it then writes the columns back and, when
-// accumulating, updates V's 2W columns as V J.  A sweep is nc/W - 1 launches;
-// sweeps repeat until one performs no rotation.
+// round-robin over block pairs; a workgroup forms the Gram matrix of its pair
+// (2W columns), runs one cyclic sweep over the 2W(2W-1)/2 column pairs on it
+// (W disjoint pairs at a time), recording the rotations in a 2W x 2W matrix
+// J, and then updates the pair's columns of X (and, when accumulating, of V)
+// as X J.  A sweep is nc/W - 1 launches; sweeps repeat until one performs no
+// rotation.
 struct JacobiBlockArgs {
   double *X;
   int nr;
@@ -618,32 +618,6 @@ struct JacobiBlockArgs {
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// One 32-bit DPP lane permutation applied to both halves of a double.
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double x) {
-  const uint64_t b = __builtin_bit_cast(uint64_t, x);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF,
-                                                            true);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL,
-                                                            0xF, 0xF, true);
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
-// Wave-wide sum, identical in every lane: each level adds a value and its
-// partner's with the operands swapped between the two lanes, which IEEE
-// addition makes bitwise equal.  The first four levels stay inside a row of
-// 16 lanes (DPP: quad permutations, half-row and row mirrors); the last two
-// cross rows.
-__device__ __forceinline__ double wave_sum_fast(double v) {
-  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp_f64<0x141>(v);  // row_half_mirror
-  v += dpp_f64<0x140>(v);  // row_mirror
-  v += __shfl_xor(v, 16, 64);
-  v += __shfl_xor(v, 32, 64);
   return v;
 }
 
@@ -664,126 +638,505 @@ __device__ __forceinline__ void rr_pair(int nc, int r, int p, int &a, int &b) {
   }
 }
 
-// L[c * ldl + i] = src[gcol(c) * lds + i] for the flattened index
-// e = c * rows + i < total; eight loads per thread are in flight at once.
-template <int NT, class GCol>
-__device__ __forceinline__ void copy_in(double *L, int ldl, const double *__restrict__ src,
-                                        int64_t lds, int rows, int total, const GCol &gcol) {
-  for (int e0 = threadIdx.x; e0 < total; e0 += 8 * NT) {
-    double v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = e0 + u * NT;
-      if (e < total) {
-        const int c = e / rows, i = e - c * rows;
-        v[u] = src[gcol(c) * lds + i];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = e0 + u * NT;
-      if (e < total) {
-        const int c = e / rows, i = e - c * rows;
-        L[c * ldl + i] = v[u];
-      }
-    }
-  }
-}
+// Block width of the Gram form (block pairs of 2W columns).
+constexpr int kJacobiGramW = 16;
 
-template <int W, int KR>
-__global__ __launch_bounds__(64 * W) void jacobi_block_kernel(JacobiBlockArgs ja) {
-  constexpr int C = 2 * W;            // columns of a block pair
-  constexpr int NRMAX = 64 * KR;      // rows held (KR per lane)
-  constexpr int LDL = NRMAX + 2;      // LDS column stride (breaks bank aliasing)
-  constexpr int NT = 64 * W;          // one wave per column pair of a round
-  __shared__ double L[C * LDL];
-  __shared__ double J[C * C];         // column-major: J[c * C + k]
+// Gram form of the block step, for any row count.  The workgroup forms the
+// 2W x 2W Gram matrix G = X_p^T X_p of its column pair on FP64 matrix cores,
+// runs the cyclic sweep of 2x2 rotations on G itself (a rotation's decision
+// and angle use the same three entries -- two squared norms and an inner
+// product -- that the column form computes from the columns; after it G is
+// updated as J^T G J instead of being recomputed), and applies the
+// accumulated rotation to the 2W columns of X (and of V) as one matrix
+// product.  Every launch starts from a freshly formed G, so a sweep without
+// rotations has tested the inner products of the columns themselves.
+template <int W>
+__global__ __launch_bounds__(256) void jacobi_gram_kernel(JacobiBlockArgs ja) {
+  constexpr int C = 2 * W;                // columns of a block pair
+  static_assert(C == 16 || C == 32, "block pairs of 16 or 32 columns");
+  constexpr int NB = C / 16;              // 16-column blocks of the MFMA tiles
+  constexpr int NUP = NB * (NB + 1) / 2;  // Gram tiles on or above the diagonal
+  constexpr int NT = 256;
+  constexpr int LG = C + 1;               // LDS row stride of G and J
+  constexpr int U = 8;                    // 4-row steps per batch of loads
+  using D4 = double __attribute__((ext_vector_type(4)));
+  __shared__ double Gs[2][C * LG];
+  __shared__ double Js[2][C * LG];
+  __shared__ double part[4][NUP][256];
+  __shared__ double cself[C], cpart[C], dg[C];
+  __shared__ int pidx[C], rotc[C];
   const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int lr = lane >> 4, lc = lane & 15;
   const int nr = ja.nr;
   int ba, bb;
   rr_pair(ja.nblocks, ja.round, (int)blockIdx.x, ba, bb);
   auto gcol = [&](int c) -> int64_t { return c < W ? (int64_t)ba * W + c : (int64_t)bb * W + (c - W); };
-  // Copies run over the flattened (column, row) index in batches of 8 loads
-  // per thread, issued before any of them is waited for.
-  const int total = C * nr;
-  copy_in<NT>(L, LDL, ja.X, ja.ldx, nr, total, gcol);
-  if (ja.V)
-    for (int e = tid; e < C * C; e += NT) J[e] = (e / C == e % C) ? 1.0 : 0.0;
+
+  // 1. G = X_p^T X_p.  A 16x16x4 MFMA takes A[i][k] = X_p[r + k][16 bi + i]
+  // and B[k][j] = X_p[r + k][16 bj + j]: lane (k = lane / 16, i = j = lane % 16)
+  // supplies the same element to both.  Wave w sums a contiguous quarter of
+  // the 4-row steps; the quarters are added in wave order.
+  {
+    const double *xcol[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) xcol[b] = ja.X + gcol(16 * b + lc) * ja.ldx;
+    D4 acc[NUP];
+#pragma unroll
+    for (int u = 0; u < NUP; ++u) acc[u] = D4{0, 0, 0, 0};
+    const int nsteps = (nr + 3) >> 2;
+    const int per = (nsteps + 3) >> 2;
+    const int s_beg = wave * per, s_end = min(nsteps, s_beg + per);
+    for (int s0 = s_beg; s0 < s_end; s0 += U) {
+      double x[U][NB];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int row = 4 * (s0 + u) + lr;
+        const bool in = s0 + u < s_end && row < nr;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) x[u][b] = in ? xcol[b][row] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        int t = 0;
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+          for (int bj = bi; bj < NB; ++bj, ++t)
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u][bi], x[u][bj], acc[t], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NUP; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) part[wave][u][v * 64 + lane] = acc[u][v];
+  }
+  for (int e = tid; e < C * LG; e += NT) Js[0][e] = (e / LG == e % LG) ? 1.0 : 0.0;
   __syncthreads();
-  const int team = tid >> 6, lt = tid & 63;
+  for (int e = tid; e < NUP * 256; e += NT) {
+    const int u = e >> 8, r = e & 255, v = r >> 6, ln = r & 63;
+    int bi = 0, bj = 0, t = 0;
+    for (int a = 0; a < NB; ++a)
+      for (int b = a; b < NB; ++b, ++t)
+        if (t == u) { bi = a; bj = b; }
+    const int i = 16 * bi + (ln >> 4) + 4 * v, j = 16 * bj + (ln & 15);
+    if (bi == bj && i > j) continue;  // the diagonal tiles' upper halves are mirrored
+    const double s = ((part[0][u][r] + part[1][u][r]) + part[2][u][r]) + part[3][u][r];
+    Gs[0][i * LG + j] = s;
+    Gs[0][j * LG + i] = s;
+  }
+  __syncthreads();
+
+  // 2. One cyclic sweep over the 2W(2W-1)/2 pairs on G, W disjoint pairs per
+  // round, accumulating J.
   const double floor2 = *ja.floor2;
   bool any = false;
+  int cur = 0;
   for (int ir = 0; ir < C - 1; ++ir) {
-    int ca, cb;
-    rr_pair(C, ir, team, ca, cb);
-    double *xa = L + ca * LDL, *xb = L + cb * LDL;
-    // the pair's rows of this lane, read once and kept for the rotation
-    double u[KR], v[KR];
-#pragma unroll
-    for (int q = 0; q < KR; ++q) {
-      const int i = lt + 64 * q;
-      u[q] = i < nr ? xa[i] : 0.0;
-      v[q] = i < nr ? xb[i] : 0.0;
-    }
-    double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll
-    for (int q = 0; q < KR; ++q) {
-      al += u[q] * u[q];
-      be += v[q] * v[q];
-      ga += u[q] * v[q];
-    }
-    al = wave_sum_fast(al);
-    be = wave_sum_fast(be);
-    ga = wave_sum_fast(ga);
-    // A column whose norm is at the rounding level of the whole matrix has no
-    // relative accuracy left, so its orthogonality cannot improve: such pairs
-    // count as converged (otherwise a rank-deficient input never converges).
-    if (fabs(ga) > ja.tol * sqrt(al * be) && ga != 0.0 && fmin(al, be) > floor2) {
-      // rotation zeroing the (a, b) entry of the 2x2 Gram [al ga; ga be]
-      const double zeta = (be - al) / (2.0 * ga);
-      const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-      const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-#pragma unroll
-      for (int q = 0; q < KR; ++q) {
-        const int i = lt + 64 * q;
-        if (i < nr) {
-          xa[i] = c * u[q] - sn * v[q];
-          xb[i] = sn * u[q] + c * v[q];
-        }
+    if (tid < C / 2) {
+      int a, b;
+      rr_pair(C, ir, tid, a, b);
+      const double *G = Gs[cur];
+      const double al = G[a * LG + a], be = G[b * LG + b], ga = G[a * LG + b];
+      double c = 1.0, sn = 0.0, t = 0.0;
+      bool rot = false;
+      // A column whose norm is at the rounding level of the whole matrix has
+      // no relative accuracy left, so its orthogonality cannot improve: such
+      // pairs count as converged (otherwise a rank-deficient input never
+      // converges).
+      if (fabs(ga) > ja.tol * sqrt(al * be) && ga != 0.0 && fmin(al, be) > floor2) {
+        // rotation zeroing the (a, b) entry of the 2x2 Gram [al ga; ga be]
+        const double zeta = (be - al) / (2.0 * ga);
+        t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        c = 1.0 / sqrt(1.0 + t * t);
+        sn = c * t;
+        rot = true;
       }
-      if (ja.V) {
-        double *Ja = J + ca * C, *Jb = J + cb * C;
-        for (int i = lt; i < C; i += 64) {
-          const double u = Ja[i], v = Jb[i];
-          Ja[i] = c * u - sn * v;
-          Jb[i] = sn * u + c * v;
-        }
-      }
-      any = true;
+      // column a of the rotation is c e_a - sn e_b, column b is sn e_a + c e_b
+      pidx[a] = b;
+      pidx[b] = a;
+      cself[a] = c;
+      cpart[a] = -sn;
+      cself[b] = c;
+      cpart[b] = sn;
+      dg[a] = -t * ga;  // the new diagonal: al - t ga and be + t ga
+      dg[b] = t * ga;
+      rotc[a] = rot;
+      rotc[b] = rot;
+      any |= rot;
     }
     __syncthreads();
-  }
-  for (int e = tid; e < total; e += NT) {
-    const int c = e / nr, i = e - c * nr;
-    ja.X[gcol(c) * ja.ldx + i] = L[c * LDL + i];
+    const double *G = Gs[cur];
+    const double *J = Js[cur];
+    double *G2 = Gs[cur ^ 1];
+    double *J2 = Js[cur ^ 1];
+    for (int e = tid; e < C * C; e += NT) {
+      const int i = e / C, j = e - (e / C) * C;
+      const int pi = pidx[i], pj = pidx[j];
+      if (i <= j) {
+        double g;
+        if (rotc[i] && j == i)
+          g = G[i * LG + i] + dg[i];
+        else if (rotc[i] && j == pi)
+          g = 0.0;
+        else
+          g = cself[i] * (cself[j] * G[i * LG + j] + cpart[j] * G[i * LG + pj]) +
+              cpart[i] * (cself[j] * G[pi * LG + j] + cpart[j] * G[pi * LG + pj]);
+        G2[i * LG + j] = g;
+        G2[j * LG + i] = g;
+      }
+      J2[i * LG + j] = cself[j] * J[i * LG + j] + cpart[j] * J[i * LG + pj];
+    }
+    __syncthreads();
+    cur ^= 1;
   }
   const bool rotated = __syncthreads_or(any);
-  if (ja.V && rotated) {
-    // V's block-pair columns <- (those columns) J, staged through LDS
-    // (nc <= NRMAX is guaranteed by the host's choice of W)
-    copy_in<NT>(L, LDL, ja.V, ja.nc, ja.nc, C * ja.nc, gcol);
-    __syncthreads();
-    for (int c = 0; c < C; ++c) {
-      const double *Jc = J + c * C;
-      double *dst = ja.V + gcol(c) * ja.nc;
-      for (int i = tid; i < ja.nc; i += NT) {
-        double acc = 0.0;
-        for (int k = 0; k < C; ++k) acc += L[k * LDL + i] * Jc[k];
-        dst[i] = acc;
+  if (!rotated) return;
+
+  // 3. X_p <- X_p J (and V_p <- V_p J), 16 rows at a time on matrix cores:
+  // A[i][k] = P[16 rb + i][4 ks + k] (lane: i = lane % 16, k = lane / 16),
+  // B[k][j] = J[4 ks + k][16 cb + j]; the result's lane holds rows
+  // 16 rb + lane / 16 + 4 v of column 16 cb + lane % 16.  A wave reads all 2W
+  // columns of its rows before it writes them back.
+  const double *J = Js[cur];
+  double jb[C / 4][NB];
+#pragma unroll
+  for (int ks = 0; ks < C / 4; ++ks)
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) jb[ks][cb] = J[(4 * ks + lr) * LG + 16 * cb + lc];
+  auto apply = [&](double *P, int64_t ld, int rows) {
+    double *pin[C / 4];
+    double *pout[NB];
+#pragma unroll
+    for (int ks = 0; ks < C / 4; ++ks) pin[ks] = P + gcol(4 * ks + lr) * ld;
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) pout[cb] = P + gcol(16 * cb + lc) * ld;
+    const int nrb = (rows + 15) >> 4;
+    for (int rb0 = wave; rb0 < nrb; rb0 += 8) {
+      double a[2][C / 4];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int row = 16 * (rb0 + 4 * h) + lc;
+        const bool in = rb0 + 4 * h < nrb && row < rows;
+#pragma unroll
+        for (int ks = 0; ks < C / 4; ++ks) a[h][ks] = in ? pin[ks][row] : 0.0;
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int rb = rb0 + 4 * h;
+        if (rb >= nrb) break;
+        D4 d[NB];
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) {
+          d[cb] = D4{0, 0, 0, 0};
+#pragma unroll
+          for (int ks = 0; ks < C / 4; ++ks)
+            d[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h][ks], jb[ks][cb], d[cb], 0, 0, 0);
+        }
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = 16 * rb + lr + 4 * v;
+            if (row < rows) pout[cb][row] = d[cb][v];
+          }
+      }
+    }
+  };
+  apply(ja.X, ja.ldx, nr);
+  if (ja.V) apply(ja.V, ja.nc, ja.nc);
+  if (tid == 0) atomicAdd(ja.rot, 1u);
+}
+
+// The Gram form for block pairs of 16 columns with at most 1024 rows (and V
+// of at most 1024 rows), where the block step is bound by latencies:
+//  - the pair's columns are read from global memory once, all loads in
+//    flight, into LDS (column-major, stride 1026 doubles, which keeps both
+//    the Gram reads and the update reads to at most two-way bank conflicts;
+//    rows past nr are zero), and V's 16 columns are prefetched into
+//    registers in the layout of the update;
+//  - a round of the sweep has one barrier: while 256 threads apply round r's
+//    rotations to G and J, eight threads of another wave form the three
+//    entries of G that round r + 1's pairs need (with the same arithmetic as
+//    the full update) and compute round r + 1's rotations;
+//  - the updated columns go back through LDS so that every global store is a
+//    run of consecutive rows.
+constexpr int kJg16Rows = 1024, kJg16Ld = 1026;
+
+struct JgRound {  // round r's rotations, per column (16 columns)
+  double cself[16], cpart[16], dg[16];
+  int rotc[16];
+};
+
+// Partner of column x in round r of the round-robin over 16 columns (the
+// pairing rr_pair(16, r, .) makes): 15 meets r, any other x meets
+// 2r - x mod 15.
+__device__ __forceinline__ int jg_partner(int r, int x) {
+  if (x == 15) return r;
+  if (x == r) return 15;
+  const int y = 2 * r - x;
+  return y < 0 ? y + 15 : (y >= 15 ? y - 15 : y);
+}
+
+// Entry (i, j) of J_r^T G J_r from the round's rotation coefficients of
+// columns i and j (cs: on the column itself, cp: on its partner) and the four
+// entries of G it combines; an entry of a rotated pair's own 2x2 block is set
+// by the rotation's closed form instead.
+__device__ __forceinline__ double jg_entry(double csi, double cpi, double csj, double cpj,
+                                           int roti, double dgi, bool diag, bool pair,
+                                           double gij, double gipj, double gpij, double gpipj) {
+  // explicit fused operations: every thread that forms an entry rounds it alike
+  const double g = fma(csi, fma(csj, gij, cpj * gipj), cpi * fma(csj, gpij, cpj * gpipj));
+  return roti ? (diag ? gij + dgi : (pair ? 0.0 : g)) : g;
+}
+
+// 1/x and 1/sqrt(x) for normal x: the hardware approximations refined by two
+// Newton steps each (the rotation's latency chain is the sweep's critical
+// path; the IEEE division and square root sequences are several times longer).
+__device__ __forceinline__ double jg_rcp(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return fma(y, fma(-x, y, 1.0), y);
+}
+__device__ __forceinline__ double jg_rsqrt(double x) {
+  const double h = 0.5 * x;
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(y, fma(-h * y, y, 0.5), y);
+  return fma(y, fma(-h * y, y, 0.5), y);
+}
+
+// The rotation of pair (a, b) from the entries al = g_aa, be = g_bb, ga = g_ab.
+__device__ __forceinline__ void jg_set_rotation(JgRound &P, int a, int b, double al, double be,
+                                                double ga, double tol, double floor2,
+                                                bool &any) {
+  // a column at the rounding level of the whole matrix counts as converged
+  const bool rot = fabs(ga) > tol * sqrt(al * be) && ga != 0.0 && fmin(al, be) > floor2;
+  // t = tan of the angle zeroing the (a, b) entry of [al ga; ga be]: the
+  // smaller root of t^2 + 2 zeta t - 1 = 0, zeta = (be - al) / (2 ga).  It is
+  // formed whether or not the pair rotates (the test is off the critical
+  // path) and discarded when it does not.
+  const double zeta = (be - al) * jg_rcp(2.0 * ga);
+  const double az = fabs(zeta);
+  const double q = fma(zeta, zeta, 1.0);
+  const double tr = az > 1e150 ? 0.5 * jg_rcp(zeta) : copysign(jg_rcp(az + q * jg_rsqrt(q)), zeta);
+  const double cr = jg_rsqrt(fma(tr, tr, 1.0));
+  const double t = rot ? tr : 0.0, c = rot ? cr : 1.0, sn = rot ? cr * tr : 0.0;
+  // column a of the rotation is c e_a - sn e_b, column b is sn e_a + c e_b;
+  // the new diagonal entries are al - t ga and be + t ga
+  P.cself[a] = c;
+  P.cpart[a] = -sn;
+  P.cself[b] = c;
+  P.cpart[b] = sn;
+  P.dg[a] = -t * ga;
+  P.dg[b] = t * ga;
+  P.rotc[a] = rot;
+  P.rotc[b] = rot;
+  any |= rot;
+}
+
+__global__ __launch_bounds__(512) void jacobi_gram16_kernel(JacobiBlockArgs ja) {
+  constexpr int W = 8, C = 16, NT = 512, LG = C + 1, NW = NT / 64;
+  constexpr int LD = kJg16Ld;
+  constexpr int XH = kJg16Rows / NT;          // rows per thread and column (2)
+  constexpr int RBW = kJg16Rows / 16 / NW;    // 16-row blocks per wave (8)
+  constexpr int PT = 256;                     // first thread of the pair wave
+  using D4 = double __attribute__((ext_vector_type(4)));
+  __shared__ double Xs[C * LD];
+  __shared__ double Gs[2][C * LG];
+  __shared__ double Js[2][C * LG];
+  __shared__ double part[NW][256];
+  __shared__ JgRound Ps[2];
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int lr = lane >> 4, lc = lane & 15;
+  const int nr = ja.nr, nv = ja.V ? ja.nc : 0;
+  int ba, bb;
+  rr_pair(ja.nblocks, ja.round, (int)blockIdx.x, ba, bb);
+  auto gcol = [&](int c) -> int64_t { return c < W ? (int64_t)ba * W + c : (int64_t)bb * W + (c - W); };
+
+  // 0. X_p into registers (thread: rows tid and tid + 512 of every column),
+  // V_p into registers in the update's operand layout: row block
+  // wave + 8 q, lane (lr, lc) -> row 16 rb + lc of column 4 ks + lr.
+  double xv[C][XH];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const double *col = ja.X + gcol(c) * ja.ldx;
+#pragma unroll
+    for (int h = 0; h < XH; ++h) {
+      const int i = tid + NT * h;
+      xv[c][h] = i < nr ? col[i] : 0.0;
+    }
+  }
+  double vv[RBW][C / 4];
+  if (nv > 0) {
+#pragma unroll
+    for (int ks = 0; ks < C / 4; ++ks) {
+      const double *col = ja.V + gcol(4 * ks + lr) * ja.nc;
+#pragma unroll
+      for (int q = 0; q < RBW; ++q) {
+        const int row = 16 * (wave + NW * q) + lc;
+        vv[q][ks] = row < nv ? col[row] : 0.0;
       }
     }
   }
-  if (rotated && tid == 0) atomicAdd(ja.rot, 1u);
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int h = 0; h < XH; ++h) Xs[c * LD + tid + NT * h] = xv[c][h];
+  for (int e = tid; e < C * LG; e += NT) Js[0][e] = (e / LG == e % LG) ? 1.0 : 0.0;
+  __syncthreads();
+
+  // 1. G = X_p^T X_p on matrix cores (A[i][k] = B[k][j]^T: lane (k, i) holds
+  // row 4 s + k of column i); wave w sums the steps s = w mod 8 into two
+  // accumulators, the waves' sums are added in wave order.
+  {
+    constexpr int U = 8;
+    D4 acc0 = D4{0, 0, 0, 0}, acc1 = D4{0, 0, 0, 0};
+    const int nsteps = (nr + 3) >> 2;
+    for (int s0 = wave; s0 < nsteps; s0 += NW * U) {
+      double x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int st = s0 + NW * u;  // rows of steps past nr are zero in Xs
+        x[u] = st < nsteps ? Xs[lc * LD + 4 * st + lr] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; u += 2) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u], x[u], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u + 1], x[u + 1], acc1, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) part[wave][v * 64 + lane] = acc0[v] + acc1[v];
+  }
+  __syncthreads();
+  if (tid < 256) {
+    const int v = tid >> 6, ln = tid & 63;
+    const int i = (ln >> 4) + 4 * v, j = ln & 15;
+    double s = part[0][tid];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) s += part[w][tid];
+    if (i <= j) {
+      Gs[0][i * LG + j] = s;
+      Gs[0][j * LG + i] = s;
+    }
+  }
+  __syncthreads();
+
+  // 2. One cyclic sweep over the 120 pairs on G, 8 disjoint pairs per round.
+  // Every LDS read a thread needs in a round is issued at once: the partners
+  // follow from the round number.
+  const double floor2 = *ja.floor2, tol = ja.tol;
+  bool any = false;
+  if (tid >= PT && tid < PT + C / 2) {
+    int a, b;
+    rr_pair(C, 0, tid - PT, a, b);
+    const double *G = Gs[0];
+    jg_set_rotation(Ps[0], a, b, G[a * LG + a], G[b * LG + b], G[a * LG + b], tol, floor2, any);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int ir = 0; ir < C - 1; ++ir) {
+    const JgRound &P = Ps[ir & 1];
+    const double *G = Gs[cur];
+    if (tid < C * C) {
+      const double *J = Js[cur];
+      double *G2 = Gs[cur ^ 1];
+      double *J2 = Js[cur ^ 1];
+      const int i = tid >> 4, j = tid & 15;
+      const int pi = jg_partner(ir, i), pj = jg_partner(ir, j);
+      const double csi = P.cself[i], cpi = P.cpart[i], csj = P.cself[j], cpj = P.cpart[j];
+      const double g = jg_entry(csi, cpi, csj, cpj, P.rotc[i], P.dg[i], j == i, j == pi,
+                                G[i * LG + j], G[i * LG + pj], G[pi * LG + j], G[pi * LG + pj]);
+      const double jn = fma(csj, J[i * LG + j], cpj * J[i * LG + pj]);
+      if (i <= j) {
+        G2[i * LG + j] = g;
+        G2[j * LG + i] = g;
+      }
+      J2[i * LG + j] = jn;
+    } else if (tid >= PT && tid < PT + C / 2 && ir + 1 < C - 1) {
+      // the next round's pair (a, b) needs entries (a, a), (b, b), (a, b) of
+      // the updated G: formed here exactly as the threads above form them
+      int a, b;
+      rr_pair(C, ir + 1, tid - PT, a, b);
+      const int pa = jg_partner(ir, a), pb = jg_partner(ir, b);
+      const double csa = P.cself[a], cpa = P.cpart[a], csb = P.cself[b], cpb = P.cpart[b];
+      const int rota = P.rotc[a], rotb = P.rotc[b];
+      const double dga = P.dg[a], dgb = P.dg[b];
+      const double al = jg_entry(csa, cpa, csa, cpa, rota, dga, true, false, G[a * LG + a],
+                                 G[a * LG + pa], G[pa * LG + a], G[pa * LG + pa]);
+      const double be = jg_entry(csb, cpb, csb, cpb, rotb, dgb, true, false, G[b * LG + b],
+                                 G[b * LG + pb], G[pb * LG + b], G[pb * LG + pb]);
+      const double ga = jg_entry(csa, cpa, csb, cpb, rota, dga, false, b == pa, G[a * LG + b],
+                                 G[a * LG + pb], G[pa * LG + b], G[pa * LG + pb]);
+      jg_set_rotation(Ps[(ir + 1) & 1], a, b, al, be, ga, tol, floor2, any);
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  const bool rotated = __syncthreads_or(any);
+  if (!rotated) return;
+
+  // 3. X_p <- X_p J and V_p <- V_p J on matrix cores, 16 rows per product:
+  // A[i][k] = P[16 rb + i][4 ks + k] (lane (k, i)), B[k][j] = J[4 ks + k][j];
+  // the result's lane (r, j) holds rows 16 rb + r + 4 v of column j.  Results
+  // are written into Xs (a wave only overwrites rows it has read) and then
+  // stored column by column.
+  const double *J = Js[cur];
+  double jb[C / 4];
+#pragma unroll
+  for (int ks = 0; ks < C / 4; ++ks) jb[ks] = J[(4 * ks + lr) * LG + lc];
+  auto update = [&](const double (&a)[RBW][C / 4], int rows) {
+    D4 d[RBW];
+#pragma unroll
+    for (int q = 0; q < RBW; ++q) d[q] = D4{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < C / 4; ++ks)
+#pragma unroll
+      for (int q = 0; q < RBW; ++q)
+        d[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q][ks], jb[ks], d[q], 0, 0, 0);
+#pragma unroll
+    for (int q = 0; q < RBW; ++q) {
+      const int rb = wave + NW * q;
+      if (16 * rb < rows)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Xs[lc * LD + 16 * rb + lr + 4 * v] = d[q][v];
+    }
+  };
+  {
+    double xa[RBW][C / 4];  // rows past nr are zero in Xs
+#pragma unroll
+    for (int q = 0; q < RBW; ++q)
+#pragma unroll
+      for (int ks = 0; ks < C / 4; ++ks)
+        xa[q][ks] = Xs[(4 * ks + lr) * LD + 16 * (wave + NW * q) + lc];
+    update(xa, nr);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    double *col = ja.X + gcol(c) * ja.ldx;
+#pragma unroll
+    for (int h = 0; h < XH; ++h) {
+      const int i = tid + NT * h;
+      if (i < nr) col[i] = Xs[c * LD + i];
+    }
+  }
+  if (nv > 0) {
+    __syncthreads();  // Xs is free again
+    update(vv, nv);
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      double *col = ja.V + gcol(c) * ja.nc;
+#pragma unroll
+      for (int h = 0; h < XH; ++h) {
+        const int i = tid + NT * h;
+        if (i < nv) col[i] = Xs[c * LD + i];
+      }
+    }
+  }
+  if (tid == 0) atomicAdd(ja.rot, 1u);
 }
 
 // sigma_j = ||x_j||; order by decreasing sigma (ties by index) into S, and
@@ -977,7 +1330,8 @@ int eye(double *M, int64_t n, int64_t ld, hipStream_t s) {
 // One launch per round, nblocks - 1 rounds per sweep; after each sweep the
 // rotation counter is read back and the sweeps stop at the first one without
 // rotations.  *sweeps = max_sweeps + 1 when that never happens.
-template <int W, int KR>
+// LDS16 selects the LDS-staged kernel for 16-column block pairs (W = 8).
+template <int W, bool LDS16>
 static Task jacobi_sweeps_task(DevCtx &ctx, JacobiBlockArgs ja, int max_sweeps, int *sweeps) {
   ja.nblocks = ja.nc / W;
   *sweeps = max_sweeps + 1;
@@ -986,7 +1340,10 @@ static Task jacobi_sweeps_task(DevCtx &ctx, JacobiBlockArgs ja, int max_sweeps, 
     if (hipGetLastError() != hipSuccess) co_return BSRHT_EDEVICE;
     for (int r = 0; r < ja.nblocks - 1; ++r) {
       ja.round = r;
-      jacobi_block_kernel<W, KR><<<(unsigned)(ja.nblocks / 2), 64 * W, 0, ctx.s>>>(ja);
+      if constexpr (LDS16)
+        jacobi_gram16_kernel<<<(unsigned)(ja.nblocks / 2), 512, 0, ctx.s>>>(ja);
+      else
+        jacobi_gram_kernel<W><<<(unsigned)(ja.nblocks / 2), 256, 0, ctx.s>>>(ja);
       if (hipGetLastError() != hipSuccess) co_return BSRHT_EDEVICE;
     }
     unsigned int rot = 0;
@@ -999,33 +1356,14 @@ static Task jacobi_sweeps_task(DevCtx &ctx, JacobiBlockArgs ja, int max_sweeps, 
   co_return BSRHT_OK;
 }
 
-// Block width W and rows per lane KR (64 KR >= rows) for a problem whose
-// LDS copy holds `rows` rows.  Measured on MI355X (graded 320..1024-column
-// problems): narrower blocks give more workgroups per round and win up to
-// 512 rows; beyond that the LDS capacity decides.
-static void jacobi_shape(int64_t rows, int *W, int *KR) {
-  if (rows <= 512) {
-    *W = 8;
-    *KR = 8;
-  } else if (rows <= 1024) {
-    *W = 8;
-    *KR = 16;
-  } else if (rows <= 2048) {
-    *W = 4;
-    *KR = 32;
-  } else {
-    *W = 2;
-    *KR = 64;
-  }
-}
-
 Task jacobi_svd_task(DevCtx &ctx, double *X, int64_t nr, int64_t nc, int64_t ldx, double *V,
                      double *S, double *Us, int64_t ldu, int32_t *perm, unsigned int *flags,
-                     int max_sweeps, int32_t *info, int W, int KR) {
+                     int max_sweeps, int32_t *info, int form) {
   if (nc <= 0) co_return BSRHT_OK;
   const int64_t rows = V ? std::max(nr, nc) : nr;
-  if (W == 0) jacobi_shape(rows, &W, &KR);
-  if (nc > 4096 || nr > 4096 || (nc % 32) != 0 || rows > 64 * (int64_t)KR)
+  if (form == 0) form = rows <= kJg16Rows ? 1 : 2;
+  if (nc > 4096 || nr > 4096 || (nc % 32) != 0 || form < 1 || form > 2 ||
+      (form == 1 && rows > kJg16Rows))
     co_return BSRHT_EUNSUPPORTED;
   hipStream_t s = ctx.s;
   if (V) {
@@ -1047,16 +1385,10 @@ Task jacobi_svd_task(DevCtx &ctx, double *X, int64_t nr, int64_t nc, int64_t ldx
   noise_floor_kernel<<<1, 1024, 0, s>>>(X, nr, nc, ldx, floor2);
   if (hipGetLastError() != hipSuccess) co_return BSRHT_EDEVICE;
   int sweeps = 0, st;
-  switch (W * 1000 + KR) {
-    case 16008: st = co_await jacobi_sweeps_task<16, 8>(ctx, ja, max_sweeps, &sweeps); break;
-    case 8008: st = co_await jacobi_sweeps_task<8, 8>(ctx, ja, max_sweeps, &sweeps); break;
-    case 8016: st = co_await jacobi_sweeps_task<8, 16>(ctx, ja, max_sweeps, &sweeps); break;
-    case 4008: st = co_await jacobi_sweeps_task<4, 8>(ctx, ja, max_sweeps, &sweeps); break;
-    case 4016: st = co_await jacobi_sweeps_task<4, 16>(ctx, ja, max_sweeps, &sweeps); break;
-    case 4032: st = co_await jacobi_sweeps_task<4, 32>(ctx, ja, max_sweeps, &sweeps); break;
-    case 2064: st = co_await jacobi_sweeps_task<2, 64>(ctx, ja, max_sweeps, &sweeps); break;
-    default: co_return BSRHT_EUNSUPPORTED;
-  }
+  if (form == 1)
+    st = co_await jacobi_sweeps_task<8, true>(ctx, ja, max_sweeps, &sweeps);
+  else
+    st = co_await jacobi_sweeps_task<kJacobiGramW, false>(ctx, ja, max_sweeps, &sweeps);
   if (st != BSRHT_OK) co_return st;
   if (sweeps > max_sweeps && info) {
     or_bits_kernel<<<1, 1, 0, s>>>(info, BSRHT_INFO_JACOBI_NOCONV);
@@ -1070,17 +1402,17 @@ Task jacobi_svd_task(DevCtx &ctx, double *X, int64_t nr, int64_t nc, int64_t ldx
 
 int jacobi_svd_shape(double *X, int64_t nr, int64_t nc, int64_t ldx, double *V, double *S,
                      double *Us, int64_t ldu, int32_t *perm, unsigned int *flags, int max_sweeps,
-                     int32_t *info, int W, int KR, hipStream_t s) {
+                     int32_t *info, int form, hipStream_t s) {
   DevCtx ctx;
   ctx.s = s;
   return run_blocking(jacobi_svd_task(ctx, X, nr, nc, ldx, V, S, Us, ldu, perm, flags,
-                                      max_sweeps, info, W, KR));
+                                      max_sweeps, info, form));
 }
 
 int jacobi_svd(double *X, int64_t nr, int64_t nc, int64_t ldx, double *V, double *S,
                double *Us, int64_t ldu, int32_t *perm, unsigned int *flags, int max_sweeps,
                int32_t *info, hipStream_t s) {
-  return jacobi_svd_shape(X, nr, nc, ldx, V, S, Us, ldu, perm, flags, max_sweeps, info, 0, 0, s);
+  return jacobi_svd_shape(X, nr, nc, ldx, V, S, Us, ldu, perm, flags, max_sweeps, info, 0, s);
 }
 
 int transpose_f32_f64(const float *src, int64_t rows, int64_t cols, int64_t lds, double *dst,

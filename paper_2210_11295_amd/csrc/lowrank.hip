@@ -208,7 +208,7 @@ Task small_svd_task(DevCtx &ctx, SvdBufs<A> &b, const double *R, int64_t nc0, in
   BSRHT_CO_TRY(fill_f64(b.X, nc * nc, 0.0, ctx.s));
   BSRHT_CO_TRY(scale_cols_f64(R, nc0, nc0, nc0, ldr, nullptr, b.X, nc, ctx.s));  // ld ldr -> nc
   co_return co_await jacobi_svd_task(ctx, b.X, nc, nc, nc, eigen ? b.V : nullptr, b.S, b.Vs, nc,
-                                     b.perm, b.flags, kMaxSweeps, info, 0, 0);
+                                     b.perm, b.flags, kMaxSweeps, info, 0);
 }
 
 template <class A>

@@ -191,6 +191,6 @@ Task rsvd_task(DevCtx &ctx, const bsrht_plan_s *plan, const float *A, int64_t m,
                size_t ws_bytes);
 Task jacobi_svd_task(DevCtx &ctx, double *X, int64_t nr, int64_t nc, int64_t ldx, double *V,
                      double *S, double *Us, int64_t ldu, int32_t *perm, unsigned int *flags,
-                     int max_sweeps, int32_t *info, int W, int KR);
+                     int max_sweeps, int32_t *info, int form);
 
 }  // namespace bsrht

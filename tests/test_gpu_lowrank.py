@@ -52,12 +52,12 @@ def test_rsvd_matches_oracle(n, m, p, l, k):
 
 
 @pytest.mark.parametrize("n,m,p,l,k", [
-    (8192, 1500, 2, 1100, 50),    # SVD of R on 1120 columns: blocks of 4
-    (8192, 2600, 1, 2200, 40),    # 2208 columns: blocks of 2
-    (4096, 900, 4, 700, 30),      # 704 columns: blocks of 8
+    (8192, 1500, 2, 1100, 50),    # SVD of R on 1120 columns: streamed 32-column pairs
+    (8192, 2600, 1, 2200, 40),    # 2208 columns: streamed 32-column pairs
+    (4096, 900, 4, 700, 30),      # 704 columns: 16-column pairs staged in LDS
 ])
 def test_rsvd_large_sketch_sizes(n, m, p, l, k):
-    """Sketch sizes that take every column-block width of the Jacobi SVD."""
+    """Sketch sizes that take both forms of the Jacobi SVD's block step."""
     dev = device()
     say("rsvd large l", n, m, p, l, k)
     A = workloads.gaussian_cols(n, m, "pow1.5", n + m + l, device=dev)
