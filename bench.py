@@ -131,7 +131,7 @@ def bench_split_bf16(bs, A, cfg, steps, warmup, Y_fp32):
             "ms_per_step": round(elapsed / steps * 1e3, 4),
             "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                         "traffic": traffic, "kernel": "fused_bf16_kernel<64>",
+                         "traffic": traffic, "kernel": "fused_bf16_kernel<8, 64, false>",
                          "kernel_avg_us": round(kern_avg_ms * 1e3, 2),
                          "alg_bytes_per_launch": alg_bytes},
             "rel_diff_vs_fp32": diff}
@@ -451,7 +451,7 @@ def main():
         "frac_hbm_peak": round(value / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "fused_fp32_kernel<64>",
+                     "traffic": traffic, "kernel": "fused_fp32_kernel<8, 64>",
                      "kernel_avg_us": round(kern_avg_ms * 1e3, 2),
                      "alg_bytes_per_launch": alg_bytes},
     }
