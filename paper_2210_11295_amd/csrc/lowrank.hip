@@ -171,6 +171,7 @@ struct NysWs {
   SvdBufs<A> fb, sv;
   void layout(A &a, const bsrht_plan_s *pl, int64_t k) {
     const int64_t l = pl->l, n = pl->n;
+    const int64_t l4 = (l + 3) & ~int64_t(3);  // Z's leading dimension bound
     W = a.template take<float>((size_t)(l * n));
     Y = a.template take<float>((size_t)(n * l));
     B = a.template take<float>((size_t)(l * l));
@@ -178,9 +179,9 @@ struct NysWs {
     apply_ws = a.template take<char>(apply_bytes);
     Bs = a.template take<double>((size_t)(l * l));
     Cinv = a.template take<double>((size_t)(l * l));
-    Mf = a.template take<double>((size_t)(l * l));
+    Mf = a.template take<double>((size_t)(l * l4));
     lam = a.template take<double>((size_t)l);
-    Z = a.template take<double>((size_t)(n * l));
+    Z = a.template take<double>((size_t)(n * l4));
     gram_part = a.template take<double>((size_t)std::max(gram_partial_elems(n, l), (int64_t)1));
     Gz = a.template take<double>((size_t)(l * l));
     Mk = a.template take<double>((size_t)(l * std::max<int64_t>(k, 1)));
@@ -445,7 +446,7 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
   BSRHT_TRY(cholesky_upper(w.Mf, l, l, (double)l * kU64, w.flag, w.chol_state, s));
   int32_t hf = 0;
   BSRHT_TRY(read_i32(w.flag, s, &hf));
-  int64_t lz = l;
+  int64_t lz = l, ldz = l;  // columns of Z and its leading dimension
   if (hf == 0) {
     // 3. Z = Y C^{-1}
     BSRHT_TRY(trinv_upper(w.Mf, l, l, w.Cinv, l, s));
@@ -476,29 +477,31 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
       }
     if (idx.empty()) return BSRHT_EDEVICE;
     lz = (int64_t)idx.size();
-    // Mf = V_+ Lam_+^{-1/2} (l x lz): gather the kept columns on the host side
-    // of the index list, scale on the device.
+    // Z (n x lz) and Mf get a leading dimension rounded up to 4 elements,
+    // which the large-tile GEMM kernel needs for its 16-byte loads.
+    ldz = (lz + 3) & ~int64_t(3);
+    // Mf = V_+ Lam_+^{-1/2} (l x lz, leading dimension ldz, zero padded)
     std::vector<double> Vh((size_t)(l * nce));
     if (copy_to_host(Vh.data(), w.fb.Vs, sizeof(double) * Vh.size(), s) != BSRHT_OK)
       return BSRHT_EDEVICE;
-    std::vector<double> Mh((size_t)(l * lz));
+    std::vector<double> Mh((size_t)(l * ldz), 0.0);
     for (int64_t i = 0; i < l; ++i)
       for (int64_t c = 0; c < lz; ++c)
-        Mh[(size_t)(i * lz + c)] = Vh[(size_t)(i * nce + idx[(size_t)c])] * sc[(size_t)c];
+        Mh[(size_t)(i * ldz + c)] = Vh[(size_t)(i * nce + idx[(size_t)c])] * sc[(size_t)c];
     if (copy_to_device(w.Mf, Mh.data(), sizeof(double) * Mh.size(), s) != BSRHT_OK)
       return BSRHT_EDEVICE;
     GemmDesc d;
     d.M = n; d.N = lz; d.K = l;
     d.sai = l; d.sak = 1;
-    d.sbk = lz; d.sbj = 1;
-    d.ldc = lz;
+    d.sbk = ldz; d.sbj = 1;
+    d.ldc = ldz;
     BSRHT_TRY(gemm_f32f64_f64(d, w.Y, w.Mf, w.Z, s));
     or_info_kernel<<<1, 1, 0, s>>>(info, BSRHT_INFO_CHOL_FALLBACK);
     BSRHT_LAUNCH_CHECK();
   }
   // 4. R-factor of Z: Gz = Z^T Z = R^T R
   const int gsz = gram_splits(n, lz);
-  BSRHT_TRY(gram_f64(w.Z, n, lz, lz, 1, w.Gz, lz, w.gram_part, gsz, s));
+  BSRHT_TRY(gram_f64(w.Z, n, lz, ldz, 1, w.Gz, lz, w.gram_part, gsz, s));
   BSRHT_TRY(scale_cols_f64(w.Gz, lz, lz, lz, lz, nullptr, w.Bs, lz, s));
   BSRHT_TRY(cholesky_upper(w.Gz, lz, lz, 1e-15 * (double)lz, w.flag + 1, w.chol_state, s));
   int32_t hz = 0;
@@ -523,7 +526,7 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
   BSRHT_TRY(scale_cols_f64(w.sv.Vs, lz, keep, k, nce, w.sv.inv, w.Mk, k, s));
   GemmDesc d;
   d.M = n; d.N = k; d.K = lz;
-  d.sai = lz; d.sak = 1;
+  d.sai = ldz; d.sak = 1;
   d.sbk = k; d.sbj = 1;
   d.ldc = k;
   return gemm_f64f64_f32(d, w.Z, w.Mk, U, s);
