@@ -279,7 +279,17 @@ __global__ __launch_bounds__(NW * 64) void fused_bf16_kernel(Bf16Args a) {
   cta.w = __builtin_amdgcn_readfirstlane(tid >> 6);
   cta.q4 = cta.lane & 15;
   cta.g = cta.lane >> 4;
-  const int c0 = (a.tile0 + (int)blockIdx.x) * kCT;
+  int bx = blockIdx.x, by = blockIdx.y;
+  {
+    const int nwg = (int)(gridDim.x * gridDim.y);
+    if ((nwg & 7) == 0) {
+      const int lin = (int)(blockIdx.x + gridDim.x * blockIdx.y);
+      const int idx = (lin & 7) * (nwg >> 3) + (lin >> 3);
+      bx = idx % (int)gridDim.x;
+      by = idx / (int)gridDim.x;
+    }
+  }
+  const int c0 = (a.tile0 + bx) * kCT;
   cta.row_bytes = (int)(a.lda * 4);
   if constexpr (RAGGED) {
     // Columns past m load a valid neighbour (column m-1); they never reach Y.
@@ -299,7 +309,7 @@ __global__ __launch_bounds__(NW * 64) void fused_bf16_kernel(Bf16Args a) {
   }
   cta.hop_lds = &Hop[cta.lane];
   __syncthreads();
-  const int q0 = blockIdx.y * a.chunks_per_split;
+  const int q0 = by * a.chunks_per_split;
   const int q1 = min(q0 + a.chunks_per_split, a.total_chunks);
   cta.j = blockIdx.z * (NW * 64) + tid;
   cta.jok = cta.j < a.l;
@@ -320,7 +330,7 @@ __global__ __launch_bounds__(NW * 64) void fused_bf16_kernel(Bf16Args a) {
   }
 
   if (cta.jok) {
-    float *o = a.out + (int64_t)blockIdx.y * a.split_stride + (int64_t)cta.j * a.ldo + c0;
+    float *o = a.out + (int64_t)by * a.split_stride + (int64_t)cta.j * a.ldo + c0;
     const int ncol = min(kCT, a.m - c0);
 #pragma unroll
     for (int k = 0; k < kCT; ++k)

@@ -196,13 +196,26 @@ __global__ __launch_bounds__(NW * 64) void fused_fp32_kernel(FusedArgs a) {
   const int tid = threadIdx.x;
   cta.lane = tid & 63;
   cta.w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int c0 = blockIdx.x * kCT;
+  // XCD-aware tile order: workgroups are dealt to the 8 XCDs round-robin, so
+  // linear id k runs on XCD k mod 8; give each XCD a contiguous range of
+  // (split, column tile) pairs in row-major order.
+  int bx = blockIdx.x, by = blockIdx.y;
+  {
+    const int nwg = (int)(gridDim.x * gridDim.y);
+    if ((nwg & 7) == 0) {
+      const int lin = (int)(blockIdx.x + gridDim.x * blockIdx.y);
+      const int idx = (lin & 7) * (nwg >> 3) + (lin >> 3);
+      bx = idx % (int)gridDim.x;
+      by = idx / (int)gridDim.x;
+    }
+  }
+  const int c0 = bx * kCT;
   // Columns past m load a valid neighbour (column m-1); they never reach Y.
   const int cc = min(c0 + cta.lane, a.m - 1) - c0;
   cta.voff = cc * 4;
   cta.row_bytes = (int)(a.lda * 4);
   cta.wavebase = a.A + c0 + (int64_t)(cta.w * BR) * a.lda;
-  const int q0 = blockIdx.y * a.chunks_per_split;
+  const int q0 = by * a.chunks_per_split;
   const int q1 = min(q0 + a.chunks_per_split, a.total_chunks);
   cta.j = blockIdx.z * (NW * 64) + tid;
   cta.jok = cta.j < a.l;
@@ -223,7 +236,7 @@ __global__ __launch_bounds__(NW * 64) void fused_fp32_kernel(FusedArgs a) {
   }
 
   if (cta.jok) {
-    float *o = a.out + (int64_t)blockIdx.y * a.split_stride + (int64_t)cta.j * a.ldo + c0;
+    float *o = a.out + (int64_t)by * a.split_stride + (int64_t)cta.j * a.ldo + c0;
     const int ncol = min(kCT, a.m - c0);
 #pragma unroll
     for (int k = 0; k < kCT; ++k)
