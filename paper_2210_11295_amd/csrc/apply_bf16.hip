@@ -322,11 +322,16 @@ __global__ __launch_bounds__(NW * 64) void fused_bf16_kernel(Bf16Args a) {
 #pragma unroll
   for (int k = 0; k < kCT; ++k) cta.acc[k] = 0.f;
 
+  // One step per iteration and an explicit copy of the prefetched chunk (two
+  // alternating step bodies made the register allocator spill into the
+  // gather, where a reload waits for the whole prefetch).
   float4 bufA[Cta::NT], bufB[Cta::NT];
   if (q0 < q1) cta.template load<0, Cta::NT>(bufA, cta.chunk_base(q0));
-  for (int q = q0; q < q1; q += 2) {
+#pragma nounroll
+  for (int q = q0; q < q1; ++q) {
     cta.step(q, q1, bufA, bufB);
-    if (q + 1 < q1) cta.step(q + 1, q1, bufB, bufA);
+#pragma unroll
+    for (int t = 0; t < Cta::NT; ++t) bufA[t] = bufB[t];
   }
 
   if (cta.jok) {

@@ -122,10 +122,7 @@ struct FusedCta {
   const FusedArgs &a;
   int lane, w, j, pos, cpb_log2, voff, row_bytes;
   bool jok;
-  // R_j's chunk-index bits, kept in LDS rather than a register: registers
-  // are tightest in the gather, and a spill reload there (a vector-memory
-  // access) would wait for the whole prefetch of the next chunk.
-  uint32_t rhi;
+  uint32_t rhi;  // R_j's chunk-index bits (R_j >> log2 b)
   int cur_block;
   uint32_t dtbit;
   const float *wavebase;  // A + c0 + w*BR*lda (wave-uniform)
@@ -191,7 +188,6 @@ template <int NW, int BR>
 __global__ __launch_bounds__(NW * 64) void fused_fp32_kernel(FusedArgs a) {
   using Cta = FusedCta<NW, BR>;
   __shared__ __attribute__((aligned(16))) float T[Cta::B * kLDT];
-  __shared__ uint32_t Rhi[NW * 64];
   Cta cta(T, a);
   const int tid = threadIdx.x;
   cta.lane = tid & 63;
@@ -228,11 +224,17 @@ __global__ __launch_bounds__(NW * 64) void fused_fp32_kernel(FusedArgs a) {
 #pragma unroll
   for (int k = 0; k < kCT; ++k) cta.acc[k] = 0.f;
 
+  // One step per iteration and an explicit copy of the prefetched chunk: with
+  // two alternating step bodies the register allocator ran out of the 256
+  // registers and spilled R_j's chunk bits, whose reload in the gather (a
+  // vector-memory access) waited for the whole prefetch of the next chunk.
   float bufA[BR], bufB[BR];
   if (q0 < q1) load_rows<BR>(bufA, cta.chunk_base(q0), cta.voff, cta.row_bytes);
-  for (int q = q0; q < q1; q += 2) {
+#pragma nounroll
+  for (int q = q0; q < q1; ++q) {
     cta.step(q, q1, bufA, bufB);
-    if (q + 1 < q1) cta.step(q + 1, q1, bufB, bufA);
+#pragma unroll
+    for (int t = 0; t < BR; ++t) bufA[t] = bufB[t];
   }
 
   if (cta.jok) {
