@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -96,6 +98,37 @@ def _copy_calibration(A):
     del B
 
 
+def _kernel_stats(bs):
+    """Median / p10 / p90 of the per-launch kernel times recorded since
+    timing_enable, in microseconds."""
+    us = np.array(bs.timing_samples(), dtype=np.float64) * 1e3
+    if us.size == 0:
+        return {}
+    return {"kernel_median_us": round(float(np.median(us)), 2),
+            "kernel_p10_us": round(float(np.percentile(us, 10)), 2),
+            "kernel_p90_us": round(float(np.percentile(us, 90)), 2)}
+
+
+def bench_stream_read(bs, A, reps=20, warmup=3):
+    """Read-only reference over the same buffer: one pass of the library's
+    plain read kernel (16-byte non-temporal loads) per repetition."""
+    import torch
+    out = torch.empty(bs.STREAM_BLOCKS, dtype=torch.float32, device=A.device)
+    for _ in range(warmup):
+        bs.stream_read(A, out)
+    torch.cuda.synchronize()
+    bs.timing_enable(bs.TIMING_STREAM)
+    for _ in range(reps):
+        bs.stream_read(A, out)
+    torch.cuda.synchronize()
+    stats = _kernel_stats(bs)
+    bs.timing_enable(bs.TIMING_OFF)
+    gbs = A.numel() * 4 / (stats["kernel_median_us"] * 1e-6) / 1e9
+    log(f"bench: read-only reference {gbs:.1f} GB/s (median of {reps})")
+    return {"GBs": round(gbs, 2), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "kernel": "stream_read_kernel", "reps": reps, **stats}
+
+
 def bench_split_bf16(bs, A, cfg, steps, warmup, Y_fp32):
     """The same sketch with the H_16 factor on BF16 matrix cores (A split
     into BF16 hi + lo, FP32 accumulation), on the same A and plan seed."""
@@ -116,6 +149,7 @@ def bench_split_bf16(bs, A, cfg, steps, warmup, Y_fp32):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kern_ms, launches = bs.timing_read()
+    stats = _kernel_stats(bs)
     bs.timing_enable(bs.TIMING_OFF)
     kern_avg_ms = kern_ms / max(launches, 1)
     bytes_a = n * m * 4
@@ -132,7 +166,7 @@ def bench_split_bf16(bs, A, cfg, steps, warmup, Y_fp32):
             "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                          "traffic": traffic, "kernel": "fused_bf16_kernel<8, 64, false>",
-                         "kernel_avg_us": round(kern_avg_ms * 1e3, 2),
+                         "kernel_avg_us": round(kern_avg_ms * 1e3, 2), **stats,
                          "alg_bytes_per_launch": alg_bytes},
             "rel_diff_vs_fp32": diff}
 
@@ -417,6 +451,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kern_ms, launches = bs.timing_read()
+    stats = _kernel_stats(bs)
     bs.timing_enable(bs.TIMING_OFF)
     elapsed = t1 - t0
     bytes_a = n * m * 4
@@ -432,6 +467,7 @@ def main():
         _copy_calibration(A)
 
     traffic = _traffic("traffic_fused_fp32_sketch_2p20x1024.json", ["apply_fp32.hip"], alg_bytes)
+    stream_ref = bench_stream_read(bs, A)
     out = {
         "metric": "block-SRHT sketch GB/s of A (FP32 fused apply)",
         "value": round(value, 2),
@@ -452,8 +488,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "fused_fp32_kernel<8, 64>",
-                     "kernel_avg_us": round(kern_avg_ms * 1e3, 2),
-                     "alg_bytes_per_launch": alg_bytes},
+                     "kernel_avg_us": round(kern_avg_ms * 1e3, 2), **stats,
+                     "alg_bytes_per_launch": alg_bytes,
+                     "frac_of_stream_read": round(achieved / stream_ref["GBs"], 4)},
+        "stream_read": stream_ref,
     }
     if args.only == "sketch":
         args.skip_lowrank = True

@@ -212,8 +212,29 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k,
 #define BSRHT_TIMING_APPLY_FP32 1 /* the fused FP32 sketch kernel          */
 #define BSRHT_TIMING_APPLY_BF16 2 /* the split-BF16 matrix-core kernel     */
 #define BSRHT_TIMING_GEMM_AQ 3    /* Z = A Q of the randomized SVD          */
+#define BSRHT_TIMING_STREAM 4     /* bsrht_stream_read                       */
 int bsrht_timing_enable(int which);
 int bsrht_timing_read(double *total_ms, int64_t *launches);
+/*
+ * The per-launch durations (milliseconds, in launch order) recorded since
+ * bsrht_timing_enable: up to cap of them are written to ms (host); *count
+ * receives the number of recorded launches.  Waits for the recorded events.
+ * BSRHT_EINVAL for cap < 0 or ms == NULL with cap > 0.
+ */
+int bsrht_timing_samples(float *ms, int64_t cap, int64_t *count);
+
+/*
+ * Read-bandwidth reference (measurement, not part of the computation): reads
+ * x[0 .. 4*floor(count/4)) once from device memory with 16-byte
+ * non-temporal loads and writes one partial sum per workgroup to out
+ * (BSRHT_STREAM_BLOCKS floats, device, caller-owned).  x must be 16-byte
+ * aligned (else BSRHT_EINVAL).  Stream-ordered; timed under
+ * BSRHT_TIMING_STREAM.  Its rate over a buffer larger than the 256 MB last
+ * level cache is the read rate the sketch kernels' HBM traffic is compared
+ * with.
+ */
+#define BSRHT_STREAM_BLOCKS 4096
+int bsrht_stream_read(const float *x, int64_t count, float *out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -35,6 +35,8 @@ TIMING_OFF = 0
 TIMING_APPLY_FP32 = 1
 TIMING_APPLY_BF16 = 2
 TIMING_GEMM_AQ = 3
+TIMING_STREAM = 4
+STREAM_BLOCKS = 4096
 JOB_SKETCH = 0
 JOB_RSVD = 1
 
@@ -65,6 +67,8 @@ _SIGS = {
     "bsrht_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "bsrht_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(_c_i64)]),
+    "bsrht_timing_samples": (ctypes.c_int, [_c_vp, _c_i64, ctypes.POINTER(_c_i64)]),
+    "bsrht_stream_read": (ctypes.c_int, [_c_vp, _c_i64, _c_vp, _c_vp]),
     "nystrom": (ctypes.c_int, [_c_vp, _c_vp, _c_i64, _c_i64, _c_vp, _c_vp, _c_vp, _c_vp,
                                _c_sz, _c_vp]),
 }
@@ -172,6 +176,27 @@ def timing_read():
     n = _c_i64()
     _check("bsrht_timing_read", lib().bsrht_timing_read(ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def timing_samples(cap=100000):
+    """Per-launch kernel milliseconds (launch order) since timing_enable."""
+    buf = (ctypes.c_float * max(cap, 1))()
+    n = _c_i64()
+    _check("bsrht_timing_samples", lib().bsrht_timing_samples(buf, cap, ctypes.byref(n)))
+    return [float(buf[i]) for i in range(min(n.value, cap))]
+
+
+def stream_read(x, out=None, stream=None):
+    """Read-bandwidth reference: one pass over the contiguous float32 device
+    tensor x; returns the per-workgroup partial sums (STREAM_BLOCKS floats)."""
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.float32 \
+            or not x.is_contiguous():
+        raise ValueError("x must be a contiguous float32 tensor on a GPU")
+    if out is None:
+        out = torch.empty(STREAM_BLOCKS, dtype=torch.float32, device=x.device)
+    _check("bsrht_stream_read", lib().bsrht_stream_read(_ptr(x), x.numel(), _ptr(out),
+                                                        _stream_ptr(stream)))
+    return out
 
 
 def bsrht_plan_bytes(n, p, l):

@@ -1,6 +1,7 @@
 // Instrumentation: HIP events recorded around the launches of one chosen
 // kernel, on the stream that kernel runs on, so a benchmark can report that
-// kernel's own duration next to the whole call's.
+// kernel's own duration next to the whole call's; and a plain read kernel
+// that measures the HBM read rate the sketch kernels are compared with.
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -21,6 +22,40 @@ struct TimingState {
 
 TimingState g_timing;
 std::mutex g_timing_mu;
+
+constexpr int kStreamThreads = 256;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Reads x[0 .. n4) once (16-byte non-temporal loads, eight in flight per
+// thread, grid-stride so that the whole grid sweeps one contiguous region at
+// a time) and writes one partial sum per workgroup, which keeps the loads
+// live.  The sums are not part of any result.
+__global__ __launch_bounds__(kStreamThreads) void stream_read_kernel(const f32x4 *__restrict__ x,
+                                                                     int64_t n4,
+                                                                     float *__restrict__ out) {
+  __shared__ float red[kStreamThreads];
+  const int64_t stride = (int64_t)gridDim.x * kStreamThreads;
+  int64_t i = (int64_t)blockIdx.x * kStreamThreads + threadIdx.x;
+  float acc = 0.f;
+  for (; i + 7 * stride < n4; i += 8 * stride) {
+    f32x4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = __builtin_nontemporal_load(x + i + u * stride);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);
+  }
+  for (; i < n4; i += stride) {
+    const f32x4 v = __builtin_nontemporal_load(x + i);
+    acc += (v.x + v.y) + (v.z + v.w);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = kStreamThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
 
 }  // namespace
 
@@ -86,6 +121,34 @@ int bsrht_timing_enable(int which) {
   g_timing.which = which;
   g_timing.used = 0;
   return BSRHT_OK;
+}
+
+int bsrht_timing_samples(float *ms, int64_t cap, int64_t *count) {
+  if (cap < 0 || (cap > 0 && !ms)) return BSRHT_EINVAL;
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  int64_t k = 0;
+  for (size_t i = 0; i < g_timing.used; ++i) {
+    if (!g_timing.done[i]) continue;
+    if (hipEventSynchronize(g_timing.events[i].second) != hipSuccess) return BSRHT_EDEVICE;
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, g_timing.events[i].first, g_timing.events[i].second) !=
+        hipSuccess)
+      return BSRHT_EDEVICE;
+    if (k < cap) ms[k] = t;
+    ++k;
+  }
+  if (count) *count = k;
+  return BSRHT_OK;
+}
+
+int bsrht_stream_read(const float *x, int64_t count, float *out, void *stream) {
+  if (!x || !out || count < 0 || ((uintptr_t)x & 15) != 0) return BSRHT_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int slot = timing_begin(BSRHT_TIMING_STREAM, s);
+  stream_read_kernel<<<BSRHT_STREAM_BLOCKS, kStreamThreads, 0, s>>>(
+      reinterpret_cast<const f32x4 *>(x), count / 4, out);
+  timing_end(slot, s);
+  return hipGetLastError() == hipSuccess ? BSRHT_OK : BSRHT_EDEVICE;
 }
 
 int bsrht_timing_read(double *total_ms, int64_t *launches) {
