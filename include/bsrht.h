@@ -150,6 +150,44 @@ size_t bsrht_apply_workspace(bsrht_plan_t plan, int64_t m);
 int bsrht_apply(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda,
                 float *Y, int64_t ldy, void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * Several FP32 sketches (eq. (2.4) each, as bsrht_apply) in one persistent
+ * launch: the workgroup tiles of all items run from a descriptor table in
+ * device memory, followed by one launch that sums every item's row-split
+ * partials.  For many small sketches this replaces two launches per item by
+ * a fixed three-kernel sequence, which is captured into a HIP graph on the
+ * first call for a given (device, table) and replayed by later calls with the
+ * table rewritten (the descriptors are copied in, stream-ordered, before each
+ * replay).
+ *
+ * items      : host array of count items; each item is exactly the argument
+ *              set of a bsrht_apply call (ws of >= bsrht_apply_workspace(plan,
+ *              m) bytes, m >= 1), and its Y is bitwise the result that call
+ *              would give (same launch decomposition and summation order).
+ *              Items must not share Y or ws.
+ * count      : 0 .. BSRHT_BATCH_MAX (0 is a no-op).
+ * table      : device memory of table_bytes >= bsrht_batch_table_bytes(),
+ *              caller-owned, overwritten by each call.  Calls that use the
+ *              same table must be ordered (one stream, or synchronised).
+ * Errors     : BSRHT_EINVAL for bad arguments; BSRHT_EUNSUPPORTED for an item
+ *              whose plan is split-BF16 or whose blocks are shorter than 64
+ *              rows (use bsrht_apply); BSRHT_ENOMEM for a short workspace.
+ *              Nothing is enqueued when an item is rejected.
+ */
+#define BSRHT_BATCH_MAX 64
+typedef struct bsrht_apply_item_s {
+  bsrht_plan_t plan;
+  const float *A;
+  int64_t m, lda;
+  float *Y;
+  int64_t ldy;
+  void *ws;
+  size_t ws_bytes;
+} bsrht_apply_item_t;
+size_t bsrht_batch_table_bytes(void);
+int bsrht_apply_batch(const bsrht_apply_item_t *items, int count, void *table,
+                      size_t table_bytes, void *stream);
+
 /* Workspace bytes rsvd needs for an n x m input and target rank k. */
 size_t rsvd_workspace(bsrht_plan_t plan, int64_t m, int64_t k);
 

@@ -20,7 +20,8 @@ __all__ = [
     "nystrom_workspace", "WITH_REPLACEMENT", "WITHOUT_REPLACEMENT", "FP32",
     "SPLIT_BF16", "INFO_CHOL_FALLBACK", "INFO_RANK_CLAMPED", "INFO_QB_FALLBACK",
     "INFO_JACOBI_NOCONV", "EXPORTED_SYMBOLS", "JOB_SKETCH", "JOB_RSVD", "JobDesc",
-    "JobResult", "ServerStats", "Server", "bsrht_job_bytes",
+    "JobResult", "ServerStats", "Server", "bsrht_job_bytes", "apply_batch",
+    "batch_table_bytes", "ApplyItem", "BATCH_MAX",
 ]
 
 WITH_REPLACEMENT = 0
@@ -68,6 +69,8 @@ _SIGS = {
     "bsrht_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(_c_i64)]),
     "bsrht_timing_samples": (ctypes.c_int, [_c_vp, _c_i64, ctypes.POINTER(_c_i64)]),
+    "bsrht_batch_table_bytes": (_c_sz, []),
+    "bsrht_apply_batch": (ctypes.c_int, [_c_vp, ctypes.c_int, _c_vp, _c_sz, _c_vp]),
     "bsrht_stream_read": (ctypes.c_int, [_c_vp, _c_i64, _c_vp, _c_vp]),
     "nystrom": (ctypes.c_int, [_c_vp, _c_vp, _c_i64, _c_i64, _c_vp, _c_vp, _c_vp, _c_vp,
                                _c_sz, _c_vp]),
@@ -270,6 +273,41 @@ def bsrht_apply(plan, A, Y=None, ws=None, stream=None):
         plan.handle, _ptr(A), m, max(A.stride(0), m), _ptr(Y), max(Y.stride(0), m),
         _ptr(ws), ws.numel(), _stream_ptr(stream)))
     return Y
+
+
+BATCH_MAX = 64
+
+
+class ApplyItem(ctypes.Structure):
+    """bsrht_apply_item_t of include/bsrht.h: one bsrht_apply argument set."""
+    _fields_ = [("plan", _c_vp), ("A", _c_vp), ("m", _c_i64), ("lda", _c_i64),
+                ("Y", _c_vp), ("ldy", _c_i64), ("ws", _c_vp), ("ws_bytes", _c_sz)]
+
+
+def batch_table_bytes():
+    return int(lib().bsrht_batch_table_bytes())
+
+
+def apply_batch(items, table, stream=None):
+    """Several FP32 sketches in one persistent, graph-replayed launch.
+
+    items: sequence of (plan, A, Y, ws) with bsrht_apply's meaning (ws of at
+    least bsrht_apply_workspace(plan, m) bytes); table: a device uint8 tensor
+    of batch_table_bytes() bytes.  Each Y is bitwise what bsrht_apply gives."""
+    arr = (ApplyItem * max(len(items), 1))()
+    for i, (plan, A, Y, ws) in enumerate(items):
+        _check_matrix("A", A)
+        _check_matrix("Y", Y)
+        n, m = A.shape
+        if n != plan.n or Y.shape[0] != plan.l or Y.shape[1] != m:
+            raise ValueError("item shapes do not match its plan")
+        arr[i] = ApplyItem(plan.handle.value if isinstance(plan.handle, ctypes.c_void_p)
+                           else plan.handle, A.data_ptr(), m, max(A.stride(0), m),
+                           Y.data_ptr(), max(Y.stride(0), m),
+                           ws.data_ptr() if ws is not None and ws.numel() else None,
+                           ws.numel() if ws is not None else 0)
+    _check("bsrht_apply_batch", lib().bsrht_apply_batch(
+        arr, len(items), _ptr(table), table.numel(), _stream_ptr(stream)))
 
 
 def rsvd_workspace(plan, m, k):

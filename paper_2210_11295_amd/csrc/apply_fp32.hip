@@ -25,6 +25,10 @@
 // 1/sqrt(l) (the product sqrt(r/l) * 1/sqrt(r) of eq. (2.3)).
 #include <limits.h>
 
+#include <cstring>
+#include <mutex>
+#include <vector>
+
 #include "common.h"
 
 namespace bsrht {
@@ -184,27 +188,17 @@ struct FusedCta {
   }
 };
 
+// One workgroup's share of a launch: column tile bx, row split by, sample
+// group bz (T: the chunk buffer in LDS, NW*BR*kLDT floats).  Shared by the
+// single-job kernel and the persistent batch kernel, so that a job's result
+// does not depend on which of them ran it.
 template <int NW, int BR>
-__global__ __launch_bounds__(NW * 64) void fused_fp32_kernel(FusedArgs a) {
+__device__ __forceinline__ void fused_tile(const FusedArgs &a, float *T, int bx, int by, int bz) {
   using Cta = FusedCta<NW, BR>;
-  __shared__ __attribute__((aligned(16))) float T[Cta::B * kLDT];
   Cta cta(T, a);
   const int tid = threadIdx.x;
   cta.lane = tid & 63;
   cta.w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  // XCD-aware tile order: workgroups are dealt to the 8 XCDs round-robin, so
-  // linear id k runs on XCD k mod 8; give each XCD a contiguous range of
-  // (split, column tile) pairs in row-major order.
-  int bx = blockIdx.x, by = blockIdx.y;
-  {
-    const int nwg = (int)(gridDim.x * gridDim.y);
-    if ((nwg & 7) == 0) {
-      const int lin = (int)(blockIdx.x + gridDim.x * blockIdx.y);
-      const int idx = (lin & 7) * (nwg >> 3) + (lin >> 3);
-      bx = idx % (int)gridDim.x;
-      by = idx / (int)gridDim.x;
-    }
-  }
   const int c0 = bx * kCT;
   // Columns past m load a valid neighbour (column m-1); they never reach Y.
   const int cc = min(c0 + cta.lane, a.m - 1) - c0;
@@ -213,7 +207,7 @@ __global__ __launch_bounds__(NW * 64) void fused_fp32_kernel(FusedArgs a) {
   cta.wavebase = a.A + c0 + (int64_t)(cta.w * BR) * a.lda;
   const int q0 = by * a.chunks_per_split;
   const int q1 = min(q0 + a.chunks_per_split, a.total_chunks);
-  cta.j = blockIdx.z * (NW * 64) + tid;
+  cta.j = bz * (NW * 64) + tid;
   cta.jok = cta.j < a.l;
   const int rj = cta.jok ? a.R[cta.j] : 0;
   cta.pos = rj & (Cta::B - 1);
@@ -244,6 +238,25 @@ __global__ __launch_bounds__(NW * 64) void fused_fp32_kernel(FusedArgs a) {
     for (int k = 0; k < kCT; ++k)
       if (k < ncol) o[k] = cta.acc[k] * a.scale;
   }
+}
+
+template <int NW, int BR>
+__global__ __launch_bounds__(NW * 64) void fused_fp32_kernel(FusedArgs a) {
+  __shared__ __attribute__((aligned(16))) float T[NW * BR * kLDT];
+  // XCD-aware tile order: workgroups are dealt to the 8 XCDs round-robin, so
+  // linear id k runs on XCD k mod 8; give each XCD a contiguous range of
+  // (split, column tile) pairs in row-major order.
+  int bx = blockIdx.x, by = blockIdx.y;
+  {
+    const int nwg = (int)(gridDim.x * gridDim.y);
+    if ((nwg & 7) == 0) {
+      const int lin = (int)(blockIdx.x + gridDim.x * blockIdx.y);
+      const int idx = (lin & 7) * (nwg >> 3) + (lin >> 3);
+      bx = idx % (int)gridDim.x;
+      by = idx / (int)gridDim.x;
+    }
+  }
+  fused_tile<NW, BR>(a, T, bx, by, (int)blockIdx.z);
 }
 
 // Y[j, c] = scale * sum_s part[s][j][c], splits summed in ascending order.
@@ -343,6 +356,86 @@ int launch_fused(const Launch &L, FusedArgs &a, hipStream_t s) {
   return BSRHT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Batches of small sketches: one persistent launch per workgroup shape runs
+// the workgroup tiles of every job in the batch, read from a descriptor table
+// in device memory, and one persistent launch sums the row-split partials.
+// Each job keeps exactly the launch decomposition bsrht_apply would use (the
+// same template instance, chunk ranges, row splits and summation order), so
+// its result is bitwise the single call's.
+constexpr int kBatchMax = BSRHT_BATCH_MAX;
+
+struct BatchItem {
+  FusedArgs a;          // the single-job launch's arguments
+  int br, ctiles, splits, groups;
+  int wg_begin;         // first work item of the job in its list
+  int64_t red_begin;    // first element of the job in the reduce (splits > 1)
+  const float *part;    // row-split partials (splits > 1)
+  float *Y;
+  int64_t ldy;
+  int l, m;
+  int64_t split_stride;
+  float scale;
+};
+
+struct BatchList {  // jobs of one workgroup shape (8 or 16 waves)
+  int count, total_wg;
+  int64_t total_red;
+  BatchItem items[kBatchMax];
+};
+
+struct BatchTable {
+  BatchList nw8, nw16;
+};
+
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void fused_batch_kernel(const BatchList *__restrict__ L) {
+  __shared__ __attribute__((aligned(16))) float T[(NW == 8 ? 8 * 64 : 16 * 16) * kLDT];
+  const int total = L->total_wg, count = L->count;
+  for (int w = (int)blockIdx.x; w < total; w += (int)gridDim.x) {
+    int k = 0;  // the job whose work items contain w
+    while (k + 1 < count && L->items[k + 1].wg_begin <= w) ++k;
+    const BatchItem &it = L->items[k];
+    int loc = w - it.wg_begin;
+    const int bx = loc % it.ctiles;
+    loc /= it.ctiles;
+    const int by = loc % it.splits, bz = loc / it.splits;
+    const FusedArgs a = it.a;
+    if constexpr (NW == 16) {
+      fused_tile<16, 16>(a, T, bx, by, bz);
+    } else {
+      switch (it.br) {
+        case 64: fused_tile<8, 64>(a, T, bx, by, bz); break;
+        case 32: fused_tile<8, 32>(a, T, bx, by, bz); break;
+        case 16: fused_tile<8, 16>(a, T, bx, by, bz); break;
+        default: fused_tile<8, 8>(a, T, bx, by, bz); break;
+      }
+    }
+    __syncthreads();  // the next work item reuses T
+  }
+}
+
+// Y = scale * (sum of the splits in ascending order), as reduce_splits_kernel,
+// over the partials of every job of both lists.
+__global__ void reduce_batch_kernel(const BatchTable *__restrict__ tb) {
+  const int64_t n8 = tb->nw8.total_red, total = n8 + tb->nw16.total_red;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const BatchList &L = idx < n8 ? tb->nw8 : tb->nw16;
+    const int64_t e = idx < n8 ? idx : idx - n8;
+    int k = 0;  // the last job whose elements start at or before e
+    while (k + 1 < L.count && L.items[k + 1].red_begin <= e) ++k;
+    const BatchItem &it = L.items[k];
+    const int64_t loc = e - it.red_begin;
+    const int j = (int)(loc / it.m);
+    const int c = (int)(loc - (int64_t)j * it.m);
+    const float *pp = it.part + (int64_t)j * it.m + c;
+    float sum = 0.f;
+    for (int sp = 0; sp < it.splits; ++sp) sum += pp[(int64_t)sp * it.split_stride];
+    it.Y[(int64_t)j * it.ldy + c] = sum * it.scale;
+  }
+}
+
 }  // namespace
 
 size_t apply_fp32_ws_bytes(const bsrht_plan_s *plan, int64_t m) {
@@ -366,24 +459,16 @@ int reduce_splits(const float *part, int splits, int64_t split_stride, int64_t l
   return BSRHT_OK;
 }
 
-int apply_fp32(const bsrht_plan_s *pl, const float *A, int64_t m, int64_t lda, float *Y,
-               int64_t ldy, void *ws, size_t ws_bytes, hipStream_t s) {
-  const float scale = 1.0f / sqrtf((float)pl->l);
-  const Launch L = choose_launch(pl, m, lda);
-  if (L.direct) {
-    const int64_t total = pl->l * m;
-    const int tb = 256;
-    direct_kernel<<<(unsigned)((total + tb - 1) / tb), tb, 0, s>>>(
-        A, lda, (int)m, pl->R, pl->Dbits, pl->Dtbits, pl->dt_words, (int)pl->l, pl->p,
-        pl->log2r, Y, ldy, scale);
-    BSRHT_LAUNCH_CHECK();
-    return BSRHT_OK;
-  }
+namespace {
+
+// The fused launch's arguments for one sketch (checks the launch limits and
+// the workspace).
+int fused_args(const bsrht_plan_s *pl, const float *A, int64_t m, int64_t lda, float *Y,
+               int64_t ldy, void *ws, size_t ws_bytes, const Launch &L, FusedArgs &a) {
   if (L.groups > 65535 || L.ctiles <= 0) return BSRHT_EUNSUPPORTED;
   // Row offsets inside one wave's BR rows are 32-bit buffer offsets.
   if ((int64_t)L.br * lda * 4 >= (int64_t(1) << 31)) return BSRHT_EUNSUPPORTED;
   if (ws_bytes < L.ws || (L.ws && !ws)) return BSRHT_ENOMEM;
-  FusedArgs a;
   a.A = A;
   a.lda = lda;
   a.m = (int)m;
@@ -404,7 +489,90 @@ int apply_fp32(const bsrht_plan_s *pl, const float *A, int64_t m, int64_t lda, f
     a.out = Y;
     a.ldo = ldy;
     a.split_stride = 0;
-    a.scale = scale;
+    a.scale = 1.0f / sqrtf((float)pl->l);
+  }
+  return BSRHT_OK;
+}
+
+// The batch's two persistent sketch launches and its reduce, captured once
+// per (device, descriptor table) into a graph that later calls replay: the
+// kernels read everything else from the table.
+// Each entry also owns the pinned staging of the table's descriptors and an
+// event recorded after their copy, so the staging is rewritten only once
+// the previous copy has run.
+struct BatchGraph {
+  int device;
+  const void *table;
+  hipGraphExec_t exec;
+  char *pinned;
+  hipEvent_t copied;
+};
+std::mutex g_batch_mu;
+std::vector<BatchGraph> g_batch_graphs;
+
+int batch_graph(const void *table, BatchGraph *out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return BSRHT_EDEVICE;
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  for (const BatchGraph &g : g_batch_graphs)
+    if (g.device == dev && g.table == table) {
+      *out = g;
+      return BSRHT_OK;
+    }
+  void *pin = nullptr;
+  hipEvent_t ev = nullptr;
+  if (hipHostMalloc(&pin, sizeof(BatchTable), hipHostMallocDefault) != hipSuccess)
+    return BSRHT_EDEVICE;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipHostFree(pin);
+    return BSRHT_EDEVICE;
+  }
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return BSRHT_EDEVICE;
+  const BatchTable *tb = static_cast<const BatchTable *>(table);
+  const unsigned cus = (unsigned)device_cu_count();
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    fused_batch_kernel<8><<<cus, 8 * 64, 0, cs>>>(&tb->nw8);
+    fused_batch_kernel<16><<<cus, 16 * 64, 0, cs>>>(&tb->nw16);
+    reduce_batch_kernel<<<4 * cus, 256, 0, cs>>>(tb);
+    ok = hipGetLastError() == hipSuccess;
+    ok = hipStreamEndCapture(cs, &graph) == hipSuccess && ok;
+  }
+  ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cs);
+  if (!ok) {
+    (void)hipEventDestroy(ev);
+    (void)hipHostFree(pin);
+    return BSRHT_EDEVICE;
+  }
+  g_batch_graphs.push_back({dev, table, exec, static_cast<char *>(pin), ev});
+  *out = g_batch_graphs.back();
+  return BSRHT_OK;
+}
+
+}  // namespace
+
+int apply_fp32(const bsrht_plan_s *pl, const float *A, int64_t m, int64_t lda, float *Y,
+               int64_t ldy, void *ws, size_t ws_bytes, hipStream_t s) {
+  const float scale = 1.0f / sqrtf((float)pl->l);
+  const Launch L = choose_launch(pl, m, lda);
+  if (L.direct) {
+    const int64_t total = pl->l * m;
+    const int tb = 256;
+    direct_kernel<<<(unsigned)((total + tb - 1) / tb), tb, 0, s>>>(
+        A, lda, (int)m, pl->R, pl->Dbits, pl->Dtbits, pl->dt_words, (int)pl->l, pl->p,
+        pl->log2r, Y, ldy, scale);
+    BSRHT_LAUNCH_CHECK();
+    return BSRHT_OK;
+  }
+  FusedArgs a;
+  {
+    const int st = fused_args(pl, A, m, lda, Y, ldy, ws, ws_bytes, L, a);
+    if (st != BSRHT_OK) return st;
   }
   int st;
   if (L.nw == 16) {
@@ -442,6 +610,60 @@ int bsrht_apply(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, float
   if (plan->precision == BSRHT_SPLIT_BF16)
     return apply_split_bf16(plan, A, m, lda, Y, ldy, ws, ws_bytes, s);
   return apply_fp32(plan, A, m, lda, Y, ldy, ws, ws_bytes, s);
+}
+
+size_t bsrht_batch_table_bytes(void) { return sizeof(BatchTable); }
+
+int bsrht_apply_batch(const bsrht_apply_item_t *items, int count, void *table,
+                      size_t table_bytes, void *stream) {
+  if (count < 0 || count > kBatchMax || (count > 0 && !items) || !table ||
+      table_bytes < sizeof(BatchTable))
+    return BSRHT_EINVAL;
+  if (count == 0) return BSRHT_OK;
+  std::vector<char> hbuf(sizeof(BatchTable), 0);
+  BatchTable &h = *reinterpret_cast<BatchTable *>(hbuf.data());
+  for (int i = 0; i < count; ++i) {
+    const bsrht_apply_item_t &in = items[i];
+    const bsrht_plan_s *pl = in.plan;
+    const int64_t m = in.m;
+    if (!pl || m < 1 || !in.A || !in.Y || in.lda < m || in.ldy < m || m > INT_MAX)
+      return BSRHT_EINVAL;
+    if (pl->precision != BSRHT_FP32 || pl->l * m > ((int64_t)1 << 40)) return BSRHT_EUNSUPPORTED;
+    const Launch L = choose_launch(pl, m, in.lda);
+    if (L.direct) return BSRHT_EUNSUPPORTED;
+    BatchList &bl = L.nw == 16 ? h.nw16 : h.nw8;
+    BatchItem &it = bl.items[bl.count];
+    const int st = fused_args(pl, in.A, m, in.lda, in.Y, in.ldy, in.ws, in.ws_bytes, L, it.a);
+    if (st != BSRHT_OK) return st;
+    const int64_t wgs = (int64_t)L.ctiles * L.splits * L.groups;
+    if (bl.total_wg + wgs > INT_MAX) return BSRHT_EUNSUPPORTED;
+    it.br = L.br;
+    it.ctiles = L.ctiles;
+    it.splits = L.splits;
+    it.groups = L.groups;
+    it.wg_begin = bl.total_wg;
+    bl.total_wg += (int)wgs;
+    it.red_begin = bl.total_red;
+    it.part = static_cast<const float *>(in.ws);
+    it.Y = in.Y;
+    it.ldy = in.ldy;
+    it.l = (int)pl->l;
+    it.m = (int)m;
+    it.split_stride = pl->l * m;
+    it.scale = 1.0f / sqrtf((float)pl->l);
+    if (L.splits > 1) bl.total_red += pl->l * m;
+    ++bl.count;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  BatchGraph g;
+  BSRHT_TRY(batch_graph(table, &g));
+  if (hipEventSynchronize(g.copied) != hipSuccess) return BSRHT_EDEVICE;
+  std::memcpy(g.pinned, hbuf.data(), sizeof(BatchTable));
+  if (hipMemcpyAsync(table, g.pinned, sizeof(BatchTable), hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      hipEventRecord(g.copied, s) != hipSuccess || hipGraphLaunch(g.exec, s) != hipSuccess)
+    return BSRHT_EDEVICE;
+  return BSRHT_OK;
 }
 
 }  // extern "C"
