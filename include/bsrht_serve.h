@@ -17,7 +17,12 @@
  * coroutine that queues its kernels on its slot's stream and suspends where
  * the algorithm needs a value from the device (a Cholesky flag, a Jacobi
  * sweep count); the server resumes it once the event recorded there has
- * completed.  There are no worker threads: jobs advance inside
+ * completed.  Small FP32 sketch jobs (blocks of >= 64 rows, A of at most
+ * 64 MiB) that are ready together run as one batched launch on one slot
+ * (bsrht_apply_batch: persistent kernels replayed from a captured HIP graph;
+ * each result is bitwise the single call's); up to BSRHT_BATCH_MAX such jobs
+ * are admitted beyond the slot count, and each slot keeps its descriptor
+ * table in the arena (bsrht_batch_table_bytes bytes).  There are no worker threads: jobs advance inside
  * bsrht_server_submit, bsrht_server_poll and bsrht_server_drain, which make
  * every HIP call of the server, so a client keeps polling while jobs run.
  *
@@ -88,6 +93,8 @@ typedef struct {
   int64_t peak_arena_bytes;  /* high-water mark of arena bytes in use */
   int peak_running;          /* high-water mark of concurrently running jobs */
   int64_t queued;            /* waiting for admission now */
+  int64_t batches;           /* batched launches of small sketch jobs */
+  int64_t batched_jobs;      /* jobs that ran in them */
 } bsrht_server_stats_t;
 
 /* Arena bytes a job needs when its plan is not cached (workspace + tables);

@@ -98,7 +98,8 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", _c_i64), ("completed", _c_i64), ("rejected", _c_i64),
                 ("plan_hits", _c_i64), ("plan_misses", _c_i64), ("plan_evictions", _c_i64),
                 ("backfilled", _c_i64), ("peak_arena_bytes", _c_i64),
-                ("peak_running", ctypes.c_int), ("queued", _c_i64)]
+                ("peak_running", ctypes.c_int), ("queued", _c_i64),
+                ("batches", _c_i64), ("batched_jobs", _c_i64)]
 
 
 # the declarations of include/bsrht_serve.h

@@ -29,6 +29,8 @@ constexpr double kMaxBypassSeconds = 0.1;  // after this, nothing passes the old
 constexpr int kMaxWorkers = 64;
 constexpr size_t kStagingHalf = 64 * 1024;  // pinned bytes per direction per stream slot
 constexpr double kPollSleep = 20e-6;        // seconds between executor passes while waiting
+constexpr int kBatchJobs = BSRHT_BATCH_MAX;    // small sketch jobs fused into one launch
+constexpr int64_t kBatchJobBytes = 64 << 20;   // A of at most this many bytes is "small"
 
 size_t round_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -142,10 +144,27 @@ bool valid_job(const bsrht_job_t &j, bool fake) {
   return j.U && j.S && j.V && j.info;
 }
 
+// A job whose sketch may run fused with other small ones in one batched,
+// graph-replayed launch (bsrht_apply_batch): FP32, blocks of >= 64 rows, A
+// of at most kBatchJobBytes.
+bool batchable(const bsrht_job_t &j) {
+  return j.kind == BSRHT_JOB_SKETCH && j.precision == BSRHT_FP32 && j.n / j.p >= 64 &&
+         j.n * j.m * 4 <= kBatchJobBytes;
+}
+
 // The work of one job on its slot's stream, ending when the stream has
 // finished it.
 Task sketch_job(DevCtx &ctx, bsrht_plan_t plan, const bsrht_job_t j, void *ws, size_t ws_bytes) {
   const int st = bsrht_apply(plan, j.A, j.m, j.lda, j.Y, j.ldy, ws, ws_bytes, ctx.s);
+  if (st != BSRHT_OK) co_return st;
+  co_return co_await drained(ctx);
+}
+
+// Several small sketch jobs as one batched launch on the slot's stream.
+Task batch_job(DevCtx &ctx, std::vector<bsrht_apply_item_t> items, void *table,
+               size_t table_bytes) {
+  const int st =
+      bsrht_apply_batch(items.data(), (int)items.size(), table, table_bytes, ctx.s);
   if (st != BSRHT_OK) co_return st;
   co_return co_await drained(ctx);
 }
@@ -160,7 +179,11 @@ Task rsvd_job(DevCtx &ctx, bsrht_plan_t plan, const bsrht_job_t j, void *ws, siz
 struct Slot {
   DevCtx ctx;
   Job *job = nullptr;
+  std::vector<Job *> batch;  // the jobs of a batched launch (job == nullptr then)
+  size_t table_off = 0;      // the slot's batch descriptor table in the arena
+  bool has_table = false;
   std::optional<Task> task;
+  bool busy() const { return job != nullptr || !batch.empty(); }
 };
 
 }  // namespace
@@ -261,14 +284,20 @@ struct bsrht_server_s {
     }
   }
 
-  // Admits waiting jobs while a worker is free (called with mu held).
+  // Admits waiting jobs while a worker is free (called with mu held).  The
+  // GPU executor also admits up to kBatchJobs small sketch jobs beyond that,
+  // which a free slot then runs as one batched launch.
   void admit() {
-    while (!queue.empty() && (int)ready.size() + running < nworkers) {
+    while (!queue.empty()) {
+      const int busy = (int)ready.size() + running;
+      const bool room = busy < nworkers;
+      if (!room && (fake || busy >= nworkers + kBatchJobs)) break;
       const bool overdue = now() - queue.front()->t_submit > kMaxBypassSeconds;
       const int window = overdue ? 1 : std::min<int>((int)queue.size(), kBackfillWindow);
       bool admitted = false;
       for (int i = 0; i < window; ++i) {
         Job *jb = queue[(size_t)i];
+        if (!room && !batchable(jb->j)) continue;
         if (!reserve(jb)) continue;
         if (i > 0) ++st.backfilled;
         queue.erase(queue.begin() + i);
@@ -326,8 +355,9 @@ struct bsrht_server_s {
   }
 
   // ---- GPU executor ----
-  void start_job(Slot &sl, Job *jb) {
-    sl.job = jb;
+  // Marks the job running and builds its plan on the slot's stream when it is
+  // not cached yet; false (job retired) when the plan cannot be built.
+  bool begin_job(Slot &sl, Job *jb) {
     ++running;
     st.peak_running = std::max(st.peak_running, running);
     jb->t_start = now();
@@ -341,10 +371,41 @@ struct bsrht_server_s {
       pe->status = rc;
     }
     if (pe->state == PlanEntry::FAILED) {
-      sl.job = nullptr;
       retire(jb, pe->status, now());
-      return;
+      return false;
     }
+    return true;
+  }
+
+  void start_batch(Slot &sl, std::vector<Job *> &jobs) {
+    std::vector<bsrht_apply_item_t> items;
+    for (Job *jb : jobs) {
+      if (!begin_job(sl, jb)) continue;
+      sl.batch.push_back(jb);
+      const bsrht_job_t &j = jb->j;
+      bsrht_apply_item_t it;
+      it.plan = jb->pe->plan;
+      it.A = j.A;
+      it.m = j.m;
+      it.lda = j.lda;
+      it.Y = j.Y;
+      it.ldy = j.ldy;
+      it.ws = jb->has_ws ? base + jb->ws_off : nullptr;
+      it.ws_bytes = jb->ws_bytes;
+      items.push_back(it);
+    }
+    if (items.empty()) return;
+    ++st.batches;
+    st.batched_jobs += (int64_t)items.size();
+    sl.task.emplace(batch_job(sl.ctx, std::move(items), base + sl.table_off,
+                              bsrht_batch_table_bytes()));
+    sl.task->start();
+  }
+
+  void start_job(Slot &sl, Job *jb) {
+    if (!begin_job(sl, jb)) return;
+    sl.job = jb;
+    PlanEntry *pe = jb->pe;
     void *ws = jb->has_ws ? base + jb->ws_off : nullptr;
     if (jb->j.kind == BSRHT_JOB_SKETCH)
       sl.task.emplace(sketch_job(sl.ctx, pe->plan, jb->j, ws, jb->ws_bytes));
@@ -357,7 +418,10 @@ struct bsrht_server_s {
     Job *jb = sl.job;
     sl.job = nullptr;
     sl.task.reset();
-    retire(jb, rc, now());
+    const double t = now();
+    if (jb) retire(jb, rc, t);
+    for (Job *b : sl.batch) retire(b, rc, t);
+    sl.batch.clear();
   }
 
   // One executor pass: resume jobs whose awaited event has completed, retire
@@ -367,7 +431,7 @@ struct bsrht_server_s {
     for (bool moved = true; moved;) {
       moved = false;
       for (Slot &sl : slots) {
-        if (!sl.job) continue;
+        if (!sl.busy()) continue;
         if (!sl.task->done()) {
           const hipError_t q = hipEventQuery(sl.ctx.ev);
           if (q == hipErrorNotReady) continue;
@@ -386,7 +450,25 @@ struct bsrht_server_s {
       }
       admit();
       for (Slot &sl : slots) {
-        if (sl.job || ready.empty()) continue;
+        if (sl.busy() || ready.empty()) continue;
+        if (sl.has_table && batchable(ready.front()->j)) {
+          // the small sketch jobs among the ready ones, in order
+          std::vector<Job *> b;
+          for (auto it = ready.begin(); it != ready.end() && (int)b.size() < kBatchJobs;) {
+            if (batchable((*it)->j)) {
+              b.push_back(*it);
+              it = ready.erase(it);
+            } else {
+              ++it;
+            }
+          }
+          if (b.size() >= 2) {
+            start_batch(sl, b);
+            moved = true;
+            continue;
+          }
+          ready.push_front(b[0]);
+        }
         Job *jb = ready.front();
         ready.pop_front();
         start_job(sl, jb);
@@ -414,6 +496,8 @@ struct bsrht_server_s {
       sl.ctx.blocking = false;
       sl.ctx.pinned = static_cast<char *>(pin);
       sl.ctx.half_bytes = kStagingHalf;
+      // a slot without room for a descriptor table runs small jobs one by one
+      sl.has_table = arena.alloc(bsrht_batch_table_bytes(), &sl.table_off);
     }
     return BSRHT_OK;
   }

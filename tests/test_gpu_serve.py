@@ -100,3 +100,42 @@ def test_mix_equals_alone_and_matches_oracle():
             assert err <= 1.01 * err_o + 1e-6, (js, err, err_o)
         checked += 1
     assert checked >= 4
+
+
+def test_small_sketch_jobs_run_batched_and_equal_alone():
+    """A burst of small FP32 sketch jobs (with a few RSVD and split-BF16 jobs
+    between them) on two slots: the small sketches run as batched launches
+    (one persistent, graph-replayed launch per batch), and every job's result
+    is bitwise the single call's."""
+    dev = device()
+    rs = np.random.default_rng(11)
+    jobs = []
+    for i in range(90):
+        n = 1 << int(rs.integers(10, 15))
+        p = int(rs.choice([1, 4, 16]))
+        m = int(rs.integers(1, 200))
+        k = int(rs.integers(1, 20))
+        kind = bs.JOB_RSVD if i % 15 == 7 else bs.JOB_SKETCH
+        prec = bs.SPLIT_BF16 if i % 11 == 3 else bs.FP32
+        l = min(int(rs.choice([32, 100, 300, 700])), n) if kind == bs.JOB_SKETCH else 2 * k + 8
+        jobs.append(dict(id=i, kind=kind, n=n, m=m, p=p, l=l, k=k, prec=prec,
+                         seed=int(rs.integers(0, 3)), data=int(rs.integers(0, 2 ** 31))))
+    arena = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    payloads = {js["id"]: _payload(js, dev) for js in jobs}
+    torch.cuda.synchronize()
+    with bs.Server(arena=arena, workers=2) as srv:
+        for js in jobs:
+            A, out = payloads[js["id"]]
+            srv.submit(_desc(js, A, out))
+        srv.drain()
+        res = {r.id: r for r in srv.poll(1000)}
+        st = srv.stats()
+    say("stats", st)
+    assert len(res) == len(jobs) and all(r.status == 0 for r in res.values())
+    assert st["batches"] >= 1 and st["batched_jobs"] >= 2 * st["batches"]
+    for js in jobs:
+        A, out = payloads[js["id"]]
+        ref = _alone(js, A)
+        torch.cuda.synchronize()
+        for name, t in ref.items():
+            assert torch.equal(out[name], t), (js, name)
