@@ -378,6 +378,68 @@ def bench_nystrom(bs, reps):
             "info": int(info.item())}
 
 
+def bench_serving_small(bs, njobs=3000, rate=None, streams=SERVE_STREAMS, seed=1):
+    """Small FP32 sketch jobs (n = 2^a, a in 12..16; m log-uniform in
+    [16, 512]; p in {1, 4, 16}; l in {64, 128, 256, 512}: 60 plans, which the
+    server's cache keeps), submitted as one burst (or at
+    Poisson arrivals of `rate` jobs/s), run once with the server's batched
+    launches of small jobs and once with every job alone on a slot.  At
+    offered rates the slots keep up with (tens of thousands of jobs/s) no
+    batch ever forms; a backlog is where fusion acts, so the default is a
+    burst.  Payloads are slices of a few device matrices prepared beforehand
+    (inputs are read-only; each job has its own output).  Reports jobs/s
+    (jobs over first arrival to last completion) and p50/p99 latency from the
+    scheduled arrival."""
+    import torch
+    dev = torch.device("cuda:0")
+    rs = np.random.default_rng(seed)
+    t = np.cumsum(rs.exponential(1.0 / rate, size=njobs)) if rate else np.zeros(njobs)
+    pool = [torch.randn(1 << 16, 512, device=dev) for _ in range(4)]
+    jobs = []
+    for i in range(njobs):
+        n = 1 << int(rs.integers(12, 17))
+        m = int(round(math.exp(rs.uniform(math.log(16), math.log(512)))))
+        p = int(rs.choice([1, 4, 16]))
+        l = min(int(rs.choice([64, 128, 256, 512])), n)
+        A = pool[i % len(pool)][:n, :m]
+        Y = torch.empty(l, m, device=dev)
+        desc = bs.sketch_job(i, (n, p, l, 0, bs.WITH_REPLACEMENT, bs.FP32), A, Y)
+        jobs.append((i, float(t[i]), desc, A, Y))
+    torch.cuda.synchronize()
+    arena = torch.empty(8 << 30, dtype=torch.uint8, device=dev)
+    out = {"jobs": njobs, "offered_jobs_per_s": rate if rate else "burst",
+           "stream_slots": streams}
+    for mode in ("batched", "alone"):
+        lat = {}
+        with bs.Server(arena=arena, workers=streams) as srv:
+            srv.set_batching(mode == "batched")
+            t0 = srv.clock() + 0.02
+            if rate:
+                for (i, arr, desc, A, Y) in jobs:
+                    while srv.clock() < t0 + arr:
+                        for r in srv.poll(256):
+                            lat[r.id] = r.t_done - (t0 + jobs[r.id][1])
+                    srv.submit(desc)
+            else:
+                while srv.clock() < t0:
+                    pass
+                srv.submit_many([js[2] for js in jobs])
+            srv.drain()
+            for r in srv.poll(njobs):
+                lat[r.id] = r.t_done - (t0 + jobs[r.id][1])
+            st = srv.stats()
+        L = np.array([lat[i] for i in range(njobs)]) * 1e3
+        span = max(lat[i] + jobs[i][1] for i in range(njobs)) - jobs[0][1]
+        out[mode] = {"jobs_per_s": round(njobs / span, 1),
+                     "p50_ms": round(float(np.percentile(L, 50)), 3),
+                     "p99_ms": round(float(np.percentile(L, 99)), 3),
+                     "batches": st["batches"], "batched_jobs": st["batched_jobs"]}
+        log(f"bench: small sketch serving ({mode}): {out[mode]}")
+    del arena, pool
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -393,7 +455,8 @@ def main():
                     help="jobs of the serving workload (0 skips it)")
     ap.add_argument("--serve-streams", type=int, default=SERVE_STREAMS)
     ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--only", choices=["all", "sketch", "bf16", "rsvd", "nystrom", "serve"],
+    ap.add_argument("--only", choices=["all", "sketch", "bf16", "rsvd", "nystrom", "serve",
+                                       "serve_small"],
                     default="all",
                     help="profiling aid: run one part ('bf16', 'rsvd', 'nystrom' and 'serve' print only "
                          "that part's JSON object)")
@@ -411,6 +474,9 @@ def main():
     if args.only == "serve":
         print(json.dumps({"serving": bench_serving(bs, args.serve_jobs, args.serve_streams,
                                                    rate=args.serve_rate)}), flush=True)
+        return
+    if args.only == "serve_small":
+        print(json.dumps({"serving_small_sketch": bench_serving_small(bs)}), flush=True)
         return
     if args.only == "nystrom":
         print(json.dumps({"nystrom": bench_nystrom(bs, args.lowrank_reps)}), flush=True)
@@ -510,6 +576,7 @@ def main():
     if args.serve_jobs > 0 and args.only == "all":
         out["serving"] = bench_serving(bs, args.serve_jobs, args.serve_streams,
                                        rate=args.serve_rate)
+        out["serving_small_sketch"] = bench_serving_small(bs)
     print(json.dumps(out), flush=True)
 
 

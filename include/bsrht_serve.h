@@ -22,7 +22,8 @@
  * (bsrht_apply_batch: persistent kernels replayed from a captured HIP graph;
  * each result is bitwise the single call's); up to BSRHT_BATCH_MAX such jobs
  * are admitted beyond the slot count, and each slot keeps its descriptor
- * table in the arena (bsrht_batch_table_bytes bytes).  There are no worker threads: jobs advance inside
+ * table in the arena (bsrht_batch_table_bytes bytes).  There are no worker
+ * threads: jobs advance inside
  * bsrht_server_submit, bsrht_server_poll and bsrht_server_drain, which make
  * every HIP call of the server, so a client keeps polling while jobs run.
  *
@@ -123,11 +124,25 @@ int bsrht_server_create_fake(size_t arena_bytes, int workers, double seconds_per
  * BSRHT_ENOMEM when the job alone needs more than the whole arena. */
 int bsrht_server_submit(bsrht_server_t srv, const bsrht_job_t *job);
 
+/*
+ * Submits jobs[0 .. count) in order under one lock, then admits and starts
+ * what fits (a burst of jobs arrives together, which is what lets small
+ * sketch jobs be batched).  Each job is checked as by bsrht_server_submit;
+ * the first rejected job stops the call: *accepted receives the number of
+ * jobs submitted before it, and its status is returned.
+ */
+int bsrht_server_submit_many(bsrht_server_t srv, const bsrht_job_t *jobs, int count,
+                             int *accepted);
+
 /* Advances running jobs, then moves up to max finished results into out
  * (completion order) and stores their number in *count; waits up to
  * timeout_s seconds for the first one when none is ready (0 = do not wait). */
 int bsrht_server_poll(bsrht_server_t srv, bsrht_job_result_t *out, int max, double timeout_s,
                       int *count);
+
+/* Turns the batched launches of small sketch jobs on (default) or off; off,
+ * every job runs alone on a slot.  Applies to jobs started afterwards. */
+int bsrht_server_set_batching(bsrht_server_t srv, int on);
 
 /* Runs / waits until every submitted job has finished. */
 int bsrht_server_drain(bsrht_server_t srv);

@@ -109,6 +109,9 @@ _SIGS.update({
     "bsrht_server_create_fake": (ctypes.c_int, [_c_sz, ctypes.c_int, ctypes.c_double,
                                                 ctypes.POINTER(_c_vp)]),
     "bsrht_server_submit": (ctypes.c_int, [_c_vp, ctypes.POINTER(JobDesc)]),
+    "bsrht_server_set_batching": (ctypes.c_int, [_c_vp, ctypes.c_int]),
+    "bsrht_server_submit_many": (ctypes.c_int, [_c_vp, ctypes.POINTER(JobDesc), ctypes.c_int,
+                                                ctypes.POINTER(ctypes.c_int)]),
     "bsrht_server_poll": (ctypes.c_int, [_c_vp, ctypes.POINTER(JobResult), ctypes.c_int,
                                          ctypes.c_double, ctypes.POINTER(ctypes.c_int)]),
     "bsrht_server_drain": (ctypes.c_int, [_c_vp]),
@@ -394,6 +397,15 @@ class Server:
         st = lib().bsrht_server_submit(self.handle, ctypes.byref(job))
         _check("bsrht_server_submit", st)
 
+    def submit_many(self, jobs):
+        """Submits a list of JobDesc at once; returns how many were accepted
+        (raises on the first rejected one after submitting those before it)."""
+        arr = (JobDesc * max(len(jobs), 1))(*jobs)
+        acc = ctypes.c_int()
+        st = lib().bsrht_server_submit_many(self.handle, arr, len(jobs), ctypes.byref(acc))
+        _check("bsrht_server_submit_many", st)
+        return acc.value
+
     def poll(self, max_results=256, timeout=0.0):
         buf = (JobResult * max_results)()
         c = ctypes.c_int()
@@ -408,6 +420,9 @@ class Server:
         out = ServerStats()
         _check("bsrht_server_stats", lib().bsrht_server_stats(self.handle, ctypes.byref(out)))
         return {name: getattr(out, name) for name, _ in ServerStats._fields_}
+
+    def set_batching(self, on):
+        _check("bsrht_server_set_batching", lib().bsrht_server_set_batching(self.handle, int(on)))
 
     def clock(self):
         return float(lib().bsrht_server_clock(self.handle))

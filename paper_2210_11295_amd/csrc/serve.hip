@@ -193,6 +193,7 @@ using namespace bsrht;
 
 struct bsrht_server_s {
   bool fake = false;
+  bool batching = true;  // small sketch jobs may run as batched launches
   double sec_per_gb = 0.0;
   char *base = nullptr;
   size_t arena_bytes = 0;
@@ -291,7 +292,7 @@ struct bsrht_server_s {
     while (!queue.empty()) {
       const int busy = (int)ready.size() + running;
       const bool room = busy < nworkers;
-      if (!room && (fake || busy >= nworkers + kBatchJobs)) break;
+      if (!room && (fake || !batching || busy >= nworkers + kBatchJobs)) break;
       const bool overdue = now() - queue.front()->t_submit > kMaxBypassSeconds;
       const int window = overdue ? 1 : std::min<int>((int)queue.size(), kBackfillWindow);
       bool admitted = false;
@@ -451,7 +452,7 @@ struct bsrht_server_s {
       admit();
       for (Slot &sl : slots) {
         if (sl.busy() || ready.empty()) continue;
-        if (sl.has_table && batchable(ready.front()->j)) {
+        if (batching && sl.has_table && batchable(ready.front()->j)) {
           // the small sketch jobs among the ready ones, in order
           std::vector<Job *> b;
           for (auto it = ready.begin(); it != ready.end() && (int)b.size() < kBatchJobs;) {
@@ -581,6 +582,44 @@ int bsrht_server_submit(bsrht_server_t srv, const bsrht_job_t *job) {
   return BSRHT_OK;
 }
 
+int bsrht_server_submit_many(bsrht_server_t srv, const bsrht_job_t *jobs, int count,
+                             int *accepted) {
+  if (!srv || count < 0 || (count > 0 && !jobs) || !accepted) return BSRHT_EINVAL;
+  *accepted = 0;
+  std::vector<Job *> made;
+  int rc = BSRHT_OK;
+  for (int i = 0; i < count; ++i) {
+    const bsrht_job_t &j = jobs[i];
+    if (!valid_job(j, srv->fake)) {
+      rc = BSRHT_EINVAL;
+    } else if (bsrht_job_bytes(&j) > srv->arena_bytes) {
+      rc = BSRHT_ENOMEM;
+    } else {
+      Job *jb = new (std::nothrow) Job;
+      if (!jb) {
+        rc = BSRHT_ENOMEM;
+      } else {
+        jb->j = j;
+        made.push_back(jb);
+        continue;
+      }
+    }
+    break;  // the first rejected job stops the call
+  }
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (rc != BSRHT_OK) ++srv->st.rejected;
+  const double t = srv->now();
+  for (Job *jb : made) {
+    jb->t_submit = t;
+    srv->queue.push_back(jb);
+    ++srv->st.submitted;
+  }
+  *accepted = (int)made.size();
+  srv->admit();
+  if (!srv->fake) srv->pump();
+  return rc;
+}
+
 int bsrht_server_poll(bsrht_server_t srv, bsrht_job_result_t *out, int max, double timeout_s,
                       int *count) {
   if (!srv || !count || max < 0 || (max > 0 && !out)) return BSRHT_EINVAL;
@@ -629,6 +668,13 @@ int bsrht_server_stats(bsrht_server_t srv, bsrht_server_stats_t *out) {
   std::lock_guard<std::mutex> lk(srv->mu);
   *out = srv->st;
   out->queued = (int64_t)srv->queue.size();
+  return BSRHT_OK;
+}
+
+int bsrht_server_set_batching(bsrht_server_t srv, int on) {
+  if (!srv) return BSRHT_EINVAL;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  srv->batching = on != 0;
   return BSRHT_OK;
 }
 

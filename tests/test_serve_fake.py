@@ -150,3 +150,17 @@ def test_invalid_server_arguments():
     assert L.bsrht_server_create(None, 1 << 20, 2, ctypes.byref(h)) == -1
     assert L.bsrht_server_create(ctypes.c_void_p(4096 + 8), 1 << 20, 2, ctypes.byref(h)) == -1
     assert L.bsrht_server_create(ctypes.c_void_p(4096), 1 << 20, 0, ctypes.byref(h)) == -1
+
+
+def test_submit_many_stops_at_the_first_rejected_job():
+    with bs.Server(fake_bytes=1 << 30, workers=3, seconds_per_gb=0.1) as srv:
+        assert srv.submit_many([job(i) for i in range(5)]) == 5
+        with pytest.raises(bs.BsrhtError) as e:
+            srv.submit_many([job(10), job(11), job(12, p=3), job(13)])
+        assert e.value.status == -1
+        srv.drain()
+        res = srv.poll(64)
+        assert sorted(r.id for r in res) == [0, 1, 2, 3, 4, 10, 11]
+        st = srv.stats()
+        assert st["submitted"] == 7 and st["rejected"] == 1 and st["completed"] == 7
+        assert srv.submit_many([]) == 0
