@@ -171,6 +171,54 @@ def bench_split_bf16(bs, A, cfg, steps, warmup, Y_fp32):
             "rel_diff_vs_fp32": diff}
 
 
+def bench_right(bs, A, cfg, steps, warmup, Y_col):
+    """The sketch applied from the right, Y = A^T Omega^T, on the transpose of
+    the same input (1024 x 2^20 row-major: the orientation of Algorithm 1),
+    with the same plan; compared with the column sketch of A."""
+    import torch
+    n, m, p, l, seed = cfg["n"], cfg["m"], cfg["p"], cfg["l"], cfg["seed"]
+    At = A.t().contiguous()
+    plan = bs.Plan(n, p, l, seed, device=A.device)
+    Y = torch.empty(m, l, dtype=torch.float32, device=A.device)
+    ws = torch.empty(max(1, bs.bsrht_apply_right_workspace(plan, m)), dtype=torch.uint8,
+                     device=A.device)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        bs.bsrht_apply_right(plan, At, Y, ws, stream)
+    torch.cuda.synchronize()
+    bs.timing_enable(bs.TIMING_APPLY_RIGHT)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        bs.bsrht_apply_right(plan, At, Y, ws, stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern_ms, launches = bs.timing_read()
+    stats = _kernel_stats(bs)
+    bs.timing_enable(bs.TIMING_OFF)
+    kern_avg_ms = kern_ms / max(launches, 1)
+    bytes_a = n * m * 4
+    table_bytes = 4 * l + 4 * ((n + 31) // 32) + 4 * p * ((l + 31) // 32)
+    alg_bytes = bytes_a + 4 * l * m + table_bytes
+    achieved = alg_bytes / (kern_avg_ms * 1e-3) / 1e9
+    diff = float((Y.double() - Y_col.double().t()).norm() / Y_col.double().norm())
+    log(f"bench: right apply {bytes_a * steps / elapsed / 1e9:.1f} GB/s whole call; kernel "
+        f"{kern_avg_ms * 1e3:.1f} us -> {achieved:.1f} GB/s; rel diff vs column sketch "
+        f"{diff:.2e}")
+    traffic = _traffic("traffic_right_fp32_sketch_1024x2p20.json", ["apply_right.hip"],
+                       alg_bytes)
+    del At
+    return {"value": round(bytes_a * steps / elapsed / 1e9, 2), "unit": "GB/s",
+            "ms_per_step": round(elapsed / steps * 1e3, 4),
+            "workload": f"Y = A Omega^T, A {m} x {n} float32 row-major (the transpose of the "
+                        f"column workload), p={p}, l={l}, seed {seed}",
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "traffic": traffic, "kernel": "right_fp32_kernel<8>",
+                         "kernel_avg_us": round(kern_avg_ms * 1e3, 2), **stats,
+                         "alg_bytes_per_launch": alg_bytes},
+            "rel_diff_vs_column_sketch": diff}
+
+
 def _fro_error(A, U, S, V, chunk=1 << 16):
     """||A - U diag(S) V^T||_F / ||A||_F in FP64 on the device (measurement)."""
     import torch
@@ -455,11 +503,11 @@ def main():
                     help="jobs of the serving workload (0 skips it)")
     ap.add_argument("--serve-streams", type=int, default=SERVE_STREAMS)
     ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--only", choices=["all", "sketch", "bf16", "rsvd", "nystrom", "serve",
-                                       "serve_small"],
+    ap.add_argument("--only", choices=["all", "sketch", "bf16", "right", "rsvd", "nystrom",
+                                       "serve", "serve_small"],
                     default="all",
-                    help="profiling aid: run one part ('bf16', 'rsvd', 'nystrom' and 'serve' print only "
-                         "that part's JSON object)")
+                    help="profiling aid: run one part ('bf16', 'right', 'rsvd', 'nystrom' and "
+                         "'serve' print only that part's JSON object)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -498,6 +546,13 @@ def main():
         if args.copy_calibration:
             _copy_calibration(A)
         print(json.dumps({"split_bf16": out_b}), flush=True)
+        return
+    if args.only == "right":
+        Yf = bs.bsrht_apply(plan, A)
+        out_r = bench_right(bs, A, cfg, args.steps, args.warmup, Yf)
+        if args.copy_calibration:
+            _copy_calibration(A)
+        print(json.dumps({"right_apply": out_r}), flush=True)
         return
     Y = torch.empty(l, m, dtype=torch.float32, device=dev)
     ws = torch.empty(max(1, bs.bsrht_apply_workspace(plan, m)), dtype=torch.uint8, device=dev)
@@ -563,6 +618,7 @@ def main():
         args.skip_lowrank = True
     else:
         out["split_bf16"] = bench_split_bf16(bs, A, cfg, args.steps, args.warmup, Y)
+        out["right_apply"] = bench_right(bs, A, cfg, args.steps, args.warmup, Y)
     if not args.skip_lowrank:
         out["rsvd"] = bench_rsvd(bs, A, plan, cfg, args.lowrank_reps)
     if not args.skip_cpu_baseline:

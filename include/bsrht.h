@@ -150,6 +150,34 @@ size_t bsrht_apply_workspace(bsrht_plan_t plan, int64_t m);
 int bsrht_apply(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda,
                 float *Y, int64_t ldy, void *ws, size_t ws_bytes, void *stream);
 
+/* Workspace bytes bsrht_apply_right needs for an m x n input (0 is possible). */
+size_t bsrht_apply_right_workspace(bsrht_plan_t plan, int64_t m);
+
+/*
+ * Y = A Omega^T: the same block SRHT applied from the right, to the rows of
+ * A along their contiguous dimension (the sketch A Omega^T of Algorithm 1,
+ * section 3.1, in the paper's own orientation; eq. (2.3)-(2.4) per row).
+ * Equal to (Omega A^T)^T up to FP32 rounding; A is read once from HBM and no
+ * block's full transform is stored.  The sum over blocks is taken in a fixed
+ * order, so results are bitwise repeatable.  The butterflies run in FP32
+ * whatever the plan's precision (the split-BF16 form is a bsrht_apply
+ * variant only).  Blocks of r >= 256 columns take the streaming kernel;
+ * shorter blocks an O(n) per output direct evaluation.
+ *
+ * A   : device float32, m x n (n = the plan's n), row-major, leading
+ *       dimension lda >= n.
+ * m   : number of rows, m >= 0 (m == 0 is a no-op).
+ * Y   : device float32, m x l, row-major, leading dimension ldy >= l; must
+ *       not overlap A.
+ * ws  : device workspace of ws_bytes >= bsrht_apply_right_workspace(plan, m)
+ *       (may be NULL when that is 0).
+ * Returns BSRHT_OK, BSRHT_EINVAL (NULL pointers, lda < n, ldy < l, m > 2^31-1),
+ * BSRHT_ENOMEM (workspace too small), BSRHT_EUNSUPPORTED (l*m > 2^40) or
+ * BSRHT_EDEVICE; nothing is enqueued on an error.
+ */
+int bsrht_apply_right(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda,
+                      float *Y, int64_t ldy, void *ws, size_t ws_bytes, void *stream);
+
 /*
  * Several FP32 sketches (eq. (2.4) each, as bsrht_apply) in one persistent
  * launch: the workgroup tiles of all items run from a descriptor table in
@@ -251,6 +279,7 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k,
 #define BSRHT_TIMING_APPLY_BF16 2 /* the split-BF16 matrix-core kernel     */
 #define BSRHT_TIMING_GEMM_AQ 3    /* Z = A Q of the randomized SVD          */
 #define BSRHT_TIMING_STREAM 4     /* bsrht_stream_read                       */
+#define BSRHT_TIMING_APPLY_RIGHT 5 /* the FP32 sketch kernel of bsrht_apply_right */
 int bsrht_timing_enable(int which);
 int bsrht_timing_read(double *total_ms, int64_t *launches);
 /*

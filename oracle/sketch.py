@@ -101,3 +101,19 @@ def sketch_entry(plan, column, j):
     for i in range(plan.p):
         total += plan.Dt[i][j] * np.dot(h, plan.D[i] * col[i * r:(i + 1) * r])
     return total / np.sqrt(plan.l)
+
+
+def sketch_right(plan, A):
+    """Y = A @ Omega^T (m x l, float64): the sketch applied from the right, to
+    the rows of an m x n A, as in Algorithm 1 (section 3.1).  By definition
+    A Omega^T = (Omega A^T)^T, so this is eq. (2.4) on A^T, transposed."""
+    A = np.asarray(A)
+    if A.ndim != 2 or A.shape[1] != plan.n:
+        raise ValueError("A must have n columns")
+    return sketch(plan, A.T).T
+
+
+def sketch_right_entry(plan, row, j):
+    """One entry Y[g, j] of A @ Omega^T from a single row of A (length n)."""
+    return sketch_entry(plan, row, j)
+

@@ -21,7 +21,8 @@ __all__ = [
     "SPLIT_BF16", "INFO_CHOL_FALLBACK", "INFO_RANK_CLAMPED", "INFO_QB_FALLBACK",
     "INFO_JACOBI_NOCONV", "EXPORTED_SYMBOLS", "JOB_SKETCH", "JOB_RSVD", "JobDesc",
     "JobResult", "ServerStats", "Server", "bsrht_job_bytes", "apply_batch",
-    "batch_table_bytes", "ApplyItem", "BATCH_MAX",
+    "batch_table_bytes", "ApplyItem", "BATCH_MAX", "bsrht_apply_right",
+    "bsrht_apply_right_workspace",
 ]
 
 WITH_REPLACEMENT = 0
@@ -37,6 +38,7 @@ TIMING_APPLY_FP32 = 1
 TIMING_APPLY_BF16 = 2
 TIMING_GEMM_AQ = 3
 TIMING_STREAM = 4
+TIMING_APPLY_RIGHT = 5
 STREAM_BLOCKS = 4096
 JOB_SKETCH = 0
 JOB_RSVD = 1
@@ -61,6 +63,9 @@ _SIGS = {
     "bsrht_apply_workspace": (_c_sz, [_c_vp, _c_i64]),
     "bsrht_apply": (ctypes.c_int, [_c_vp, _c_vp, _c_i64, _c_i64, _c_vp, _c_i64, _c_vp,
                                    _c_sz, _c_vp]),
+    "bsrht_apply_right_workspace": (_c_sz, [_c_vp, _c_i64]),
+    "bsrht_apply_right": (ctypes.c_int, [_c_vp, _c_vp, _c_i64, _c_i64, _c_vp, _c_i64, _c_vp,
+                                         _c_sz, _c_vp]),
     "rsvd_workspace": (_c_sz, [_c_vp, _c_i64, _c_i64]),
     "rsvd": (ctypes.c_int, [_c_vp, _c_vp, _c_i64, _c_i64, _c_i64, _c_vp, _c_vp, _c_vp,
                             _c_vp, _c_vp, _c_sz, _c_vp]),
@@ -275,6 +280,30 @@ def bsrht_apply(plan, A, Y=None, ws=None, stream=None):
         ws = _workspace(need, A.device)
     _check("bsrht_apply", lib().bsrht_apply(
         plan.handle, _ptr(A), m, max(A.stride(0), m), _ptr(Y), max(Y.stride(0), m),
+        _ptr(ws), ws.numel(), _stream_ptr(stream)))
+    return Y
+
+
+def bsrht_apply_right_workspace(plan, m):
+    return int(lib().bsrht_apply_right_workspace(plan.handle, m))
+
+
+def bsrht_apply_right(plan, A, Y=None, ws=None, stream=None):
+    """Y = A Omega^T for a row-major float32 m x n device tensor A (Y: m x l)."""
+    _check_matrix("A", A)
+    m, n = A.shape
+    if n != plan.n:
+        raise ValueError(f"A has {n} columns, the plan expects {plan.n}")
+    if Y is None:
+        Y = torch.empty(m, plan.l, dtype=torch.float32, device=A.device)
+    _check_matrix("Y", Y)
+    if tuple(Y.shape) != (m, plan.l):
+        raise ValueError(f"Y must be {m} x {plan.l}")
+    need = bsrht_apply_right_workspace(plan, m)
+    if ws is None:
+        ws = _workspace(need, A.device)
+    _check("bsrht_apply_right", lib().bsrht_apply_right(
+        plan.handle, _ptr(A), m, max(A.stride(0), n), _ptr(Y), max(Y.stride(0), plan.l),
         _ptr(ws), ws.numel(), _stream_ptr(stream)))
     return Y
 

@@ -103,6 +103,11 @@ int apply_split_bf16(const bsrht_plan_s *plan, const float *A, int64_t m,
                      size_t ws_bytes, hipStream_t s);
 size_t apply_split_bf16_ws_bytes(const bsrht_plan_s *plan, int64_t m);
 size_t apply_fp32_ws_bytes(const bsrht_plan_s *plan, int64_t m);
+// Y = A Omega^T for row-major A (m x n, lda) into Y (m x l, ldy); ws must
+// hold apply_right_ws_bytes(plan, m).
+size_t apply_right_ws_bytes(const bsrht_plan_s *plan, int64_t m);
+int apply_right_fp32(const bsrht_plan_s *plan, const float *A, int64_t m, int64_t lda,
+                     float *Y, int64_t ldy, void *ws, size_t ws_bytes, hipStream_t s);
 // Y[j][c] = scale * sum_s part[s][j][c] over the splits in ascending order.
 int reduce_splits(const float *part, int splits, int64_t split_stride, int64_t l, int64_t m,
                   float *Y, int64_t ldy, float scale, hipStream_t s);

@@ -148,6 +148,26 @@ def test_sketch_entry_matches_sketch():
         assert abs(sketch.sketch_entry(plan, A[:, c], j) - Y[j, c]) < 1e-12 * np.abs(Y).max()
 
 
+@pytest.mark.parametrize("n,p,l,mode", CASES)
+def test_right_sketch_is_omega_applied_from_the_right(n, p, l, mode):
+    """A Omega^T (Algorithm 1's orientation) equals the closed-form Omega
+    multiplied from the right, entry by entry; the rows are independent."""
+    plan = rng.Plan(n, p, l, 8, mode)
+    A = np.random.default_rng(2).standard_normal((5, n))
+    Y = sketch.sketch_right(plan, A)
+    assert Y.shape == (5, l)
+    assert metrics.rel_fro(Y, A @ sketch.omega_explicit(plan).T) < 1e-13
+    assert metrics.rel_fro(sketch.sketch_right(plan, A[3:4]), Y[3:4]) < 1e-15
+
+
+def test_right_sketch_entry_matches():
+    plan = rng.Plan(2048, 4, 40, 12)
+    A = np.random.default_rng(7).standard_normal((3, 2048))
+    Y = sketch.sketch_right(plan, A)
+    for g, j in [(0, 0), (1, 7), (2, 39), (0, 20)]:
+        assert abs(sketch.sketch_right_entry(plan, A[g], j) - Y[g, j]) < 1e-12 * np.abs(Y).max()
+
+
 @pytest.mark.parametrize("mutation", ["drop_D", "drop_Dt", "swap_blocks", "no_scale",
                                       "skip_stage", "lo_hi_swap"])
 def test_pins_catch_planted_mistakes(mutation, monkeypatch):

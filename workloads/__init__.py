@@ -13,7 +13,9 @@ Recipes (seeded; torch generators, float64 formation, one rounding to float32)
   spd(n, d, spectrum, seed):  A = X diag(s) X^T, X = orth(N(0,1)^{n x d}).
   gaussian_cols(n, m, spectrum, seed):  A = X diag(s) with X ~ N(0,1)
       (the serving payload; W = I).
+  gaussian_rows(m, n, spectrum, seed):  A = diag(s) X with X ~ N(0,1)
+      (inputs sketched along their rows).
 """
 
-from .gen import (SPECTRA, lowrank_tall, spd, gaussian_cols, haar,  # noqa: F401
-                  CONFIGS, serving_jobs)
+from .gen import (SPECTRA, lowrank_tall, spd, gaussian_cols, gaussian_rows,  # noqa: F401
+                  haar, CONFIGS, serving_jobs)

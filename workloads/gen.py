@@ -19,6 +19,10 @@ CONFIGS = {
     "c2_fp32_apply": dict(n=1 << 20, m=1024, p=16, l=512, k=256, spectrum="exp64", seed=0),
     "c3_split_bf16": dict(n=1 << 20, m=1024, p=16, l=512, k=256, spectrum="exp64", seed=0),
     "c5_nystrom": dict(n=65536, d=4096, p=64, l=1024, k=512, spectrum="cube", seed=0),
+    # The large sketch workload in the orientation of Algorithm 1: the
+    # transpose (m x n, row-major) of the 2^20 x 1024 input, sketched from the
+    # right along its contiguous dimension.
+    "right_apply_large": dict(n=1 << 20, m=1024, p=16, l=512, spectrum="exp64", seed=0),
 }
 
 
@@ -81,6 +85,15 @@ def gaussian_cols(n, m, spectrum, seed, device="cpu"):
     s = _spectrum(spectrum, m, device).to(torch.float32)
     X = torch.randn(n, m, generator=g, dtype=torch.float32, device=device)
     return X * s[None, :]
+
+
+def gaussian_rows(m, n, spectrum, seed, device="cpu"):
+    """A = diag(s) X (m x n float32), X ~ N(0, 1): gaussian_cols transposed in
+    shape, for inputs sketched along their rows."""
+    g = _gen(seed, device)
+    s = _spectrum(spectrum, m, device).to(torch.float32)
+    X = torch.randn(m, n, generator=g, dtype=torch.float32, device=device)
+    return s[:, None] * X
 
 
 def serving_jobs(count, rate, seed):
