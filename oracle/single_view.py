@@ -23,9 +23,10 @@ the minimiser of ||Phi (A - Q C P^T) Psi^T||_F over C, the core problem
 that defines the approximation in section 3.3.  Step 6 as printed lacks the
 transpose on P Vt_k.
 
-Every step is a plain library call: Householder QR, least squares (LAPACK
-gelsd) and an SVD, so the oracle shares no algorithm with the GPU path
-(Cholesky-QR, normal equations on well-conditioned embeddings, Jacobi).
+Every step is a plain library call: SVDs (LAPACK gesdd) for the range bases
+and the core, least squares (gelsd), so the oracle shares no algorithm with
+the GPU path (Cholesky-QR, normal equations on well-conditioned embeddings,
+Jacobi).
 """
 
 import numpy as np
@@ -42,11 +43,22 @@ def sketches(omega, gamma, phi, psi, A):
     return X, Y, Z
 
 
+def orth(M):
+    """An orthonormal basis of range(M): the left singular vectors whose
+    singular values exceed numpy's numerical-rank tolerance
+    (max(shape) * eps * sigma_max).  For a full-rank M this spans the same
+    space as a QR factor; for a rank-deficient sketch (two samples that give
+    collinear rows, e.g. a repeated index when p = 1) it spans range(M) only,
+    where a QR factor would add completion columns outside it."""
+    U, sg, _ = np.linalg.svd(M, full_matrices=False)
+    tol = max(M.shape) * np.finfo(np.float64).eps * sg[0]
+    return U[:, sg > tol]
+
+
 def bases(X, Y):
-    """Step 2: Q = orth(Y), P = orth(X) (reduced Householder QR)."""
-    Q, _ = np.linalg.qr(Y, mode="reduced")
-    P, _ = np.linalg.qr(X, mode="reduced")
-    return Q, P
+    """Step 2: Q = orth(Y), P = orth(X) (section 3.3 defines Q and P as
+    orthonormal bases of range(A Omega^T) and range(A^T Gamma^T))."""
+    return orth(Y), orth(X)
 
 
 def core_matrix(PhQ, Z, PsP):
@@ -58,7 +70,7 @@ def core_matrix(PhQ, Z, PsP):
 
 def single_view(omega, gamma, phi, psi, A, k):
     """Algorithm 3: returns (U N1 x k', S k', V N2 x k'), A ~= U diag(S) V^T,
-    k' = min(k, l)."""
+    k' = min(k, rank of the core)."""
     A = np.asarray(A, dtype=np.float64)
     X, Y, Z = sketches(omega, gamma, phi, psi, A)
     Q, P = bases(X, Y)

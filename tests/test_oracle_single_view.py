@@ -101,6 +101,20 @@ def test_sketches_are_the_three_products():
     assert metrics.rel_fro(Z, E(ph) @ A @ E(ps_).T) < 1e-13
 
 
+def test_rank_deficient_sketch_keeps_only_its_range():
+    """p = 1 with replacement and l close to r repeats samples: Y has collinear
+    columns, and Q spans exactly range(Y) (its projector fixes Y)."""
+    N1, N2, l, s = 512, 64, 48, 64
+    om, ga, ph, ps_ = _plans(N1, N2, l, s, pl=(1, 1), ps=(1, 1))
+    assert len(set(om.R.tolist())) < l
+    A = _decaying(N1, N2, 9)
+    X, Y, Z = sv.sketches(om, ga, ph, ps_, A)
+    Q, P = sv.bases(X, Y)
+    assert Q.shape[1] == np.linalg.matrix_rank(Y) < l
+    assert metrics.rel_fro(Q @ (Q.T @ Y), Y) < 1e-13
+    assert np.max(np.abs(Q.T @ Q - np.eye(Q.shape[1]))) < 1e-13
+
+
 MUTATIONS = {
     "bases_swapped": lambda X, Y: tuple(np.linalg.qr(M, mode="reduced")[0] for M in (X, Y)),
     "core_transpose_for_pinv": lambda PhQ, Z, PsP: PhQ.T @ Z @ PsP,
