@@ -266,6 +266,44 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k,
             float *U, double *lambda, int32_t *info, void *ws,
             size_t ws_bytes, void *stream);
 
+/* Workspace bytes rsvd_single_view needs (0 for inconsistent plans or k < 1). */
+size_t rsvd_single_view_workspace(bsrht_plan_t omega, bsrht_plan_t gamma,
+                                  bsrht_plan_t phi, bsrht_plan_t psi, int64_t k);
+
+/*
+ * Single-view randomized SVD (section 3.3, Algorithm 3) of an N1 x N2 A with
+ * four block SRHTs: omega (l x N2) and psi (s x N2) sketch the rows of A
+ * from the right (bsrht_apply_right), gamma (l x N1) and phi (s x N1) its
+ * columns (bsrht_apply), l <= s.  Forms X^T = Gamma A, Y = A Omega^T and the
+ * core sketch Z = Phi A Psi^T, orthonormal bases Q of range(Y) and P of
+ * range(X) (Cholesky-QR2 in FP64; a rank deficient sketch keeps the
+ * directions of its Gram's eigen split above l*2^-53 relative and sets
+ * BSRHT_INFO_QB_FALLBACK), the core C = (Phi Q)^+ Z ((Psi P)^T)^+ by FP64
+ * normal equations (an eigen pseudo-inverse and BSRHT_INFO_CHOL_FALLBACK if
+ * a Gram is singular), and the SVD C = Ut St Vt^T by one-sided Jacobi;
+ * returns A ~= U diag(S) V^T with U = Q Ut_k, S = St_k, V = P Vt_k.  Entries
+ * beyond the numerical rank of C are zero (BSRHT_INFO_RANK_CLAMPED).  A is
+ * read three times.  Synchronises the stream where a Cholesky flag or the
+ * eigenvalues of a fallback are needed.
+ *
+ * omega, gamma, phi, psi: plans with omega->n == psi->n == N2,
+ *     gamma->n == phi->n == N1, omega->l == gamma->l == l,
+ *     phi->l == psi->l == s >= l (independent seeds); else BSRHT_EINVAL.
+ *     The column sketches run in their plans' precision; the row sketches
+ *     in FP32.
+ * A   : device float32, N1 x N2 row-major, lda >= N2.
+ * k   : target rank >= 1.
+ * U   : device float32, N1 x k row-major;  S: device float64[k];
+ * V   : device float32, N2 x k row-major;  info: device int32 (BSRHT_INFO_*).
+ * ws  : device workspace of ws_bytes >= rsvd_single_view_workspace(...).
+ * Returns BSRHT_OK, BSRHT_EINVAL, BSRHT_ENOMEM, BSRHT_EUNSUPPORTED (l > 4096
+ * or N1, N2 >= 2^31) or BSRHT_EDEVICE.
+ */
+int rsvd_single_view(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi,
+                     bsrht_plan_t psi, const float *A, int64_t lda, int64_t k,
+                     float *U, double *S, float *V, int32_t *info, void *ws,
+                     size_t ws_bytes, void *stream);
+
 /*
  * Instrumentation (not part of the computation).  bsrht_timing_enable(which)
  * makes the library record a pair of HIP events on the launching stream

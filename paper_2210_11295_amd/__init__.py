@@ -22,7 +22,7 @@ __all__ = [
     "INFO_JACOBI_NOCONV", "EXPORTED_SYMBOLS", "JOB_SKETCH", "JOB_RSVD", "JobDesc",
     "JobResult", "ServerStats", "Server", "bsrht_job_bytes", "apply_batch",
     "batch_table_bytes", "ApplyItem", "BATCH_MAX", "bsrht_apply_right",
-    "bsrht_apply_right_workspace",
+    "bsrht_apply_right_workspace", "rsvd_single_view", "rsvd_single_view_workspace",
 ]
 
 WITH_REPLACEMENT = 0
@@ -70,6 +70,9 @@ _SIGS = {
     "rsvd": (ctypes.c_int, [_c_vp, _c_vp, _c_i64, _c_i64, _c_i64, _c_vp, _c_vp, _c_vp,
                             _c_vp, _c_vp, _c_sz, _c_vp]),
     "nystrom_workspace": (_c_sz, [_c_vp, _c_i64]),
+    "rsvd_single_view_workspace": (_c_sz, [_c_vp, _c_vp, _c_vp, _c_vp, _c_i64]),
+    "rsvd_single_view": (ctypes.c_int, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_i64, _c_i64,
+                                        _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_sz, _c_vp]),
     "bsrht_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "bsrht_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(_c_i64)]),
@@ -363,6 +366,35 @@ def rsvd(plan, A, k, ws=None, stream=None):
     _check("rsvd", lib().rsvd(plan.handle, _ptr(A), m, max(A.stride(0), m), k, _ptr(U),
                               _ptr(S), _ptr(V), _ptr(info), _ptr(ws), ws.numel(),
                               _stream_ptr(stream)))
+    return U, S, V, info
+
+
+def rsvd_single_view_workspace(omega, gamma, phi, psi, k):
+    return int(lib().rsvd_single_view_workspace(omega.handle, gamma.handle, phi.handle,
+                                                psi.handle, k))
+
+
+def rsvd_single_view(omega, gamma, phi, psi, A, k, ws=None, stream=None):
+    """Single-view RSVD (Algorithm 3) of the N1 x N2 A with Omega (l x N2),
+    Gamma (l x N1), Phi (s x N1), Psi (s x N2): returns (U N1 x k, S k
+    float64, V N2 x k, info), A ~= U diag(S) V^T."""
+    _check_matrix("A", A)
+    N1, N2 = A.shape
+    if N1 != gamma.n or N2 != omega.n:
+        raise ValueError(f"A is {N1} x {N2}; the plans expect {gamma.n} x {omega.n}")
+    dev = A.device
+    U = torch.empty(N1, k, dtype=torch.float32, device=dev)
+    S = torch.empty(k, dtype=torch.float64, device=dev)
+    V = torch.empty(N2, k, dtype=torch.float32, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    if ws is None:
+        need = rsvd_single_view_workspace(omega, gamma, phi, psi, k)
+        if need == 0:
+            raise ValueError("inconsistent single-view plans")
+        ws = _workspace(need, dev)
+    _check("rsvd_single_view", lib().rsvd_single_view(
+        omega.handle, gamma.handle, phi.handle, psi.handle, _ptr(A), max(A.stride(0), N2), k,
+        _ptr(U), _ptr(S), _ptr(V), _ptr(info), _ptr(ws), ws.numel(), _stream_ptr(stream)))
     return U, S, V, info
 
 

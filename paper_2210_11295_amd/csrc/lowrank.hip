@@ -11,6 +11,8 @@
 // Remark 3.1's fallback (a square root from an eigendecomposition, keeping
 // eigenvalues above tau * lambda_max) changes the sizes of the later steps,
 // so the path is chosen on the host.
+#include <limits.h>
+
 #include <algorithm>
 #include <vector>
 
@@ -530,6 +532,317 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
   d.sbk = k; d.sbj = 1;
   d.ldc = k;
   return gemm_f64f64_f32(d, w.Z, w.Mk, U, s);
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------------
+// Single-view randomized SVD (section 3.3, Algorithm 3) for an N1 x N2
+// row-major A with four block SRHTs: Omega (l x N2) and Psi (s x N2) act on
+// the rows of A from the right, Gamma (l x N1) and Phi (s x N1) on its columns.
+//   1. X^T = Gamma A (l x N2), Y = A Omega^T (N1 x l), Z = (Phi A) Psi^T (s x s)
+//   2. Q = orth(Y), P = orth(X) (Cholesky-QR2 in FP64, eigen split when the
+//      sketch is rank deficient)
+//   3. Phi Q (s x lq), Psi P (s x lp)
+//   4. C = (Phi Q)^+ Z ((Psi P)^T)^+ through the normal equations: Phi and Psi
+//      are embeddings of the orthonormal Q and P, so the Grams of Phi Q and
+//      Psi P are well conditioned (singular values near 1); G^{-1} = F F^T with
+//      F the inverse Cholesky factor, or the eigen pseudo-inverse if a pivot
+//      fails
+//   5. C = Ut St Vt^T by one-sided Jacobi (Vt accumulated), k leading terms
+//   6. U = Q (C Vt_k St_k^{-1}) = Q Ut_k, S = St_k, V = P Vt_k
+// A is read three times (two column sketches, one row sketch).
+namespace bsrht {
+namespace {
+
+template <class A>
+struct SvWs {
+  float *Xt, *Y, *W, *Zs, *Q32, *P32, *PhQ, *PsP, *Mu32, *Vk32;
+  void *apply_ws;
+  size_t apply_bytes;
+  double *G, *Gs, *F, *Q1, *G2, *C2inv, *gram_part;
+  double *Gc, *F1, *F2, *T1, *T2, *T3t, *T4t, *Ct, *Mv, *Mu;
+  int32_t *flag;
+  void *chol_state;
+  SvdBufs<A> qb, sv;
+  void layout(A &a, const bsrht_plan_s *om, const bsrht_plan_s *ga, const bsrht_plan_s *ph,
+              const bsrht_plan_s *ps, int64_t k) {
+    const int64_t N1 = ga->n, N2 = om->n, l = om->l, s = ph->l;
+    const int64_t Nm = std::max(N1, N2);
+    Xt = a.template take<float>((size_t)(l * N2));
+    Y = a.template take<float>((size_t)(N1 * l));
+    W = a.template take<float>((size_t)(s * N2));
+    Zs = a.template take<float>((size_t)(s * s));
+    // The column sketches of Q and P have lq, lp <= l columns; the workspace
+    // of a sketch is not monotonic in its column count, so take the maximum.
+    size_t ab = std::max({apply_ws_bytes(ga, N2), apply_right_ws_bytes(om, N1),
+                          apply_ws_bytes(ph, N2), apply_right_ws_bytes(ps, s)});
+    for (int64_t c = 1; c <= l; ++c)
+      ab = std::max({ab, apply_ws_bytes(ph, c), apply_ws_bytes(ps, c)});
+    apply_bytes = ab;
+    apply_ws = a.template take<char>(apply_bytes);
+    G = a.template take<double>((size_t)(l * l));
+    Gs = a.template take<double>((size_t)(l * l));
+    F = a.template take<double>((size_t)(l * l));
+    Q1 = a.template take<double>((size_t)(Nm * l));
+    G2 = a.template take<double>((size_t)(l * l));
+    C2inv = a.template take<double>((size_t)(l * l));
+    gram_part = a.template take<double>((size_t)std::max(
+        {gram_partial_elems(N1, l), gram_partial_elems(N2, l), gram_partial_elems(s, l),
+         (int64_t)1}));
+    Q32 = a.template take<float>((size_t)(N1 * l));
+    P32 = a.template take<float>((size_t)(N2 * l));
+    PhQ = a.template take<float>((size_t)(s * l));
+    PsP = a.template take<float>((size_t)(s * l));
+    Gc = a.template take<double>((size_t)(l * l));
+    F1 = a.template take<double>((size_t)(l * l));
+    F2 = a.template take<double>((size_t)(l * l));
+    T1 = a.template take<double>((size_t)(l * s));
+    T2 = a.template take<double>((size_t)(l * s));
+    T3t = a.template take<double>((size_t)(l * l));
+    T4t = a.template take<double>((size_t)(l * l));
+    Ct = a.template take<double>((size_t)(l * l));
+    Mv = a.template take<double>((size_t)(l * k));
+    Mu = a.template take<double>((size_t)(l * k));
+    Mu32 = a.template take<float>((size_t)(l * k));
+    Vk32 = a.template take<float>((size_t)(l * k));
+    flag = a.template take<int32_t>(4);
+    chol_state = a.template take<char>(cholesky_state_bytes());
+    qb.take(a, svd_pad(l), l);
+    sv.take(a, svd_pad(l), k);
+  }
+};
+
+// F (n x nf, row-major, leading dimension nf) with F F^T = G^{-1} for the
+// symmetric positive semi-definite n x n G (overwritten): F = C^{-1} for the
+// Cholesky factor G = C^T C, or, when a pivot is <= tol * max(diag(G)),
+// F = V_+ Lam_+^{-1/2} from G's eigen split with the eigenvalues above
+// n u lambda_max (then F F^T = G^+ and *fell_back is set).
+template <class A>
+int inv_factor(double *G, int64_t n, double tol, double *F, int64_t *nf, bool *fell_back,
+               SvWs<A> &w, int32_t *info, hipStream_t s) {
+  BSRHT_TRY(scale_cols_f64(G, n, n, n, n, nullptr, w.Gs, n, s));
+  BSRHT_TRY(cholesky_upper(G, n, n, tol, w.flag, w.chol_state, s));
+  int32_t hf = 0;
+  BSRHT_TRY(read_i32(w.flag, s, &hf));
+  *fell_back = hf != 0;
+  if (hf == 0) {
+    *nf = n;
+    return trinv_upper(G, n, n, F, n, s);
+  }
+  BSRHT_TRY(small_svd(w.qb, w.Gs, n, n, true, info, s));
+  std::vector<double> ev((size_t)n);
+  if (copy_to_host(ev.data(), w.qb.S, sizeof(double) * (size_t)n, s) != BSRHT_OK)
+    return BSRHT_EDEVICE;
+  int64_t keep = 0;
+  for (int64_t i = 0; i < n; ++i)
+    if (ev[(size_t)i] > (double)n * kU64 * ev[0] && ev[(size_t)i] > 0.0) ++keep;
+  if (keep < 1) keep = 1;
+  std::vector<double> sc((size_t)keep);
+  for (int64_t i = 0; i < keep; ++i) sc[(size_t)i] = 1.0 / sqrt(std::max(ev[(size_t)i], 1e-300));
+  if (copy_to_device(w.qb.inv, sc.data(), sizeof(double) * (size_t)keep, s) != BSRHT_OK)
+    return BSRHT_EDEVICE;
+  BSRHT_TRY(scale_cols_f64(w.qb.Vs, n, keep, keep, svd_pad(n), w.qb.inv, F, keep, s));
+  *nf = keep;
+  return BSRHT_OK;
+}
+
+// Q32 (rows x lk, leading dimension lk): an orthonormal basis of the columns
+// of X (rows x l, X[r][c] = X[r*sr + c*sc]) by Cholesky-QR2 in FP64; a rank
+// deficient X keeps the lk <= l directions of its Gram's eigen split.
+template <class A>
+int orth_basis(const float *X, int64_t rows, int64_t l, int64_t sr, int64_t sc, float *Q32,
+               int64_t *lk_out, SvWs<A> &w, int32_t *info, hipStream_t s) {
+  BSRHT_TRY(gram_f32(X, rows, l, sr, sc, w.G, l, w.gram_part, gram_splits(rows, l), s));
+  int64_t lk = l;
+  bool fb = false;
+  BSRHT_TRY(inv_factor(w.G, l, (double)l * kU64, w.F, &lk, &fb, w, info, s));
+  {
+    GemmDesc d;
+    d.M = rows; d.N = lk; d.K = l;
+    d.sai = sr; d.sak = sc;
+    d.sbk = lk; d.sbj = 1;
+    d.ldc = lk;
+    BSRHT_TRY(gemm_f32f64_f64(d, X, w.F, w.Q1, s));
+  }
+  if (fb) {
+    or_info_kernel<<<1, 1, 0, s>>>(info, BSRHT_INFO_QB_FALLBACK);
+    BSRHT_LAUNCH_CHECK();
+  }
+  // second pass: G2 = Q1^T Q1 = C2^T C2, Q = Q1 C2^{-1}
+  BSRHT_TRY(gram_f64(w.Q1, rows, lk, lk, 1, w.G2, lk, w.gram_part, gram_splits(rows, lk), s));
+  BSRHT_TRY(cholesky_upper(w.G2, lk, lk, 1e-14, w.flag + 1, w.chol_state, s));
+  int32_t hf2 = 0;
+  BSRHT_TRY(read_i32(w.flag + 1, s, &hf2));
+  if (hf2 != 0) {  // Q1 is orthonormal to O(eps kappa^2): should not happen
+    debug_report(__FILE__, __LINE__, "second Cholesky-QR pass", BSRHT_EDEVICE);
+    return BSRHT_EDEVICE;
+  }
+  BSRHT_TRY(trinv_upper(w.G2, lk, lk, w.C2inv, lk, s));
+  GemmDesc d;
+  d.M = rows; d.N = lk; d.K = lk;
+  d.sai = lk; d.sak = 1;
+  d.sbk = lk; d.sbj = 1;
+  d.ldc = lk;
+  BSRHT_TRY(gemm_f64f64_f32(d, w.Q1, w.C2inv, Q32, s));
+  *lk_out = lk;
+  return BSRHT_OK;
+}
+
+int sketch_cols(const bsrht_plan_s *pl, const float *X, int64_t m, int64_t ldx, float *Y,
+                int64_t ldy, void *ws, size_t ws_bytes, hipStream_t s) {
+  if (pl->precision == BSRHT_SPLIT_BF16)
+    return apply_split_bf16(pl, X, m, ldx, Y, ldy, ws, ws_bytes, s);
+  return apply_fp32(pl, X, m, ldx, Y, ldy, ws, ws_bytes, s);
+}
+
+bool sv_shapes_ok(const bsrht_plan_s *om, const bsrht_plan_s *ga, const bsrht_plan_s *ph,
+                  const bsrht_plan_s *ps) {
+  return om && ga && ph && ps && om->n == ps->n && ga->n == ph->n && om->l == ga->l &&
+         ph->l == ps->l && om->l <= ph->l;
+}
+
+}  // namespace
+}  // namespace bsrht
+
+extern "C" {
+
+size_t rsvd_single_view_workspace(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi,
+                                  bsrht_plan_t psi, int64_t k) {
+  if (!sv_shapes_ok(omega, gamma, phi, psi) || k < 1) return 0;
+  SizeOnly so;
+  SvWs<SizeOnly> w;
+  w.layout(so, omega, gamma, phi, psi, k);
+  return align256(so.sz.used);
+}
+
+int rsvd_single_view(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi, bsrht_plan_t psi,
+                     const float *A, int64_t lda, int64_t k, float *U, double *S, float *V,
+                     int32_t *info, void *ws, size_t ws_bytes, void *stream) {
+  if (!sv_shapes_ok(omega, gamma, phi, psi) || !A || !U || !S || !V || !info || k < 1 ||
+      lda < omega->n)
+    return BSRHT_EINVAL;
+  const int64_t N1 = gamma->n, N2 = omega->n, l = omega->l, s_ = phi->l;
+  if (svd_pad(l) > 4096 || N1 > INT_MAX || N2 > INT_MAX) return BSRHT_EUNSUPPORTED;
+  if (ws_bytes < rsvd_single_view_workspace(omega, gamma, phi, psi, k) || !ws)
+    return BSRHT_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  Carve cv(ws, ws_bytes);
+  SvWs<Carve> w;
+  w.layout(cv, omega, gamma, phi, psi, k);
+  if (cv.overflow) return BSRHT_ENOMEM;
+  zero_i32_kernel<<<1, 64, 0, s>>>(info, 1);
+  BSRHT_LAUNCH_CHECK();
+
+  // 1. the three sketches
+  BSRHT_TRY(sketch_cols(gamma, A, N2, lda, w.Xt, N2, w.apply_ws, w.apply_bytes, s));
+  BSRHT_TRY(apply_right_fp32(omega, A, N1, lda, w.Y, l, w.apply_ws, w.apply_bytes, s));
+  BSRHT_TRY(sketch_cols(phi, A, N2, lda, w.W, N2, w.apply_ws, w.apply_bytes, s));
+  BSRHT_TRY(apply_right_fp32(psi, w.W, s_, N2, w.Zs, s_, w.apply_ws, w.apply_bytes, s));
+  // 2. bases Q = orth(Y) (N1 x lq), P = orth(X) = orth(Xt^T) (N2 x lp)
+  int64_t lq = l, lp = l;
+  BSRHT_TRY(orth_basis(w.Y, N1, l, l, 1, w.Q32, &lq, w, info, s));
+  BSRHT_TRY(orth_basis(w.Xt, N2, l, 1, N2, w.P32, &lp, w, info, s));
+  // 3. Phi Q (s x lq), Psi P (s x lp)
+  BSRHT_TRY(sketch_cols(phi, w.Q32, lq, lq, w.PhQ, lq, w.apply_ws, w.apply_bytes, s));
+  BSRHT_TRY(sketch_cols(psi, w.P32, lp, lp, w.PsP, lp, w.apply_ws, w.apply_bytes, s));
+  // 4. C = (Phi Q)^+ Z ((Psi P)^T)^+, computed as C^T (lp x lq) in Ct
+  int64_t nf1 = lq, nf2 = lp;
+  bool fb1 = false, fb2 = false;
+  BSRHT_TRY(gram_f32(w.PhQ, s_, lq, lq, 1, w.Gc, lq, w.gram_part, gram_splits(s_, lq), s));
+  BSRHT_TRY(inv_factor(w.Gc, lq, (double)lq * kU64, w.F1, &nf1, &fb1, w, info, s));
+  BSRHT_TRY(gram_f32(w.PsP, s_, lp, lp, 1, w.Gc, lp, w.gram_part, gram_splits(s_, lp), s));
+  BSRHT_TRY(inv_factor(w.Gc, lp, (double)lp * kU64, w.F2, &nf2, &fb2, w, info, s));
+  if (fb1 || fb2) {
+    or_info_kernel<<<1, 1, 0, s>>>(info, BSRHT_INFO_CHOL_FALLBACK);
+    BSRHT_LAUNCH_CHECK();
+  }
+  {
+    GemmDesc d;  // T1 = (Phi Q)^T Z  (lq x s)
+    d.M = lq; d.N = s_; d.K = s_;
+    d.sai = 1; d.sak = lq;
+    d.sbk = s_; d.sbj = 1;
+    d.ldc = s_;
+    BSRHT_TRY(gemm_f32f32_f64(d, w.PhQ, w.Zs, w.T1, s));
+  }
+  {
+    GemmDesc d;  // T2 = F1^T T1  (nf1 x s)
+    d.M = nf1; d.N = s_; d.K = lq;
+    d.sai = 1; d.sak = nf1;
+    d.sbk = s_; d.sbj = 1;
+    d.ldc = s_;
+    BSRHT_TRY(gemm_f64(d, w.F1, w.T1, w.T2, s));
+  }
+  {
+    GemmDesc d;  // C1 = F1 T2 = (Phi Q)^+ Z  (lq x s), into T1
+    d.M = lq; d.N = s_; d.K = nf1;
+    d.sai = nf1; d.sak = 1;
+    d.sbk = s_; d.sbj = 1;
+    d.ldc = s_;
+    BSRHT_TRY(gemm_f64(d, w.F1, w.T2, w.T1, s));
+  }
+  {
+    GemmDesc d;  // T3t = (Psi P)^T C1^T  (lp x lq)
+    d.M = lp; d.N = lq; d.K = s_;
+    d.sai = 1; d.sak = lp;
+    d.sbk = 1; d.sbj = s_;
+    d.ldc = lq;
+    BSRHT_TRY(gemm_f32f64_f64(d, w.PsP, w.T1, w.T3t, s));
+  }
+  {
+    GemmDesc d;  // T4t = F2^T T3t  (nf2 x lq)
+    d.M = nf2; d.N = lq; d.K = lp;
+    d.sai = 1; d.sak = nf2;
+    d.sbk = lq; d.sbj = 1;
+    d.ldc = lq;
+    BSRHT_TRY(gemm_f64(d, w.F2, w.T3t, w.T4t, s));
+  }
+  {
+    GemmDesc d;  // Ct = F2 T4t = C^T  (lp x lq)
+    d.M = lp; d.N = lq; d.K = nf2;
+    d.sai = nf2; d.sak = 1;
+    d.sbk = lq; d.sbj = 1;
+    d.ldc = lq;
+    BSRHT_TRY(gemm_f64(d, w.F2, w.T4t, w.Ct, s));
+  }
+  // 5. SVD of C: the row-major lp x lq Ct is C in column-major order; the
+  // one-sided Jacobi on its (zero padded) columns accumulates Vt.
+  const int64_t L = svd_pad(std::max(lq, lp));
+  BSRHT_TRY(fill_f64(w.sv.X, L * L, 0.0, s));
+  BSRHT_TRY(scale_cols_f64(w.Ct, lp, lq, lq, lq, nullptr, w.sv.X, L, s));
+  BSRHT_TRY(jacobi_svd(w.sv.X, L, L, L, w.sv.V, w.sv.S, w.sv.Vs, L, w.sv.perm, w.sv.flags,
+                       kMaxSweeps, info, s));
+  // 6. S = St_k, V = P Vt_k, U = Q (C Vt_k St_k^{-1})
+  const int64_t avail = std::min(lq, lp);
+  finish_sigma_kernel<<<(unsigned)((k + 255) / 256), 256, 0, s>>>(
+      w.sv.S, avail, k, sqrt((double)L * kU64), 1, w.sv.inv, S, info);
+  BSRHT_LAUNCH_CHECK();
+  const int64_t keep = std::min(k, avail);
+  BSRHT_TRY(scale_cols_f64_f32(w.sv.Vs, lp, keep, k, L, nullptr, w.Vk32, k, s));
+  {
+    GemmDesc d;
+    d.M = N2; d.N = k; d.K = lp;
+    d.sai = lp; d.sak = 1;
+    d.sbk = k; d.sbj = 1;
+    d.ldc = k;
+    BSRHT_TRY(gemm_f32(d, w.P32, w.Vk32, V, s));
+  }
+  BSRHT_TRY(scale_cols_f64(w.sv.Vs, lp, keep, k, L, w.sv.inv, w.Mv, k, s));
+  {
+    GemmDesc d;  // Mu = C Mv = Ct^T Mv  (lq x k)
+    d.M = lq; d.N = k; d.K = lp;
+    d.sai = 1; d.sak = lq;
+    d.sbk = k; d.sbj = 1;
+    d.ldc = k;
+    BSRHT_TRY(gemm_f64(d, w.Ct, w.Mv, w.Mu, s));
+  }
+  BSRHT_TRY(scale_cols_f64_f32(w.Mu, lq, k, k, k, nullptr, w.Mu32, k, s));
+  GemmDesc d;
+  d.M = N1; d.N = k; d.K = lq;
+  d.sai = lq; d.sak = 1;
+  d.sbk = k; d.sbj = 1;
+  d.ldc = k;
+  return gemm_f32(d, w.Q32, w.Mu32, U, s);
 }
 
 }  // extern "C"
