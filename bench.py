@@ -259,6 +259,36 @@ def bench_rsvd(bs, A, plan, cfg, reps):
             "rel_fro_error": err, "info": int(info.item())}
 
 
+def bench_single_view(bs, A, cfg, reps):
+    """Algorithm 3 (single-view RSVD) at full size on the same A: rank k,
+    Omega and Gamma with l = 512 rows, Phi and Psi with s = 2l = 1024 rows
+    (Gamma, Phi: p = 16 over the 2^20 rows; Omega, Psi: p = 1 over the 1024
+    columns, without replacement); A is read three times."""
+    import torch
+    n, m, p, l, k, seed = cfg["n"], cfg["m"], cfg["p"], cfg["l"], cfg["k"], cfg["seed"]
+    s = 2 * l
+    dev = A.device
+    # Omega and Psi sample the 1024 columns without replacement (a repeated
+    # index of a p = 1 plan gives collinear sketch rows); Gamma and Phi draw
+    # 512 and 1024 of 65536 per block with replacement.
+    wor = bs.WITHOUT_REPLACEMENT
+    plans = [bs.Plan(m, 1, l, seed + 1, wor, device=dev), bs.Plan(n, p, l, seed + 2, device=dev),
+             bs.Plan(n, p, s, seed + 3, device=dev), bs.Plan(m, 1, s, seed + 4, wor, device=dev)]
+    ws = torch.empty(max(1, bs.rsvd_single_view_workspace(*plans, k)), dtype=torch.uint8,
+                     device=dev)
+    log(f"bench: single-view rsvd rank {k} (workspace {ws.numel() / 2**30:.2f} GiB)")
+    U, S, V, info = bs.rsvd_single_view(*plans, A, k, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        U, S, V, info = bs.rsvd_single_view(*plans, A, k, ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    err = _fro_error(A, U, S, V)
+    return {"ms": round(dt * 1e3, 2), "k": k, "l": l, "s": s, "passes_over_A": 3,
+            "rel_fro_error": err, "info": int(info.item())}
+
+
 def bench_serving(bs, njobs, streams, rate=200.0, arena_gib=32, ahead=16, live_gib=64):
     """Serving workload: Poisson arrivals at `rate` jobs/s of sketch + RSVD
     jobs with seeded random shapes (n = 2^a, a in 14..20; m log-uniform in
@@ -503,8 +533,8 @@ def main():
                     help="jobs of the serving workload (0 skips it)")
     ap.add_argument("--serve-streams", type=int, default=SERVE_STREAMS)
     ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--only", choices=["all", "sketch", "bf16", "right", "rsvd", "nystrom",
-                                       "serve", "serve_small"],
+    ap.add_argument("--only", choices=["all", "sketch", "bf16", "right", "rsvd", "single_view",
+                                       "nystrom", "serve", "serve_small"],
                     default="all",
                     help="profiling aid: run one part ('bf16', 'right', 'rsvd', 'nystrom' and "
                          "'serve' print only that part's JSON object)")
@@ -539,6 +569,10 @@ def main():
     plan = bs.Plan(n, p, l, seed, device=dev)
     if args.only == "rsvd":
         print(json.dumps({"rsvd": bench_rsvd(bs, A, plan, cfg, args.lowrank_reps)}), flush=True)
+        return
+    if args.only == "single_view":
+        print(json.dumps({"rsvd_single_view": bench_single_view(bs, A, cfg, args.lowrank_reps)}),
+              flush=True)
         return
     if args.only == "bf16":
         Yf = bs.bsrht_apply(plan, A)
@@ -621,6 +655,7 @@ def main():
         out["right_apply"] = bench_right(bs, A, cfg, args.steps, args.warmup, Y)
     if not args.skip_lowrank:
         out["rsvd"] = bench_rsvd(bs, A, plan, cfg, args.lowrank_reps)
+        out["rsvd_single_view"] = bench_single_view(bs, A, cfg, args.lowrank_reps)
     if not args.skip_cpu_baseline:
         log("bench: timing the CPU oracle on one block")
         out["cpu_baseline"] = cpu_baseline(A, cfg)

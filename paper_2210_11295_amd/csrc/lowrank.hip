@@ -568,7 +568,7 @@ struct SvWs {
   void layout(A &a, const bsrht_plan_s *om, const bsrht_plan_s *ga, const bsrht_plan_s *ph,
               const bsrht_plan_s *ps, int64_t k) {
     const int64_t N1 = ga->n, N2 = om->n, l = om->l, s = ph->l;
-    const int64_t Nm = std::max(N1, N2);
+    const int64_t Nm = std::max(N1, N2), l4 = (l + 3) & ~int64_t(3);
     Xt = a.template take<float>((size_t)(l * N2));
     Y = a.template take<float>((size_t)(N1 * l));
     W = a.template take<float>((size_t)(s * N2));
@@ -583,15 +583,15 @@ struct SvWs {
     apply_ws = a.template take<char>(apply_bytes);
     G = a.template take<double>((size_t)(l * l));
     Gs = a.template take<double>((size_t)(l * l));
-    F = a.template take<double>((size_t)(l * l));
-    Q1 = a.template take<double>((size_t)(Nm * l));
+    F = a.template take<double>((size_t)(l4 * l4));
+    Q1 = a.template take<double>((size_t)(Nm * l4));
     G2 = a.template take<double>((size_t)(l * l));
-    C2inv = a.template take<double>((size_t)(l * l));
+    C2inv = a.template take<double>((size_t)(l4 * l4));
     gram_part = a.template take<double>((size_t)std::max(
         {gram_partial_elems(N1, l), gram_partial_elems(N2, l), gram_partial_elems(s, l),
          (int64_t)1}));
-    Q32 = a.template take<float>((size_t)(N1 * l));
-    P32 = a.template take<float>((size_t)(N2 * l));
+    Q32 = a.template take<float>((size_t)(N1 * l4));
+    P32 = a.template take<float>((size_t)(N2 * l4));
     PhQ = a.template take<float>((size_t)(s * l));
     PsP = a.template take<float>((size_t)(s * l));
     Gc = a.template take<double>((size_t)(l * l));
@@ -647,9 +647,13 @@ int inv_factor(double *G, int64_t n, double tol, double *F, int64_t *nf, bool *f
   return BSRHT_OK;
 }
 
-// Q32 (rows x lk, leading dimension lk): an orthonormal basis of the columns
-// of X (rows x l, X[r][c] = X[r*sr + c*sc]) by Cholesky-QR2 in FP64; a rank
-// deficient X keeps the lk <= l directions of its Gram's eigen split.
+// Q32 (rows x lk, leading dimension ld4(lk)): an orthonormal basis of the
+// columns of X (rows x l, X[r][c] = X[r*sr + c*sc]) by Cholesky-QR2 in FP64;
+// a rank deficient X keeps the lk <= l directions of its Gram's eigen split.
+// Leading dimensions are rounded up to 4 elements, which the large-tile GEMM
+// kernel needs for its 16-byte loads.
+inline int64_t ld4(int64_t x) { return (x + 3) & ~int64_t(3); }
+
 template <class A>
 int orth_basis(const float *X, int64_t rows, int64_t l, int64_t sr, int64_t sc, float *Q32,
                int64_t *lk_out, SvWs<A> &w, int32_t *info, hipStream_t s) {
@@ -657,20 +661,25 @@ int orth_basis(const float *X, int64_t rows, int64_t l, int64_t sr, int64_t sc, 
   int64_t lk = l;
   bool fb = false;
   BSRHT_TRY(inv_factor(w.G, l, (double)l * kU64, w.F, &lk, &fb, w, info, s));
+  const int64_t ldk = ld4(lk);
+  if (ldk != lk) {  // F (l x lk) into a zero padded l x ldk copy in C2inv
+    BSRHT_TRY(scale_cols_f64(w.F, l, lk, ldk, lk, nullptr, w.C2inv, ldk, s));
+    BSRHT_TRY(scale_cols_f64(w.C2inv, l, ldk, ldk, ldk, nullptr, w.F, ldk, s));
+  }
   {
     GemmDesc d;
-    d.M = rows; d.N = lk; d.K = l;
+    d.M = rows; d.N = ldk; d.K = l;
     d.sai = sr; d.sak = sc;
-    d.sbk = lk; d.sbj = 1;
-    d.ldc = lk;
+    d.sbk = ldk; d.sbj = 1;
+    d.ldc = ldk;
     BSRHT_TRY(gemm_f32f64_f64(d, X, w.F, w.Q1, s));
   }
   if (fb) {
     or_info_kernel<<<1, 1, 0, s>>>(info, BSRHT_INFO_QB_FALLBACK);
     BSRHT_LAUNCH_CHECK();
   }
-  // second pass: G2 = Q1^T Q1 = C2^T C2, Q = Q1 C2^{-1}
-  BSRHT_TRY(gram_f64(w.Q1, rows, lk, lk, 1, w.G2, lk, w.gram_part, gram_splits(rows, lk), s));
+  // second pass: G2 = Q1^T Q1 = C2^T C2, Q = Q1 C2^{-1} (padding columns stay 0)
+  BSRHT_TRY(gram_f64(w.Q1, rows, lk, ldk, 1, w.G2, lk, w.gram_part, gram_splits(rows, lk), s));
   BSRHT_TRY(cholesky_upper(w.G2, lk, lk, 1e-14, w.flag + 1, w.chol_state, s));
   int32_t hf2 = 0;
   BSRHT_TRY(read_i32(w.flag + 1, s, &hf2));
@@ -678,12 +687,14 @@ int orth_basis(const float *X, int64_t rows, int64_t l, int64_t sr, int64_t sc, 
     debug_report(__FILE__, __LINE__, "second Cholesky-QR pass", BSRHT_EDEVICE);
     return BSRHT_EDEVICE;
   }
-  BSRHT_TRY(trinv_upper(w.G2, lk, lk, w.C2inv, lk, s));
+  BSRHT_TRY(trinv_upper(w.G2, lk, lk, w.F, ldk, s));
+  BSRHT_TRY(scale_cols_f64(w.F, lk, lk, ldk, ldk, nullptr, w.C2inv, ldk, s));
+  if (ldk > lk) BSRHT_TRY(fill_f64(w.C2inv + lk * ldk, (ldk - lk) * ldk, 0.0, s));
   GemmDesc d;
-  d.M = rows; d.N = lk; d.K = lk;
-  d.sai = lk; d.sak = 1;
-  d.sbk = lk; d.sbj = 1;
-  d.ldc = lk;
+  d.M = rows; d.N = ldk; d.K = ldk;
+  d.sai = ldk; d.sak = 1;
+  d.sbk = ldk; d.sbj = 1;
+  d.ldc = ldk;
   BSRHT_TRY(gemm_f64f64_f32(d, w.Q1, w.C2inv, Q32, s));
   *lk_out = lk;
   return BSRHT_OK;
@@ -743,9 +754,10 @@ int rsvd_single_view(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi, b
   int64_t lq = l, lp = l;
   BSRHT_TRY(orth_basis(w.Y, N1, l, l, 1, w.Q32, &lq, w, info, s));
   BSRHT_TRY(orth_basis(w.Xt, N2, l, 1, N2, w.P32, &lp, w, info, s));
+  const int64_t ldq = ld4(lq), ldp = ld4(lp);  // leading dimensions of Q32, P32
   // 3. Phi Q (s x lq), Psi P (s x lp)
-  BSRHT_TRY(sketch_cols(phi, w.Q32, lq, lq, w.PhQ, lq, w.apply_ws, w.apply_bytes, s));
-  BSRHT_TRY(sketch_cols(psi, w.P32, lp, lp, w.PsP, lp, w.apply_ws, w.apply_bytes, s));
+  BSRHT_TRY(sketch_cols(phi, w.Q32, lq, ldq, w.PhQ, lq, w.apply_ws, w.apply_bytes, s));
+  BSRHT_TRY(sketch_cols(psi, w.P32, lp, ldp, w.PsP, lp, w.apply_ws, w.apply_bytes, s));
   // 4. C = (Phi Q)^+ Z ((Psi P)^T)^+, computed as C^T (lp x lq) in Ct
   int64_t nf1 = lq, nf2 = lp;
   bool fb1 = false, fb2 = false;
@@ -805,29 +817,43 @@ int rsvd_single_view(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi, b
     d.ldc = lq;
     BSRHT_TRY(gemm_f64(d, w.F2, w.T4t, w.Ct, s));
   }
-  // 5. SVD of C: the row-major lp x lq Ct is C in column-major order; the
-  // one-sided Jacobi on its (zero padded) columns accumulates Vt.
+  // 5. SVD of C (lq x lp), preconditioned: the Cholesky factor R of the FP64
+  // Gram C^T C = R^T R has the singular values and right singular vectors of
+  // C, and the one-sided Jacobi converges on R's columns in far fewer sweeps
+  // than on C's.  If that Cholesky fails (C numerically rank deficient), the
+  // Jacobi runs on C itself: the row-major lp x lq Ct is C in column-major
+  // order, and the rotations (Vt) are accumulated.
   const int64_t L = svd_pad(std::max(lq, lp));
-  BSRHT_TRY(fill_f64(w.sv.X, L * L, 0.0, s));
-  BSRHT_TRY(scale_cols_f64(w.Ct, lp, lq, lq, lq, nullptr, w.sv.X, L, s));
-  BSRHT_TRY(jacobi_svd(w.sv.X, L, L, L, w.sv.V, w.sv.S, w.sv.Vs, L, w.sv.perm, w.sv.flags,
-                       kMaxSweeps, info, s));
+  int64_t ldv = L;  // leading dimension of the right singular vectors in sv.Vs
+  BSRHT_TRY(gram_f64(w.Ct, lq, lp, 1, lq, w.Gc, lp, w.gram_part, gram_splits(lq, lp), s));
+  BSRHT_TRY(cholesky_upper(w.Gc, lp, lp, (double)lp * kU64, w.flag + 2, w.chol_state, s));
+  int32_t hc = 0;
+  BSRHT_TRY(read_i32(w.flag + 2, s, &hc));
+  if (hc == 0) {
+    BSRHT_TRY(small_svd(w.sv, w.Gc, lp, lp, false, info, s));
+    ldv = svd_pad(lp);
+  } else {
+    BSRHT_TRY(fill_f64(w.sv.X, L * L, 0.0, s));
+    BSRHT_TRY(scale_cols_f64(w.Ct, lp, lq, lq, lq, nullptr, w.sv.X, L, s));
+    BSRHT_TRY(jacobi_svd(w.sv.X, L, L, L, w.sv.V, w.sv.S, w.sv.Vs, L, w.sv.perm, w.sv.flags,
+                         kMaxSweeps, info, s));
+  }
   // 6. S = St_k, V = P Vt_k, U = Q (C Vt_k St_k^{-1})
   const int64_t avail = std::min(lq, lp);
   finish_sigma_kernel<<<(unsigned)((k + 255) / 256), 256, 0, s>>>(
       w.sv.S, avail, k, sqrt((double)L * kU64), 1, w.sv.inv, S, info);
   BSRHT_LAUNCH_CHECK();
   const int64_t keep = std::min(k, avail);
-  BSRHT_TRY(scale_cols_f64_f32(w.sv.Vs, lp, keep, k, L, nullptr, w.Vk32, k, s));
+  BSRHT_TRY(scale_cols_f64_f32(w.sv.Vs, lp, keep, k, ldv, nullptr, w.Vk32, k, s));
   {
     GemmDesc d;
     d.M = N2; d.N = k; d.K = lp;
-    d.sai = lp; d.sak = 1;
+    d.sai = ldp; d.sak = 1;
     d.sbk = k; d.sbj = 1;
     d.ldc = k;
     BSRHT_TRY(gemm_f32(d, w.P32, w.Vk32, V, s));
   }
-  BSRHT_TRY(scale_cols_f64(w.sv.Vs, lp, keep, k, L, w.sv.inv, w.Mv, k, s));
+  BSRHT_TRY(scale_cols_f64(w.sv.Vs, lp, keep, k, ldv, w.sv.inv, w.Mv, k, s));
   {
     GemmDesc d;  // Mu = C Mv = Ct^T Mv  (lq x k)
     d.M = lq; d.N = k; d.K = lp;
@@ -839,7 +865,7 @@ int rsvd_single_view(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi, b
   BSRHT_TRY(scale_cols_f64_f32(w.Mu, lq, k, k, k, nullptr, w.Mu32, k, s));
   GemmDesc d;
   d.M = N1; d.N = k; d.K = lq;
-  d.sai = lq; d.sak = 1;
+  d.sai = ldq; d.sak = 1;
   d.sbk = k; d.sbj = 1;
   d.ldc = k;
   return gemm_f32(d, w.Q32, w.Mu32, U, s);
