@@ -541,8 +541,11 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
 // row-major A with four block SRHTs: Omega (l x N2) and Psi (s x N2) act on
 // the rows of A from the right, Gamma (l x N1) and Phi (s x N1) on its columns.
 //   1. X^T = Gamma A (l x N2), Y = A Omega^T (N1 x l), Z = (Phi A) Psi^T (s x s)
-//   2. Q = orth(Y), P = orth(X) (Cholesky-QR2 in FP64, eigen split when the
-//      sketch is rank deficient)
+//   2. Q = orth(Y), P = orth(X).  Q is kept implicit, Q = Y F with F the
+//      inverse Cholesky factor of the FP64 Gram Y^T Y (the randomized SVD
+//      treats its tall factor Z the same way): only Phi Q = (Phi Y) F and
+//      U = Y (F M) are needed.  P (N2 x l) is formed by Cholesky-QR2.  A rank
+//      deficient sketch keeps the directions of its Gram's eigen split.
 //   3. Phi Q (s x lq), Psi P (s x lp)
 //   4. C = (Phi Q)^+ Z ((Psi P)^T)^+ through the normal equations: Phi and Psi
 //      are embeddings of the orthonormal Q and P, so the Grams of Phi Q and
@@ -557,18 +560,18 @@ namespace {
 
 template <class A>
 struct SvWs {
-  float *Xt, *Y, *W, *Zs, *Q32, *P32, *PhQ, *PsP, *Mu32, *Vk32;
+  float *Xt, *Y, *W, *Zs, *PhY, *P32, *PsP, *Mu32, *Vk32;
   void *apply_ws;
   size_t apply_bytes;
-  double *G, *Gs, *F, *Q1, *G2, *C2inv, *gram_part;
-  double *Gc, *F1, *F2, *T1, *T2, *T3t, *T4t, *Ct, *Mv, *Mu;
+  double *G, *Gs, *F, *Fq, *Q1, *G2, *C2inv, *gram_part;
+  double *PhQ, *Gc, *F1, *F2, *T1, *T2, *T3t, *T4t, *Ct, *Mv, *Mu;
   int32_t *flag;
   void *chol_state;
   SvdBufs<A> qb, sv;
   void layout(A &a, const bsrht_plan_s *om, const bsrht_plan_s *ga, const bsrht_plan_s *ph,
               const bsrht_plan_s *ps, int64_t k) {
     const int64_t N1 = ga->n, N2 = om->n, l = om->l, s = ph->l;
-    const int64_t Nm = std::max(N1, N2), l4 = (l + 3) & ~int64_t(3);
+    const int64_t l4 = (l + 3) & ~int64_t(3);
     Xt = a.template take<float>((size_t)(l * N2));
     Y = a.template take<float>((size_t)(N1 * l));
     W = a.template take<float>((size_t)(s * N2));
@@ -577,22 +580,23 @@ struct SvWs {
     // of a sketch is not monotonic in its column count, so take the maximum.
     size_t ab = std::max({apply_ws_bytes(ga, N2), apply_right_ws_bytes(om, N1),
                           apply_ws_bytes(ph, N2), apply_right_ws_bytes(ps, s)});
-    for (int64_t c = 1; c <= l; ++c)
-      ab = std::max({ab, apply_ws_bytes(ph, c), apply_ws_bytes(ps, c)});
+    for (int64_t c = 1; c <= l; ++c) ab = std::max(ab, apply_ws_bytes(ps, c));
+    ab = std::max(ab, apply_ws_bytes(ph, l));
     apply_bytes = ab;
     apply_ws = a.template take<char>(apply_bytes);
     G = a.template take<double>((size_t)(l * l));
     Gs = a.template take<double>((size_t)(l * l));
     F = a.template take<double>((size_t)(l4 * l4));
-    Q1 = a.template take<double>((size_t)(Nm * l4));
+    Fq = a.template take<double>((size_t)(l * l));
+    Q1 = a.template take<double>((size_t)(N2 * l4));
     G2 = a.template take<double>((size_t)(l * l));
     C2inv = a.template take<double>((size_t)(l4 * l4));
     gram_part = a.template take<double>((size_t)std::max(
         {gram_partial_elems(N1, l), gram_partial_elems(N2, l), gram_partial_elems(s, l),
          (int64_t)1}));
-    Q32 = a.template take<float>((size_t)(N1 * l4));
+    PhY = a.template take<float>((size_t)(s * l));
     P32 = a.template take<float>((size_t)(N2 * l4));
-    PhQ = a.template take<float>((size_t)(s * l));
+    PhQ = a.template take<double>((size_t)(s * l));
     PsP = a.template take<float>((size_t)(s * l));
     Gc = a.template take<double>((size_t)(l * l));
     F1 = a.template take<double>((size_t)(l * l));
@@ -750,18 +754,34 @@ int rsvd_single_view(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi, b
   BSRHT_TRY(apply_right_fp32(omega, A, N1, lda, w.Y, l, w.apply_ws, w.apply_bytes, s));
   BSRHT_TRY(sketch_cols(phi, A, N2, lda, w.W, N2, w.apply_ws, w.apply_bytes, s));
   BSRHT_TRY(apply_right_fp32(psi, w.W, s_, N2, w.Zs, s_, w.apply_ws, w.apply_bytes, s));
-  // 2. bases Q = orth(Y) (N1 x lq), P = orth(X) = orth(Xt^T) (N2 x lp)
+  // 2. Q = Y Fq implicitly (N1 x lq), P = orth(X) = orth(Xt^T) (N2 x lp)
   int64_t lq = l, lp = l;
-  BSRHT_TRY(orth_basis(w.Y, N1, l, l, 1, w.Q32, &lq, w, info, s));
+  {
+    bool fbq = false;
+    BSRHT_TRY(gram_f32(w.Y, N1, l, l, 1, w.G, l, w.gram_part, gram_splits(N1, l), s));
+    BSRHT_TRY(inv_factor(w.G, l, (double)l * kU64, w.Fq, &lq, &fbq, w, info, s));
+    if (fbq) {
+      or_info_kernel<<<1, 1, 0, s>>>(info, BSRHT_INFO_QB_FALLBACK);
+      BSRHT_LAUNCH_CHECK();
+    }
+  }
   BSRHT_TRY(orth_basis(w.Xt, N2, l, 1, N2, w.P32, &lp, w, info, s));
-  const int64_t ldq = ld4(lq), ldp = ld4(lp);  // leading dimensions of Q32, P32
-  // 3. Phi Q (s x lq), Psi P (s x lp)
-  BSRHT_TRY(sketch_cols(phi, w.Q32, lq, ldq, w.PhQ, lq, w.apply_ws, w.apply_bytes, s));
+  const int64_t ldp = ld4(lp);  // leading dimension of P32
+  // 3. Phi Q = (Phi Y) Fq (s x lq, FP64), Psi P (s x lp)
+  BSRHT_TRY(sketch_cols(phi, w.Y, l, l, w.PhY, l, w.apply_ws, w.apply_bytes, s));
+  {
+    GemmDesc d;
+    d.M = s_; d.N = lq; d.K = l;
+    d.sai = l; d.sak = 1;
+    d.sbk = lq; d.sbj = 1;
+    d.ldc = lq;
+    BSRHT_TRY(gemm_f32f64_f64(d, w.PhY, w.Fq, w.PhQ, s));
+  }
   BSRHT_TRY(sketch_cols(psi, w.P32, lp, ldp, w.PsP, lp, w.apply_ws, w.apply_bytes, s));
   // 4. C = (Phi Q)^+ Z ((Psi P)^T)^+, computed as C^T (lp x lq) in Ct
   int64_t nf1 = lq, nf2 = lp;
   bool fb1 = false, fb2 = false;
-  BSRHT_TRY(gram_f32(w.PhQ, s_, lq, lq, 1, w.Gc, lq, w.gram_part, gram_splits(s_, lq), s));
+  BSRHT_TRY(gram_f64(w.PhQ, s_, lq, lq, 1, w.Gc, lq, w.gram_part, gram_splits(s_, lq), s));
   BSRHT_TRY(inv_factor(w.Gc, lq, (double)lq * kU64, w.F1, &nf1, &fb1, w, info, s));
   BSRHT_TRY(gram_f32(w.PsP, s_, lp, lp, 1, w.Gc, lp, w.gram_part, gram_splits(s_, lp), s));
   BSRHT_TRY(inv_factor(w.Gc, lp, (double)lp * kU64, w.F2, &nf2, &fb2, w, info, s));
@@ -770,18 +790,18 @@ int rsvd_single_view(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi, b
     BSRHT_LAUNCH_CHECK();
   }
   {
-    GemmDesc d;  // T1 = (Phi Q)^T Z  (lq x s)
-    d.M = lq; d.N = s_; d.K = s_;
-    d.sai = 1; d.sak = lq;
-    d.sbk = s_; d.sbj = 1;
-    d.ldc = s_;
-    BSRHT_TRY(gemm_f32f32_f64(d, w.PhQ, w.Zs, w.T1, s));
+    GemmDesc d;  // T1^T = Z^T (Phi Q)  (s x lq), in T1
+    d.M = s_; d.N = lq; d.K = s_;
+    d.sai = 1; d.sak = s_;
+    d.sbk = lq; d.sbj = 1;
+    d.ldc = lq;
+    BSRHT_TRY(gemm_f32f64_f64(d, w.Zs, w.PhQ, w.T1, s));
   }
   {
-    GemmDesc d;  // T2 = F1^T T1  (nf1 x s)
+    GemmDesc d;  // T2 = F1^T T1  (nf1 x s), T1[kk][j] read from T1^T
     d.M = nf1; d.N = s_; d.K = lq;
     d.sai = 1; d.sak = nf1;
-    d.sbk = s_; d.sbj = 1;
+    d.sbk = 1; d.sbj = lq;
     d.ldc = s_;
     BSRHT_TRY(gemm_f64(d, w.F1, w.T1, w.T2, s));
   }
@@ -862,13 +882,21 @@ int rsvd_single_view(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi, b
     d.ldc = k;
     BSRHT_TRY(gemm_f64(d, w.Ct, w.Mv, w.Mu, s));
   }
-  BSRHT_TRY(scale_cols_f64_f32(w.Mu, lq, k, k, k, nullptr, w.Mu32, k, s));
+  {
+    GemmDesc d;  // Mq = Fq Mu  (l x k), in Mv: U = Q Mu = Y Mq
+    d.M = l; d.N = k; d.K = lq;
+    d.sai = lq; d.sak = 1;
+    d.sbk = k; d.sbj = 1;
+    d.ldc = k;
+    BSRHT_TRY(gemm_f64(d, w.Fq, w.Mu, w.Mv, s));
+  }
+  BSRHT_TRY(scale_cols_f64_f32(w.Mv, l, k, k, k, nullptr, w.Mu32, k, s));
   GemmDesc d;
-  d.M = N1; d.N = k; d.K = lq;
-  d.sai = ldq; d.sak = 1;
+  d.M = N1; d.N = k; d.K = l;
+  d.sai = l; d.sak = 1;
   d.sbk = k; d.sbj = 1;
   d.ldc = k;
-  return gemm_f32(d, w.Q32, w.Mu32, U, s);
+  return gemm_f32(d, w.Y, w.Mu32, U, s);
 }
 
 }  // extern "C"
