@@ -14,6 +14,8 @@ Modules
            per-block FWHT + subsample + signs + sum (section 2, eq. (2.4)).
   lowrank  Algorithm 1 (RSVD) and Algorithm 2 (Nystrom), section 3.
   single_view  Algorithm 3 (single-view RSVD), section 3.3.
+  dense    Gaussian and Rademacher comparison sketches (section 4) from
+           the same Philox stream.
   metrics  relative errors used by the parity tests.
 
 Every function cites the passage it follows.  Functions without an
