@@ -305,6 +305,35 @@ int rsvd_single_view(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi,
                      size_t ws_bytes, void *stream);
 
 /*
+ * Dense comparison sketches (section 4 compares the block SRHT with Gaussian
+ * embeddings): Y = G A for an l x n Gaussian or Rademacher G, drawn from the
+ * same Philox4x64-10 as the block SRHT tables, key (seed, 0):
+ *   BSRHT_DENSE_GAUSSIAN   G[j][x] = z / sqrt(l), Box-Muller on word
+ *       q = (x & 7) >> 1 of philox((x >> 3, j, 4, 0)): u1 from its low,
+ *       u2 from its high 32 bits, u = (w + 1/2) 2^-32, z = sqrt(-2 ln u1) *
+ *       cos(2 pi u2) for even x, * sin(2 pi u2) for odd x (FP64, rounded once
+ *       to FP32);
+ *   BSRHT_DENSE_RADEMACHER G[j][x] = +-1 / sqrt(l), bit (x & 255) of
+ *       philox((x >> 8, j, 5, 0)), bit 1 -> -1.
+ * G is materialised in the workspace (l x n FP32), then the product runs on
+ * the FP32 matrix cores with the n-long contraction split into FP64 partials
+ * summed in a fixed order (bitwise repeatable).
+ *
+ * A  : device float32, n x m, leading dimension lda >= m.
+ * Y  : device float32, l x m, leading dimension ldy >= m.
+ * ws : device workspace of ws_bytes >= bsrht_dense_workspace(n, l, m).
+ * Returns BSRHT_OK, BSRHT_EINVAL (unknown kind, n or l < 1, m < 0, NULL
+ * pointers, short leading dimensions), BSRHT_ENOMEM, BSRHT_EUNSUPPORTED
+ * (a size >= 2^31) or BSRHT_EDEVICE; m == 0 is a no-op.
+ */
+#define BSRHT_DENSE_GAUSSIAN 0
+#define BSRHT_DENSE_RADEMACHER 1
+size_t bsrht_dense_workspace(int64_t n, int64_t l, int64_t m);
+int bsrht_dense_sketch(int kind, uint64_t seed, int64_t n, int64_t l, const float *A,
+                       int64_t m, int64_t lda, float *Y, int64_t ldy, void *ws,
+                       size_t ws_bytes, void *stream);
+
+/*
  * Instrumentation (not part of the computation).  bsrht_timing_enable(which)
  * makes the library record a pair of HIP events on the launching stream
  * around every launch of the selected kernel, until called again with 0;
@@ -318,6 +347,7 @@ int rsvd_single_view(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi,
 #define BSRHT_TIMING_GEMM_AQ 3    /* Z = A Q of the randomized SVD          */
 #define BSRHT_TIMING_STREAM 4     /* bsrht_stream_read                       */
 #define BSRHT_TIMING_APPLY_RIGHT 5 /* the FP32 sketch kernel of bsrht_apply_right */
+#define BSRHT_TIMING_DENSE_GEMM 6  /* the product of bsrht_dense_sketch (GEMM + reduce) */
 int bsrht_timing_enable(int which);
 int bsrht_timing_read(double *total_ms, int64_t *launches);
 /*

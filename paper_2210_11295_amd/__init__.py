@@ -23,6 +23,7 @@ __all__ = [
     "JobResult", "ServerStats", "Server", "bsrht_job_bytes", "apply_batch",
     "batch_table_bytes", "ApplyItem", "BATCH_MAX", "bsrht_apply_right",
     "bsrht_apply_right_workspace", "rsvd_single_view", "rsvd_single_view_workspace",
+    "bsrht_dense_sketch", "bsrht_dense_workspace", "DENSE_GAUSSIAN", "DENSE_RADEMACHER",
 ]
 
 WITH_REPLACEMENT = 0
@@ -39,6 +40,9 @@ TIMING_APPLY_BF16 = 2
 TIMING_GEMM_AQ = 3
 TIMING_STREAM = 4
 TIMING_APPLY_RIGHT = 5
+TIMING_DENSE_GEMM = 6
+DENSE_GAUSSIAN = 0
+DENSE_RADEMACHER = 1
 STREAM_BLOCKS = 4096
 JOB_SKETCH = 0
 JOB_RSVD = 1
@@ -71,6 +75,9 @@ _SIGS = {
                             _c_vp, _c_vp, _c_sz, _c_vp]),
     "nystrom_workspace": (_c_sz, [_c_vp, _c_i64]),
     "rsvd_single_view_workspace": (_c_sz, [_c_vp, _c_vp, _c_vp, _c_vp, _c_i64]),
+    "bsrht_dense_workspace": (_c_sz, [_c_i64, _c_i64, _c_i64]),
+    "bsrht_dense_sketch": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint64, _c_i64, _c_i64, _c_vp,
+                                          _c_i64, _c_i64, _c_vp, _c_i64, _c_vp, _c_sz, _c_vp]),
     "rsvd_single_view": (ctypes.c_int, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_i64, _c_i64,
                                         _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_sz, _c_vp]),
     "bsrht_timing_enable": (ctypes.c_int, [ctypes.c_int]),
@@ -367,6 +374,28 @@ def rsvd(plan, A, k, ws=None, stream=None):
                               _ptr(S), _ptr(V), _ptr(info), _ptr(ws), ws.numel(),
                               _stream_ptr(stream)))
     return U, S, V, info
+
+
+def bsrht_dense_workspace(n, l, m):
+    return int(lib().bsrht_dense_workspace(n, l, m))
+
+
+def bsrht_dense_sketch(kind, seed, l, A, Y=None, ws=None, stream=None):
+    """Y = G A for a dense Gaussian (DENSE_GAUSSIAN) or Rademacher
+    (DENSE_RADEMACHER) l x n G drawn from (seed); A: n x m float32."""
+    _check_matrix("A", A)
+    n, m = A.shape
+    if Y is None:
+        Y = torch.empty(l, m, dtype=torch.float32, device=A.device)
+    _check_matrix("Y", Y)
+    if tuple(Y.shape) != (l, m):
+        raise ValueError(f"Y must be {l} x {m}")
+    if ws is None:
+        ws = _workspace(bsrht_dense_workspace(n, l, m), A.device)
+    _check("bsrht_dense_sketch", lib().bsrht_dense_sketch(
+        kind, ctypes.c_uint64(int(seed) & (2 ** 64 - 1)), n, l, _ptr(A), m, max(A.stride(0), m),
+        _ptr(Y), max(Y.stride(0), m), _ptr(ws), ws.numel(), _stream_ptr(stream)))
+    return Y
 
 
 def rsvd_single_view_workspace(omega, gamma, phi, psi, k):

@@ -30,6 +30,13 @@ int gemm_f64f64_f32(const GemmDesc &d, const double *A, const double *B, float *
 int gemm_f32f32_f64(const GemmDesc &d, const float *A, const float *B, double *C,
                     hipStream_t s);
 
+// C = A B (FP32 operands on the FP32 matrix cores) with the K range split
+// into `splits` FP32-accumulated partials, stored as FP64 at
+// partials + s*M*N (splits*M*N doubles) and summed in split order into C
+// (row-major, d.ldc; alpha = 1, beta = 0).  splits <= 1 is gemm_f32.
+int gemm_f32_splitk(const GemmDesc &d, const float *A, const float *B, float *C,
+                    double *partials, int splits, hipStream_t s);
+
 // G = X^T X (K x K FP64) for X[r][c] = X[r*sr + c*sc], r < n, c < K; the row
 // range is split into `splits` FP64 partials (K*K each, in `partials`)
 // summed in split order.

@@ -379,6 +379,24 @@ int gemm_f32f32_f64(const GemmDesc &d, const float *A, const float *B, double *C
   return gemm_launch<float, float, double, true>(d, A, B, C, s);
 }
 
+int gemm_f32_splitk(const GemmDesc &d0, const float *A, const float *B, float *C,
+                    double *partials, int splits, hipStream_t s) {
+  if (d0.M <= 0 || d0.N <= 0) return BSRHT_OK;
+  if (splits <= 1) return gemm_f32(d0, A, B, C, s);
+  GemmDesc d = d0;
+  d.splits = splits;
+  d.split_stride = d.M * d.N;
+  d.ldc = d.N;
+  d.alpha = 1.0;
+  d.beta = 0.0;
+  BSRHT_TRY((gemm_launch<float, float, double, false>(d, A, B, partials, s)));
+  const int64_t total = d.M * d.N;
+  reduce_partials_kernel<float><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(
+      partials, splits, d.M, d.N, C, d0.ldc, false);
+  BSRHT_LAUNCH_CHECK();
+  return BSRHT_OK;
+}
+
 // G = X^T X (K x K, FP64) for X with rows r < n, X[r][c] = X[r*sr + c*sc],
 // split over rows into `splits` FP64 partials summed in order.
 template <typename TX>
