@@ -219,6 +219,46 @@ def bench_right(bs, A, cfg, steps, warmup, Y_col):
             "rel_diff_vs_column_sketch": diff}
 
 
+def bench_dense(bs, A, cfg, steps, warmup, bsrht_ms):
+    """The dense comparison sketches of section 4 on the same A and l: a
+    Gaussian and a Rademacher G (l x n) generated into the workspace, then
+    Y = G A on the FP32 matrix cores.  bsrht_ms: the block SRHT sketch's
+    time per call on the same input."""
+    import torch
+    n, m, l, seed = cfg["n"], cfg["m"], cfg["l"], cfg["seed"]
+    ws = torch.empty(max(1, bs.bsrht_dense_workspace(n, l, m)), dtype=torch.uint8,
+                     device=A.device)
+    Y = torch.empty(l, m, dtype=torch.float32, device=A.device)
+    out = {}
+    for name, kind in (("gaussian", bs.DENSE_GAUSSIAN), ("rademacher", bs.DENSE_RADEMACHER)):
+        for _ in range(warmup):
+            bs.bsrht_dense_sketch(kind, seed, l, A, Y, ws)
+        torch.cuda.synchronize()
+        bs.timing_enable(bs.TIMING_DENSE_GEMM)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            bs.bsrht_dense_sketch(kind, seed, l, A, Y, ws)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        gms, gl = bs.timing_read()
+        bs.timing_enable(bs.TIMING_OFF)
+        gemm_ms = gms / max(gl, 1)
+        flops = 2.0 * l * m * n
+        tf = flops / (gemm_ms * 1e-3) / 1e12
+        log(f"bench: dense {name} sketch {dt * 1e3:.2f} ms per call, product {gemm_ms:.2f} ms "
+            f"-> {tf:.1f} TFLOP/s; block SRHT {bsrht_ms:.3f} ms")
+        out[name] = {"ms_per_call": round(dt * 1e3, 3), "product_ms": round(gemm_ms, 3),
+                     "generate_ms": round(dt * 1e3 - gemm_ms, 3),
+                     "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": 157.3,
+                                  "unit": "TFLOP/s", "frac": round(tf / 157.3, 4),
+                                  "kernel": "gemm_big_kernel<float, float, double> split-K + "
+                                            "reduce_partials_kernel",
+                                  "alg_flops_per_launch": flops},
+                     "bsrht_speedup": round(dt * 1e3 / bsrht_ms, 2)}
+    del ws
+    return out
+
+
 def _fro_error(A, U, S, V, chunk=1 << 16):
     """||A - U diag(S) V^T||_F / ||A||_F in FP64 on the device (measurement)."""
     import torch
@@ -533,8 +573,8 @@ def main():
                     help="jobs of the serving workload (0 skips it)")
     ap.add_argument("--serve-streams", type=int, default=SERVE_STREAMS)
     ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--only", choices=["all", "sketch", "bf16", "right", "rsvd", "single_view",
-                                       "nystrom", "serve", "serve_small"],
+    ap.add_argument("--only", choices=["all", "sketch", "bf16", "right", "dense", "rsvd",
+                                       "single_view", "nystrom", "serve", "serve_small"],
                     default="all",
                     help="profiling aid: run one part ('bf16', 'right', 'rsvd', 'nystrom' and "
                          "'serve' print only that part's JSON object)")
@@ -580,6 +620,16 @@ def main():
         if args.copy_calibration:
             _copy_calibration(A)
         print(json.dumps({"split_bf16": out_b}), flush=True)
+        return
+    if args.only == "dense":
+        bs.bsrht_apply(plan, A)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            bs.bsrht_apply(plan, A)
+        torch.cuda.synchronize()
+        bms = (time.perf_counter() - t0) / 5 * 1e3
+        print(json.dumps({"dense_sketch": bench_dense(bs, A, cfg, 5, 1, bms)}), flush=True)
         return
     if args.only == "right":
         Yf = bs.bsrht_apply(plan, A)
@@ -653,6 +703,7 @@ def main():
     else:
         out["split_bf16"] = bench_split_bf16(bs, A, cfg, args.steps, args.warmup, Y)
         out["right_apply"] = bench_right(bs, A, cfg, args.steps, args.warmup, Y)
+        out["dense_sketch"] = bench_dense(bs, A, cfg, 5, 1, elapsed / args.steps * 1e3)
     if not args.skip_lowrank:
         out["rsvd"] = bench_rsvd(bs, A, plan, cfg, args.lowrank_reps)
         out["rsvd_single_view"] = bench_single_view(bs, A, cfg, args.lowrank_reps)
