@@ -31,6 +31,13 @@ Tables
 Keying by (seed, block, index) makes a p = 1 plan with the same r and seed
 reproduce block 0 of any plan: the 2**16-row subsample check relies on it.
 
+Blocks whose size r is not a power of two (section 2: a partial SRHT, the
+first r columns of an SRHT of size r' = the next power of two, i.e. the input
+block padded with zeros to r' rows).  R is drawn from [0, r') and D^(i) holds
+the first r entries of block i's stream, so a plan with such an r equals the
+power-of-two plan (p r', p) on the input with r' - r zero rows appended to
+every block.
+
 The oracle's Philox is checked against numpy.random.Philox, an independent
 library implementation of the same published generator.
 """
@@ -123,10 +130,11 @@ def sample_rows(r, l, seed, sampling=WITH_REPLACEMENT):
 class Plan:
     """The random tables of one block SRHT Omega (l x n), eq. (2.3).
 
-    n rows of the sketched matrix split into p blocks of r = n/p rows each;
-    r must be a power of two (padding is not modelled).  Holds
-      R   : (l,)   int64 sample indices in [0, r), shared by all blocks
-      D   : (p, r) float64 +-1, input signs D^(i)
+    n rows of the sketched matrix split into p blocks of r = n/p rows each,
+    each padded with zeros to rp = the next power of two >= r (rp = r when r
+    is a power of two: no padding).  Holds
+      R   : (l,)   int64 sample indices in [0, rp), shared by all blocks
+      D   : (p, r) float64 +-1, input signs D^(i) of the r real rows
       Dt  : (p, l) float64 +-1, output signs Dt^(i)
     plus the raw 0/1 bits, for comparison with tables exported by the GPU
     library.
@@ -137,14 +145,13 @@ class Plan:
         if p < 1 or n < 1 or n % p:
             raise ValueError("p must divide n")
         r = n // p
-        if r & (r - 1):
-            raise ValueError("r = n/p must be a power of two")
+        rp = 1 << (r - 1).bit_length()
         if not 1 <= l <= n:
             raise ValueError("need 1 <= l <= n")
-        self.n, self.p, self.l, self.r = n, p, l, r
+        self.n, self.p, self.l, self.r, self.rp = n, p, l, r, rp
         self.seed = int(seed) & MASK64
         self.sampling = sampling
-        self.R = sample_rows(r, l, self.seed, sampling)
+        self.R = sample_rows(rp, l, self.seed, sampling)
         self.D_bits = np.stack([sign_bits(r, i, TAG_D, self.seed) for i in range(p)])
         self.Dt_bits = np.stack([sign_bits(l, i, TAG_DT, self.seed) for i in range(p)])
         self.D = signs_from_bits(self.D_bits)

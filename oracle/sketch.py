@@ -15,6 +15,11 @@ Kronecker power in natural order), the scale sqrt(r/l) * (1/sqrt(r)) is
 
     Omega[j, i*r + x] = Dt^(i)_j * (-1)^popcount(R_j & x) * D^(i)_x / sqrt(l).
 
+A block size r that is not a power of two gives section 2's partial SRHT:
+Omega^(i) is the first r columns of the SRHT of size rp (the next power of
+two), i.e. the block is padded with rp - r zero rows; the closed form above
+holds for x < r with R_j in [0, rp).
+
 Two independent computations are provided and must agree:
   omega_explicit : the closed form above, entry by entry (small n only);
   sketch         : per block, signs -> radix-2 FWHT -> gather R -> signs,
@@ -67,11 +72,15 @@ def fwht_rows(B):
 
 
 def block_partial(plan, A, i):
-    """Omega^(i) A^(i) without the final 1/sqrt(l): Dt^(i) R H_r D^(i) A^(i)."""
-    r = plan.r
+    """Omega^(i) A^(i) without the final 1/sqrt(l): Dt^(i) R H_r D^(i) A^(i).
+
+    A block of r rows that is not a power of two is padded with zero rows to
+    rp (section 2's partial SRHT: the first r columns of H_rp)."""
+    r, rp = plan.r, plan.rp
     Ai = np.asarray(A[i * r:(i + 1) * r], dtype=np.float64)
-    B = plan.D[i][:, None] * Ai          # D^(i): flip row signs
-    B = fwht_rows(B)                     # H_r (unscaled)
+    B = np.zeros((rp,) + Ai.shape[1:])
+    B[:r] = plan.D[i][:, None] * Ai      # D^(i): flip row signs; zero padding
+    B = fwht_rows(B)                     # H_rp (unscaled)
     S = B[plan.R, :]                     # R: keep rows R_j, draw order
     return plan.Dt[i][:, None] * S       # Dt^(i): flip sample signs
 

@@ -87,8 +87,10 @@ def test_without_replacement_needs_l_le_r():
 
 
 def test_plan_validation():
+    pl = rng.Plan(12, 1, 4, 0)     # r = 12: a partial SRHT padded to 16
+    assert pl.rp == 16 and np.all(pl.R < 16)
     with pytest.raises(ValueError):
-        rng.Plan(12, 1, 4, 0)      # r not a power of two
+        rng.Plan(12, 2, 10, 0, rng.WITHOUT_REPLACEMENT)   # r = 6, r' = 8 < l
     with pytest.raises(ValueError):
         rng.Plan(16, 3, 4, 0)      # p does not divide n
     with pytest.raises(ValueError):

@@ -148,6 +148,69 @@ def test_sketch_entry_matches_sketch():
         assert abs(sketch.sketch_entry(plan, A[:, c], j) - Y[j, c]) < 1e-12 * np.abs(Y).max()
 
 
+PADDED_CASES = [
+    # n, p, l, mode  -- block sizes r that are not powers of two (partial SRHT)
+    (300, 3, 20, rng.WITH_REPLACEMENT),      # r = 100 -> 128
+    (1000, 8, 40, rng.WITH_REPLACEMENT),     # r = 125 -> 128
+    (96, 1, 30, rng.WITHOUT_REPLACEMENT),    # r = 96 -> 128, l <= r'
+    (770, 5, 64, rng.WITH_REPLACEMENT),      # r = 154 -> 256
+    (7, 7, 5, rng.WITH_REPLACEMENT),         # r = 1 (no padding)
+    (513, 1, 9, rng.WITH_REPLACEMENT),       # r = 513 -> 1024
+]
+
+
+def _pad_blocks(A, p, r, rp):
+    """A with rp - r zero rows appended to each of its p blocks of r rows."""
+    out = np.zeros((p * rp,) + A.shape[1:])
+    for i in range(p):
+        out[i * rp:i * rp + r] = A[i * r:(i + 1) * r]
+    return out
+
+
+@pytest.mark.parametrize("n,p,l,mode", PADDED_CASES)
+def test_partial_srht_explicit_equals_padded_fwht(n, p, l, mode):
+    """Section 2's partial SRHT: the closed form restricted to the r real
+    columns of each block equals the FWHT path on zero-padded blocks, and every
+    entry is +-1/sqrt(l) with unit columns."""
+    plan = rng.Plan(n, p, l, 5, mode)
+    Om = sketch.omega_explicit(plan)
+    A = np.random.default_rng(3).standard_normal((n, 6))
+    assert metrics.rel_fro(sketch.sketch(plan, A), Om @ A) < 1e-13
+    assert np.all(np.abs(np.abs(Om) * np.sqrt(l) - 1.0) < 1e-15)
+    assert np.allclose(np.linalg.norm(Om, axis=0), 1.0, atol=1e-14)
+
+
+@pytest.mark.parametrize("n,p,l,mode", PADDED_CASES)
+def test_partial_srht_is_the_power_of_two_plan_on_padded_input(n, p, l, mode):
+    """The tables are keyed by (block, index): a plan with r rows per block is
+    the (p r', p) plan on the input with zero rows appended to every block."""
+    plan = rng.Plan(n, p, l, 11, mode)
+    r, rp = plan.r, plan.rp
+    full = rng.Plan(p * rp, p, l, 11, mode)
+    assert np.array_equal(plan.R, full.R)
+    assert np.array_equal(plan.D_bits, full.D_bits[:, :r])
+    A = np.random.default_rng(4).standard_normal((n, 5))
+    assert metrics.rel_fro(sketch.sketch(plan, A), sketch.sketch(full, _pad_blocks(A, p, r, rp))) < 1e-14
+
+
+def test_partial_srht_pin_catches_padding_at_the_end(monkeypatch):
+    """Padding the whole input at its end instead of each block fails the
+    explicit-form pin."""
+    plan = rng.Plan(300, 3, 20, 5)
+
+    def bad_partial(pl, AA, i):
+        Apad = np.zeros((pl.p * pl.rp,) + AA.shape[1:])
+        Apad[:pl.n] = AA
+        Ai = Apad[i * pl.rp:(i + 1) * pl.rp]
+        B = sketch.fwht_rows(np.concatenate([pl.D[i], np.ones(pl.rp - pl.r)])[:, None] * Ai)
+        return pl.Dt[i][:, None] * B[pl.R, :]
+
+    A = np.random.default_rng(3).standard_normal((300, 4))
+    ref = sketch.omega_explicit(plan) @ A
+    monkeypatch.setattr(sketch, "block_partial", bad_partial)
+    assert metrics.rel_fro(sketch.sketch(plan, A), ref) > 1e-3
+
+
 @pytest.mark.parametrize("n,p,l,mode", CASES)
 def test_right_sketch_is_omega_applied_from_the_right(n, p, l, mode):
     """A Omega^T (Algorithm 1's orientation) equals the closed-form Omega
