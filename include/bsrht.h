@@ -79,7 +79,7 @@ const char *bsrht_strerror(int status);
 
 /*
  * Device bytes needed for the random tables of a plan with these sizes
- * (R: l int32; D: n bits; Dt: p*l bits, each region 256-byte aligned).
+ * (R: l int32; D: p*rp bits; Dt: p*l bits, each region 256-byte aligned).
  * Returns 0 if the sizes are invalid (see bsrht_plan).
  */
 size_t bsrht_plan_bytes(int64_t n, int64_t p, int64_t l);
@@ -90,13 +90,19 @@ size_t bsrht_plan_bytes(int64_t n, int64_t p, int64_t l);
  *   key = (seed, 0); one call gives 256 bits, bit b in word b/64, bit b%64;
  *   D^(i)_x  = bit (x%256) of philox((x/256, i, 2, 0)), bit 1 -> -1;
  *   Dt^(i)_j = bit (j%256) of philox((j/256, i, 3, 0)), bit 1 -> -1;
- *   R_j (with replacement)    = word0(philox((j, 0, 1, 0))) mod r;
- *   R_j (without replacement) = partial Fisher-Yates over [0, r) with
- *       t = j + floor(word0(philox((j,0,1,0))) * (r - j) / 2^64).
+ *   R_j (with replacement)    = word0(philox((j, 0, 1, 0))) mod rp;
+ *   R_j (without replacement) = partial Fisher-Yates over [0, rp) with
+ *       t = j + floor(word0(philox((j,0,1,0))) * (rp - j) / 2^64).
+ * rp is r rounded up to a power of two.  A block size r = n/p that is not a
+ * power of two gives section 2's partial SRHT: Omega^(i) is the first r
+ * columns of the rp-point SRHT, i.e. each block of A is treated as padded
+ * with rp - r zero rows (never stored).  Such plans sketch with the FP32
+ * kernels whatever their precision; bsrht_apply_right evaluates them
+ * directly (O(n) per output) and bsrht_apply_batch rejects them.
  *
  * n, p, l     : Omega is l x n with p blocks of r = n/p columns.  Requires
- *               p >= 1, p | n, r a power of two, 1 <= l <= n, and l <= r
- *               for sampling without replacement.  n < 2^31.
+ *               p >= 1, p | n, 1 <= l <= n, and l <= rp for sampling
+ *               without replacement.  n < 2^31 and p*rp < 2^31.
  * seed        : 64-bit seed.
  * sampling    : BSRHT_WITH_REPLACEMENT or BSRHT_WITHOUT_REPLACEMENT.
  * precision   : BSRHT_FP32 or BSRHT_SPLIT_BF16 (used by bsrht_apply).
@@ -123,8 +129,9 @@ int bsrht_plan_info(bsrht_plan_t plan, int64_t *n, int64_t *p, int64_t *l,
 /*
  * Copy the plan's tables to host memory (synchronises the plan's stream).
  * R     : host int32[l]            sample indices in [0, r), draw order.
- * Dbits : host uint32[ceil(n/32)]  bit (g%32) of word g/32 is the sign bit of
- *                                  D for global row g = i*r + x (1 -> -1).
+ * Dbits : host uint32[ceil(p*rp/32)]  bit (g%32) of word g/32 is the sign
+ *                                  bit of D^(i)_x for g = i*rp + x
+ *                                  (1 -> -1; g = the global row when r = rp).
  * Dtbits: host uint32[p*ceil(l/32)] bit (j%32) of word i*ceil(l/32) + j/32
  *                                  is the sign bit of Dt^(i)_j.
  * Any pointer may be NULL to skip that table.

@@ -237,6 +237,7 @@ class Plan:
         dev = torch.device(device) if device is not None else torch.device("cuda")
         self.tables = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
         self.n, self.p, self.l, self.r = int(n), int(p), int(l), int(n) // int(p)
+        self.rp = 1 << (self.r - 1).bit_length()  # block size padded to a power of two
         self.seed, self.sampling, self.precision = int(seed), int(sampling), int(precision)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.tables.device):
@@ -253,9 +254,9 @@ class Plan:
             self.handle = None
 
     def export(self):
-        """(R int32[l], Dbits uint32[ceil(n/32)], Dtbits uint32[p*ceil(l/32)])."""
+        """(R int32[l], Dbits uint32[ceil(p*rp/32)], Dtbits uint32[p*ceil(l/32)])."""
         R = np.zeros(self.l, dtype=np.int32)
-        Db = np.zeros((self.n + 31) // 32, dtype=np.uint32)
+        Db = np.zeros((self.p * self.rp + 31) // 32, dtype=np.uint32)
         Dtb = np.zeros(self.p * ((self.l + 31) // 32), dtype=np.uint32)
         _check("bsrht_plan_export", lib().bsrht_plan_export(
             self.handle, R.ctypes.data_as(_c_vp), Db.ctypes.data_as(_c_vp),

@@ -353,6 +353,10 @@ struct Launch {
 Launch choose_launch(const bsrht_plan_s *pl, int64_t m) {
   Launch L;
   int per_cu;
+  if (pl->r != pl->rp) {  // blocks padded with zeros: the FP32 kernels
+    L.fp32 = true;
+    return L;
+  }
   if (pl->l > 512 && pl->r >= 256) {
     // 16 waves, one thread per sample for l <= 1024: A is read once per
     // 1024 samples; chunks of b = 16*16 rows.

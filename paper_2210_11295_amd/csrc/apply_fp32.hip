@@ -57,6 +57,8 @@ struct FusedArgs {
   int64_t ldo;
   int64_t split_stride;
   float scale;
+  int64_t r_rows;  // rows per block in A (padded plans: r < 2^log2r)
+  int cr;          // chunks per block that hold rows of A (padded plans)
 };
 
 // Unscaled Walsh-Hadamard transform of N values held in registers.
@@ -90,6 +92,23 @@ __device__ __forceinline__ void load_rows(float (&v)[BR], const float *base, int
     v[t] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, voff, t * row_bytes, kAuxNT));
 }
 
+// The same for a wave whose first vr rows (wave-uniform, 0 <= vr <= BR) hold
+// data and the rest are the zero padding of a block: row t >= vr is read at
+// row max(vr - 1, 0) (an address inside A) and replaced by zero.
+template <int BR, int T0 = 0, int T1 = BR>
+__device__ __forceinline__ void load_rows_masked(float (&v)[BR], const float *base, int voff,
+                                                 int row_bytes, int vr) {
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(base);
+  const int last = vr > 0 ? vr - 1 : 0;
+#pragma unroll
+  for (int t = T0; t < T1; ++t) {
+    const int tr = t < last ? t : last;
+    const float x =
+        __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, voff, tr * row_bytes, kAuxNT));
+    v[t] = t < vr ? x : 0.f;
+  }
+}
+
 // D^(i) for global rows g0 .. g0+BR-1 (g0 a multiple of BR, wave-uniform):
 // flip the sign bit where the table bit is set.
 template <int BR>
@@ -115,7 +134,12 @@ __device__ __forceinline__ void apply_dsigns(float (&v)[BR], const uint32_t *__r
   }
 }
 
-template <int NW, int BR>
+// PAD: a plan whose blocks hold r rows of A, padded with zeros to
+// rp = 2^log2r.  The split ranges count the chunks that hold rows of A
+// (cr per block); chunk qr of them is chunk qp = i*(rp/B) + xhi of the padded
+// layout (signs, block index and H_{r/b} sign use qp), stored at row
+// i*r + xhi*B of A, with the rows past r read as zeros.
+template <int NW, int BR, bool PAD = false>
 struct FusedCta {
   static constexpr int B = BR * NW;
   static constexpr int LOG2B = ilog2c(B);
@@ -130,6 +154,7 @@ struct FusedCta {
   int cur_block;
   uint32_t dtbit;
   const float *wavebase;  // A + c0 + w*BR*lda (wave-uniform)
+  const float *tilebase;  // A + c0
   float acc[kCT];
 
   __device__ __forceinline__ FusedCta(float *T_, const FusedArgs &a_) : T(T_), a(a_) {}
@@ -138,12 +163,39 @@ struct FusedCta {
     return wavebase + (int64_t)q * B * a.lda;
   }
 
-  __device__ __forceinline__ void step(int q, int q1, float (&cur)[BR], float (&nxt)[BR]) {
+  // PAD: the padded-layout index of chunk qr, and where its rows of this
+  // wave start in A with the bytes they cover (0 past the block's rows).
+  __device__ __forceinline__ int padded_chunk(int qr) const {
+    const int i = qr / a.cr;
+    return (i << cpb_log2) + (qr - i * a.cr);
+  }
+  // (vr rows of the wave hold data; with none, the tile's first row of A,
+  // which always exists, stands in as the address.)
+  __device__ __forceinline__ const float *padded_base(int qr, int &vr) const {
+    const int i = qr / a.cr, xhi = qr - i * a.cr;
+    int64_t v = a.r_rows - (int64_t)xhi * B - w * BR;
+    v = v < 0 ? 0 : (v > BR ? BR : v);
+    vr = (int)v;
+    return vr > 0 ? wavebase + ((int64_t)i * a.r_rows + (int64_t)xhi * B) * a.lda : tilebase;
+  }
+  template <int T0, int T1>
+  __device__ __forceinline__ void load_chunk(float (&v)[BR], int qr) const {
+    if constexpr (PAD) {
+      int vr;
+      const float *base = padded_base(qr, vr);
+      load_rows_masked<BR, T0, T1>(v, base, voff, row_bytes, vr);
+    } else {
+      load_rows<BR, T0, T1>(v, chunk_base(qr), voff, row_bytes);
+    }
+  }
+
+  __device__ __forceinline__ void step(int qr, int q1, float (&cur)[BR], float (&nxt)[BR]) {
     // The next chunk is prefetched in two halves: the second half is issued
     // once this chunk's rows have left the registers for LDS, which keeps
     // the accumulators, one chunk and half a chunk within 256 VGPRs.
-    const bool more = q + 1 < q1;
-    if (more) load_rows<BR, 0, BR / 2>(nxt, chunk_base(q + 1), voff, row_bytes);
+    const bool more = qr + 1 < q1;
+    const int q = PAD ? padded_chunk(qr) : qr;
+    if (more) load_chunk<0, BR / 2>(nxt, qr + 1);
     apply_dsigns<BR>(cur, a.Dbits, (int64_t)q * B + w * BR);
     fwht_regs<BR>(cur);
     {
@@ -151,7 +203,7 @@ struct FusedCta {
 #pragma unroll
       for (int t = 0; t < BR; ++t) Tw[t * kLDT] = cur[t];
     }
-    if (more) load_rows<BR, BR / 2, BR>(nxt, chunk_base(q + 1), voff, row_bytes);
+    if (more) load_chunk<BR / 2, BR>(nxt, qr + 1);
     __syncthreads();
     // H_8 over w: group t holds rows t, t+BR, ..., t+7*BR.
 #pragma unroll
@@ -192,9 +244,9 @@ struct FusedCta {
 // group bz (T: the chunk buffer in LDS, NW*BR*kLDT floats).  Shared by the
 // single-job kernel and the persistent batch kernel, so that a job's result
 // does not depend on which of them ran it.
-template <int NW, int BR>
+template <int NW, int BR, bool PAD = false>
 __device__ __forceinline__ void fused_tile(const FusedArgs &a, float *T, int bx, int by, int bz) {
-  using Cta = FusedCta<NW, BR>;
+  using Cta = FusedCta<NW, BR, PAD>;
   Cta cta(T, a);
   const int tid = threadIdx.x;
   cta.lane = tid & 63;
@@ -205,6 +257,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, float *T, int bx,
   cta.voff = cc * 4;
   cta.row_bytes = (int)(a.lda * 4);
   cta.wavebase = a.A + c0 + (int64_t)(cta.w * BR) * a.lda;
+  cta.tilebase = a.A + c0;
   const int q0 = by * a.chunks_per_split;
   const int q1 = min(q0 + a.chunks_per_split, a.total_chunks);
   cta.j = bz * (NW * 64) + tid;
@@ -223,7 +276,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, float *T, int bx,
   // registers and spilled R_j's chunk bits, whose reload in the gather (a
   // vector-memory access) waited for the whole prefetch of the next chunk.
   float bufA[BR], bufB[BR];
-  if (q0 < q1) load_rows<BR>(bufA, cta.chunk_base(q0), cta.voff, cta.row_bytes);
+  if (q0 < q1) cta.template load_chunk<0, BR>(bufA, q0);
 #pragma nounroll
   for (int q = q0; q < q1; ++q) {
     cta.step(q, q1, bufA, bufB);
@@ -240,7 +293,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, float *T, int bx,
   }
 }
 
-template <int NW, int BR>
+template <int NW, int BR, bool PAD = false>
 __global__ __launch_bounds__(NW * 64) void fused_fp32_kernel(FusedArgs a) {
   __shared__ __attribute__((aligned(16))) float T[NW * BR * kLDT];
   // XCD-aware tile order: workgroups are dealt to the 8 XCDs round-robin, so
@@ -256,7 +309,7 @@ __global__ __launch_bounds__(NW * 64) void fused_fp32_kernel(FusedArgs a) {
       by = idx / (int)gridDim.x;
     }
   }
-  fused_tile<NW, BR>(a, T, bx, by, (int)blockIdx.z);
+  fused_tile<NW, BR, PAD>(a, T, bx, by, (int)blockIdx.z);
 }
 
 // Y[j, c] = scale * sum_s part[s][j][c], splits summed in ascending order.
@@ -274,26 +327,28 @@ __global__ void reduce_splits_kernel(const float *__restrict__ part, int splits,
 }
 
 // Direct evaluation of eq. (2.3) for blocks shorter than the smallest fused
-// chunk (r < 64): one thread per output entry, O(n) work each.
+// chunk (2^log2r < 64): one thread per output entry, O(n) work each.  Block i
+// holds rows i*r .. i*r + r - 1 of A (r < 2^log2r: zero padding, whose rows
+// contribute nothing); its D signs sit at bits i*2^log2r + x.
 __global__ void direct_kernel(const float *__restrict__ A, int64_t lda, int m,
                               const int32_t *__restrict__ R, const uint32_t *__restrict__ Dbits,
                               const uint32_t *__restrict__ Dtbits, int64_t dt_words, int l,
-                              int64_t p, int log2r, float *__restrict__ Y, int64_t ldy,
+                              int64_t p, int log2r, int64_t r, float *__restrict__ Y, int64_t ldy,
                               float scale) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)l * m) return;
   const int j = (int)(idx / m);
   const int c = (int)(idx - (int64_t)j * m);
-  const int64_t r = int64_t(1) << log2r;
+  const int64_t rp = int64_t(1) << log2r;
   const uint32_t rj = (uint32_t)R[j];
   float acc = 0.f;
   for (int64_t i = 0; i < p; ++i) {
     float s = 0.f;
     for (int64_t x = 0; x < r; ++x) {
-      const int64_t g = i * r + x;
-      const uint32_t d = (Dbits[g >> 5] >> (g & 31)) & 1u;
+      const int64_t gd = i * rp + x;
+      const uint32_t d = (Dbits[gd >> 5] >> (gd & 31)) & 1u;
       const uint32_t h = (uint32_t)__popc(rj & (uint32_t)x) & 1u;
-      const float v = A[g * lda + c];
+      const float v = A[(i * r + x) * lda + c];
       s += (d ^ h) ? -v : v;
     }
     const uint32_t dt = (Dtbits[i * dt_words + (j >> 5)] >> (j & 31)) & 1u;
@@ -313,7 +368,7 @@ Launch choose_launch(const bsrht_plan_s *pl, int64_t m, int64_t lda) {
   Launch L;
   (void)lda;
   int per_cu;
-  if (pl->l > 512 && pl->r >= 256) {
+  if (pl->l > 512 && pl->rp >= 256) {
     // 16 waves, one thread per sample for l <= 1024: A is read once per
     // 1024 samples instead of once per 512; chunks of b = 16*16 rows.
     L.nw = 16;
@@ -322,7 +377,7 @@ Launch choose_launch(const bsrht_plan_s *pl, int64_t m, int64_t lda) {
   } else {
     // Largest chunk b = 8*BR <= r with 8 <= BR <= 64.
     int br = 64;
-    while (br >= 8 && (int64_t)br * 8 > pl->r) br >>= 1;
+    while (br >= 8 && (int64_t)br * 8 > pl->rp) br >>= 1;
     if (br < 8) {
       L.direct = true;
       return L;
@@ -332,7 +387,8 @@ Launch choose_launch(const bsrht_plan_s *pl, int64_t m, int64_t lda) {
     per_cu = br * 8 * kLDT * 4 > 80 * 1024 ? 1 : 2;
   }
   L.b = L.br * L.nw;
-  L.total_chunks = (int)(pl->n / L.b);
+  // Chunks that hold rows of A: all of them, or ceil(r / b) per padded block.
+  L.total_chunks = (int)(pl->p * ((pl->r + L.b - 1) / L.b));
   L.ctiles = (int)((m + kCT - 1) / kCT);
   const int spp = L.nw * 64;
   L.groups = (int)((pl->l + spp - 1) / spp);
@@ -346,11 +402,11 @@ Launch choose_launch(const bsrht_plan_s *pl, int64_t m, int64_t lda) {
   return L;
 }
 
-template <int NW, int BR>
+template <int NW, int BR, bool PAD = false>
 int launch_fused(const Launch &L, FusedArgs &a, hipStream_t s) {
   dim3 grid((unsigned)L.ctiles, (unsigned)L.splits, (unsigned)L.groups);
   const int tslot = timing_begin(BSRHT_TIMING_APPLY_FP32, s);
-  fused_fp32_kernel<NW, BR><<<grid, NW * 64, 0, s>>>(a);
+  fused_fp32_kernel<NW, BR, PAD><<<grid, NW * 64, 0, s>>>(a);
   timing_end(tslot, s);
   BSRHT_LAUNCH_CHECK();
   return BSRHT_OK;
@@ -480,6 +536,8 @@ int fused_args(const bsrht_plan_s *pl, const float *A, int64_t m, int64_t lda, f
   a.log2r = pl->log2r;
   a.chunks_per_split = L.cps;
   a.total_chunks = L.total_chunks;
+  a.r_rows = pl->r;
+  a.cr = (int)((pl->r + L.b - 1) / L.b);
   if (L.splits > 1) {
     a.out = static_cast<float *>(ws);
     a.ldo = m;
@@ -563,9 +621,10 @@ int apply_fp32(const bsrht_plan_s *pl, const float *A, int64_t m, int64_t lda, f
   if (L.direct) {
     const int64_t total = pl->l * m;
     const int tb = 256;
+    if ((total + tb - 1) / tb > INT_MAX) return BSRHT_EUNSUPPORTED;
     direct_kernel<<<(unsigned)((total + tb - 1) / tb), tb, 0, s>>>(
         A, lda, (int)m, pl->R, pl->Dbits, pl->Dtbits, pl->dt_words, (int)pl->l, pl->p,
-        pl->log2r, Y, ldy, scale);
+        pl->log2r, pl->r, Y, ldy, scale);
     BSRHT_LAUNCH_CHECK();
     return BSRHT_OK;
   }
@@ -575,7 +634,18 @@ int apply_fp32(const bsrht_plan_s *pl, const float *A, int64_t m, int64_t lda, f
     if (st != BSRHT_OK) return st;
   }
   int st;
-  if (L.nw == 16) {
+  if (pl->r != pl->rp) {  // padded blocks: their own instances
+    if (L.nw == 16) {
+      st = launch_fused<16, 16, true>(L, a, s);
+    } else {
+      switch (L.br) {
+        case 64: st = launch_fused<8, 64, true>(L, a, s); break;
+        case 32: st = launch_fused<8, 32, true>(L, a, s); break;
+        case 16: st = launch_fused<8, 16, true>(L, a, s); break;
+        default: st = launch_fused<8, 8, true>(L, a, s); break;
+      }
+    }
+  } else if (L.nw == 16) {
     st = launch_fused<16, 16>(L, a, s);
   } else {
     switch (L.br) {
@@ -628,7 +698,8 @@ int bsrht_apply_batch(const bsrht_apply_item_t *items, int count, void *table,
     const int64_t m = in.m;
     if (!pl || m < 1 || !in.A || !in.Y || in.lda < m || in.ldy < m || m > INT_MAX)
       return BSRHT_EINVAL;
-    if (pl->precision != BSRHT_FP32 || pl->l * m > ((int64_t)1 << 40)) return BSRHT_EUNSUPPORTED;
+    if (pl->precision != BSRHT_FP32 || pl->r != pl->rp || pl->l * m > ((int64_t)1 << 40))
+      return BSRHT_EUNSUPPORTED;
     const Launch L = choose_launch(pl, m, in.lda);
     if (L.direct) return BSRHT_EUNSUPPORTED;
     BatchList &bl = L.nw == 16 ? h.nw16 : h.nw8;

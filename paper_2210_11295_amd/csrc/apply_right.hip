@@ -302,28 +302,30 @@ __global__ __launch_bounds__(NW * 64) void right_fp32_kernel(RightArgs a) {
 }
 
 // Direct evaluation of eq. (2.3) from the right for blocks shorter than the
-// smallest chunk (r < 256): one thread per output entry, O(n) work each.
+// smallest chunk (2^log2r < 256) and for blocks padded with zeros (r <
+// 2^log2r: columns i*r .. i*r + r - 1 of A, D signs at bits i*2^log2r + x):
+// one thread per output entry, O(n) work each.
 __global__ void right_direct_kernel(const float *__restrict__ A, int64_t lda, int m,
                                     const int32_t *__restrict__ R,
                                     const uint32_t *__restrict__ Dbits,
                                     const uint32_t *__restrict__ Dtbits, int64_t dt_words,
-                                    int l, int64_t p, int log2r, float *__restrict__ Y,
-                                    int64_t ldy, float scale) {
+                                    int l, int64_t p, int log2r, int64_t r,
+                                    float *__restrict__ Y, int64_t ldy, float scale) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)l * m) return;
   const int g = (int)(idx / l);
   const int j = (int)(idx - (int64_t)g * l);
-  const int64_t r = int64_t(1) << log2r;
+  const int64_t rp = int64_t(1) << log2r;
   const uint32_t rj = (uint32_t)R[j];
   const float *row = A + (int64_t)g * lda;
   float acc = 0.f;
   for (int64_t i = 0; i < p; ++i) {
     float s = 0.f;
     for (int64_t x = 0; x < r; ++x) {
-      const int64_t c = i * r + x;
-      const uint32_t d = (Dbits[c >> 5] >> (c & 31)) & 1u;
+      const int64_t cd = i * rp + x;
+      const uint32_t d = (Dbits[cd >> 5] >> (cd & 31)) & 1u;
       const uint32_t h = (uint32_t)__popc(rj & (uint32_t)x) & 1u;
-      const float v = row[c];
+      const float v = row[i * r + x];
       s += (d ^ h) ? -v : v;
     }
     const uint32_t dt = (Dtbits[i * dt_words + (j >> 5)] >> (j & 31)) & 1u;
@@ -341,7 +343,7 @@ struct RightLaunch {
 
 RightLaunch choose_right(const bsrht_plan_s *pl, int64_t m) {
   RightLaunch L;
-  if (pl->r < 256) {
+  if (pl->rp < 256 || pl->r != pl->rp) {
     L.direct = true;
     return L;
   }
@@ -390,7 +392,7 @@ int apply_right_fp32(const bsrht_plan_s *pl, const float *A, int64_t m, int64_t 
     if ((total + tb - 1) / tb > INT_MAX) return BSRHT_EUNSUPPORTED;
     right_direct_kernel<<<(unsigned)((total + tb - 1) / tb), tb, 0, s>>>(
         A, lda, (int)m, pl->R, pl->Dbits, pl->Dtbits, pl->dt_words, (int)pl->l, pl->p,
-        pl->log2r, Y, ldy, scale);
+        pl->log2r, pl->r, Y, ldy, scale);
     BSRHT_LAUNCH_CHECK();
     return BSRHT_OK;
   }

@@ -8,12 +8,13 @@
 #include "../../include/bsrht.h"
 
 struct bsrht_plan_s {
-  int64_t n, p, l, r;
+  int64_t n, p, l, r;  // r = n/p rows per block
+  int64_t rp;          // 2^log2r >= r: a block is padded with zeros to rp rows
   int log2r;
   uint64_t seed;
   int sampling, precision;
   int32_t *R;         // device, l entries in [0, r), draw order
-  uint32_t *Dbits;    // device, ceil(n/32) words; bit g = sign of D at global row g
+  uint32_t *Dbits;    // device, ceil(p*rp/32) words; bit i*rp + x = sign of D^(i)_x
   uint32_t *Dtbits;   // device, p * dt_words words; block i at i*dt_words
   int64_t d_words, dt_words;
   hipStream_t stream; // stream the tables were written on

@@ -24,8 +24,10 @@ int device_cu_count() {
   return cus;
 }
 
-// D sign bits: one thread per 32-bit word of the global bitmask (bit g is
-// global row g = i*r + x of A).  Block i, position x uses bit x%256 of
+// D sign bits: one thread per 32-bit word of the bitmask over the padded
+// block layout (bit g = i*rp + x for block i, position x < rp; rp = 2^log2r;
+// positions x >= r of a padded block multiply zeros).  Block i, position x
+// uses bit x%256 of
 // philox((x/256, i, tag D, 0)).  For r >= 32 a word lies inside one block and
 // one 256-bit output, so one generator call serves the whole word.
 __global__ void build_d_kernel(uint32_t *Dbits, int64_t words, int64_t n,
@@ -78,10 +80,17 @@ __global__ void build_r_kernel(int32_t *R, int64_t l, int64_t r, uint64_t seed) 
   R[j] = (int32_t)(o.w[0] & (uint64_t)(r - 1));
 }
 
+// Rows per block padded to a power of two (section 2's partial SRHT).
+static int64_t padded_block(int64_t r) {
+  int64_t rp = 1;
+  while (rp < r) rp <<= 1;
+  return rp;
+}
+
 static bool valid_sizes(int64_t n, int64_t p, int64_t l) {
   if (n < 1 || p < 1 || l < 1 || n >= (int64_t(1) << 31)) return false;
   if (n % p) return false;
-  if (!is_pow2(n / p)) return false;
+  if (p * padded_block(n / p) >= (int64_t(1) << 31)) return false;
   if (l > n) return false;
   return true;
 }
@@ -109,7 +118,7 @@ size_t bsrht_plan_bytes(int64_t n, int64_t p, int64_t l) {
   if (!valid_sizes(n, p, l)) return 0;
   Sizer sz;
   sz.take<int32_t>((size_t)l);
-  sz.take<uint32_t>((size_t)((n + 31) / 32));
+  sz.take<uint32_t>((size_t)((p * padded_block(n / p) + 31) / 32));
   sz.take<uint32_t>((size_t)(p * ((l + 31) / 32)));
   return align256(sz.used);
 }
@@ -123,8 +132,8 @@ int bsrht_plan(int64_t n, int64_t p, int64_t l, uint64_t seed, int sampling,
   if (sampling != BSRHT_WITH_REPLACEMENT && sampling != BSRHT_WITHOUT_REPLACEMENT)
     return BSRHT_EINVAL;
   if (precision != BSRHT_FP32 && precision != BSRHT_SPLIT_BF16) return BSRHT_EINVAL;
-  const int64_t r = n / p;
-  if (sampling == BSRHT_WITHOUT_REPLACEMENT && l > r) return BSRHT_EINVAL;
+  const int64_t r = n / p, rp = padded_block(r);
+  if (sampling == BSRHT_WITHOUT_REPLACEMENT && l > rp) return BSRHT_EINVAL;
   if (!dev_mem) return BSRHT_EINVAL;
   if (dev_bytes < bsrht_plan_bytes(n, p, l)) return BSRHT_ENOMEM;
 
@@ -134,11 +143,12 @@ int bsrht_plan(int64_t n, int64_t p, int64_t l, uint64_t seed, int sampling,
   pl->p = p;
   pl->l = l;
   pl->r = r;
-  pl->log2r = ilog2_i64(r);
+  pl->rp = rp;
+  pl->log2r = ilog2_i64(rp);
   pl->seed = seed;
   pl->sampling = sampling;
   pl->precision = precision;
-  pl->d_words = (n + 31) / 32;
+  pl->d_words = (p * rp + 31) / 32;
   pl->dt_words = (l + 31) / 32;
   pl->stream = (hipStream_t)stream;
   if (hipGetDevice(&pl->device) != hipSuccess) {
@@ -153,11 +163,11 @@ int bsrht_plan(int64_t n, int64_t p, int64_t l, uint64_t seed, int sampling,
 
   const int tb = 256;
   build_d_kernel<<<(unsigned)((pl->d_words + tb - 1) / tb), tb, 0, s>>>(
-      pl->Dbits, pl->d_words, n, pl->log2r, seed);
+      pl->Dbits, pl->d_words, p * rp, pl->log2r, seed);
   build_dt_kernel<<<(unsigned)((p * pl->dt_words + tb - 1) / tb), tb, 0, s>>>(
       pl->Dtbits, p, pl->dt_words, l, seed);
   if (sampling == BSRHT_WITH_REPLACEMENT) {
-    build_r_kernel<<<(unsigned)((l + tb - 1) / tb), tb, 0, s>>>(pl->R, l, r, seed);
+    build_r_kernel<<<(unsigned)((l + tb - 1) / tb), tb, 0, s>>>(pl->R, l, rp, seed);
   } else {
     // Partial Fisher-Yates is sequential in j; it runs on the host with the
     // same generator and is uploaded once.  A sparse pool keeps it O(l).
@@ -170,7 +180,7 @@ int bsrht_plan(int64_t n, int64_t p, int64_t l, uint64_t seed, int sampling,
     for (int64_t j = 0; j < l; ++j) {
       Philox4 o = philox4x64_10((uint64_t)j, 0, kTagR, 0, seed, 0);
       uint64_t hi, lo;
-      mul_hilo64(o.w[0], (uint64_t)(r - j), hi, lo);
+      mul_hilo64(o.w[0], (uint64_t)(rp - j), hi, lo);
       const int64_t t = j + (int64_t)hi;
       const int64_t pj = get(j), pt = get(t);
       pool[j] = pt;

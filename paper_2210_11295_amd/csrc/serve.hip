@@ -114,10 +114,11 @@ bsrht_plan_s shape_of(const bsrht_job_t &j) {
   int lg = 0;
   while ((int64_t(1) << lg) < s.r) ++lg;
   s.log2r = lg;
+  s.rp = int64_t(1) << lg;
   s.seed = j.seed;
   s.sampling = j.sampling;
   s.precision = j.precision;
-  s.d_words = (j.n + 31) / 32;
+  s.d_words = (j.p * s.rp + 31) / 32;
   s.dt_words = (j.l + 31) / 32;
   return s;
 }
@@ -133,7 +134,7 @@ bool valid_job(const bsrht_job_t &j, bool fake) {
   if (j.m < 1 || j.m > INT32_MAX || bsrht_plan_bytes(j.n, j.p, j.l) == 0) return false;
   if (j.sampling != BSRHT_WITH_REPLACEMENT && j.sampling != BSRHT_WITHOUT_REPLACEMENT)
     return false;
-  if (j.sampling == BSRHT_WITHOUT_REPLACEMENT && j.l > j.n / j.p) return false;
+  if (j.sampling == BSRHT_WITHOUT_REPLACEMENT && j.l > shape_of(j).rp) return false;
   if (j.precision != BSRHT_FP32 && j.precision != BSRHT_SPLIT_BF16) return false;
   if (j.lda < j.m) return false;
   if (j.kind == BSRHT_JOB_SKETCH && j.ldy < j.m) return false;
@@ -148,8 +149,9 @@ bool valid_job(const bsrht_job_t &j, bool fake) {
 // graph-replayed launch (bsrht_apply_batch): FP32, blocks of >= 64 rows, A
 // of at most kBatchJobBytes.
 bool batchable(const bsrht_job_t &j) {
-  return j.kind == BSRHT_JOB_SKETCH && j.precision == BSRHT_FP32 && j.n / j.p >= 64 &&
-         j.n * j.m * 4 <= kBatchJobBytes;
+  const int64_t r = j.n / j.p;
+  return j.kind == BSRHT_JOB_SKETCH && j.precision == BSRHT_FP32 && r >= 64 &&
+         (r & (r - 1)) == 0 && j.n * j.m * 4 <= kBatchJobBytes;
 }
 
 // The work of one job on its slot's stream, ending when the stream has

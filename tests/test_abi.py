@@ -39,7 +39,8 @@ def test_library_exports_every_declared_symbol():
 
 @pytest.mark.parametrize("n,p,l,ok", [
     (4096, 4, 128, True), (1 << 20, 16, 512, True), (40, 40, 5, True), (64, 1, 64, True),
-    (12, 1, 4, False),      # r not a power of two
+    (12, 1, 4, True),       # r = 12: partial SRHT, blocks padded to 16
+    (300, 3, 20, True),     # r = 100 -> 128
     (16, 3, 4, False),      # p does not divide n
     (16, 2, 17, False),     # l > n
     (16, 2, 0, False),      # l = 0
@@ -52,7 +53,8 @@ def test_plan_bytes_validation(n, p, l, ok):
         assert nb == 0
         return
     a256 = lambda x: (x + 255) // 256 * 256
-    expect = a256(a256(a256(4 * l) + 4 * ((n + 31) // 32)) + 4 * p * ((l + 31) // 32))
+    rp = 1 << (n // p - 1).bit_length()
+    expect = a256(a256(a256(4 * l) + 4 * ((p * rp + 31) // 32)) + 4 * p * ((l + 31) // 32))
     assert nb == expect
 
 
