@@ -103,3 +103,50 @@ def nystrom(plan, A, k, u=U_FP64):
     kk = min(int(k), St.shape[0])
     Uh = Z @ (VtT.T[:, :kk] / St[:kk])         # step 6 (read with Z, see above)
     return Uh, St[:kk] ** 2, fb
+
+
+def nystrom_shifted(plan, A, k, u=U_FP64):
+    """Algorithm 2 on the shifted matrix A + nu I, the alternative to Remark
+    3.1 that section 3.2 cites (Li et al., Algorithm 971, ACM TOMS 2017):
+    the shift makes Omega (A + nu I) Omega^T positive definite, and nu is
+    subtracted from the computed eigenvalues.  Reading: nu = sqrt(n) u ||Y||_F
+    with u the unit roundoff of the sketch precision (2^-53 here, 2^-24 for
+    an FP32 sketch), and since (A + nu I) Omega^T = Y + nu Omega^T only the
+    sketch is shifted.  Returns (U_hat n x k', lam k', nu, fallback_taken) with
+    lam = max(sigma^2 - nu, 0)."""
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[0]
+    Om = _omega_rows(plan)                     # Omega (l x n), closed form
+    Y = sketch(plan, A.T).T                    # step 1: Y = A Omega^T
+    nu = np.sqrt(n) * u * np.linalg.norm(Y)
+    Ynu = Y + nu * Om.T                        # (A + nu I) Omega^T
+    B = sketch(plan, Ynu)
+    B = 0.5 * (B + B.T)
+    tau = plan.l * u
+    C = _cholesky_upper_or_none(B, tau)
+    fb = C is None
+    if not fb:
+        Z = sla.solve_triangular(C, Ynu.T, trans="T", lower=False).T
+    else:
+        lam_b, Vb = np.linalg.eigh(B)
+        keep = lam_b > tau * lam_b.max()
+        Z = Ynu @ (Vb[:, keep] / np.sqrt(lam_b[keep]))
+    R = np.linalg.qr(Z, mode="r")
+    _, St, VtT = np.linalg.svd(R)
+    kk = min(int(k), St.shape[0])
+    Uh = Z @ (VtT.T[:, :kk] / St[:kk])
+    return Uh, np.maximum(St[:kk] ** 2 - nu, 0.0), nu, fb
+
+
+def _omega_rows(plan):
+    """Omega (l x n) from eq. (2.3) entry by entry: the sketch of the
+    identity, column block by column block (no size limit, O(l n log r))."""
+    n = plan.n
+    cols = []
+    for c0 in range(0, n, 4096):
+        c1 = min(n, c0 + 4096)
+        E = np.zeros((n, c1 - c0))
+        E[np.arange(c0, c1), np.arange(c1 - c0)] = 1.0
+        cols.append(sketch(plan, E))
+    return np.concatenate(cols, axis=1)
+

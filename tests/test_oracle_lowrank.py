@@ -154,3 +154,33 @@ def test_nystrom_near_optimal_and_bound():
     tail_d = metrics.optimal_trace_error(A, l // 4)
     assert opt <= err * (1 + 1e-9) and err <= opt + 3 * tail_d
     assert err < 1.5 * opt
+
+
+def test_shifted_nystrom_is_nystrom_of_the_shifted_matrix():
+    """Shifting only the sketch, Y + nu Omega^T, is Algorithm 2 on A + nu I
+    (formed explicitly here and run through the unshifted oracle) with nu
+    subtracted from the eigenvalues."""
+    n, p, l, k = 1024, 4, 64, 20
+    A = _spd(n, 200, 3)
+    plan = rng.Plan(n, p, l, 5)
+    U, lam, nu, fb = lowrank.nystrom_shifted(plan, A, k, u=2.0 ** -24)
+    assert nu > 0 and not fb
+    U2, lam2, fb2 = lowrank.nystrom(plan, A + nu * np.eye(n), k, u=2.0 ** -24)
+    assert np.allclose(lam, np.maximum(lam2 - nu, 0.0), rtol=1e-9, atol=1e-14)
+    assert np.max(np.abs(U.T @ U - np.eye(k))) < 1e-10
+
+
+def test_shifted_nystrom_needs_no_fallback_on_a_rank_deficient_matrix():
+    """Rank 30 < l: Omega A Omega^T is singular (the unshifted method takes
+    Remark 3.1's fallback); the shifted one factors it directly and still
+    recovers A up to the shift's size.  (Sampling without replacement: with
+    replacement two rows of Omega can be collinear, and then no shift of A
+    makes Omega (A + nu I) Omega^T definite.)"""
+    n, p, l, kk = 1024, 4, 48, 30
+    A = _spd(n, kk, 7, decay=lambda j: 1.0 + 0.0 * j)
+    plan = rng.Plan(n, p, l, 9, rng.WITHOUT_REPLACEMENT)
+    _, _, fb0 = lowrank.nystrom(plan, A, kk)
+    assert fb0
+    U, lam, nu, fb = lowrank.nystrom_shifted(plan, A, kk)
+    assert not fb
+    assert np.linalg.norm(A - (U * lam) @ U.T) / np.linalg.norm(A) < 1e3 * nu
