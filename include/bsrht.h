@@ -273,6 +273,21 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k,
             float *U, double *lambda, int32_t *info, void *ws,
             size_t ws_bytes, void *stream);
 
+/*
+ * Shifted Nystrom: Algorithm 2 on A + nu I, the alternative to Remark 3.1's
+ * fallback that section 3.2 cites (Li et al., Algorithm 971, ACM TOMS 2017).
+ * The sketch is shifted, Y + nu Omega^T = (A + nu I) Omega^T, with
+ * nu = sqrt(n) u_s ||Y||_F (u_s the unit roundoff of the sketch: 2^-24 for
+ * FP32, 2^-17 for split-BF16; computed on the device), which makes
+ * Omega (A + nu I) Omega^T positive definite whenever Omega has full row
+ * rank; lambda = max(sigma^2 - nu, 0).  Arguments, workspace
+ * (nystrom_workspace) and errors as for nystrom; the Remark 3.1 fallback
+ * remains for a rank deficient Omega (info bit BSRHT_INFO_CHOL_FALLBACK).
+ */
+int nystrom_shifted(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k,
+                    float *U, double *lambda, int32_t *info, void *ws,
+                    size_t ws_bytes, void *stream);
+
 /* Workspace bytes rsvd_single_view needs (0 for inconsistent plans or k < 1). */
 size_t rsvd_single_view_workspace(bsrht_plan_t omega, bsrht_plan_t gamma,
                                   bsrht_plan_t phi, bsrht_plan_t psi, int64_t k);

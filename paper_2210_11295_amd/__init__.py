@@ -24,6 +24,7 @@ __all__ = [
     "batch_table_bytes", "ApplyItem", "BATCH_MAX", "bsrht_apply_right",
     "bsrht_apply_right_workspace", "rsvd_single_view", "rsvd_single_view_workspace",
     "bsrht_dense_sketch", "bsrht_dense_workspace", "DENSE_GAUSSIAN", "DENSE_RADEMACHER",
+    "nystrom_shifted",
 ]
 
 WITH_REPLACEMENT = 0
@@ -89,6 +90,8 @@ _SIGS = {
     "bsrht_stream_read": (ctypes.c_int, [_c_vp, _c_i64, _c_vp, _c_vp]),
     "nystrom": (ctypes.c_int, [_c_vp, _c_vp, _c_i64, _c_i64, _c_vp, _c_vp, _c_vp, _c_vp,
                                _c_sz, _c_vp]),
+    "nystrom_shifted": (ctypes.c_int, [_c_vp, _c_vp, _c_i64, _c_i64, _c_vp, _c_vp, _c_vp,
+                                       _c_vp, _c_sz, _c_vp]),
 }
 
 
@@ -432,8 +435,9 @@ def nystrom_workspace(plan, k):
     return int(lib().nystrom_workspace(plan.handle, k))
 
 
-def nystrom(plan, A, k, ws=None, stream=None):
-    """Nystrom (Algorithm 2) of symmetric PSD A: returns (U n x k, lambda k float64, info)."""
+def nystrom(plan, A, k, ws=None, stream=None, shifted=False):
+    """Nystrom (Algorithm 2) of symmetric PSD A: returns (U n x k, lambda k float64, info).
+    shifted=True runs it on A + nu I and subtracts nu (nystrom_shifted)."""
     _check_matrix("A", A)
     n = A.shape[0]
     if A.shape[1] != n or n != plan.n:
@@ -444,10 +448,16 @@ def nystrom(plan, A, k, ws=None, stream=None):
     info = torch.zeros(1, dtype=torch.int32, device=dev)
     if ws is None:
         ws = _workspace(nystrom_workspace(plan, k), dev)
-    _check("nystrom", lib().nystrom(plan.handle, _ptr(A), max(A.stride(0), n), k, _ptr(U),
-                                    _ptr(lam), _ptr(info), _ptr(ws), ws.numel(),
-                                    _stream_ptr(stream)))
+    name = "nystrom_shifted" if shifted else "nystrom"
+    _check(name, getattr(lib(), name)(plan.handle, _ptr(A), max(A.stride(0), n), k, _ptr(U),
+                                      _ptr(lam), _ptr(info), _ptr(ws), ws.numel(),
+                                      _stream_ptr(stream)))
     return U, lam, info
+
+
+def nystrom_shifted(plan, A, k, ws=None, stream=None):
+    """Shifted Nystrom (on A + nu I, nu subtracted): returns (U, lambda, info)."""
+    return nystrom(plan, A, k, ws, stream, shifted=True)
 
 
 def bsrht_job_bytes(job):

@@ -88,6 +88,64 @@ __global__ void zero_i32_kernel(int32_t *p, int n) {
   if (i < n) p[i] = 0;
 }
 
+// Shifted Nystrom.  Sum of squares of the n x l FP32 matrix Y (leading
+// dimension ldy) in FP64: kSsqBlocks fixed grid-stride partial sums, then
+// one block sums them in order and stores nu = c * sqrt(sum) (c =
+// sqrt(n) u_s) at nu[0], so the shift never leaves the device.
+constexpr int kSsqBlocks = 1024;
+__global__ void ssq_partial_kernel(const float *__restrict__ Y, int64_t n, int64_t l, int64_t ldy,
+                                   double *__restrict__ part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  const int64_t total = n * l;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+       e += (int64_t)kSsqBlocks * 256) {
+    const int64_t g = e / l, j = e - g * l;
+    const double v = (double)Y[g * ldy + j];
+    acc += v * v;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void shift_of_kernel(const double *__restrict__ part, double c, double *__restrict__ nu) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < kSsqBlocks; ++b) s += part[b];
+  nu[0] = c * sqrt(s);
+}
+
+// Y[g][j] += nu * Omega[j][g] (eq. (2.3) entry by entry from the plan's
+// tables; block i = g / r, position x = g - i r, D bit at i*rp + x), i.e.
+// Y + nu Omega^T = (A + nu I) Omega^T.
+__global__ void add_shift_kernel(float *__restrict__ Y, int64_t n, int64_t l, int64_t ldy,
+                                 const int32_t *__restrict__ R,
+                                 const uint32_t *__restrict__ Dbits,
+                                 const uint32_t *__restrict__ Dtbits, int64_t dt_words, int64_t r,
+                                 int64_t rp, const double *__restrict__ nu, float inv_sqrt_l) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * l) return;
+  const int64_t g = e / l, j = e - g * l;
+  const int64_t i = g / r, x = g - i * r;
+  const int64_t gd = i * rp + x;
+  const uint32_t d = (Dbits[gd >> 5] >> (gd & 31)) & 1u;
+  const uint32_t h = (uint32_t)__popc((uint32_t)R[j] & (uint32_t)x) & 1u;
+  const uint32_t dt = (Dtbits[i * dt_words + (j >> 5)] >> (j & 31)) & 1u;
+  const float om = (d ^ h ^ dt) ? -inv_sqrt_l : inv_sqrt_l;
+  Y[g * ldy + j] += (float)nu[0] * om;
+}
+
+// lambda_j = max(lambda_j - nu, 0): the eigenvalues of A from those of A + nu I.
+__global__ void unshift_kernel(double *__restrict__ lam, int64_t k, const double *__restrict__ nu) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < k) lam[j] = fmax(lam[j] - nu[0], 0.0);
+}
+
 // Size of the small SVD problems: a multiple of 32 (the block Jacobi pairs
 // column blocks of up to 16); the padding is zero rows and columns.
 inline int64_t svd_pad(int64_t x) { return (x + 31) & ~int64_t(31); }
@@ -170,6 +228,7 @@ struct NysWs {
   double *Bs, *Cinv, *Mf, *lam, *Z, *gram_part, *Gz, *Mk;
   int32_t *flag;
   void *chol_state;
+  double *ssq;  // shifted variant: kSsqBlocks partial sums, then nu
   SvdBufs<A> fb, sv;
   void layout(A &a, const bsrht_plan_s *pl, int64_t k) {
     const int64_t l = pl->l, n = pl->n;
@@ -189,6 +248,7 @@ struct NysWs {
     Mk = a.template take<double>((size_t)(l * std::max<int64_t>(k, 1)));
     flag = a.template take<int32_t>(4);
     chol_state = a.template take<char>(cholesky_state_bytes());
+    ssq = a.template take<double>((size_t)kSsqBlocks + 1);
     fb.take(a, svd_pad(l), l);
     sv.take(a, svd_pad(l), k);
   }
@@ -418,8 +478,15 @@ size_t nystrom_workspace(bsrht_plan_t plan, int64_t k) {
   return align256(so.sz.used);
 }
 
-int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U, double *lambda,
-            int32_t *info, void *ws, size_t ws_bytes, void *stream) {
+}  // extern "C"
+
+namespace bsrht {
+
+// Algorithm 2; with `shifted`, on A + nu I (the sketch Y + nu Omega^T) with nu
+// subtracted from the eigenvalues at the end.
+int nystrom_impl(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
+                 double *lambda, int32_t *info, void *ws, size_t ws_bytes, void *stream,
+                 bool shifted) {
   if (!plan || !A || !U || !lambda || !info || k < 1 || lda < plan->n) return BSRHT_EINVAL;
   if (ws_bytes < nystrom_workspace(plan, k) || !ws) return BSRHT_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
@@ -440,6 +507,17 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
   // 1. Y = A Omega^T = (Omega A)^T (A symmetric)
   BSRHT_TRY(sketch(A, n, lda, w.W));
   BSRHT_TRY(transpose_f32(w.W, l, n, n, w.Y, l, s));
+  if (shifted) {
+    if ((n * l + 255) / 256 > INT_MAX) return BSRHT_EUNSUPPORTED;
+    // nu = sqrt(n) u_s ||Y||_F (u_s: unit roundoff of the sketch), Y += nu Omega^T
+    const double us = plan->precision == BSRHT_SPLIT_BF16 ? 0x1p-17 : kU32;
+    ssq_partial_kernel<<<kSsqBlocks, 256, 0, s>>>(w.Y, n, l, l, w.ssq);
+    shift_of_kernel<<<1, 64, 0, s>>>(w.ssq, sqrt((double)n) * us, w.ssq + kSsqBlocks);
+    add_shift_kernel<<<(unsigned)((n * l + 255) / 256), 256, 0, s>>>(
+        w.Y, n, l, l, plan->R, plan->Dbits, plan->Dtbits, plan->dt_words, plan->r, plan->rp,
+        w.ssq + kSsqBlocks, (float)(1.0 / sqrt((double)l)));
+    BSRHT_LAUNCH_CHECK();
+  }
   // 2. Cholesky factor of Omega Y (symmetrised)
   BSRHT_TRY(sketch(w.Y, l, l, w.B));
   sym_f64_kernel<<<(unsigned)((l * l + 255) / 256), 256, 0, s>>>(w.B, l, l, w.Bs, l);
@@ -531,7 +609,26 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
   d.sai = ldz; d.sak = 1;
   d.sbk = k; d.sbj = 1;
   d.ldc = k;
-  return gemm_f64f64_f32(d, w.Z, w.Mk, U, s);
+  BSRHT_TRY(gemm_f64f64_f32(d, w.Z, w.Mk, U, s));
+  if (shifted) {
+    unshift_kernel<<<(unsigned)((k + 255) / 256), 256, 0, s>>>(lambda, k, w.ssq + kSsqBlocks);
+    BSRHT_LAUNCH_CHECK();
+  }
+  return BSRHT_OK;
+}
+
+}  // namespace bsrht
+
+extern "C" {
+
+int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U, double *lambda,
+            int32_t *info, void *ws, size_t ws_bytes, void *stream) {
+  return nystrom_impl(plan, A, lda, k, U, lambda, info, ws, ws_bytes, stream, false);
+}
+
+int nystrom_shifted(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
+                    double *lambda, int32_t *info, void *ws, size_t ws_bytes, void *stream) {
+  return nystrom_impl(plan, A, lda, k, U, lambda, info, ws, ws_bytes, stream, true);
 }
 
 }  // extern "C"

@@ -197,3 +197,52 @@ def test_nystrom_fallback_exact_recovery():
     say("  fallback err", err, "info", info)
     assert info & bs.INFO_CHOL_FALLBACK
     assert err < 1e-4
+
+
+@pytest.mark.parametrize("n,p,l,k,spec", [
+    (4096, 4, 256, 64, "inv_sq"),
+    (2048, 8, 128, 40, "inv_sq"),
+    (4096, 16, 200, 50, "pow1.5"),
+])
+def test_nystrom_shifted_matches_oracle(n, p, l, k, spec):
+    """Shifted Nystrom (A + nu I, nu = sqrt(n) 2^-24 ||Y||_F for the FP32
+    sketch) against the oracle's shifted Nystrom with the same rule."""
+    dev = device()
+    say("nystrom shifted", n, p, l, k, spec)
+    A = workloads.spd(n, 512, spec, 11, device=dev)
+    plan = bs.Plan(n, p, l, 12, rng.WITHOUT_REPLACEMENT, device=dev)
+    U, lam, info = bs.nystrom_shifted(plan, A, k)
+    torch.cuda.synchronize()
+    Ah = to64(A)
+    err = metrics.trace_error(Ah, to64(U), to64(lam))
+    Uo, lo, nu, fb = lowrank.nystrom_shifted(rng.Plan(n, p, l, 12, rng.WITHOUT_REPLACEMENT), Ah, k,
+                                             u=2.0 ** -24)
+    err_o = metrics.trace_error(Ah, Uo, lo)
+    say("  err gpu", err, "oracle", err_o, "nu", nu, "info", int(info.item()))
+    assert err <= 1.01 * err_o
+    assert not fb and int(info.item()) == 0
+    assert np.allclose(to64(lam), lo, rtol=1e-3, atol=1e-3 * lo[0])
+    Uh = to64(U)
+    assert np.max(np.abs(Uh.T @ Uh - np.eye(k))) < 1e-3
+
+
+def test_nystrom_shifted_needs_no_fallback():
+    """Rank-20 SPD input with l = 48 (sampled without replacement): the
+    unshifted method needs Remark 3.1's fallback, the shifted one factors
+    directly.  Its error is the shift's (nu ~ 2.5e-6 here, at FP32 sketch
+    precision, against eigenvalues down to 1/400): both sides give ~2e-3, and
+    the GPU must stay within 1% of the oracle's shifted result."""
+    dev = device()
+    n, p, l, k = 2048, 4, 48, 20
+    A = workloads.spd(n, 20, "inv_sq", 15, device=dev)
+    plan = bs.Plan(n, p, l, 16, rng.WITHOUT_REPLACEMENT, device=dev)
+    U, lam, info = bs.nystrom_shifted(plan, A, k)
+    torch.cuda.synchronize()
+    Ah = to64(A)
+    err = metrics.trace_error(Ah, to64(U), to64(lam))
+    Uo, lo, nu, fb = lowrank.nystrom_shifted(rng.Plan(n, p, l, 16, rng.WITHOUT_REPLACEMENT), Ah,
+                                             k, u=2.0 ** -24)
+    err_o = metrics.trace_error(Ah, Uo, lo)
+    say("  shifted rank-20 err", err, "oracle", err_o, "info", int(info.item()))
+    assert int(info.item()) & bs.INFO_CHOL_FALLBACK == 0 and not fb
+    assert err <= 1.01 * err_o
