@@ -482,18 +482,33 @@ def bench_nystrom(bs, reps):
         bs.timing_enable(bs.TIMING_OFF)
         apply[f"apply_{name}_GBs"] = round(n * n * 4 / (ams / al * 1e-3) / 1e9, 1)
         del W, aws
-    # trace error via the structure: A - U diag(lam) U^T lies in span[X, U]
-    B, _ = torch.linalg.qr(torch.cat([X, U.double()], dim=1))
-    XtB = X.T @ B
-    UtB = U.double().T @ B
-    E = (XtB.T * s[None, :]) @ XtB - (UtB.T * lam[None, :]) @ UtB
-    ev = torch.linalg.eigvalsh(0.5 * (E + E.T))
-    err = float(ev.abs().sum() / s.sum())
+    def trace_err(U, lam):
+        # A - U diag(lam) U^T lies in span[X, U]: eigenvalues of its compression
+        B, _ = torch.linalg.qr(torch.cat([X, U.double()], dim=1))
+        XtB = X.T @ B
+        UtB = U.double().T @ B
+        E = (XtB.T * s[None, :]) @ XtB - (UtB.T * lam[None, :]) @ UtB
+        ev = torch.linalg.eigvalsh(0.5 * (E + E.T))
+        return float(ev.abs().sum() / s.sum())
+
+    err = trace_err(U, lam)
     opt = float(s[k:].sum() / s.sum())
+    # the shifted variant (A + nu I, nu subtracted) on the same plan and A
+    Us, lams, infos = bs.nystrom_shifted(plan, A, k, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        Us, lams, infos = bs.nystrom_shifted(plan, A, k, ws)
+    torch.cuda.synchronize()
+    dts = (time.perf_counter() - t0) / reps
+    shifted = {"ms": round(dts * 1e3, 2), "trace_rel_error": trace_err(Us, lams),
+               "info": int(infos.item())}
+    log(f"bench: nystrom {dt * 1e3:.1f} ms err {err:.3e} (info {int(info.item())}); shifted "
+        f"{dts * 1e3:.1f} ms err {shifted['trace_rel_error']:.3e} (info {shifted['info']})")
     return {"ms": round(dt * 1e3, 2), "n": n, "l": l, "k": k, "p": p,
             "sketch_kernel_ms_per_call": round(kms / max(reps, 1), 3), **apply,
             "trace_rel_error": err, "optimal_trace_rel_error": opt,
-            "info": int(info.item())}
+            "info": int(info.item()), "shifted": shifted}
 
 
 def bench_serving_small(bs, njobs=3000, rate=None, streams=SERVE_STREAMS, seed=1):
