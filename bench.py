@@ -259,6 +259,50 @@ def bench_dense(bs, A, cfg, steps, warmup, bsrht_ms):
     return out
 
 
+def bench_partial(bs, steps=10, warmup=2):
+    """The partial block SRHT (section 2: blocks padded with zeros to a power
+    of two) on section 4.2's tall-skinny shape on one GPU: A 10^7 x 200 FP32
+    (8 GB), p = 16 (r = 625000 rows, padded to 2^20), l = 2000.  l > 1024
+    samples take two passes over A (one per 1024 samples)."""
+    import torch
+    import workloads
+    n, m, p, l, seed = 10 ** 7, 200, 16, 2000, 0
+    dev = torch.device("cuda:0")
+    A = workloads.gaussian_cols(n, m, "inv_sq", seed, device=dev)
+    plan = bs.Plan(n, p, l, seed, device=dev)
+    Y = torch.empty(l, m, dtype=torch.float32, device=dev)
+    ws = torch.empty(max(1, bs.bsrht_apply_workspace(plan, m)), dtype=torch.uint8, device=dev)
+    for _ in range(warmup):
+        bs.bsrht_apply(plan, A, Y, ws)
+    torch.cuda.synchronize()
+    bs.timing_enable(bs.TIMING_APPLY_FP32)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        bs.bsrht_apply(plan, A, Y, ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    kms, kl = bs.timing_read()
+    stats = _kernel_stats(bs)
+    bs.timing_enable(bs.TIMING_OFF)
+    kern_ms = kms / max(kl, 1)
+    passes = (l + 1023) // 1024
+    alg = n * m * 4 + l * m * 4
+    achieved = alg / (kern_ms * 1e-3) / 1e9
+    log(f"bench: partial block SRHT n=1e7: {dt * 1e3:.3f} ms per call, kernel {kern_ms:.3f} ms "
+        f"-> {achieved:.1f} GB/s ({passes} passes over A)")
+    del A, ws
+    torch.cuda.empty_cache()
+    return {"workload": f"A {n} x {m} float32, p={p} (r={n // p} padded to {plan.rp}), l={l}, "
+                        f"seed {seed}", "ms_per_call": round(dt * 1e3, 3),
+            "GBs_of_A": round(n * m * 4 / dt / 1e9, 1), "passes_over_A": passes,
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "frac_per_pass": round(achieved * passes / HBM_PEAK_GBS, 4),
+                         "kernel": "fused_fp32_kernel<16, 16, true>",
+                         "kernel_avg_us": round(kern_ms * 1e3, 2), **stats,
+                         "alg_bytes_per_launch": alg}}
+
+
 def _fro_error(A, U, S, V, chunk=1 << 16):
     """||A - U diag(S) V^T||_F / ||A||_F in FP64 on the device (measurement)."""
     import torch
@@ -588,8 +632,9 @@ def main():
                     help="jobs of the serving workload (0 skips it)")
     ap.add_argument("--serve-streams", type=int, default=SERVE_STREAMS)
     ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--only", choices=["all", "sketch", "bf16", "right", "dense", "rsvd",
-                                       "single_view", "nystrom", "serve", "serve_small"],
+    ap.add_argument("--only", choices=["all", "sketch", "bf16", "right", "dense", "partial",
+                                       "rsvd", "single_view", "nystrom", "serve",
+                                       "serve_small"],
                     default="all",
                     help="profiling aid: run one part ('bf16', 'right', 'rsvd', 'nystrom' and "
                          "'serve' print only that part's JSON object)")
@@ -613,6 +658,9 @@ def main():
         return
     if args.only == "nystrom":
         print(json.dumps({"nystrom": bench_nystrom(bs, args.lowrank_reps)}), flush=True)
+        return
+    if args.only == "partial":
+        print(json.dumps({"partial_sketch": bench_partial(bs)}), flush=True)
         return
     cfg = dict(workloads.CONFIGS["c2_fp32_apply"])
     n, m, p, l, seed = cfg["n"], cfg["m"], cfg["p"], cfg["l"], cfg["seed"]
@@ -730,6 +778,7 @@ def main():
         torch.cuda.empty_cache()
         out["nystrom"] = bench_nystrom(bs, args.lowrank_reps)
         torch.cuda.empty_cache()
+        out["partial_sketch"] = bench_partial(bs)
     if args.serve_jobs > 0 and args.only == "all":
         out["serving"] = bench_serving(bs, args.serve_jobs, args.serve_streams,
                                        rate=args.serve_rate)

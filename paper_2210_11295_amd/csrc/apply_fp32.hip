@@ -94,18 +94,17 @@ __device__ __forceinline__ void load_rows(float (&v)[BR], const float *base, int
 
 // The same for a wave whose first vr rows (wave-uniform, 0 <= vr <= BR) hold
 // data and the rest are the zero padding of a block: row t >= vr is read at
-// row max(vr - 1, 0) (an address inside A) and replaced by zero.
+// row max(vr - 1, 0), an address inside A.  The caller zeroes those rows when
+// it uses them (doing it here would make the wave wait for the loads).
 template <int BR, int T0 = 0, int T1 = BR>
-__device__ __forceinline__ void load_rows_masked(float (&v)[BR], const float *base, int voff,
-                                                 int row_bytes, int vr) {
+__device__ __forceinline__ void load_rows_clamped(float (&v)[BR], const float *base, int voff,
+                                                  int row_bytes, int vr) {
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(base);
   const int last = vr > 0 ? vr - 1 : 0;
 #pragma unroll
   for (int t = T0; t < T1; ++t) {
     const int tr = t < last ? t : last;
-    const float x =
-        __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, voff, tr * row_bytes, kAuxNT));
-    v[t] = t < vr ? x : 0.f;
+    v[t] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, voff, tr * row_bytes, kAuxNT));
   }
 }
 
@@ -163,29 +162,35 @@ struct FusedCta {
     return wavebase + (int64_t)q * B * a.lda;
   }
 
-  // PAD: the padded-layout index of chunk qr, and where its rows of this
-  // wave start in A with the bytes they cover (0 past the block's rows).
-  __device__ __forceinline__ int padded_chunk(int qr) const {
-    const int i = qr / a.cr;
-    return (i << cpb_log2) + (qr - i * a.cr);
-  }
-  // (vr rows of the wave hold data; with none, the tile's first row of A,
-  // which always exists, stands in as the address.)
-  __device__ __forceinline__ const float *padded_base(int qr, int &vr) const {
-    const int i = qr / a.cr, xhi = qr - i * a.cr;
-    int64_t v = a.r_rows - (int64_t)xhi * B - w * BR;
+  // PAD: the current chunk is chunk cx of block ci (chunk ci*(rp/B) + cx of
+  // the padded layout; its rows start at row ci*r + cx*B of A), and cvr of
+  // this wave's rows hold data.  (ci, cx) advance by one chunk per step, so
+  // no division runs per chunk; the next chunk's address is ready before its
+  // loads are issued.
+  int ci = 0, cx = 0, cvr = BR;
+  // Where this wave's rows of chunk x of block i start in A and how many
+  // hold data (with none, the tile's first row of A, which always exists,
+  // stands in as the address).  Every quantity is wave-uniform;
+  // readfirstlane states it, so the row offsets stay scalar.
+  __device__ __forceinline__ const float *padded_base(int i, int x, int &vr) const {
+    int64_t v = a.r_rows - (int64_t)x * B - w * BR;
     v = v < 0 ? 0 : (v > BR ? BR : v);
-    vr = (int)v;
-    return vr > 0 ? wavebase + ((int64_t)i * a.r_rows + (int64_t)xhi * B) * a.lda : tilebase;
+    vr = __builtin_amdgcn_readfirstlane((int)v);
+    if (vr == 0) return tilebase;
+    const int64_t row = (int64_t)i * a.r_rows + (int64_t)x * B;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)row);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)row >> 32));
+    return wavebase + (int64_t)(((uint64_t)hi << 32) | lo) * a.lda;
   }
-  template <int T0, int T1>
-  __device__ __forceinline__ void load_chunk(float (&v)[BR], int qr) const {
+  // First chunk q0 of this workgroup's range.
+  __device__ __forceinline__ void load_first(float (&v)[BR], int q0) {
     if constexpr (PAD) {
-      int vr;
-      const float *base = padded_base(qr, vr);
-      load_rows_masked<BR, T0, T1>(v, base, voff, row_bytes, vr);
+      ci = __builtin_amdgcn_readfirstlane(q0 / a.cr);
+      cx = q0 - ci * a.cr;
+      const float *base = padded_base(ci, cx, cvr);
+      load_rows_clamped<BR>(v, base, voff, row_bytes, cvr);
     } else {
-      load_rows<BR, T0, T1>(v, chunk_base(qr), voff, row_bytes);
+      load_rows<BR>(v, chunk_base(q0), voff, row_bytes);
     }
   }
 
@@ -194,8 +199,21 @@ struct FusedCta {
     // once this chunk's rows have left the registers for LDS, which keeps
     // the accumulators, one chunk and half a chunk within 256 VGPRs.
     const bool more = qr + 1 < q1;
-    const int q = PAD ? padded_chunk(qr) : qr;
-    if (more) load_chunk<0, BR / 2>(nxt, qr + 1);
+    int q = qr;
+    int ni = 0, nx = 0, nvr = BR;
+    const float *nbase = nullptr;
+    if constexpr (PAD) {
+      q = (ci << cpb_log2) + cx;
+      ni = cx + 1 == a.cr ? ci + 1 : ci;
+      nx = cx + 1 == a.cr ? 0 : cx + 1;
+      if (more) nbase = padded_base(ni, nx, nvr);
+      if (more) load_rows_clamped<BR, 0, BR / 2>(nxt, nbase, voff, row_bytes, nvr);
+#pragma unroll
+      for (int t = 0; t < BR; ++t)  // the block's zero padding
+        if (t >= cvr) cur[t] = 0.f;
+    } else {
+      if (more) load_rows<BR, 0, BR / 2>(nxt, chunk_base(qr + 1), voff, row_bytes);
+    }
     apply_dsigns<BR>(cur, a.Dbits, (int64_t)q * B + w * BR);
     fwht_regs<BR>(cur);
     {
@@ -203,7 +221,14 @@ struct FusedCta {
 #pragma unroll
       for (int t = 0; t < BR; ++t) Tw[t * kLDT] = cur[t];
     }
-    if (more) load_chunk<BR / 2, BR>(nxt, qr + 1);
+    if constexpr (PAD) {
+      if (more) load_rows_clamped<BR, BR / 2, BR>(nxt, nbase, voff, row_bytes, nvr);
+      ci = ni;
+      cx = nx;
+      cvr = nvr;
+    } else {
+      if (more) load_rows<BR, BR / 2, BR>(nxt, chunk_base(qr + 1), voff, row_bytes);
+    }
     __syncthreads();
     // H_8 over w: group t holds rows t, t+BR, ..., t+7*BR.
 #pragma unroll
@@ -276,7 +301,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, float *T, int bx,
   // registers and spilled R_j's chunk bits, whose reload in the gather (a
   // vector-memory access) waited for the whole prefetch of the next chunk.
   float bufA[BR], bufB[BR];
-  if (q0 < q1) cta.template load_chunk<0, BR>(bufA, q0);
+  if (q0 < q1) cta.load_first(bufA, q0);
 #pragma nounroll
   for (int q = q0; q < q1; ++q) {
     cta.step(q, q1, bufA, bufB);
