@@ -63,6 +63,7 @@ struct Bf16Args {
   int64_t ldo;
   int64_t split_stride;
   float scale;
+  const int32_t *order;  // sample of each gather lane (16-wave workgroups)
 };
 
 // hi/lo BF16 split of two values, packed two per dword (first value low).
@@ -311,8 +312,14 @@ __global__ __launch_bounds__(NW * 64) void fused_bf16_kernel(Bf16Args a) {
   __syncthreads();
   const int q0 = by * a.chunks_per_split;
   const int q1 = min(q0 + a.chunks_per_split, a.total_chunks);
-  cta.j = blockIdx.z * (NW * 64) + tid;
-  cta.jok = cta.j < a.l;
+  // 16-wave workgroups take the samples in the plan's bank-spreading lane
+  // order, as in the FP32 kernel.
+  const int lidx = blockIdx.z * (NW * 64) + tid;
+  cta.jok = lidx < a.l;
+  if constexpr (NW == 16)
+    cta.j = cta.jok ? a.order[lidx] : lidx;
+  else
+    cta.j = lidx;
   const int rj = cta.jok ? a.R[cta.j] : 0;
   cta.pos = rj & (Cta::B - 1);
   cta.rhi = (uint32_t)rj >> Cta::LOG2B;
@@ -433,6 +440,7 @@ int apply_split_bf16(const bsrht_plan_s *pl, const float *A, int64_t m, int64_t 
   a.lda = lda;
   a.m = (int)m;
   a.R = pl->R;
+  a.order = pl->order;
   a.Dbits = pl->Dbits;
   a.Dtbits = pl->Dtbits;
   a.dt_words = (int)pl->dt_words;

@@ -59,6 +59,7 @@ struct FusedArgs {
   float scale;
   int64_t r_rows;  // rows per block in A (padded plans: r < 2^log2r)
   int cr;          // chunks per block that hold rows of A (padded plans)
+  const int32_t *order;  // sample of each gather lane (16-wave workgroups)
 };
 
 // Unscaled Walsh-Hadamard transform of N values held in registers.
@@ -285,8 +286,15 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, float *T, int bx,
   cta.tilebase = a.A + c0;
   const int q0 = by * a.chunks_per_split;
   const int q1 = min(q0 + a.chunks_per_split, a.total_chunks);
-  cta.j = bz * (NW * 64) + tid;
-  cta.jok = cta.j < a.l;
+  // 16-wave workgroups serve l > 512, where the gather's LDS reads dominate:
+  // their lanes take the samples in the plan's bank-spreading order (the
+  // 8-wave kernel is bound by HBM and keeps draw order).
+  const int lidx = bz * (NW * 64) + tid;
+  cta.jok = lidx < a.l;
+  if constexpr (NW == 16)
+    cta.j = cta.jok ? a.order[lidx] : lidx;
+  else
+    cta.j = lidx;
   const int rj = cta.jok ? a.R[cta.j] : 0;
   cta.pos = rj & (Cta::B - 1);
   cta.rhi = (uint32_t)rj >> Cta::LOG2B;
@@ -341,14 +349,16 @@ __global__ __launch_bounds__(NW * 64) void fused_fp32_kernel(FusedArgs a) {
 __global__ void reduce_splits_kernel(const float *__restrict__ part, int splits,
                                      int64_t split_stride, int l, int m,
                                      float *__restrict__ Y, int64_t ldy, float scale) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)l * m) return;
-  const int j = (int)(idx / m);
-  const int c = (int)(idx - (int64_t)j * m);
-  const float *p = part + (int64_t)j * m + c;
-  float s = 0.f;
-  for (int sp = 0; sp < splits; ++sp) s += p[(int64_t)sp * split_stride];
-  Y[(int64_t)j * ldy + c] = s * scale;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (int64_t)l * m;
+       idx += stride) {
+    const int j = (int)(idx / m);
+    const int c = (int)(idx - (int64_t)j * m);
+    const float *p = part + (int64_t)j * m + c;
+    float s = 0.f;
+    for (int sp = 0; sp < splits; ++sp) s += p[(int64_t)sp * split_stride];
+    Y[(int64_t)j * ldy + c] = s * scale;
+  }
 }
 
 // Direct evaluation of eq. (2.3) for blocks shorter than the smallest fused
@@ -534,7 +544,7 @@ int reduce_splits(const float *part, int splits, int64_t split_stride, int64_t l
                   float *Y, int64_t ldy, float scale, hipStream_t s) {
   const int64_t total = l * m;
   const int tb = 256;
-  reduce_splits_kernel<<<(unsigned)((total + tb - 1) / tb), tb, 0, s>>>(
+  reduce_splits_kernel<<<stride_grid(total, tb), tb, 0, s>>>(
       part, splits, split_stride, (int)l, (int)m, Y, ldy, scale);
   BSRHT_LAUNCH_CHECK();
   return BSRHT_OK;
@@ -554,6 +564,7 @@ int fused_args(const bsrht_plan_s *pl, const float *A, int64_t m, int64_t lda, f
   a.lda = lda;
   a.m = (int)m;
   a.R = pl->R;
+  a.order = pl->order;
   a.Dbits = pl->Dbits;
   a.Dtbits = pl->Dtbits;
   a.dt_words = (int)pl->dt_words;
@@ -646,7 +657,7 @@ int apply_fp32(const bsrht_plan_s *pl, const float *A, int64_t m, int64_t lda, f
   if (L.direct) {
     const int64_t total = pl->l * m;
     const int tb = 256;
-    if ((total + tb - 1) / tb > INT_MAX) return BSRHT_EUNSUPPORTED;
+    if (total > kMaxGridItems) return BSRHT_EUNSUPPORTED;
     direct_kernel<<<(unsigned)((total + tb - 1) / tb), tb, 0, s>>>(
         A, lda, (int)m, pl->R, pl->Dbits, pl->Dtbits, pl->dt_words, (int)pl->l, pl->p,
         pl->log2r, pl->r, Y, ldy, scale);

@@ -389,7 +389,7 @@ int apply_right_fp32(const bsrht_plan_s *pl, const float *A, int64_t m, int64_t 
   if (L.direct) {
     const int64_t total = pl->l * m;
     const int tb = 256;
-    if ((total + tb - 1) / tb > INT_MAX) return BSRHT_EUNSUPPORTED;
+    if (total > kMaxGridItems) return BSRHT_EUNSUPPORTED;
     right_direct_kernel<<<(unsigned)((total + tb - 1) / tb), tb, 0, s>>>(
         A, lda, (int)m, pl->R, pl->Dbits, pl->Dtbits, pl->dt_words, (int)pl->l, pl->p,
         pl->log2r, pl->r, Y, ldy, scale);

@@ -13,9 +13,11 @@ struct bsrht_plan_s {
   int log2r;
   uint64_t seed;
   int sampling, precision;
-  int32_t *R;         // device, l entries in [0, r), draw order
+  int32_t *R;         // device, l entries in [0, rp), draw order
   uint32_t *Dbits;    // device, ceil(p*rp/32) words; bit i*rp + x = sign of D^(i)_x
   uint32_t *Dtbits;   // device, p * dt_words words; block i at i*dt_words
+  int32_t *order;     // device, l entries: the sample served by each gather lane
+                      // of the 16-wave column kernels (a permutation of 0..l-1)
   int64_t d_words, dt_words;
   hipStream_t stream; // stream the tables were written on
   int device;
@@ -54,6 +56,17 @@ void debug_report(const char *file, int line, const char *what, int status);
   } while (0)
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Work items one launch dimension can dispatch (grid size x workgroup size
+// must fit in 32 bits), less one workgroup of slack.
+constexpr int64_t kMaxGridItems = int64_t(0xFFFFFFFF) - 1024;
+
+// Workgroups of tb threads for a grid-stride loop over `total` items: one
+// per tb items, at most 65536 (each thread then takes several items).
+inline unsigned stride_grid(int64_t total, int tb) {
+  const int64_t g = (total + tb - 1) / tb;
+  return (unsigned)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
+}
 
 inline bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 

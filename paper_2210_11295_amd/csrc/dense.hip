@@ -309,13 +309,15 @@ __global__ __launch_bounds__(kBThreads) void gemm_big_kernel(GemmDesc d, const T
 template <typename TC>
 __global__ void reduce_partials_kernel(const double *__restrict__ P, int splits, int64_t M,
                                        int64_t N, TC *__restrict__ C, int64_t ldc, bool mirror) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= M * N) return;
-  const int64_t i = idx / N, j = idx - i * N;
-  const int64_t src = (mirror && i / kBM > j / kBN) ? j * N + i : idx;
-  double s = 0.0;
-  for (int sp = 0; sp < splits; ++sp) s += P[(int64_t)sp * M * N + src];
-  C[i * ldc + j] = (TC)s;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < M * N;
+       idx += stride) {
+    const int64_t i = idx / N, j = idx - i * N;
+    const int64_t src = (mirror && i / kBM > j / kBN) ? j * N + i : idx;
+    double s = 0.0;
+    for (int sp = 0; sp < splits; ++sp) s += P[(int64_t)sp * M * N + src];
+    C[i * ldc + j] = (TC)s;
+  }
 }
 
 // C[i][j] = C[j][i] for the elements of tiles below the diagonal.
@@ -391,7 +393,7 @@ int gemm_f32_splitk(const GemmDesc &d0, const float *A, const float *B, float *C
   d.beta = 0.0;
   BSRHT_TRY((gemm_launch<float, float, double, false>(d, A, B, partials, s)));
   const int64_t total = d.M * d.N;
-  reduce_partials_kernel<float><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(
+  reduce_partials_kernel<float><<<stride_grid(total, 256), 256, 0, s>>>(
       partials, splits, d.M, d.N, C, d0.ldc, false);
   BSRHT_LAUNCH_CHECK();
   return BSRHT_OK;
@@ -431,7 +433,7 @@ static int gram_impl(const TX *X, int64_t n, int64_t K, int64_t sr, int64_t sc, 
   d.split_stride = K * K;
   int st = gemm_launch<TX, TX, double, true>(d, X, X, partials, s);
   if (st != BSRHT_OK) return st;
-  reduce_partials_kernel<double><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(
+  reduce_partials_kernel<double><<<stride_grid(total, 256), 256, 0, s>>>(
       partials, splits, K, K, G, ldg, d.upper_tiles);
   BSRHT_LAUNCH_CHECK();
   return BSRHT_OK;
@@ -1273,15 +1275,17 @@ template <typename TS, typename TD>
 __global__ void scale_cols_kernel(const TS *__restrict__ src, int64_t rows, int64_t cols_keep,
                                   int64_t cols_out, int64_t lds, const double *__restrict__ scale,
                                   TD *__restrict__ dst, int64_t ldd) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= rows * cols_out) return;
-  const int64_t i = idx / cols_out, j = idx % cols_out;
-  double v = 0.0;
-  if (j < cols_keep) {
-    v = (double)src[i * lds + j];
-    if (scale) v *= scale[j];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < rows * cols_out;
+       idx += stride) {
+    const int64_t i = idx / cols_out, j = idx % cols_out;
+    double v = 0.0;
+    if (j < cols_keep) {
+      v = (double)src[i * lds + j];
+      if (scale) v *= scale[j];
+    }
+    dst[i * ldd + j] = (TD)v;
   }
-  dst[i * ldd + j] = (TD)v;
 }
 
 }  // namespace
@@ -1460,7 +1464,7 @@ static int scale_cols_impl(const TS *src, int64_t rows, int64_t keep, int64_t ou
                            const double *scale, TD *dst, int64_t ldd, hipStream_t s) {
   const int64_t total = rows * out;
   if (total <= 0) return BSRHT_OK;
-  scale_cols_kernel<TS, TD><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(
+  scale_cols_kernel<TS, TD><<<stride_grid(total, 256), 256, 0, s>>>(
       src, rows, keep, out, lds, scale, dst, ldd);
   BSRHT_LAUNCH_CHECK();
   return BSRHT_OK;

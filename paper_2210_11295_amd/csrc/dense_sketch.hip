@@ -25,46 +25,51 @@ namespace {
 
 enum : uint64_t { kTagGauss = 4, kTagRad = 5 };
 
-// One thread per 8 consecutive columns x0 .. x0+7 of row j.
+// One work item per 8 consecutive columns x0 .. x0+7 of row j; a grid-stride
+// loop covers every item, so the grid stays within the dispatch limits.
 __global__ void gen_gauss_kernel(float *__restrict__ G, int64_t l, int64_t n, int64_t ldg,
                                  uint64_t seed, double scale) {
   const int64_t n8 = (n + 7) >> 3;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= l * n8) return;
-  const int64_t j = idx / n8, x0 = (idx - j * n8) << 3;
-  const Philox4 o = philox4x64_10((uint64_t)(x0 >> 3), (uint64_t)j, kTagGauss, 0, seed, 0);
-  float z[8];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < l * n8;
+       idx += stride) {
+    const int64_t j = idx / n8, x0 = (idx - j * n8) << 3;
+    const Philox4 o = philox4x64_10((uint64_t)(x0 >> 3), (uint64_t)j, kTagGauss, 0, seed, 0);
+    float z[8];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const double u1 = ((double)(uint32_t)o.w[q] + 0.5) * 0x1p-32;
-    const double u2 = ((double)(uint32_t)(o.w[q] >> 32) + 0.5) * 0x1p-32;
-    const double rho = sqrt(-2.0 * log(u1));
-    double sn, cs;
-    sincospi(2.0 * u2, &sn, &cs);
-    z[2 * q] = (float)(rho * cs * scale);
-    z[2 * q + 1] = (float)(rho * sn * scale);
-  }
-  float *row = G + j * ldg + x0;
-  if (x0 + 8 <= n && ((ldg & 3) == 0)) {
-    reinterpret_cast<float4 *>(row)[0] = make_float4(z[0], z[1], z[2], z[3]);
-    reinterpret_cast<float4 *>(row)[1] = make_float4(z[4], z[5], z[6], z[7]);
-  } else {
-    for (int e = 0; e < 8 && x0 + e < n; ++e) row[e] = z[e];
+    for (int q = 0; q < 4; ++q) {
+      const double u1 = ((double)(uint32_t)o.w[q] + 0.5) * 0x1p-32;
+      const double u2 = ((double)(uint32_t)(o.w[q] >> 32) + 0.5) * 0x1p-32;
+      const double rho = sqrt(-2.0 * log(u1));
+      double sn, cs;
+      sincospi(2.0 * u2, &sn, &cs);
+      z[2 * q] = (float)(rho * cs * scale);
+      z[2 * q + 1] = (float)(rho * sn * scale);
+    }
+    float *row = G + j * ldg + x0;
+    if (x0 + 8 <= n && ((uintptr_t)row & 15) == 0) {
+      reinterpret_cast<float4 *>(row)[0] = make_float4(z[0], z[1], z[2], z[3]);
+      reinterpret_cast<float4 *>(row)[1] = make_float4(z[4], z[5], z[6], z[7]);
+    } else {
+      for (int e = 0; e < 8 && x0 + e < n; ++e) row[e] = z[e];
+    }
   }
 }
 
-// One thread per 8 consecutive columns; 32 neighbouring threads share a
-// 256-bit output.
+// One work item per 8 consecutive columns (32 neighbouring items share a
+// 256-bit output); grid-stride as above.
 __global__ void gen_rademacher_kernel(float *__restrict__ G, int64_t l, int64_t n, int64_t ldg,
                                       uint64_t seed, float scale) {
   const int64_t n8 = (n + 7) >> 3;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= l * n8) return;
-  const int64_t j = idx / n8, x0 = (idx - j * n8) << 3;
-  const Philox4 o = philox4x64_10((uint64_t)(x0 >> 8), (uint64_t)j, kTagRad, 0, seed, 0);
-  float *row = G + j * ldg + x0;
-  for (int e = 0; e < 8 && x0 + e < n; ++e)
-    row[e] = philox_bit(o, (uint32_t)((x0 + e) & 255)) ? -scale : scale;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < l * n8;
+       idx += stride) {
+    const int64_t j = idx / n8, x0 = (idx - j * n8) << 3;
+    const Philox4 o = philox4x64_10((uint64_t)(x0 >> 8), (uint64_t)j, kTagRad, 0, seed, 0);
+    float *row = G + j * ldg + x0;
+    for (int e = 0; e < 8 && x0 + e < n; ++e)
+      row[e] = philox_bit(o, (uint32_t)((x0 + e) & 255)) ? -scale : scale;
+  }
 }
 
 struct DenseLayout {
@@ -116,8 +121,7 @@ int bsrht_dense_sketch(int kind, uint64_t seed, int64_t n, int64_t l, const floa
   float *G = static_cast<float *>(ws);
   double *part = reinterpret_cast<double *>(static_cast<char *>(ws) + L.g_bytes);
   const int64_t total = l * ((n + 7) >> 3);
-  const unsigned blocks = (unsigned)((total + 255) / 256);
-  if ((total + 255) / 256 > INT_MAX) return BSRHT_EUNSUPPORTED;
+  const unsigned blocks = stride_grid(total, 256);
   if (kind == BSRHT_DENSE_GAUSSIAN)
     gen_gauss_kernel<<<blocks, 256, 0, s>>>(G, l, n, L.ldg, seed, 1.0 / sqrt((double)l));
   else

@@ -514,7 +514,7 @@ int nystrom_impl(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, floa
   BSRHT_TRY(sketch(A, n, lda, w.W));
   BSRHT_TRY(transpose_f32(w.W, l, n, n, w.Y, l, s));
   if (shifted) {
-    if ((n * l + 255) / 256 > INT_MAX) return BSRHT_EUNSUPPORTED;
+    if (n * l > kMaxGridItems) return BSRHT_EUNSUPPORTED;
     // nu = sqrt(n) u_s ||Y||_F (u_s: unit roundoff of the sketch), Y += nu Omega^T
     const double us = plan->precision == BSRHT_SPLIT_BF16 ? 0x1p-17 : kU32;
     ssq_partial_kernel<<<kSsqBlocks, 256, 0, s>>>(w.Y, n, l, l, w.ssq);
