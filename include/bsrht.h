@@ -79,8 +79,9 @@ const char *bsrht_strerror(int status);
 
 /*
  * Device bytes needed for the random tables of a plan with these sizes
- * (R: l int32; D: p*rp bits; Dt: p*l bits; the column kernels' gather lane
- * order: l int32; each region 256-byte aligned).
+ * (R: l int32; D: p*rp bits; Dt: p*l bits; two gather lane orders, for the
+ * column and the right-side kernels: l int32 each; each region 256-byte
+ * aligned).
  * Returns 0 if the sizes are invalid (see bsrht_plan).
  */
 size_t bsrht_plan_bytes(int64_t n, int64_t p, int64_t l);

@@ -59,6 +59,7 @@ struct RightArgs {
   int64_t ldo;
   int64_t split_stride;
   float scale;
+  const int32_t *order;  // sample of each gather lane
 };
 
 // Unscaled Walsh-Hadamard transform of N values held in registers.
@@ -263,9 +264,12 @@ __global__ __launch_bounds__(NW * 64) void right_fp32_kernel(RightArgs a) {
   }
   const int q0 = by * a.chunks_per_split;
   const int q1 = min(q0 + a.chunks_per_split, a.total_chunks);
-  cta.j = (int)blockIdx.z * (NW * 64) + tid;
-  cta.jok = cta.j < a.l;
-  cta.jc = min(cta.j, a.l - 1);
+  // Lanes take the samples in the plan's bank-spreading order for this
+  // gather (round-robin over (R_j >> 2) mod 16).
+  const int lidx = (int)blockIdx.z * (NW * 64) + tid;
+  cta.jok = lidx < a.l;
+  cta.j = cta.jok ? a.order[lidx] : lidx;
+  cta.jc = cta.jok ? cta.j : a.l - 1;
   const int rj = cta.jok ? a.R[cta.j] : 0;
   cta.pos = rj & (Cta::B - 1);
   cta.swz = (cta.pos >> 2) & 15;
@@ -405,6 +409,7 @@ int apply_right_fp32(const bsrht_plan_s *pl, const float *A, int64_t m, int64_t 
   a.lda = lda;
   a.m = (int)m;
   a.R = pl->R;
+  a.order = pl->order_right;
   a.Dbits = pl->Dbits;
   a.Dtbits = pl->Dtbits;
   a.dt_words = (int)pl->dt_words;

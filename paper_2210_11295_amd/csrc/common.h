@@ -18,6 +18,7 @@ struct bsrht_plan_s {
   uint32_t *Dtbits;   // device, p * dt_words words; block i at i*dt_words
   int32_t *order;     // device, l entries: the sample served by each gather lane
                       // of the 16-wave column kernels (a permutation of 0..l-1)
+  int32_t *order_right;  // device, l entries: the same for the right-side kernel
   int64_t d_words, dt_words;
   hipStream_t stream; // stream the tables were written on
   int device;

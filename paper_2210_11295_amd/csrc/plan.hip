@@ -80,27 +80,29 @@ __global__ void build_r_kernel(int32_t *R, int64_t l, int64_t r, uint64_t seed) 
   R[j] = (int32_t)(o.w[0] & (uint64_t)(r - 1));
 }
 
-// Gather lane order.  In the column kernels' gather every lane reads one
-// 16-byte quad of the LDS row R_j mod b of its sample; rows are 17 quads
-// apart, so the quad's bank group is (R_j + c) mod 16 for the c-th quad, and
-// lanes whose samples share R_j mod 16 (but not the row) conflict.  Within
-// each consecutive group of 1024 samples this orders the samples round-robin
-// over the residues R_j mod 16 (round k takes the k-th sample, in draw
-// order, of every residue that has one), so that most aligned 16-lane groups
-// hold 16 distinct residues.  Sample (residue v, rank k) goes to position
+// Gather lane orders.  In the gathers every lane reads 16-byte quads of the
+// LDS data of its sample's position R_j mod b, and lanes whose samples fall
+// in the same bank group (but not the same row) conflict.  Column kernels:
+// rows are 17 quads apart, so the c-th quad's bank group is (R_j + c) mod 16
+// and the key is R_j mod 16.  Right-side kernel: position x holds 16 quads
+// swizzled by (x >> 2) mod 16, so the key is (R_j >> 2) mod 16.  Within each
+// consecutive group of 1024 samples an order takes the samples round-robin
+// over the key (round k takes the k-th sample, in draw order, of every key
+// value that has one), so that most aligned 16-lane groups hold 16 distinct
+// keys.  Sample (key v, rank k) goes to position
 //   sum_u min(k, size_u) + #{u < v : size_u > k}
-// of its group (size_u: samples of residue u in the group), a bijection.
+// of its group (size_u: samples with key u in the group), a bijection.
 // Only the assignment of samples to lanes changes: each sample's sum runs in
 // the same order, so the sketch is bitwise the same as in draw order.
 __global__ __launch_bounds__(1024) void build_order_kernel(const int32_t *__restrict__ R,
                                                            int32_t *__restrict__ order,
-                                                           int64_t l) {
+                                                           int64_t l, int shift) {
   __shared__ int cnt[16][16];  // [wave][residue]: counts, then exclusive prefix
   __shared__ int size[16];
   const int64_t j0 = (int64_t)blockIdx.x * 1024;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const bool ok = j0 + t < l;
-  const int rho = ok ? (R[j0 + t] & 15) : 16;
+  const int rho = ok ? ((R[j0 + t] >> shift) & 15) : 16;
   int rank = 0;
   for (int v = 0; v < 16; ++v) {
     const unsigned long long msk = __ballot(rho == v);
@@ -170,6 +172,7 @@ size_t bsrht_plan_bytes(int64_t n, int64_t p, int64_t l) {
   sz.take<uint32_t>((size_t)((p * padded_block(n / p) + 31) / 32));
   sz.take<uint32_t>((size_t)(p * ((l + 31) / 32)));
   sz.take<int32_t>((size_t)l);
+  sz.take<int32_t>((size_t)l);
   return align256(sz.used);
 }
 
@@ -210,6 +213,7 @@ int bsrht_plan(int64_t n, int64_t p, int64_t l, uint64_t seed, int sampling,
   pl->Dbits = cv.take<uint32_t>((size_t)pl->d_words);
   pl->Dtbits = cv.take<uint32_t>((size_t)(p * pl->dt_words));
   pl->order = cv.take<int32_t>((size_t)l);
+  pl->order_right = cv.take<int32_t>((size_t)l);
   hipStream_t s = pl->stream;
 
   const int tb = 256;
@@ -245,7 +249,9 @@ int bsrht_plan(int64_t n, int64_t p, int64_t l, uint64_t seed, int sampling,
       return BSRHT_EDEVICE;
     }
   }
-  build_order_kernel<<<(unsigned)((l + 1023) / 1024), 1024, 0, s>>>(pl->R, pl->order, l);
+  build_order_kernel<<<(unsigned)((l + 1023) / 1024), 1024, 0, s>>>(pl->R, pl->order, l, 0);
+  build_order_kernel<<<(unsigned)((l + 1023) / 1024), 1024, 0, s>>>(pl->R, pl->order_right, l,
+                                                                    2);
   if (hipGetLastError() != hipSuccess) {
     delete pl;
     return BSRHT_EDEVICE;

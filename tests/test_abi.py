@@ -54,7 +54,9 @@ def test_plan_bytes_validation(n, p, l, ok):
         return
     a256 = lambda x: (x + 255) // 256 * 256
     rp = 1 << (n // p - 1).bit_length()
+    # R, D bits, Dt bits, then the two gather lane orders (l int32 each)
     expect = a256(a256(a256(4 * l) + 4 * ((p * rp + 31) // 32)) + 4 * p * ((l + 31) // 32))
+    expect = a256(a256(expect + 4 * l) + 4 * l)
     assert nb == expect
 
 

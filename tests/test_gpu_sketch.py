@@ -71,13 +71,13 @@ def _align256(x):
     return (x + 255) // 256 * 256
 
 
-def _round_robin_order(R):
-    """The gather lane order the plan stores: per group of 1024 samples, the
-    samples taken round-robin over the residues R_j mod 16 (round k holds the
-    k-th sample, in draw order, of each residue that has one)."""
+def _round_robin_order(key):
+    """A gather lane order the plan stores: per group of 1024 samples, the
+    samples taken round-robin over key_j in 0..15 (round k holds the k-th
+    sample, in draw order, of each key value that has one)."""
     out = []
-    for g0 in range(0, len(R), 1024):
-        rho = R[g0:g0 + 1024] % 16
+    for g0 in range(0, len(key), 1024):
+        rho = key[g0:g0 + 1024]
         buckets = [list(np.nonzero(rho == v)[0] + g0) for v in range(16)]
         for k in range(max(len(b) for b in buckets)):
             out += [b[k] for b in buckets if k < len(b)]
@@ -86,20 +86,22 @@ def _round_robin_order(R):
 
 @pytest.mark.parametrize("n,p,l,seed,mode", TABLE_CASES + [(10_000_000, 16, 2000, 0, 0)])
 def test_gather_lane_order(n, p, l, seed, mode):
-    """The lane order region of the plan tables (after R, D and Dt) is a
-    permutation of the samples within each 1024-sample group, equal to the
-    round-robin order over R_j mod 16."""
+    """The two lane order regions of the plan tables (after R, D and Dt) are
+    permutations of the samples within each 1024-sample group, equal to the
+    round-robin orders over R_j mod 16 (column kernels) and (R_j >> 2) mod 16
+    (right-side kernel)."""
     dev = device()
     say("lane order", n, p, l, seed, mode)
     plan = bs.Plan(n, p, l, seed, mode, device=dev)
     R = plan.export()[0].astype(np.int64)
     off = (_align256(4 * l) + _align256(4 * ((p * plan.rp + 31) // 32))
            + _align256(4 * p * ((l + 31) // 32)))
-    order = plan.tables[off:off + 4 * l].view(torch.int32).cpu().numpy().astype(np.int64)
-    torch.cuda.synchronize()
-    for g0 in range(0, l, 1024):
-        assert sorted(order[g0:g0 + 1024].tolist()) == list(range(g0, min(l, g0 + 1024)))
-    assert np.array_equal(order, _round_robin_order(R))
+    for shift in (0, 2):
+        order = plan.tables[off:off + 4 * l].view(torch.int32).cpu().numpy().astype(np.int64)
+        for g0 in range(0, l, 1024):
+            assert sorted(order[g0:g0 + 1024].tolist()) == list(range(g0, min(l, g0 + 1024)))
+        assert np.array_equal(order, _round_robin_order((R >> shift) & 15))
+        off += _align256(4 * l)
 
 
 SKETCH_CASES = [
