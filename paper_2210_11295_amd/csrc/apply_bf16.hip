@@ -63,7 +63,7 @@ struct Bf16Args {
   int64_t ldo;
   int64_t split_stride;
   float scale;
-  const int32_t *order;  // sample of each gather lane (16-wave workgroups)
+  const int32_t *order;  // sample of each gather lane
 };
 
 // hi/lo BF16 split of two values, packed two per dword (first value low).
@@ -312,14 +312,11 @@ __global__ __launch_bounds__(NW * 64) void fused_bf16_kernel(Bf16Args a) {
   __syncthreads();
   const int q0 = by * a.chunks_per_split;
   const int q1 = min(q0 + a.chunks_per_split, a.total_chunks);
-  // 16-wave workgroups take the samples in the plan's bank-spreading lane
-  // order, as in the FP32 kernel.
+  // Lanes take the samples in the plan's bank-spreading order, as in the
+  // FP32 kernel.
   const int lidx = blockIdx.z * (NW * 64) + tid;
   cta.jok = lidx < a.l;
-  if constexpr (NW == 16)
-    cta.j = cta.jok ? a.order[lidx] : lidx;
-  else
-    cta.j = lidx;
+  cta.j = cta.jok ? a.order[lidx] : lidx;
   const int rj = cta.jok ? a.R[cta.j] : 0;
   cta.pos = rj & (Cta::B - 1);
   cta.rhi = (uint32_t)rj >> Cta::LOG2B;

@@ -59,7 +59,7 @@ struct FusedArgs {
   float scale;
   int64_t r_rows;  // rows per block in A (padded plans: r < 2^log2r)
   int cr;          // chunks per block that hold rows of A (padded plans)
-  const int32_t *order;  // sample of each gather lane (16-wave workgroups)
+  const int32_t *order;  // sample of each gather lane
 };
 
 // Unscaled Walsh-Hadamard transform of N values held in registers.
@@ -286,15 +286,11 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, float *T, int bx,
   cta.tilebase = a.A + c0;
   const int q0 = by * a.chunks_per_split;
   const int q1 = min(q0 + a.chunks_per_split, a.total_chunks);
-  // 16-wave workgroups serve l > 512, where the gather's LDS reads dominate:
-  // their lanes take the samples in the plan's bank-spreading order (the
-  // 8-wave kernel is bound by HBM and keeps draw order).
+  // Lanes take the samples in the plan's bank-spreading order (round-robin
+  // over R_j mod 16, the gather's LDS bank group).
   const int lidx = bz * (NW * 64) + tid;
   cta.jok = lidx < a.l;
-  if constexpr (NW == 16)
-    cta.j = cta.jok ? a.order[lidx] : lidx;
-  else
-    cta.j = lidx;
+  cta.j = cta.jok ? a.order[lidx] : lidx;
   const int rj = cta.jok ? a.R[cta.j] : 0;
   cta.pos = rj & (Cta::B - 1);
   cta.rhi = (uint32_t)rj >> Cta::LOG2B;

@@ -17,7 +17,7 @@ struct bsrht_plan_s {
   uint32_t *Dbits;    // device, ceil(p*rp/32) words; bit i*rp + x = sign of D^(i)_x
   uint32_t *Dtbits;   // device, p * dt_words words; block i at i*dt_words
   int32_t *order;     // device, l entries: the sample served by each gather lane
-                      // of the 16-wave column kernels (a permutation of 0..l-1)
+                      // of the column kernels (a permutation of 0..l-1)
   int32_t *order_right;  // device, l entries: the same for the right-side kernel
   int64_t d_words, dt_words;
   hipStream_t stream; // stream the tables were written on
