@@ -104,6 +104,39 @@ def test_gather_lane_order(n, p, l, seed, mode):
         off += _align256(4 * l)
 
 
+@pytest.mark.parametrize("n,p,l,m,precision,right", [
+    (1 << 16, 16, 512, 200, bs.FP32, False),        # 8-wave kernel
+    (1 << 16, 16, 1000, 130, bs.FP32, False),       # 16-wave kernel
+    (1 << 16, 16, 512, 200, bs.SPLIT_BF16, False),  # split-BF16, 8 waves
+    (1 << 16, 16, 1000, 70, bs.SPLIT_BF16, False),  # split-BF16, 16 waves
+    (1 << 16, 16, 512, 100, bs.FP32, True),         # right-side, b = 512
+    (1 << 14, 64, 300, 65, bs.FP32, True),          # right-side, b = 256
+])
+def test_lane_order_leaves_results_bitwise_unchanged(n, p, l, m, precision, right):
+    """The gather lane orders only assign samples to lanes: with both order
+    regions overwritten by the identity (draw order), every sketch is
+    bitwise the same."""
+    dev = device()
+    say("lane order identity", n, p, l, m, precision, right)
+    plan = bs.Plan(n, p, l, 17, bs.WITH_REPLACEMENT, precision, device=dev)
+    if right:
+        A = workloads.gaussian_rows(m, n, "inv_sq", 17, device=dev)
+        run = lambda: bs.bsrht_apply_right(plan, A).clone()
+    else:
+        A = workloads.gaussian_cols(n, m, "inv_sq", 17, device=dev)
+        run = lambda: bs.bsrht_apply(plan, A).clone()
+    Y1 = run()
+    off = (_align256(4 * l) + _align256(4 * ((p * plan.rp + 31) // 32))
+           + _align256(4 * p * ((l + 31) // 32)))
+    ident = torch.arange(l, dtype=torch.int32, device=dev)
+    for k in range(2):
+        o = off + k * _align256(4 * l)
+        plan.tables[o:o + 4 * l].view(torch.int32).copy_(ident)
+    Y2 = run()
+    torch.cuda.synchronize()
+    assert torch.equal(Y1, Y2)
+
+
 SKETCH_CASES = [
     # n, p, l, m, mode   -- spans chunk sizes 64..512, ragged column tiles,
     # several row splits and sample groups, r = 1 .. 2^14, l > r
