@@ -579,9 +579,15 @@ __global__ void chol_finish_kernel(double *G, int64_t n, int64_t ldg, const Chol
 
 // Inverse of an upper-triangular n x n matrix C (row-major): column j of
 // Ci = C^{-1} solves C x = e_j by back substitution; one wave per column, the
-// dot product of each step split across the lanes, x kept in LDS.
+// dot product of each step split across the lanes, x kept in LDS.  Lane q
+// holds the entries t = i+1+q+64u (t <= j) of row i of C in registers; the
+// next row's entries are loaded while the current step runs, at addresses
+// clamped into the row (entries past j are never used), so the loads are
+// unconditional and the wait before a step covers only the row it uses.  The
+// sum runs in the order of the plain loop over t.
 constexpr int kTrinvWaves = 4;
 
+template <int PER>  // n <= 64 * PER
 __global__ __launch_bounds__(64 * kTrinvWaves) void trinv_upper_kernel(
     const double *__restrict__ C, int64_t n, int64_t ldc, double *__restrict__ Ci, int64_t ldi) {
   extern __shared__ double s_x[];
@@ -590,15 +596,34 @@ __global__ __launch_bounds__(64 * kTrinvWaves) void trinv_upper_kernel(
   double *x = s_x + (int64_t)wv * n;
   if (j >= n) return;
   for (int64_t i = lane; i < n; i += 64) x[i] = 0.0;
+  auto load_row = [&](int64_t i, double (&v)[PER], double &d) {
+    const double *row = C + i * ldc;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int64_t t = i + 1 + lane + 64 * u;
+      v[u] = row[t <= j ? t : j];
+    }
+    d = row[i];
+  };
+  double cur[PER], nxt[PER], dcur, dnxt = 1.0;
+  load_row(j, cur, dcur);
   for (int64_t i = j; i >= 0; --i) {
+    if (i > 0) load_row(i - 1, nxt, dnxt);
     double s = 0.0;
-    for (int64_t t = i + 1 + lane; t <= j; t += 64) s += C[i * ldc + t] * x[t];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int64_t t = i + 1 + lane + 64 * u;
+      if (t <= j) s += cur[u] * x[t];
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    const double xi = (((i == j) ? 1.0 : 0.0) - s) / C[i * ldc + i];
+    const double xi = (((i == j) ? 1.0 : 0.0) - s) / dcur;
     if (lane == 0) x[i] = xi;
     __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): x[i] is in LDS before the next step
     __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) cur[u] = nxt[u];
+    dcur = dnxt;
   }
   for (int64_t i = lane; i < n; i += 64) Ci[i * ldi + j] = x[i];
 }
@@ -1337,8 +1362,14 @@ int fill_f64(double *p, int64_t count, double value, hipStream_t s) {
 int trinv_upper(const double *C, int64_t n, int64_t ldc, double *Ci, int64_t ldi, hipStream_t s) {
   if (n <= 0) return BSRHT_OK;
   if (n * kTrinvWaves * sizeof(double) > 64 * 1024) return BSRHT_EUNSUPPORTED;
-  trinv_upper_kernel<<<(unsigned)((n + kTrinvWaves - 1) / kTrinvWaves), 64 * kTrinvWaves,
-                       (size_t)n * kTrinvWaves * sizeof(double), s>>>(C, n, ldc, Ci, ldi);
+  const unsigned grid = (unsigned)((n + kTrinvWaves - 1) / kTrinvWaves);
+  const size_t lds = (size_t)n * kTrinvWaves * sizeof(double);
+  if (n <= 64 * 8)
+    trinv_upper_kernel<8><<<grid, 64 * kTrinvWaves, lds, s>>>(C, n, ldc, Ci, ldi);
+  else if (n <= 64 * 16)
+    trinv_upper_kernel<16><<<grid, 64 * kTrinvWaves, lds, s>>>(C, n, ldc, Ci, ldi);
+  else
+    trinv_upper_kernel<32><<<grid, 64 * kTrinvWaves, lds, s>>>(C, n, ldc, Ci, ldi);
   BSRHT_LAUNCH_CHECK();
   return BSRHT_OK;
 }
