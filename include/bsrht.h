@@ -130,7 +130,7 @@ int bsrht_plan_info(bsrht_plan_t plan, int64_t *n, int64_t *p, int64_t *l,
 
 /*
  * Copy the plan's tables to host memory (synchronises the plan's stream).
- * R     : host int32[l]            sample indices in [0, r), draw order.
+ * R     : host int32[l]            sample indices in [0, rp), draw order.
  * Dbits : host uint32[ceil(p*rp/32)]  bit (g%32) of word g/32 is the sign
  *                                  bit of D^(i)_x for g = i*rp + x
  *                                  (1 -> -1; g = the global row when r = rp).
