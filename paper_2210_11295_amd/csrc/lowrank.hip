@@ -85,6 +85,38 @@ __global__ void add_diag_kernel(double *M, int64_t n, int64_t ld, double c) {
   if (i < n) M[i * ld + i] += c;
 }
 
+// M[i][i] += f * v[0] for a value v[0] computed on the device.
+__global__ void add_diag_dev_kernel(double *M, int64_t n, int64_t ld, const double *__restrict__ v,
+                                    double f) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) M[i * ld + i] += f * v[0];
+}
+
+// out[c] = 1 / sqrt(max(ev[e], 1e-300)), e = idx[c] (or c without idx), c < keep:
+// the scales Lam_+^{-1/2} of an eigen split.
+__global__ void inv_sqrt_kernel(const double *__restrict__ ev, const int32_t *__restrict__ idx,
+                                int64_t keep, double *__restrict__ out) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < keep) out[c] = 1.0 / sqrt(fmax(ev[idx ? idx[c] : c], 1e-300));
+}
+
+// S[i] = sqrt(S[i]) for S[i] > 0, else 0: singular values from Gram eigenvalues.
+__global__ void sqrt_clamp_kernel(double *S, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) S[i] = S[i] > 0.0 ? sqrt(S[i]) : 0.0;
+}
+
+// M[i][c] = V[i][idx[c]] * sc[c] for c < keep, 0 for keep <= c < ldm (i < rows).
+__global__ void gather_scale_cols_kernel(const double *__restrict__ V, int64_t rows, int64_t ldv,
+                                         const int32_t *__restrict__ idx,
+                                         const double *__restrict__ sc, int64_t keep,
+                                         double *__restrict__ M, int64_t ldm) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * ldm) return;
+  const int64_t i = e / ldm, c = e - i * ldm;
+  M[e] = c < keep ? V[i * ldv + idx[c]] * sc[c] : 0.0;
+}
+
 __global__ void or_info_kernel(int32_t *info, int32_t bits) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *info |= bits;
 }
@@ -99,7 +131,8 @@ __global__ void zero_i32_kernel(int32_t *p, int n) {
 // one block sums them in order and stores nu = c * sqrt(sum) (c =
 // sqrt(n) u_s) at nu[0], so the shift never leaves the device.
 constexpr int kSsqBlocks = 1024;
-__global__ void ssq_partial_kernel(const float *__restrict__ Y, int64_t n, int64_t l, int64_t ldy,
+template <typename T>
+__global__ void ssq_partial_kernel(const T *__restrict__ Y, int64_t n, int64_t l, int64_t ldy,
                                    double *__restrict__ part) {
   __shared__ double red[256];
   double acc = 0.0;
@@ -234,7 +267,8 @@ struct NysWs {
   double *Bs, *Cinv, *Mf, *lam, *Z, *gram_part, *Gz, *Mk;
   int32_t *flag;
   void *chol_state;
-  double *ssq;  // shifted variant: kSsqBlocks partial sums, then nu
+  double *ssq;  // kSsqBlocks partial sums, then nu (shifted) or ||B||_F (fallback)
+  int32_t *kidx;  // fallback: indices of the kept eigenvalues
   SvdBufs<A> fb, sv;
   void layout(A &a, const bsrht_plan_s *pl, int64_t k) {
     const int64_t l = pl->l, n = pl->n;
@@ -255,6 +289,7 @@ struct NysWs {
     flag = a.template take<int32_t>(4);
     chol_state = a.template take<char>(cholesky_state_bytes());
     ssq = a.template take<double>((size_t)kSsqBlocks + 1);
+    kidx = a.template take<int32_t>((size_t)l);
     fb.take(a, svd_pad(l), l);
     sv.take(a, svd_pad(l), k);
   }
@@ -351,10 +386,9 @@ Task rsvd_task(DevCtx &ctx, const bsrht_plan_s *plan, const float *A, int64_t m,
       for (int64_t i = 0; i < l; ++i)
         if (ev[(size_t)i] > (double)l * kU64 * ev[0] && ev[(size_t)i] > 0.0) ++keep;
       if (keep < 1) keep = 1;
-      std::vector<double> sc((size_t)keep);
-      for (int64_t i = 0; i < keep; ++i) sc[(size_t)i] = 1.0 / sqrt(ev[(size_t)i]);
-      if (co_await upload(ctx, w.qb.inv, sc.data(), sizeof(double) * (size_t)keep) != BSRHT_OK)
-        co_return BSRHT_EDEVICE;
+      inv_sqrt_kernel<<<(unsigned)((keep + 255) / 256), 256, 0, s>>>(w.qb.S, nullptr, keep,
+                                                                    w.qb.inv);
+      BSRHT_CO_LAUNCH_CHECK();
       const int64_t nce = svd_pad(l);
       BSRHT_CO_TRY(scale_cols_f64(w.qb.Vs, l, keep, keep, nce, w.qb.inv, w.Ginv, keep, s));
       GemmDesc d;
@@ -420,12 +454,8 @@ Task rsvd_task(DevCtx &ctx, const bsrht_plan_s *plan, const float *A, int64_t m,
   const int64_t nce = svd_pad(lq);
   // singular values of Z (sqrt of the Gram eigenvalues on the fallback path)
   if (pw == 0) {
-    std::vector<double> ev((size_t)lq);
-    if (co_await readback(ctx, ev.data(), w.sv.S, sizeof(double) * (size_t)lq) != BSRHT_OK)
-      co_return BSRHT_EDEVICE;
-    for (auto &x : ev) x = x > 0.0 ? sqrt(x) : 0.0;
-    if (co_await upload(ctx, w.sv.S, ev.data(), sizeof(double) * (size_t)lq) != BSRHT_OK)
-      co_return BSRHT_EDEVICE;
+    sqrt_clamp_kernel<<<(unsigned)((lq + 255) / 256), 256, 0, s>>>(w.sv.S, lq);
+    BSRHT_CO_LAUNCH_CHECK();
   }
   // 6. U = Z Vt_k St_k^{-1}, S = St_k, V = Q Vt_k
   finish_sigma_kernel<<<(unsigned)((k + 255) / 256), 256, 0, s>>>(
@@ -517,7 +547,7 @@ int nystrom_impl(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, floa
     if (n * l > kMaxGridItems) return BSRHT_EUNSUPPORTED;
     // nu = sqrt(n) u_s ||Y||_F (u_s: unit roundoff of the sketch), Y += nu Omega^T
     const double us = plan->precision == BSRHT_SPLIT_BF16 ? 0x1p-17 : kU32;
-    ssq_partial_kernel<<<kSsqBlocks, 256, 0, s>>>(w.Y, n, l, l, w.ssq);
+    ssq_partial_kernel<float><<<kSsqBlocks, 256, 0, s>>>(w.Y, n, l, l, w.ssq);
     shift_of_kernel<<<1, 64, 0, s>>>(w.ssq, sqrt((double)n) * us, w.ssq + kSsqBlocks);
     add_shift_kernel<<<(unsigned)((n * l + 255) / 256), 256, 0, s>>>(
         w.Y, n, l, l, plan->R, plan->Dbits, plan->Dtbits, plan->dt_words, plan->r, plan->rp,
@@ -552,23 +582,18 @@ int nystrom_impl(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, floa
     // none gives a factor, the Jacobi runs on B with rotation accumulation.
     // The signed eigenvalues are taken from B itself below either way.
     bool pre = false;
-    {
-      std::vector<double> Bh((size_t)(l * l));
-      if (copy_to_host(Bh.data(), w.Bs, sizeof(double) * Bh.size(), s) != BSRHT_OK)
-        return BSRHT_EDEVICE;
-      double fro = 0.0;
-      for (double x : Bh) fro += x * x;
-      fro = sqrt(fro);
-      for (int attempt = 0; attempt < 3 && !pre; ++attempt) {
-        const double c = fro * kU32 * (double)(1 << (4 * attempt));
-        BSRHT_TRY(scale_cols_f64(w.Bs, l, l, l, l, nullptr, w.Mf, l, s));
-        add_diag_kernel<<<(unsigned)((l + 255) / 256), 256, 0, s>>>(w.Mf, l, l, c);
-        BSRHT_LAUNCH_CHECK();
-        BSRHT_TRY(cholesky_upper(w.Mf, l, l, (double)l * kU64, w.flag + 2, w.chol_state, s));
-        int32_t hc = 0;
-        BSRHT_TRY(read_i32(w.flag + 2, s, &hc));
-        pre = hc == 0;
-      }
+    ssq_partial_kernel<double><<<kSsqBlocks, 256, 0, s>>>(w.Bs, l, l, l, w.ssq);
+    shift_of_kernel<<<1, 64, 0, s>>>(w.ssq, 1.0, w.ssq + kSsqBlocks);  // ||B||_F
+    BSRHT_LAUNCH_CHECK();
+    for (int attempt = 0; attempt < 3 && !pre; ++attempt) {
+      BSRHT_TRY(scale_cols_f64(w.Bs, l, l, l, l, nullptr, w.Mf, l, s));
+      add_diag_dev_kernel<<<(unsigned)((l + 255) / 256), 256, 0, s>>>(
+          w.Mf, l, l, w.ssq + kSsqBlocks, kU32 * (double)(1 << (4 * attempt)));
+      BSRHT_LAUNCH_CHECK();
+      BSRHT_TRY(cholesky_upper(w.Mf, l, l, (double)l * kU64, w.flag + 2, w.chol_state, s));
+      int32_t hc = 0;
+      BSRHT_TRY(read_i32(w.flag + 2, s, &hc));
+      pre = hc == 0;
     }
     if (pre)
       BSRHT_TRY(small_svd(w.fb, w.Mf, l, l, false, info, s));
@@ -582,29 +607,24 @@ int nystrom_impl(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, floa
       return BSRHT_EDEVICE;
     double lmax = 0.0;
     for (double x : lam) lmax = std::max(lmax, x);
-    // kept columns in Jacobi order (descending |lambda|)
-    std::vector<int> idx;
-    std::vector<double> sc;
+    // kept columns in Jacobi order (descending |lambda|): the host decides
+    // which (it sizes the products below); the arithmetic stays on the device
+    std::vector<int32_t> idx;
     for (int64_t i = 0; i < l; ++i)
-      if (lam[(size_t)i] > (double)l * kU64 * lmax && lam[(size_t)i] > 0.0) {
-        idx.push_back((int)i);
-        sc.push_back(1.0 / sqrt(lam[(size_t)i]));
-      }
+      if (lam[(size_t)i] > (double)l * kU64 * lmax && lam[(size_t)i] > 0.0)
+        idx.push_back((int32_t)i);
     if (idx.empty()) return BSRHT_EDEVICE;
     lz = (int64_t)idx.size();
     // Z (n x lz) and Mf get a leading dimension rounded up to 4 elements,
     // which the large-tile GEMM kernel needs for its 16-byte loads.
     ldz = (lz + 3) & ~int64_t(3);
     // Mf = V_+ Lam_+^{-1/2} (l x lz, leading dimension ldz, zero padded)
-    std::vector<double> Vh((size_t)(l * nce));
-    if (copy_to_host(Vh.data(), w.fb.Vs, sizeof(double) * Vh.size(), s) != BSRHT_OK)
+    if (copy_to_device(w.kidx, idx.data(), sizeof(int32_t) * (size_t)lz, s) != BSRHT_OK)
       return BSRHT_EDEVICE;
-    std::vector<double> Mh((size_t)(l * ldz), 0.0);
-    for (int64_t i = 0; i < l; ++i)
-      for (int64_t c = 0; c < lz; ++c)
-        Mh[(size_t)(i * ldz + c)] = Vh[(size_t)(i * nce + idx[(size_t)c])] * sc[(size_t)c];
-    if (copy_to_device(w.Mf, Mh.data(), sizeof(double) * Mh.size(), s) != BSRHT_OK)
-      return BSRHT_EDEVICE;
+    inv_sqrt_kernel<<<(unsigned)((lz + 255) / 256), 256, 0, s>>>(w.lam, w.kidx, lz, w.fb.inv);
+    gather_scale_cols_kernel<<<(unsigned)((l * ldz + 255) / 256), 256, 0, s>>>(
+        w.fb.Vs, l, nce, w.kidx, w.fb.inv, lz, w.Mf, ldz);
+    BSRHT_LAUNCH_CHECK();
     GemmDesc d;
     d.M = n; d.N = lz; d.K = l;
     d.sai = l; d.sak = 1;
@@ -625,12 +645,8 @@ int nystrom_impl(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, floa
   const double *Rsrc = hz == 0 ? w.Gz : w.Bs;
   BSRHT_TRY(small_svd(w.sv, Rsrc, lz, lz, hz != 0, info, s));
   if (hz != 0) {
-    std::vector<double> ev((size_t)lz);
-    if (copy_to_host(ev.data(), w.sv.S, sizeof(double) * (size_t)lz, s) != BSRHT_OK)
-      return BSRHT_EDEVICE;
-    for (auto &x : ev) x = x > 0.0 ? sqrt(x) : 0.0;
-    if (copy_to_device(w.sv.S, ev.data(), sizeof(double) * (size_t)lz, s) != BSRHT_OK)
-      return BSRHT_EDEVICE;
+    sqrt_clamp_kernel<<<(unsigned)((lz + 255) / 256), 256, 0, s>>>(w.sv.S, lz);
+    BSRHT_LAUNCH_CHECK();
   }
   // 6. U = Z Vt_k St_k^{-1}; lambda = St_k^2
   finish_sigma_kernel<<<(unsigned)((k + 255) / 256), 256, 0, s>>>(
@@ -774,10 +790,8 @@ int inv_factor(double *G, int64_t n, double tol, double *F, int64_t *nf, bool *f
   for (int64_t i = 0; i < n; ++i)
     if (ev[(size_t)i] > (double)n * kU64 * ev[0] && ev[(size_t)i] > 0.0) ++keep;
   if (keep < 1) keep = 1;
-  std::vector<double> sc((size_t)keep);
-  for (int64_t i = 0; i < keep; ++i) sc[(size_t)i] = 1.0 / sqrt(std::max(ev[(size_t)i], 1e-300));
-  if (copy_to_device(w.qb.inv, sc.data(), sizeof(double) * (size_t)keep, s) != BSRHT_OK)
-    return BSRHT_EDEVICE;
+  inv_sqrt_kernel<<<(unsigned)((keep + 255) / 256), 256, 0, s>>>(w.qb.S, nullptr, keep, w.qb.inv);
+  BSRHT_LAUNCH_CHECK();
   BSRHT_TRY(scale_cols_f64(w.qb.Vs, n, keep, keep, svd_pad(n), w.qb.inv, F, keep, s));
   *nf = keep;
   return BSRHT_OK;
