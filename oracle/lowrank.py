@@ -74,6 +74,21 @@ def _cholesky_upper_or_none(B, tau):
     return L.T
 
 
+def _nystrom_z(Y, B, l, u):
+    """Steps 2-3 of Algorithm 2 from Y = A Omega^T and B = Omega Y: returns
+    (Z, fallback_taken) with Z Z^T = Y B^+ Y^T (Remark 3.1 when needed)."""
+    B = 0.5 * (B + B.T)                        # symmetric in exact arithmetic
+    tau = l * u
+    C = _cholesky_upper_or_none(B, tau)        # step 2
+    if C is not None:
+        Z = sla.solve_triangular(C, Y.T, trans="T", lower=False).T  # step 3
+        return Z, False
+    lam, V = np.linalg.eigh(B)                 # Remark 3.1 square root
+    keep = lam > tau * lam.max()
+    Z = Y @ (V[:, keep] / np.sqrt(lam[keep]))
+    return Z, True
+
+
 def nystrom_factor(plan, A, u=U_FP64):
     """Steps 1-3 of Algorithm 2: returns (Y, Z, fallback_taken).
 
@@ -83,26 +98,30 @@ def nystrom_factor(plan, A, u=U_FP64):
     A = np.asarray(A, dtype=np.float64)
     Y = sketch(plan, A.T).T                    # step 1: Y = A Omega^T
     B = sketch(plan, Y)                        # Omega Y
-    B = 0.5 * (B + B.T)
-    tau = plan.l * u
-    C = _cholesky_upper_or_none(B, tau)        # step 2
-    if C is not None:
-        Z = sla.solve_triangular(C, Y.T, trans="T", lower=False).T  # step 3
-        return Y, Z, False
-    lam, V = np.linalg.eigh(B)                 # Remark 3.1 square root
-    keep = lam > tau * lam.max()
-    Z = Y @ (V[:, keep] / np.sqrt(lam[keep]))
-    return Y, Z, True
+    Z, fb = _nystrom_z(Y, B, plan.l, u)
+    return Y, Z, fb
 
 
-def nystrom(plan, A, k, u=U_FP64):
-    """Algorithm 2; returns (U_hat n x k', lam k', fallback_taken)."""
-    _, Z, fb = nystrom_factor(plan, A, u)
+def nystrom_from_sketch(Y, B, k, l, u=U_FP64):
+    """Steps 2-6 of Algorithm 2 given the sketches Y = A Omega^T (n x l) and
+    B = Omega Y (l x l), however they were computed; returns
+    (U_hat n x k', lam k', fallback_taken)."""
+    Y = np.asarray(Y, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    Z, fb = _nystrom_z(Y, B, l, u)
     R = np.linalg.qr(Z, mode="r")              # step 4
     _, St, VtT = np.linalg.svd(R)              # step 5: R = Ut St Vt^T
     kk = min(int(k), St.shape[0])
     Uh = Z @ (VtT.T[:, :kk] / St[:kk])         # step 6 (read with Z, see above)
     return Uh, St[:kk] ** 2, fb
+
+
+def nystrom(plan, A, k, u=U_FP64):
+    """Algorithm 2; returns (U_hat n x k', lam k', fallback_taken)."""
+    A = np.asarray(A, dtype=np.float64)
+    Y = sketch(plan, A.T).T                    # step 1: Y = A Omega^T
+    B = sketch(plan, Y)                        # Omega Y
+    return nystrom_from_sketch(Y, B, k, plan.l, u)
 
 
 def nystrom_shifted(plan, A, k, u=U_FP64):

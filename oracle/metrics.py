@@ -49,6 +49,29 @@ def trace_error(A, U, lam):
     return num / den
 
 
+def trace_error_structured(X, s, U, lam, shift=0.0):
+    """||A - U diag(lam) U^T||_* / ||A||_* for A = X diag(s) X^T + shift I, with
+    X (n x d) orthonormal, s >= 0 and shift >= 0, without forming A.
+
+    E = A - U diag(lam) U^T maps every vector orthogonal to span[X, U] to
+    shift times itself.  With B (n x q) any orthonormal basis containing
+    span[X, U], the eigenvalues of E are those of B^T E B and shift with
+    multiplicity n - q; ||A||_* = sum(s) + n shift.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    U = np.asarray(U, dtype=np.float64)
+    s = np.asarray(s, dtype=np.float64)
+    lam = np.asarray(lam, dtype=np.float64)
+    n = X.shape[0]
+    B, _ = np.linalg.qr(np.concatenate([X, U], axis=1), mode="reduced")
+    XtB = X.T @ B
+    UtB = U.T @ B
+    E = (XtB.T * s) @ XtB - (UtB.T * lam) @ UtB + shift * np.eye(B.shape[1])
+    ev = np.linalg.eigvalsh(0.5 * (E + E.T))
+    num = float(np.sum(np.abs(ev))) + shift * (n - B.shape[1])
+    return num / (float(np.sum(s)) + n * shift)
+
+
 def optimal_fro_error(A, k):
     """||A - [[A]]_k||_F / ||A||_F from the singular values (section 3)."""
     s = np.linalg.svd(np.asarray(A, dtype=np.float64), compute_uv=False)

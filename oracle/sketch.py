@@ -96,6 +96,30 @@ def sketch(plan, A):
     return Y / np.sqrt(plan.l)
 
 
+def sketch_parallel(plan, A, workers, col_chunk=256):
+    """sketch(plan, A) with its per-block terms evaluated concurrently.
+
+    The terms block_partial(plan, A[:, c0:c1], i) are computed on a pool of
+    `workers` threads (the transform acts on each column separately, so a
+    column slice gives exactly those columns of the term); each column slice
+    then sums its blocks in order i = 0..p-1 and is scaled by 1/sqrt(l) once,
+    as sketch() does, so the result is bitwise that of sketch()."""
+    import concurrent.futures as cf
+
+    A = np.asarray(A)
+    if A.ndim != 2 or A.shape[0] != plan.n:
+        raise ValueError("A must have n rows")
+    m = A.shape[1]
+    slices = [(c0, min(m, c0 + col_chunk)) for c0 in range(0, m, col_chunk)] or [(0, 0)]
+    tasks = [(i, c0, c1) for (c0, c1) in slices for i in range(plan.p)]
+    with cf.ThreadPoolExecutor(max(1, int(workers))) as ex:
+        parts = list(ex.map(lambda t: block_partial(plan, A[:, t[1]:t[2]], t[0]), tasks))
+    Y = np.zeros((plan.l, m), dtype=np.float64)
+    for (i, c0, c1), part in zip(tasks, parts):
+        Y[:, c0:c1] += part                   # blocks of a slice arrive in order
+    return Y / np.sqrt(plan.l)
+
+
 def sketch_entry(plan, column, j):
     """One entry Y[j, c] from a single column of A (length n), eq. (2.3).
 

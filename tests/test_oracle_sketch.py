@@ -148,6 +148,17 @@ def test_sketch_entry_matches_sketch():
         assert abs(sketch.sketch_entry(plan, A[:, c], j) - Y[j, c]) < 1e-12 * np.abs(Y).max()
 
 
+@pytest.mark.parametrize("n,p,l,m,chunk", [(4096, 8, 64, 37, 8), (2048, 1, 40, 5, 256),
+                                           (3000, 6, 24, 19, 4)])
+def test_sketch_parallel_is_bitwise_sketch(n, p, l, m, chunk):
+    """The block-parallel evaluation (threads over blocks and column slices)
+    gives bitwise the sequential oracle sketch (same terms, same block order)."""
+    plan = rng.Plan(n, p, l, 3)
+    A = np.random.default_rng(6).standard_normal((n, m)).astype(np.float32)
+    assert np.array_equal(sketch.sketch_parallel(plan, A, workers=4, col_chunk=chunk),
+                          sketch.sketch(plan, A))
+
+
 PADDED_CASES = [
     # n, p, l, mode  -- block sizes r that are not powers of two (partial SRHT)
     (300, 3, 20, rng.WITH_REPLACEMENT),      # r = 100 -> 128
