@@ -111,41 +111,3 @@ def test_split_bf16_agrees_with_fp32_kernel():
     Yf = bs.bsrht_apply(bs.Plan(n, p, l, 9, device=dev), A)
     torch.cuda.synchronize()
     assert metrics.rel_fro(to64(Yb), to64(Yf)) <= TOL_BF16
-
-
-def test_split_bf16_full_size_sampled_entries():
-    """The split-BF16 sketch workload (A 2^20 x 1024 FP32, p = 16, l = 512):
-    sampled outputs against the oracle's entry-by-entry evaluation, and the
-    first block A_sub = A[0:2^16] in full through the p = 1 subsample plan."""
-    dev = device()
-    cfg = workloads.CONFIGS["c3_split_bf16"]
-    n, m, p, l, seed = cfg["n"], cfg["m"], cfg["p"], cfg["l"], cfg["seed"]
-    say("full size split-bf16", n, m, p, l)
-    A = workloads.lowrank_tall(n, m, cfg["spectrum"], seed, device=dev)
-    plan = bs.Plan(n, p, l, seed, precision=bs.SPLIT_BF16, device=dev)
-    Y = bs.bsrht_apply(plan, A)
-    torch.cuda.synchronize()
-    op = rng.Plan(n, p, l, seed)
-    rs = np.random.default_rng(1)
-    cols = rs.choice(m, 6, replace=False)
-    rows = rs.choice(l, 8, replace=False)
-    Yh = to64(Y)
-    diff = 0.0
-    ref = 0.0
-    for c in cols:
-        col = to64(A[:, int(c)])
-        for j in rows:
-            y = sketch.sketch_entry(op, col, int(j))
-            diff += (Yh[j, c] - y) ** 2
-            ref += y * y
-    err = np.sqrt(diff / ref)
-    say("  sampled rel err", err)
-    assert err <= TOL_BF16
-    r = n // p
-    sub = bs.Plan(r, 1, l, seed, precision=bs.SPLIT_BF16, device=dev)
-    Ys = bs.bsrht_apply(sub, A[:r, :128].contiguous())
-    torch.cuda.synchronize()
-    Ys_ref = sketch.sketch(rng.Plan(r, 1, l, seed), to64(A[:r, :128]))
-    err2 = metrics.rel_fro(to64(Ys), Ys_ref)
-    say("  subsample rel err", err2)
-    assert err2 <= TOL_BF16

@@ -10,7 +10,8 @@ Recipes (seeded; torch generators, float64 formation, one rounding to float32)
       X ~ N(0,1)^{n x m} / sqrt(n), W Haar-random m x m orthogonal
       (QR of a Gaussian with the signs of diag(R) folded in, Mezzadri 2007),
       s_j = spectrum(j), j = 1..m.
-  spd(n, d, spectrum, seed):  A = X diag(s) X^T, X = orth(N(0,1)^{n x d}).
+  spd(n, d, spectrum, seed, shift=0):  A = X diag(s) X^T + shift I,
+      X = orth(N(0,1)^{n x d}).
   gaussian_cols(n, m, spectrum, seed):  A = X diag(s) with X ~ N(0,1)
       (the serving payload; W = I).
   gaussian_rows(m, n, spectrum, seed):  A = diag(s) X with X ~ N(0,1)

@@ -6,6 +6,7 @@ import numpy as np
 import torch
 
 SPECTRA = {
+    "inv": lambda j: j ** -1.0,             # s_j = j^-1
     "inv_sq": lambda j: j ** -2.0,          # s_j = j^-2
     "exp64": lambda j: torch.exp(-j / 64.0),  # s_j = exp(-j/64)
     "pow1.5": lambda j: j ** -1.5,           # s_j = j^-1.5
@@ -66,13 +67,15 @@ def lowrank_tall(n, m, spectrum, seed, device="cpu", row_chunk=1 << 16):
     return A
 
 
-def spd(n, d, spectrum, seed, device="cpu", return_factors=False):
-    """A = X diag(s) X^T (n x n float32), X = orth(Gaussian n x d)."""
+def spd(n, d, spectrum, seed, device="cpu", return_factors=False, shift=0.0):
+    """A = X diag(s) X^T + shift I (n x n float32), X = orth(Gaussian n x d)."""
     g = _gen(seed, device)
     G = torch.randn(n, d, generator=g, dtype=torch.float64, device=device)
     X, _ = torch.linalg.qr(G)
     s = _spectrum(spectrum, d, device)
     A = (X * s[None, :]) @ X.T
+    if shift:
+        A.diagonal().add_(float(shift))
     A = (0.5 * (A + A.T)).to(torch.float32)  # exactly symmetric after rounding
     if return_factors:
         return A, X, s
