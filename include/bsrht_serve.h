@@ -1,10 +1,11 @@
 /*
- * bsrht_serve.h -- serving runtime for block SRHT sketch and randomized SVD
- * jobs on one GPU (continuous batching of independent jobs).
+ * bsrht_serve.h -- serving runtime for block SRHT sketch, randomized SVD and
+ * Nystrom jobs on one GPU (continuous batching of independent jobs).
  *
  * Each job is one call of bsrht.h: BSRHT_JOB_SKETCH is bsrht_apply (the
  * sketch Y = Omega A of section 2, eq. (2.4)), BSRHT_JOB_RSVD is rsvd
- * (section 3.1, Algorithm 1, which sketches first).  The server owns no
+ * (section 3.1, Algorithm 1, which sketches first), BSRHT_JOB_NYSTROM is
+ * nystrom (section 3.2, Algorithm 2 with Remark 3.1's fallback).  The server owns no
  * device memory of its own: the caller hands it one device arena at
  * creation, and every byte a job needs beyond its inputs and outputs (the
  * call's workspace and, on a plan-cache miss, the plan's sign/index tables)
@@ -54,8 +55,9 @@ extern "C" {
 
 typedef struct bsrht_server_s *bsrht_server_t;
 
-#define BSRHT_JOB_SKETCH 0 /* Y = Omega A            (bsrht_apply) */
-#define BSRHT_JOB_RSVD 1   /* sketch + Algorithm 1   (rsvd)        */
+#define BSRHT_JOB_SKETCH 0  /* Y = Omega A            (bsrht_apply) */
+#define BSRHT_JOB_RSVD 1    /* sketch + Algorithm 1   (rsvd)        */
+#define BSRHT_JOB_NYSTROM 2 /* sketch + Algorithm 2   (nystrom)     */
 
 /* One job.  Device pointers are caller-owned and must stay valid (inputs
  * unchanged, outputs untouched) from submission until the job's result has
@@ -63,9 +65,9 @@ typedef struct bsrht_server_s *bsrht_server_t;
  * precision) exactly as for bsrht_plan. */
 typedef struct {
   int64_t id;        /* caller's tag, returned with the result */
-  int kind;          /* BSRHT_JOB_SKETCH or BSRHT_JOB_RSVD */
-  int64_t n, m, p, l;
-  int64_t k;         /* RSVD target rank (ignored for SKETCH) */
+  int kind;          /* BSRHT_JOB_SKETCH, BSRHT_JOB_RSVD or BSRHT_JOB_NYSTROM */
+  int64_t n, m, p, l;  /* NYSTROM: m == n (A is n x n, symmetric PSD) */
+  int64_t k;         /* RSVD / NYSTROM target rank (ignored for SKETCH) */
   uint64_t seed;
   int sampling, precision;
   const float *A;    /* device, n x m, leading dimension lda */
@@ -73,9 +75,9 @@ typedef struct {
   float *Y;          /* SKETCH: device l x m, leading dimension ldy */
   int64_t ldy;
   float *U;          /* RSVD: device outputs as for rsvd(): U n x k, */
-  double *S;         /*   S k, V m x k (row-major), info int32       */
-  float *V;
-  int32_t *info;
+  double *S;         /*   S k, V m x k (row-major), info int32;      */
+  float *V;          /* NYSTROM: as for nystrom(): U n x k, S = lambda */
+  int32_t *info;     /*   (k, descending), info; V is not used       */
 } bsrht_job_t;
 
 typedef struct {

@@ -520,31 +520,30 @@ namespace bsrht {
 
 // Algorithm 2; with `shifted`, on A + nu I (the sketch Y + nu Omega^T) with nu
 // subtracted from the eigenvalues at the end.
-int nystrom_impl(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
-                 double *lambda, int32_t *info, void *ws, size_t ws_bytes, void *stream,
-                 bool shifted) {
-  if (!plan || !A || !U || !lambda || !info || k < 1 || lda < plan->n) return BSRHT_EINVAL;
-  if (ws_bytes < nystrom_workspace(plan, k) || !ws) return BSRHT_ENOMEM;
-  hipStream_t s = (hipStream_t)stream;
+// The argument checks are the callers' (nystrom, nystrom_shifted and the
+// server's job admission).
+Task nystrom_task(DevCtx &ctx, const bsrht_plan_s *plan, const float *A, int64_t lda, int64_t k,
+                  float *U, double *lambda, int32_t *info, void *ws, size_t ws_bytes,
+                  bool shifted) {
+  hipStream_t s = ctx.s;
   const int64_t n = plan->n, l = plan->l;
-  if (svd_pad(l) > 4096) return BSRHT_EUNSUPPORTED;
+  if (svd_pad(l) > 4096) co_return BSRHT_EUNSUPPORTED;
   Carve cv(ws, ws_bytes);
   NysWs<Carve> w;
   w.layout(cv, plan, k);
-  if (cv.overflow) return BSRHT_ENOMEM;
-  int st;
+  if (cv.overflow) co_return BSRHT_ENOMEM;
   zero_i32_kernel<<<1, 64, 0, s>>>(info, 1);
-  BSRHT_LAUNCH_CHECK();
+  BSRHT_CO_LAUNCH_CHECK();
   auto sketch = [&](const float *X, int64_t mm, int64_t ldx, float *Yo) {
     if (plan->precision == BSRHT_SPLIT_BF16)
       return apply_split_bf16(plan, X, mm, ldx, Yo, mm, w.apply_ws, w.apply_bytes, s);
     return apply_fp32(plan, X, mm, ldx, Yo, mm, w.apply_ws, w.apply_bytes, s);
   };
   // 1. Y = A Omega^T = (Omega A)^T (A symmetric)
-  BSRHT_TRY(sketch(A, n, lda, w.W));
-  BSRHT_TRY(transpose_f32(w.W, l, n, n, w.Y, l, s));
+  BSRHT_CO_TRY(sketch(A, n, lda, w.W));
+  BSRHT_CO_TRY(transpose_f32(w.W, l, n, n, w.Y, l, s));
   if (shifted) {
-    if (n * l > kMaxGridItems) return BSRHT_EUNSUPPORTED;
+    if (n * l > kMaxGridItems) co_return BSRHT_EUNSUPPORTED;
     // nu = sqrt(n) u_s ||Y||_F (u_s: unit roundoff of the sketch), Y += nu Omega^T
     const double us = plan->precision == BSRHT_SPLIT_BF16 ? 0x1p-17 : kU32;
     ssq_partial_kernel<float><<<kSsqBlocks, 256, 0, s>>>(w.Y, n, l, l, w.ssq);
@@ -552,26 +551,26 @@ int nystrom_impl(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, floa
     add_shift_kernel<<<(unsigned)((n * l + 255) / 256), 256, 0, s>>>(
         w.Y, n, l, l, plan->R, plan->Dbits, plan->Dtbits, plan->dt_words, plan->r, plan->rp,
         w.ssq + kSsqBlocks, (float)(1.0 / sqrt((double)l)));
-    BSRHT_LAUNCH_CHECK();
+    BSRHT_CO_LAUNCH_CHECK();
   }
   // 2. Cholesky factor of Omega Y (symmetrised)
-  BSRHT_TRY(sketch(w.Y, l, l, w.B));
+  BSRHT_CO_TRY(sketch(w.Y, l, l, w.B));
   sym_f64_kernel<<<(unsigned)((l * l + 255) / 256), 256, 0, s>>>(w.B, l, l, w.Bs, l);
-  BSRHT_LAUNCH_CHECK();
-  BSRHT_TRY(scale_cols_f64(w.Bs, l, l, l, l, nullptr, w.Mf, l, s));
-  BSRHT_TRY(cholesky_upper(w.Mf, l, l, (double)l * kU64, w.flag, w.chol_state, s));
+  BSRHT_CO_LAUNCH_CHECK();
+  BSRHT_CO_TRY(scale_cols_f64(w.Bs, l, l, l, l, nullptr, w.Mf, l, s));
+  BSRHT_CO_TRY(cholesky_upper(w.Mf, l, l, (double)l * kU64, w.flag, w.chol_state, s));
   int32_t hf = 0;
-  BSRHT_TRY(read_i32(w.flag, s, &hf));
+  BSRHT_CO_TRY(co_await readback(ctx, &hf, w.flag, sizeof(hf)));
   int64_t lz = l, ldz = l;  // columns of Z and its leading dimension
   if (hf == 0) {
     // 3. Z = Y C^{-1}
-    BSRHT_TRY(trinv_upper(w.Mf, l, l, w.Cinv, l, s));
+    BSRHT_CO_TRY(trinv_upper(w.Mf, l, l, w.Cinv, l, s));
     GemmDesc d;
     d.M = n; d.N = l; d.K = l;
     d.sai = l; d.sak = 1;
     d.sbk = l; d.sbj = 1;
     d.ldc = l;
-    BSRHT_TRY(gemm_f32f64_f64(d, w.Y, w.Cinv, w.Z, s));
+    BSRHT_CO_TRY(gemm_f32f64_f64(d, w.Y, w.Cinv, w.Z, s));
   } else {
     // Remark 3.1: B = V Lam V^T, keep Lam_i > l u Lam_max, Z = Y V_+ Lam_+^{-1/2}.
     // The eigenvectors come from a preconditioned problem when possible: for
@@ -584,27 +583,27 @@ int nystrom_impl(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, floa
     bool pre = false;
     ssq_partial_kernel<double><<<kSsqBlocks, 256, 0, s>>>(w.Bs, l, l, l, w.ssq);
     shift_of_kernel<<<1, 64, 0, s>>>(w.ssq, 1.0, w.ssq + kSsqBlocks);  // ||B||_F
-    BSRHT_LAUNCH_CHECK();
+    BSRHT_CO_LAUNCH_CHECK();
     for (int attempt = 0; attempt < 3 && !pre; ++attempt) {
-      BSRHT_TRY(scale_cols_f64(w.Bs, l, l, l, l, nullptr, w.Mf, l, s));
+      BSRHT_CO_TRY(scale_cols_f64(w.Bs, l, l, l, l, nullptr, w.Mf, l, s));
       add_diag_dev_kernel<<<(unsigned)((l + 255) / 256), 256, 0, s>>>(
           w.Mf, l, l, w.ssq + kSsqBlocks, kU32 * (double)(1 << (4 * attempt)));
-      BSRHT_LAUNCH_CHECK();
-      BSRHT_TRY(cholesky_upper(w.Mf, l, l, (double)l * kU64, w.flag + 2, w.chol_state, s));
+      BSRHT_CO_LAUNCH_CHECK();
+      BSRHT_CO_TRY(cholesky_upper(w.Mf, l, l, (double)l * kU64, w.flag + 2, w.chol_state, s));
       int32_t hc = 0;
-      BSRHT_TRY(read_i32(w.flag + 2, s, &hc));
+      BSRHT_CO_TRY(co_await readback(ctx, &hc, w.flag + 2, sizeof(hc)));
       pre = hc == 0;
     }
     if (pre)
-      BSRHT_TRY(small_svd(w.fb, w.Mf, l, l, false, info, s));
+      BSRHT_CO_TRY(co_await small_svd_task(ctx, w.fb, w.Mf, l, l, false, info));
     else
-      BSRHT_TRY(small_svd(w.fb, w.Bs, l, l, true, info, s));
+      BSRHT_CO_TRY(co_await small_svd_task(ctx, w.fb, w.Bs, l, l, true, info));
     const int64_t nce = svd_pad(l);
     rayleigh_kernel<<<(unsigned)l, 256, 0, s>>>(w.Bs, w.fb.Vs, l, l, nce, w.lam);
-    BSRHT_LAUNCH_CHECK();
+    BSRHT_CO_LAUNCH_CHECK();
     std::vector<double> lam((size_t)l);
-    if (copy_to_host(lam.data(), w.lam, sizeof(double) * (size_t)l, s) != BSRHT_OK)
-      return BSRHT_EDEVICE;
+    if (co_await readback(ctx, lam.data(), w.lam, sizeof(double) * (size_t)l) != BSRHT_OK)
+      co_return BSRHT_EDEVICE;
     double lmax = 0.0;
     for (double x : lam) lmax = std::max(lmax, x);
     // kept columns in Jacobi order (descending |lambda|): the host decides
@@ -613,73 +612,83 @@ int nystrom_impl(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, floa
     for (int64_t i = 0; i < l; ++i)
       if (lam[(size_t)i] > (double)l * kU64 * lmax && lam[(size_t)i] > 0.0)
         idx.push_back((int32_t)i);
-    if (idx.empty()) return BSRHT_EDEVICE;
+    if (idx.empty()) co_return BSRHT_EDEVICE;
     lz = (int64_t)idx.size();
     // Z (n x lz) and Mf get a leading dimension rounded up to 4 elements,
     // which the large-tile GEMM kernel needs for its 16-byte loads.
     ldz = (lz + 3) & ~int64_t(3);
     // Mf = V_+ Lam_+^{-1/2} (l x lz, leading dimension ldz, zero padded)
-    if (copy_to_device(w.kidx, idx.data(), sizeof(int32_t) * (size_t)lz, s) != BSRHT_OK)
-      return BSRHT_EDEVICE;
+    if (co_await upload(ctx, w.kidx, idx.data(), sizeof(int32_t) * (size_t)lz) != BSRHT_OK)
+      co_return BSRHT_EDEVICE;
     inv_sqrt_kernel<<<(unsigned)((lz + 255) / 256), 256, 0, s>>>(w.lam, w.kidx, lz, w.fb.inv);
     gather_scale_cols_kernel<<<(unsigned)((l * ldz + 255) / 256), 256, 0, s>>>(
         w.fb.Vs, l, nce, w.kidx, w.fb.inv, lz, w.Mf, ldz);
-    BSRHT_LAUNCH_CHECK();
+    BSRHT_CO_LAUNCH_CHECK();
     GemmDesc d;
     d.M = n; d.N = lz; d.K = l;
     d.sai = l; d.sak = 1;
     d.sbk = ldz; d.sbj = 1;
     d.ldc = ldz;
-    BSRHT_TRY(gemm_f32f64_f64(d, w.Y, w.Mf, w.Z, s));
+    BSRHT_CO_TRY(gemm_f32f64_f64(d, w.Y, w.Mf, w.Z, s));
     or_info_kernel<<<1, 1, 0, s>>>(info, BSRHT_INFO_CHOL_FALLBACK);
-    BSRHT_LAUNCH_CHECK();
+    BSRHT_CO_LAUNCH_CHECK();
   }
   // 4. R-factor of Z: Gz = Z^T Z = R^T R
   const int gsz = gram_splits(n, lz);
-  BSRHT_TRY(gram_f64(w.Z, n, lz, ldz, 1, w.Gz, lz, w.gram_part, gsz, s));
-  BSRHT_TRY(scale_cols_f64(w.Gz, lz, lz, lz, lz, nullptr, w.Bs, lz, s));
-  BSRHT_TRY(cholesky_upper(w.Gz, lz, lz, 1e-15 * (double)lz, w.flag + 1, w.chol_state, s));
+  BSRHT_CO_TRY(gram_f64(w.Z, n, lz, ldz, 1, w.Gz, lz, w.gram_part, gsz, s));
+  BSRHT_CO_TRY(scale_cols_f64(w.Gz, lz, lz, lz, lz, nullptr, w.Bs, lz, s));
+  BSRHT_CO_TRY(cholesky_upper(w.Gz, lz, lz, 1e-15 * (double)lz, w.flag + 1, w.chol_state, s));
   int32_t hz = 0;
-  BSRHT_TRY(read_i32(w.flag + 1, s, &hz));
+  BSRHT_CO_TRY(co_await readback(ctx, &hz, w.flag + 1, sizeof(hz)));
   // 5. SVD of R (or the eigen decomposition of Z^T Z when R is singular)
   const double *Rsrc = hz == 0 ? w.Gz : w.Bs;
-  BSRHT_TRY(small_svd(w.sv, Rsrc, lz, lz, hz != 0, info, s));
+  BSRHT_CO_TRY(co_await small_svd_task(ctx, w.sv, Rsrc, lz, lz, hz != 0, info));
   if (hz != 0) {
     sqrt_clamp_kernel<<<(unsigned)((lz + 255) / 256), 256, 0, s>>>(w.sv.S, lz);
-    BSRHT_LAUNCH_CHECK();
+    BSRHT_CO_LAUNCH_CHECK();
   }
   // 6. U = Z Vt_k St_k^{-1}; lambda = St_k^2
   finish_sigma_kernel<<<(unsigned)((k + 255) / 256), 256, 0, s>>>(
       w.sv.S, lz, k, sqrt((double)lz * kU64), 2, w.sv.inv, lambda, info);
-  BSRHT_LAUNCH_CHECK();
+  BSRHT_CO_LAUNCH_CHECK();
   const int64_t keep = std::min(k, lz);
   const int64_t nce = svd_pad(lz);
-  BSRHT_TRY(scale_cols_f64(w.sv.Vs, lz, keep, k, nce, w.sv.inv, w.Mk, k, s));
+  BSRHT_CO_TRY(scale_cols_f64(w.sv.Vs, lz, keep, k, nce, w.sv.inv, w.Mk, k, s));
   GemmDesc d;
   d.M = n; d.N = k; d.K = lz;
   d.sai = ldz; d.sak = 1;
   d.sbk = k; d.sbj = 1;
   d.ldc = k;
-  BSRHT_TRY(gemm_f64f64_f32(d, w.Z, w.Mk, U, s));
+  BSRHT_CO_TRY(gemm_f64f64_f32(d, w.Z, w.Mk, U, s));
   if (shifted) {
     unshift_kernel<<<(unsigned)((k + 255) / 256), 256, 0, s>>>(lambda, k, w.ssq + kSsqBlocks);
-    BSRHT_LAUNCH_CHECK();
+    BSRHT_CO_LAUNCH_CHECK();
   }
-  return BSRHT_OK;
+  co_return BSRHT_OK;
 }
 
 }  // namespace bsrht
 
 extern "C" {
 
+static int nystrom_blocking(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
+                            double *lambda, int32_t *info, void *ws, size_t ws_bytes,
+                            void *stream, bool shifted) {
+  if (!plan || !A || !U || !lambda || !info || k < 1 || lda < plan->n) return BSRHT_EINVAL;
+  if (ws_bytes < nystrom_workspace(plan, k) || !ws) return BSRHT_ENOMEM;
+  DevCtx ctx;
+  ctx.s = (hipStream_t)stream;
+  return run_blocking(nystrom_task(ctx, plan, A, lda, k, U, lambda, info, ws, ws_bytes, shifted));
+}
+
 int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U, double *lambda,
             int32_t *info, void *ws, size_t ws_bytes, void *stream) {
-  return nystrom_impl(plan, A, lda, k, U, lambda, info, ws, ws_bytes, stream, false);
+  return nystrom_blocking(plan, A, lda, k, U, lambda, info, ws, ws_bytes, stream, false);
 }
 
 int nystrom_shifted(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
                     double *lambda, int32_t *info, void *ws, size_t ws_bytes, void *stream) {
-  return nystrom_impl(plan, A, lda, k, U, lambda, info, ws, ws_bytes, stream, true);
+  return nystrom_blocking(plan, A, lda, k, U, lambda, info, ws, ws_bytes, stream, true);
 }
 
 }  // extern "C"

@@ -1,4 +1,4 @@
-// Serving runtime: admission of independent sketch / RSVD jobs against a
+// Serving runtime: admission of independent sketch / RSVD / Nystrom jobs against a
 // device arena (the HBM budget), a plan cache inside that arena, and an
 // event-driven executor: every admitted job is a coroutine on one of a few
 // HIP streams, resumed by the thread that calls the server whenever the event
@@ -126,11 +126,14 @@ bsrht_plan_s shape_of(const bsrht_job_t &j) {
 size_t workspace_of(const bsrht_job_t &j) {
   bsrht_plan_s s = shape_of(j);
   if (j.kind == BSRHT_JOB_SKETCH) return bsrht_apply_workspace(&s, j.m);
+  if (j.kind == BSRHT_JOB_NYSTROM) return nystrom_workspace(&s, j.k);
   return rsvd_workspace(&s, j.m, j.k);
 }
 
 bool valid_job(const bsrht_job_t &j, bool fake) {
-  if (j.kind != BSRHT_JOB_SKETCH && j.kind != BSRHT_JOB_RSVD) return false;
+  if (j.kind != BSRHT_JOB_SKETCH && j.kind != BSRHT_JOB_RSVD && j.kind != BSRHT_JOB_NYSTROM)
+    return false;
+  if (j.kind == BSRHT_JOB_NYSTROM && j.m != j.n) return false;
   if (j.m < 1 || j.m > INT32_MAX || bsrht_plan_bytes(j.n, j.p, j.l) == 0) return false;
   if (j.sampling != BSRHT_WITH_REPLACEMENT && j.sampling != BSRHT_WITHOUT_REPLACEMENT)
     return false;
@@ -138,10 +141,11 @@ bool valid_job(const bsrht_job_t &j, bool fake) {
   if (j.precision != BSRHT_FP32 && j.precision != BSRHT_SPLIT_BF16) return false;
   if (j.lda < j.m) return false;
   if (j.kind == BSRHT_JOB_SKETCH && j.ldy < j.m) return false;
-  if (j.kind == BSRHT_JOB_RSVD && j.k < 1) return false;
+  if (j.kind != BSRHT_JOB_SKETCH && j.k < 1) return false;
   if (fake) return true;
   if (!j.A) return false;
   if (j.kind == BSRHT_JOB_SKETCH) return j.Y != nullptr;
+  if (j.kind == BSRHT_JOB_NYSTROM) return j.U && j.S && j.info;
   return j.U && j.S && j.V && j.info;
 }
 
@@ -174,6 +178,14 @@ Task batch_job(DevCtx &ctx, std::vector<bsrht_apply_item_t> items, void *table,
 Task rsvd_job(DevCtx &ctx, bsrht_plan_t plan, const bsrht_job_t j, void *ws, size_t ws_bytes) {
   const int st = co_await rsvd_task(ctx, plan, j.A, j.m, j.lda, j.k, j.U, j.S, j.V, j.info, ws,
                                     ws_bytes);
+  if (st != BSRHT_OK) co_return st;
+  co_return co_await drained(ctx);
+}
+
+Task nystrom_job(DevCtx &ctx, bsrht_plan_t plan, const bsrht_job_t j, void *ws,
+                 size_t ws_bytes) {
+  const int st = co_await nystrom_task(ctx, plan, j.A, j.lda, j.k, j.U, j.S, j.info, ws,
+                                       ws_bytes, false);
   if (st != BSRHT_OK) co_return st;
   co_return co_await drained(ctx);
 }
@@ -412,6 +424,8 @@ struct bsrht_server_s {
     void *ws = jb->has_ws ? base + jb->ws_off : nullptr;
     if (jb->j.kind == BSRHT_JOB_SKETCH)
       sl.task.emplace(sketch_job(sl.ctx, pe->plan, jb->j, ws, jb->ws_bytes));
+    else if (jb->j.kind == BSRHT_JOB_NYSTROM)
+      sl.task.emplace(nystrom_job(sl.ctx, pe->plan, jb->j, ws, jb->ws_bytes));
     else
       sl.task.emplace(rsvd_job(sl.ctx, pe->plan, jb->j, ws, jb->ws_bytes));
     sl.task->start();  // runs until its first wait on the device
@@ -506,8 +520,11 @@ struct bsrht_server_s {
   }
 
   void release_device() {
+    if (!slots.empty()) (void)hipSetDevice(device);
     for (Slot &sl : slots) {
       sl.task.reset();
+      // the batched launches of this slot's table (graph, staging, event)
+      if (sl.has_table) (void)bsrht_batch_table_release(base + sl.table_off);
       if (sl.ctx.pinned) (void)hipHostFree(sl.ctx.pinned);
       if (sl.ctx.ev) (void)hipEventDestroy(sl.ctx.ev);
       if (sl.ctx.s) (void)hipStreamDestroy(sl.ctx.s);

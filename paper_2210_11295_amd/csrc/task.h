@@ -189,6 +189,9 @@ inline Drained drained(DevCtx &ctx) { return Drained{ctx}; }
 Task rsvd_task(DevCtx &ctx, const bsrht_plan_s *plan, const float *A, int64_t m, int64_t lda,
                int64_t k, float *U, double *S, float *V, int32_t *info, void *ws,
                size_t ws_bytes);
+Task nystrom_task(DevCtx &ctx, const bsrht_plan_s *plan, const float *A, int64_t lda, int64_t k,
+                  float *U, double *lambda, int32_t *info, void *ws, size_t ws_bytes,
+                  bool shifted);
 Task jacobi_svd_task(DevCtx &ctx, double *X, int64_t nr, int64_t nc, int64_t ldx, double *V,
                      double *S, double *Us, int64_t ldu, int32_t *perm, unsigned int *flags,
                      int max_sweeps, int32_t *info, int form);

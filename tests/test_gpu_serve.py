@@ -139,3 +139,83 @@ def test_small_sketch_jobs_run_batched_and_equal_alone():
         torch.cuda.synchronize()
         for name, t in ref.items():
             assert torch.equal(out[name], t), (js, name)
+
+
+def _nys_jobs(count, seed):
+    """Sketch, RSVD and Nystrom jobs in turn; Nystrom payloads are full-rank
+    SPD n x n matrices (n = 2^9 .. 2^11), so no oracle comparison below can
+    pass by exact recovery."""
+    rs = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        kind = (bs.JOB_SKETCH, bs.JOB_RSVD, bs.JOB_NYSTROM)[i % 3]
+        n = 1 << int(rs.integers(9, 12) if kind == bs.JOB_NYSTROM else rs.integers(10, 14))
+        p = int(rs.choice([1, 2, 4, 16]))
+        m = n if kind == bs.JOB_NYSTROM else int(rs.integers(1, 300))
+        k = int(rs.integers(4, 40))
+        l = min(2 * k + 8, n)
+        prec = bs.SPLIT_BF16 if i % 7 == 2 else bs.FP32
+        out.append(dict(id=i, kind=kind, n=n, m=m, p=p, l=l, k=k, prec=prec,
+                        seed=int(rs.integers(0, 4)), data=int(rs.integers(0, 2 ** 31))))
+    return out
+
+
+def _nys_payload(js, dev):
+    if js["kind"] != bs.JOB_NYSTROM:
+        return _payload(js, dev)
+    n, k = js["n"], js["k"]
+    A = workloads.spd(n, n, "inv_sq", js["data"], device=dev)
+    return A, dict(U=torch.full((n, k), float("nan"), device=dev),
+                   lam=torch.full((k,), float("nan"), dtype=torch.float64, device=dev),
+                   info=torch.zeros(1, dtype=torch.int32, device=dev))
+
+
+def test_nystrom_jobs_in_mix_equal_alone_and_match_oracle():
+    """Nystrom jobs (section 3.2, Algorithm 2) served next to sketch and RSVD
+    jobs on four slots: each result is bitwise the stand-alone nystrom call's,
+    and sampled jobs are within 1% of the FP64 oracle's trace error with the
+    same Omega."""
+    dev = device()
+    jobs = _nys_jobs(60, 17)
+    arena = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    payloads = {js["id"]: _nys_payload(js, dev) for js in jobs}
+    torch.cuda.synchronize()
+    with bs.Server(arena=arena, workers=4) as srv:
+        for js in jobs:
+            A, out = payloads[js["id"]]
+            pa = (js["n"], js["p"], js["l"], js["seed"], bs.WITH_REPLACEMENT, js["prec"])
+            if js["kind"] == bs.JOB_NYSTROM:
+                srv.submit(bs.nystrom_job(js["id"], pa, A, js["k"], out["U"], out["lam"],
+                                          out["info"]))
+            else:
+                srv.submit(_desc(js, A, out))
+        srv.drain()
+        res = {r.id: r for r in srv.poll(1000)}
+        st = srv.stats()
+    say("stats", st)
+    assert len(res) == len(jobs) and all(r.status == 0 for r in res.values())
+    assert st["peak_running"] >= 2
+    checked = 0
+    for js in jobs:
+        A, out = payloads[js["id"]]
+        if js["kind"] != bs.JOB_NYSTROM:
+            ref = _alone(js, A)
+        else:
+            plan = bs.Plan(js["n"], js["p"], js["l"], js["seed"], precision=js["prec"],
+                           device=dev)
+            U, lam, info = bs.nystrom(plan, A, js["k"])
+            ref = dict(U=U, lam=lam, info=info)
+        torch.cuda.synchronize()
+        for name, t in ref.items():
+            assert torch.equal(out[name], t), (js, name)
+        if js["kind"] == bs.JOB_NYSTROM and checked < 8:
+            Ah = to64(A)
+            err = metrics.trace_error(Ah, to64(out["U"]), to64(out["lam"]))
+            Uo, lo, fb = lowrank.nystrom(rng.Plan(js["n"], js["p"], js["l"], js["seed"]), Ah,
+                                         js["k"])
+            err_o = metrics.trace_error(Ah, Uo, lo)
+            say("  nystrom job", js["id"], js["n"], js["p"], js["l"], js["k"], "err", err,
+                "oracle", err_o)
+            assert err <= 1.01 * err_o, (js, err, err_o)
+            checked += 1
+    assert checked >= 6

@@ -164,3 +164,26 @@ def test_submit_many_stops_at_the_first_rejected_job():
         st = srv.stats()
         assert st["submitted"] == 7 and st["rejected"] == 1 and st["completed"] == 7
         assert srv.submit_many([]) == 0
+
+
+def test_nystrom_jobs_are_sized_and_validated():
+    """A Nystrom job needs a square A (m == n); its arena bytes are the
+    nystrom workspace plus the plan tables, and the scheduler runs it like
+    the other kinds."""
+    nys = job(0, n=1 << 12, m=1 << 12, p=4, l=64, k=16, kind=bs.JOB_NYSTROM)
+    need = bs.bsrht_job_bytes(nys)
+    assert need > 0
+    bad = job(1, n=1 << 12, m=100, p=4, l=64, k=16, kind=bs.JOB_NYSTROM)
+    assert bs.bsrht_job_bytes(bad) == 0
+    bad_k = job(2, n=1 << 12, m=1 << 12, p=4, l=64, k=0, kind=bs.JOB_NYSTROM)
+    assert bs.bsrht_job_bytes(bad_k) == 0
+    jobs = [job(i, n=1 << 12, m=1 << 12, p=4, l=64, k=16, kind=bs.JOB_NYSTROM)
+            for i in range(6)] + [job(10 + i) for i in range(6)]
+    with bs.Server(fake_bytes=1 << 30, workers=3, seconds_per_gb=0.5) as srv:
+        res = run_all(srv, jobs)
+        assert all(r.status == 0 for r in res)
+        held = {r.id: r.arena_bytes for r in res}
+        assert held[0] == need      # the first Nystrom job built its plan
+    with bs.Server(fake_bytes=1 << 30, workers=1) as srv:
+        with pytest.raises(bs.BsrhtError):
+            srv.submit(bad)
