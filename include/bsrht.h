@@ -225,6 +225,16 @@ size_t bsrht_batch_table_bytes(void);
 int bsrht_apply_batch(const bsrht_apply_item_t *items, int count, void *table,
                       size_t table_bytes, void *stream);
 
+/*
+ * Releases what bsrht_apply_batch keeps for `table` on the current device:
+ * its captured graph, the pinned staging of its descriptors and their copy
+ * event (a later call with the table captures them again).  Every call that
+ * used the table must have completed (the copy event is waited for; the
+ * graph launch is not).  Returns BSRHT_OK (also when nothing was kept),
+ * BSRHT_EINVAL for a NULL table, BSRHT_EDEVICE if a HIP release failed.
+ */
+int bsrht_batch_table_release(void *table);
+
 /* Workspace bytes rsvd needs for an n x m input and target rank k. */
 size_t rsvd_workspace(bsrht_plan_t plan, int64_t m, int64_t k);
 
@@ -394,6 +404,16 @@ int bsrht_timing_samples(float *ms, int64_t cap, int64_t *count);
  */
 #define BSRHT_STREAM_BLOCKS 4096
 int bsrht_stream_read(const float *x, int64_t count, float *out, void *stream);
+
+/*
+ * Releases every HIP object the library keeps for the life of the process:
+ * the timing events and, for every table and device, the graphs, pinned
+ * staging and events of bsrht_apply_batch.  Meant for the end of a program,
+ * while the HIP runtime is still up (the Python binding calls it at
+ * interpreter exit); no library call may be pending or follow except new
+ * ones, which recreate what they need.  Returns BSRHT_OK or BSRHT_EDEVICE.
+ */
+int bsrht_finalize(void);
 
 #ifdef __cplusplus
 }

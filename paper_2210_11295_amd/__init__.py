@@ -8,6 +8,7 @@ pointers.  It raises if the library has not been built; there is no other
 execution path.
 """
 
+import atexit
 import ctypes
 import os
 
@@ -19,12 +20,12 @@ __all__ = [
     "bsrht_apply", "bsrht_apply_workspace", "rsvd", "rsvd_workspace", "nystrom",
     "nystrom_workspace", "WITH_REPLACEMENT", "WITHOUT_REPLACEMENT", "FP32",
     "SPLIT_BF16", "INFO_CHOL_FALLBACK", "INFO_RANK_CLAMPED", "INFO_QB_FALLBACK",
-    "INFO_JACOBI_NOCONV", "EXPORTED_SYMBOLS", "JOB_SKETCH", "JOB_RSVD", "JobDesc",
+    "INFO_JACOBI_NOCONV", "EXPORTED_SYMBOLS", "JOB_SKETCH", "JOB_RSVD", "JOB_NYSTROM", "JobDesc",
     "JobResult", "ServerStats", "Server", "bsrht_job_bytes", "apply_batch",
     "batch_table_bytes", "ApplyItem", "BATCH_MAX", "bsrht_apply_right",
     "bsrht_apply_right_workspace", "rsvd_single_view", "rsvd_single_view_workspace",
     "bsrht_dense_sketch", "bsrht_dense_workspace", "DENSE_GAUSSIAN", "DENSE_RADEMACHER",
-    "nystrom_shifted",
+    "nystrom_shifted", "nystrom_job", "finalize",
 ]
 
 WITH_REPLACEMENT = 0
@@ -47,6 +48,7 @@ DENSE_RADEMACHER = 1
 STREAM_BLOCKS = 4096
 JOB_SKETCH = 0
 JOB_RSVD = 1
+JOB_NYSTROM = 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "_lib", "libbsrht.so")
@@ -88,6 +90,8 @@ _SIGS = {
     "bsrht_batch_table_bytes": (_c_sz, []),
     "bsrht_apply_batch": (ctypes.c_int, [_c_vp, ctypes.c_int, _c_vp, _c_sz, _c_vp]),
     "bsrht_stream_read": (ctypes.c_int, [_c_vp, _c_i64, _c_vp, _c_vp]),
+    "bsrht_batch_table_release": (ctypes.c_int, [_c_vp]),
+    "bsrht_finalize": (ctypes.c_int, []),
     "nystrom": (ctypes.c_int, [_c_vp, _c_vp, _c_i64, _c_i64, _c_vp, _c_vp, _c_vp, _c_vp,
                                _c_sz, _c_vp]),
     "nystrom_shifted": (ctypes.c_int, [_c_vp, _c_vp, _c_i64, _c_i64, _c_vp, _c_vp, _c_vp,
@@ -163,7 +167,15 @@ def lib():
             fn.restype = res
             fn.argtypes = args
         _lib = handle
+        # release the library's process-lifetime HIP objects (batch graphs,
+        # pinned staging, events) while the HIP runtime is still up
+        atexit.register(_finalize)
     return _lib
+
+
+def _finalize():
+    if _lib is not None:
+        _lib.bsrht_finalize()
 
 
 def _check(fn, status):
@@ -557,6 +569,26 @@ def sketch_job(job_id, plan_args, A, Y):
                    seed=int(seed) & (2 ** 64 - 1), sampling=sampling, precision=precision,
                    A=A.data_ptr(), lda=max(A.stride(0), m), Y=Y.data_ptr(),
                    ldy=max(Y.stride(0), m))
+
+
+def nystrom_job(job_id, plan_args, A, k, U, lam, info):
+    """JobDesc for the Nystrom approximation of the symmetric PSD n x n A into
+    caller-owned U (n x k), lam (k, float64) and info."""
+    n, p, l, seed, sampling, precision = plan_args
+    _check_matrix("A", A)
+    if A.shape[0] != A.shape[1]:
+        raise ValueError("A must be square")
+    m = A.shape[1]
+    return JobDesc(id=job_id, kind=JOB_NYSTROM, n=n, m=m, p=p, l=l, k=k,
+                   seed=int(seed) & (2 ** 64 - 1), sampling=sampling, precision=precision,
+                   A=A.data_ptr(), lda=max(A.stride(0), m), U=U.data_ptr(), S=lam.data_ptr(),
+                   info=info.data_ptr())
+
+
+def finalize():
+    """bsrht_finalize: release the library's process-lifetime HIP objects now
+    (also done automatically at interpreter exit)."""
+    _check("bsrht_finalize", lib().bsrht_finalize())
 
 
 def rsvd_job(job_id, plan_args, A, k, U, S, V, info):

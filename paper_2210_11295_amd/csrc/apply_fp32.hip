@@ -618,7 +618,11 @@ int batch_graph(const void *table, BatchGraph *out) {
     return BSRHT_EDEVICE;
   }
   hipStream_t cs = nullptr;
-  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return BSRHT_EDEVICE;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipEventDestroy(ev);
+    (void)hipHostFree(pin);
+    return BSRHT_EDEVICE;
+  }
   const BatchTable *tb = static_cast<const BatchTable *>(table);
   const unsigned cus = (unsigned)device_cu_count();
   hipGraph_t graph = nullptr;
@@ -645,6 +649,30 @@ int batch_graph(const void *table, BatchGraph *out) {
 }
 
 }  // namespace
+
+// Destroys the graph, event and pinned staging of one table on the current
+// device (all = false) or of every table on every device (all = true).  The
+// caller guarantees that no launch through these tables is still pending;
+// the copy event is waited for regardless.
+int release_batch_graphs(const void *table, bool all) {
+  int dev = 0;
+  if (!all && hipGetDevice(&dev) != hipSuccess) return BSRHT_EDEVICE;
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  int st = BSRHT_OK;
+  for (size_t i = 0; i < g_batch_graphs.size();) {
+    const BatchGraph &g = g_batch_graphs[i];
+    if (!all && (g.device != dev || g.table != table)) {
+      ++i;
+      continue;
+    }
+    if (hipEventSynchronize(g.copied) != hipSuccess) st = BSRHT_EDEVICE;
+    if (hipGraphExecDestroy(g.exec) != hipSuccess) st = BSRHT_EDEVICE;
+    if (hipEventDestroy(g.copied) != hipSuccess) st = BSRHT_EDEVICE;
+    if (hipHostFree(g.pinned) != hipSuccess) st = BSRHT_EDEVICE;
+    g_batch_graphs.erase(g_batch_graphs.begin() + (std::ptrdiff_t)i);
+  }
+  return st;
+}
 
 int apply_fp32(const bsrht_plan_s *pl, const float *A, int64_t m, int64_t lda, float *Y,
                int64_t ldy, void *ws, size_t ws_bytes, hipStream_t s) {
@@ -715,6 +743,11 @@ int bsrht_apply(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, float
 }
 
 size_t bsrht_batch_table_bytes(void) { return sizeof(BatchTable); }
+
+int bsrht_batch_table_release(void *table) {
+  if (!table) return BSRHT_EINVAL;
+  return release_batch_graphs(table, false);
+}
 
 int bsrht_apply_batch(const bsrht_apply_item_t *items, int count, void *table,
                       size_t table_bytes, void *stream) {

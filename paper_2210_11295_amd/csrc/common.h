@@ -138,4 +138,10 @@ int copy_to_device(void *dst, const void *src, size_t bytes, hipStream_t s);
 int timing_begin(int which, hipStream_t s);  // slot handle, -1 when not timing
 void timing_end(int slot, hipStream_t s);
 
+// Release of the library's process-lifetime HIP objects (bsrht_finalize):
+// the timing events, and the batched launch's graphs with their pinned
+// staging and events (every table, or one table on the current device).
+void release_timing_events();
+int release_batch_graphs(const void *table, bool all);
+
 }  // namespace bsrht

@@ -110,11 +110,29 @@ void timing_end(int slot, hipStream_t s) {
     g_timing.done[(size_t)slot] = 1;
 }
 
+void release_timing_events() {
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  for (auto &e : g_timing.events) {
+    (void)hipEventSynchronize(e.second);
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  g_timing.events.clear();
+  g_timing.done.clear();
+  g_timing.used = 0;
+  g_timing.which = 0;
+}
+
 }  // namespace bsrht
 
 using namespace bsrht;
 
 extern "C" {
+
+int bsrht_finalize(void) {
+  release_timing_events();
+  return release_batch_graphs(nullptr, true);
+}
 
 int bsrht_timing_enable(int which) {
   std::lock_guard<std::mutex> lk(g_timing_mu);
