@@ -63,28 +63,159 @@ def _traffic(profile_name, src_files, bytes_per_launch_alg):
     return doc.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(A, cfg, blocks=8):
-    """The FP64 oracle sketch timed on host cores, on a bounded sample of the
-    same workload: the first `blocks` row blocks of A (blocks * 2^16 rows x
-    1024 columns) as a plan with p = blocks and the same r, l, seed.  The
-    tables of block i depend only on (seed, i), so this is exactly the partial
-    sum of the first `blocks` terms of (2.4)."""
-    import numpy as np
-    from oracle import rng, sketch
+def _cpu_facts():
+    """CPU model, the cores this process may run on, and the BLAS threads."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = None
+    try:
+        import threadpoolctl
+        blas = [d.get("num_threads") for d in threadpoolctl.threadpool_info()
+                if d.get("user_api") == "blas"]
+    except Exception:  # noqa: BLE001 - informational only
+        pass
+    return {"cpu_model": model, "affinity_cores": len(os.sched_getaffinity(0)),
+            "blas_threads": blas}
 
-    r = cfg["n"] // cfg["p"]
-    blocks = min(blocks, cfg["p"])
-    sample = A[:blocks * r].cpu().numpy()
-    op = rng.Plan(blocks * r, blocks, cfg["l"], cfg["seed"])
+
+def _rel_errors(Y, Y_ref):
+    """Relative Frobenius error and largest entry error relative to max|Y_ref|."""
+    Yh = Y.detach().cpu().double().numpy()
+    D = Yh - Y_ref
+    return {"rel_fro": float(np.linalg.norm(D) / np.linalg.norm(Y_ref)),
+            "max_entry_rel": float(np.abs(D).max() / np.abs(Y_ref).max())}
+
+
+def cpu_baseline(bs, A, cfg, Y_fp32, Y_bf16, blocks=8):
+    """The cpu_baseline leg: the FP64 oracle on the host cores.
+
+    Timing: the oracle's sketch (numpy FP64 FWHT) on one core, on a bounded
+    sample (the first `blocks` row blocks of A as a plan with p = blocks and
+    the same r, l and seed: the tables of block i depend only on (seed, i), so
+    this is exactly the partial sum of the first terms of (2.4)); and on all
+    cores (oracle.sketch.sketch_parallel: the same per-block terms on a
+    thread per core, bitwise the sequential result) over the whole input.
+    `value` is the all-core rate, as GB/s of FP32 A.
+
+    Reference errors (FP64 oracle, same plan and FP32 input): the full-size
+    FP32 and split-BF16 sketches of the benchmark; on A_sub = A[0:r] as a
+    p = 1 plan (block 0 of the same tables) the two sketches again and the
+    rank-k randomized SVD error against the oracle's."""
+    import torch
+    from oracle import lowrank, metrics, rng, sketch
+
+    n, m, p, l, k, seed = cfg["n"], cfg["m"], cfg["p"], cfg["l"], cfg["k"], cfg["seed"]
+    r = n // p
+    facts = _cpu_facts()
+    workers = facts["affinity_cores"]
+    Ah = A.cpu().numpy()
+
+    blocks = min(blocks, p)
+    op = rng.Plan(blocks * r, blocks, l, seed)
     t0 = time.perf_counter()
-    Y = sketch.sketch(op, sample)
-    dt = time.perf_counter() - t0
-    assert np.isfinite(Y).all()
-    gbs = sample.size * 4 / dt / 1e9
-    return {"value": round(gbs, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {blocks} of {cfg['p']} row blocks: {blocks * r} x {cfg['m']} "
-                      f"float32 rows of A as a p={blocks} plan (r={r}, l={cfg['l']}, same "
-                      f"seed); numpy FP64 FWHT, single thread; {dt:.2f} s"}
+    Ys = sketch.sketch(op, Ah[:blocks * r])
+    dt1 = time.perf_counter() - t0
+    assert np.isfinite(Ys).all()
+    gbs1 = blocks * r * m * 4 / dt1 / 1e9
+    log(f"bench: oracle sketch, one core: {blocks} blocks in {dt1:.2f} s -> {gbs1:.4f} GB/s")
+
+    t0 = time.perf_counter()
+    Y_ref = sketch.sketch_parallel(rng.Plan(n, p, l, seed), Ah, workers=workers)
+    dtn = time.perf_counter() - t0
+    gbsn = n * m * 4 / dtn / 1e9
+    log(f"bench: oracle sketch, {workers} threads: whole input in {dtn:.2f} s -> {gbsn:.4f} GB/s")
+
+    errs = {"full_fp32": _rel_errors(Y_fp32, Y_ref)}
+    if Y_bf16 is not None:
+        errs["full_split_bf16"] = _rel_errors(Y_bf16, Y_ref)
+    del Y_ref
+
+    sub_op = rng.Plan(r, 1, l, seed)
+    Asub = A[:r].contiguous()
+    Ysub_ref = sketch.sketch(sub_op, Ah[:r])
+    for name, prec in (("sub_fp32", bs.FP32), ("sub_split_bf16", bs.SPLIT_BF16)):
+        Ysub = bs.bsrht_apply(bs.Plan(r, 1, l, seed, precision=prec, device=A.device), Asub)
+        torch.cuda.synchronize()
+        errs[name] = _rel_errors(Ysub, Ysub_ref)
+    sub_plan = bs.Plan(r, 1, l, seed, device=A.device)
+    U, S, V, info = bs.rsvd(sub_plan, Asub, k)
+    torch.cuda.synchronize()
+    Asub_h = Ah[:r].astype(np.float64)
+    e_gpu = metrics.lowrank_fro_error(Asub_h, U.cpu().double().numpy(),
+                                      S.cpu().double().numpy(), V.cpu().double().numpy())
+    Uo, So, Vo = lowrank.rsvd(sub_op, Asub_h, k)
+    e_or = metrics.lowrank_fro_error(Asub_h, Uo, So, Vo)
+    errs["sub_rsvd"] = {"k": k, "l": l, "gpu_rel_fro_error": e_gpu, "oracle_rel_fro_error": e_or,
+                        "ratio": e_gpu / e_or}
+    log(f"bench: errors against the FP64 oracle: {json.dumps(errs)}")
+    del Asub, Asub_h, Ah
+    return {"value": round(gbsn, 4), "unit": "GB/s", "cores": workers, "kind": "oracle",
+            "sample": f"all cores: the whole {n} x {m} float32 input (p={p}, l={l}, seed "
+                      f"{seed}), numpy FP64 FWHT, one thread per core over (block, column "
+                      f"slice) terms summed in block order; {dtn:.2f} s",
+            "one_core": {"value": round(gbs1, 4), "unit": "GB/s", "cores": 1,
+                         "seconds": round(dt1, 2),
+                         "sample": f"first {blocks} of {p} row blocks: {blocks * r} x {m} float32 "
+                                   f"rows of A as a p={blocks} plan (same r, l, seed); "
+                                   f"numpy FP64 FWHT, single thread"},
+            **facts,
+            "errors_vs_fp64_oracle": errs,
+            "sub_workload": f"A_sub = A[0:{r}] (block 0) as a p=1 plan, l={l}, seed {seed}"}
+
+
+def cpu_oracle_nystrom(bs, plan, cfg, A, X, s, trace_err):
+    """cpu_baseline leg, Nystrom workload: the reference trace errors beside
+    the GPU's (section 8d's three errors).
+
+    oracle: Algorithm 2 in FP64 on the host for the exact A = X diag(s) X^T,
+        through its structure: W = Omega A = (Omega X) diag(s) X^T with Omega X
+        from the oracle's sketch, Y = W^T, B = Omega Y, then the oracle's
+        steps 2-6 (oracle.lowrank.nystrom_from_sketch);
+    hybrid: the GPU's FP32 sketches (W = Omega A and B = Omega W^T, the
+        library's two sketch passes on the FP32 A) factored by those same
+        FP64 host steps, which isolates the precision of the sketch.
+    The errors are evaluated like the GPU's (trace_err: the eigenvalues of
+    A - U diag(lam) U^T on span[X, U])."""
+    import torch
+    from oracle import lowrank, rng, sketch
+
+    n, p, l, k, seed = cfg["n"], cfg["p"], cfg["l"], cfg["k"], cfg["seed"]
+    workers = len(os.sched_getaffinity(0))
+    dev = A.device
+    t0 = time.perf_counter()
+    op = rng.Plan(n, p, l, seed)
+    Xh = X.cpu().numpy()
+    sh = s.cpu().numpy()
+    OX = sketch.sketch_parallel(op, Xh, workers=workers)           # Omega X (l x d)
+    Yo = ((OX * sh[None, :]) @ Xh.T).T                              # Y = A Omega^T
+    Bo = sketch.sketch_parallel(op, Yo, workers=workers)           # Omega Y
+    Uo, lo, fbo = lowrank.nystrom_from_sketch(Yo, Bo, k, l)
+    e_or = trace_err(torch.from_numpy(Uo).to(dev), torch.from_numpy(lo).to(dev))
+    del Xh, OX, Yo, Bo, Uo
+    t1 = time.perf_counter()
+    W = bs.bsrht_apply(plan, A)
+    Yg = W.t().contiguous()
+    del W
+    Bg = bs.bsrht_apply(plan, Yg)
+    torch.cuda.synchronize()
+    Uh, lh, fbh = lowrank.nystrom_from_sketch(Yg.cpu().double().numpy(),
+                                              Bg.cpu().double().numpy(), k, l)
+    del Yg, Bg
+    e_hy = trace_err(torch.from_numpy(Uh).to(dev), torch.from_numpy(lh).to(dev))
+    t2 = time.perf_counter()
+    log(f"bench: nystrom reference errors: oracle {e_or:.3e} (fallback {fbo}, {t1 - t0:.1f} s), "
+        f"hybrid {e_hy:.3e} (fallback {fbh}, {t2 - t1:.1f} s)")
+    return {"oracle_trace_rel_error": e_or, "oracle_fallback": bool(fbo),
+            "hybrid_trace_rel_error": e_hy, "hybrid_fallback": bool(fbh),
+            "oracle_note": "FP64 oracle on the exact A = X diag(s) X^T (the FP32 rounding of A "
+                           "is not seen by it); hybrid = GPU FP32 sketches, FP64 host factors"}
 
 
 def _copy_calibration(A):
@@ -168,7 +299,7 @@ def bench_split_bf16(bs, A, cfg, steps, warmup, Y_fp32):
                          "traffic": traffic, "kernel": "fused_bf16_kernel<8, 64, false>",
                          "kernel_avg_us": round(kern_avg_ms * 1e3, 2), **stats,
                          "alg_bytes_per_launch": alg_bytes},
-            "rel_diff_vs_fp32": diff}
+            "rel_diff_vs_fp32": diff}, Y
 
 
 def bench_right(bs, A, cfg, steps, warmup, Y_col):
@@ -494,9 +625,10 @@ def bench_serving(bs, njobs, streams, rate=200.0, arena_gib=32, ahead=16, live_g
     return out
 
 
-def bench_nystrom(bs, reps):
+def bench_nystrom(bs, reps, with_oracle=False):
     """Algorithm 2 on the 65536 x 65536 SPD matrix (s_j = j^-3, p = 64, l = 1024,
-    rank 512), FP64 factorisations on the GPU."""
+    rank 512), FP64 factorisations on the GPU.  with_oracle: also the
+    cpu_baseline leg's reference errors (cpu_oracle_nystrom)."""
     import torch
     import workloads
     c = workloads.CONFIGS["c5_nystrom"]
@@ -556,10 +688,15 @@ def bench_nystrom(bs, reps):
                "info": int(infos.item())}
     log(f"bench: nystrom {dt * 1e3:.1f} ms err {err:.3e} (info {int(info.item())}); shifted "
         f"{dts * 1e3:.1f} ms err {shifted['trace_rel_error']:.3e} (info {shifted['info']})")
-    return {"ms": round(dt * 1e3, 2), "n": n, "l": l, "k": k, "p": p,
-            "sketch_kernel_ms_per_call": round(kms / max(reps, 1), 3), **apply,
-            "trace_rel_error": err, "optimal_trace_rel_error": opt,
-            "info": int(info.item()), "shifted": shifted}
+    res = {"ms": round(dt * 1e3, 2), "n": n, "l": l, "k": k, "p": p,
+           "sketch_kernel_ms_per_call": round(kms / max(reps, 1), 3), **apply,
+           "trace_rel_error": err, "optimal_trace_rel_error": opt,
+           "info": int(info.item()), "shifted": shifted}
+    if with_oracle:
+        del Us, U, ws
+        torch.cuda.empty_cache()
+        res.update(cpu_oracle_nystrom(bs, plan, c, A, X, s, trace_err))
+    return res
 
 
 def bench_serving_small(bs, njobs=3000, rate=None, streams=SERVE_STREAMS, seed=1):
@@ -664,7 +801,9 @@ def main():
         print(json.dumps({"serving_small_sketch": bench_serving_small(bs)}), flush=True)
         return
     if args.only == "nystrom":
-        print(json.dumps({"nystrom": bench_nystrom(bs, args.lowrank_reps)}), flush=True)
+        print(json.dumps({"nystrom": bench_nystrom(bs, args.lowrank_reps,
+                                                   with_oracle=not args.skip_cpu_baseline)}),
+              flush=True)
         return
     if args.only == "partial":
         print(json.dumps({"partial_sketch": bench_partial(bs, calibrate=args.copy_calibration)}),
@@ -687,7 +826,7 @@ def main():
         return
     if args.only == "bf16":
         Yf = bs.bsrht_apply(plan, A)
-        out_b = bench_split_bf16(bs, A, cfg, args.steps, args.warmup, Yf)
+        out_b, _ = bench_split_bf16(bs, A, cfg, args.steps, args.warmup, Yf)
         if args.copy_calibration:
             _copy_calibration(A)
         print(json.dumps({"split_bf16": out_b}), flush=True)
@@ -710,6 +849,7 @@ def main():
         print(json.dumps({"right_apply": out_r}), flush=True)
         return
     Y = torch.empty(l, m, dtype=torch.float32, device=dev)
+    Y_bf16 = None
     ws = torch.empty(max(1, bs.bsrht_apply_workspace(plan, m)), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
 
@@ -772,19 +912,20 @@ def main():
     if args.only == "sketch":
         args.skip_lowrank = True
     else:
-        out["split_bf16"] = bench_split_bf16(bs, A, cfg, args.steps, args.warmup, Y)
+        out["split_bf16"], Y_bf16 = bench_split_bf16(bs, A, cfg, args.steps, args.warmup, Y)
         out["right_apply"] = bench_right(bs, A, cfg, args.steps, args.warmup, Y)
         out["dense_sketch"] = bench_dense(bs, A, cfg, 5, 1, elapsed / args.steps * 1e3)
     if not args.skip_lowrank:
         out["rsvd"] = bench_rsvd(bs, A, plan, cfg, args.lowrank_reps)
         out["rsvd_single_view"] = bench_single_view(bs, A, cfg, args.lowrank_reps)
     if not args.skip_cpu_baseline:
-        log("bench: timing the CPU oracle on one block")
-        out["cpu_baseline"] = cpu_baseline(A, cfg)
+        log("bench: the CPU oracle (timing and reference errors)")
+        out["cpu_baseline"] = cpu_baseline(bs, A, cfg, Y, Y_bf16)
     if not args.skip_lowrank:
         del A, Y, ws
         torch.cuda.empty_cache()
-        out["nystrom"] = bench_nystrom(bs, args.lowrank_reps)
+        out["nystrom"] = bench_nystrom(bs, args.lowrank_reps,
+                                       with_oracle=not args.skip_cpu_baseline)
         torch.cuda.empty_cache()
         out["partial_sketch"] = bench_partial(bs)
     if args.serve_jobs > 0 and args.only == "all":
