@@ -159,6 +159,26 @@ size_t bsrht_apply_workspace(bsrht_plan_t plan, int64_t m);
 int bsrht_apply(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda,
                 float *Y, int64_t ldy, void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * bsrht_apply without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and result as bsrht_apply
+ * (bitwise), except that the row-split partials live in a scratch array of
+ * BSRHT_NOALLOC_SCRATCH_BYTES that the library holds in every GPU's memory
+ * for the life of the process (one per device, set up on the first call on
+ * that device).  Allocates nothing: no hipMalloc, hipFree or allocating
+ * library routine.  Every call on one GPU uses that GPU's array, and each
+ * call overwrites all of the partials it reads, so calls that follow one
+ * another on a GPU need no clearing; calls that overlap on one GPU (on
+ * different streams without ordering) race on it and must not be made.
+ * Returns BSRHT_ENOMEM, with nothing enqueued, when the call would need more
+ * than BSRHT_NOALLOC_SCRATCH_BYTES (bsrht_apply_workspace(plan, m) above it);
+ * otherwise as bsrht_apply.
+ */
+#define BSRHT_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int bsrht_apply_noalloc(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda,
+                        float *Y, int64_t ldy, void *stream);
+
 /* Workspace bytes bsrht_apply_right needs for an m x n input (0 is possible). */
 size_t bsrht_apply_right_workspace(bsrht_plan_t plan, int64_t m);
 

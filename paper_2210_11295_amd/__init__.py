@@ -70,6 +70,8 @@ _SIGS = {
     "bsrht_apply_workspace": (_c_sz, [_c_vp, _c_i64]),
     "bsrht_apply": (ctypes.c_int, [_c_vp, _c_vp, _c_i64, _c_i64, _c_vp, _c_i64, _c_vp,
                                    _c_sz, _c_vp]),
+    "bsrht_apply_noalloc": (ctypes.c_int, [_c_vp, _c_vp, _c_i64, _c_i64, _c_vp, _c_i64,
+                                           _c_vp]),
     "bsrht_apply_right_workspace": (_c_sz, [_c_vp, _c_i64]),
     "bsrht_apply_right": (ctypes.c_int, [_c_vp, _c_vp, _c_i64, _c_i64, _c_vp, _c_i64, _c_vp,
                                          _c_sz, _c_vp]),
@@ -307,6 +309,23 @@ def bsrht_apply(plan, A, Y=None, ws=None, stream=None):
     _check("bsrht_apply", lib().bsrht_apply(
         plan.handle, _ptr(A), m, max(A.stride(0), m), _ptr(Y), max(Y.stride(0), m),
         _ptr(ws), ws.numel(), _stream_ptr(stream)))
+    return Y
+
+
+NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def bsrht_apply_noalloc(plan, A, Y, stream=None):
+    """Y = Omega A through the allocation-free entry point (the partials in
+    the library's per-device scratch array; Y is the caller's)."""
+    _check_matrix("A", A)
+    n, m = A.shape
+    if n != plan.n:
+        raise ValueError(f"A has {n} rows, the plan expects {plan.n}")
+    _check_matrix("Y", Y)
+    _check("bsrht_apply_noalloc", lib().bsrht_apply_noalloc(
+        plan.handle, _ptr(A), m, max(A.stride(0), m), _ptr(Y), max(Y.stride(0), m),
+        _stream_ptr(stream)))
     return Y
 
 

@@ -722,6 +722,36 @@ int apply_fp32(const bsrht_plan_s *pl, const float *A, int64_t m, int64_t lda, f
   return BSRHT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free sketch: the row-split partials of bsrht_apply live in a
+// file-scope device array instead of a caller's workspace.  Host code never
+// passes the array's name to a kernel (on the host that name is a stand-in,
+// not a device address): the device address comes from hipGetSymbolAddress,
+// taken once per device with that device current, and is kept per device.
+constexpr size_t kNoAllocScratchBytes = BSRHT_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch`.
+int scratch_address(void **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return BSRHT_EDEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+      return BSRHT_EDEVICE;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return BSRHT_OK;
+}
+}  // namespace
+
 }  // namespace bsrht
 
 using namespace bsrht;
@@ -729,6 +759,25 @@ using namespace bsrht;
 extern "C" {
 
 size_t bsrht_apply_workspace(bsrht_plan_t plan, int64_t m) { return apply_ws_bytes(plan, m); }
+
+int bsrht_apply_noalloc(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, float *Y,
+                        int64_t ldy, void *stream) {
+  if (!plan || m < 0) return BSRHT_EINVAL;
+  if (m == 0) return BSRHT_OK;
+  if (!A || !Y || lda < m || ldy < m || m > INT_MAX) return BSRHT_EINVAL;
+  if ((int64_t)plan->l * m > ((int64_t)1 << 40)) return BSRHT_EUNSUPPORTED;
+  const size_t need = apply_ws_bytes(plan, m);
+  if (need > kNoAllocScratchBytes) return BSRHT_ENOMEM;
+  void *ws = nullptr;
+  if (need > 0) {
+    const int st = scratch_address(&ws);
+    if (st != BSRHT_OK) return st;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (plan->precision == BSRHT_SPLIT_BF16)
+    return apply_split_bf16(plan, A, m, lda, Y, ldy, ws, need, s);
+  return apply_fp32(plan, A, m, lda, Y, ldy, ws, need, s);
+}
 
 int bsrht_apply(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, float *Y,
                 int64_t ldy, void *ws, size_t ws_bytes, void *stream) {
