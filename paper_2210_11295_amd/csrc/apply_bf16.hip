@@ -24,7 +24,9 @@
 //                       * (H_b v_{x_hi})[R_j,lo].
 // A is read exactly once; the sum over blocks (2.4) stays in registers; row
 // splits write l x m partials summed in fixed order by the FP32 file's
-// reduce.  Blocks shorter than 128 rows (r < 128) have no room for an H_16
+// reduce.  As in the FP32 kernel, the 16-wave instance writes the
+// exchange's output to a second LDS buffer read by the gather, which removes
+// the barrier between the gather and the next chunk's stores.  Blocks shorter than 128 rows (r < 128) have no room for an H_16
 // tile per wave and are computed by the FP32 kernels.
 #include <limits.h>
 
@@ -110,6 +112,7 @@ struct Bf16Cta {
   static_assert(BR >= 16 && BR <= 64, "BR in {16, 32, 64}");
 
   float *T;
+  float *T2 = nullptr;  // second buffer: exchange output, gather input
   const Bf16Args &a;
   int lane, w, q4, g, j, pos, cpb_log2, row_bytes;
   int voff[RAGGED ? 4 : 1];  // byte offset of the lane's columns in its row 4t+g
@@ -234,16 +237,18 @@ struct Bf16Cta {
     mfma_store<0, NH>(cur);
     if (more) load<NT / 2, NT>(nxt, chunk_base(q + 1));
     __syncthreads();
-    // H_8 over the waves: group t holds rows t, t+BR, ..., t+7*BR.
+    // H_NW over the waves: group t holds rows t, t+BR, ..., t+(NW-1)*BR.
+    float *const Tx = T2 ? T2 : T;  // where the exchange writes and the gather reads
 #pragma unroll
     for (int gi = 0; gi < G; ++gi) {
-      float *Tg = T + (w * G + gi) * kLDT + lane;
+      const float *Tg = T + (w * G + gi) * kLDT + lane;
+      float *Og = Tx + (w * G + gi) * kLDT + lane;
       float u[NW];
 #pragma unroll
       for (int k = 0; k < NW; ++k) u[k] = Tg[k * BR * kLDT];
       fwht_regs<NW>(u);
 #pragma unroll
-      for (int k = 0; k < NW; ++k) Tg[k * BR * kLDT] = u[k];
+      for (int k = 0; k < NW; ++k) Og[k * BR * kLDT] = u[k];
     }
     __syncthreads();
     if (jok) {
@@ -255,7 +260,7 @@ struct Bf16Cta {
       const uint32_t xhi = (uint32_t)q & ((1u << cpb_log2) - 1u);
       const uint32_t par = (uint32_t)__popc(rhi & xhi) & 1u;
       const float sgn = (par ^ dtbit) ? -1.f : 1.f;
-      const float4 *row = reinterpret_cast<const float4 *>(T + pos * kLDT);
+      const float4 *row = reinterpret_cast<const float4 *>(Tx + pos * kLDT);
 #pragma unroll
       for (int c4 = 0; c4 < kCT / 4; ++c4) {
         const float4 u = row[c4];
@@ -265,16 +270,20 @@ struct Bf16Cta {
         acc[4 * c4 + 3] = fmaf(sgn, u.w, acc[4 * c4 + 3]);
       }
     }
-    __syncthreads();
+    // With two buffers the next exchange writes T2 only after the next
+    // chunk's first barrier, which every wave passes after this gather.
+    if (!T2) __syncthreads();
   }
 };
 
 template <int NW, int BR, bool RAGGED>
 __global__ __launch_bounds__(NW * 64) void fused_bf16_kernel(Bf16Args a) {
   using Cta = Bf16Cta<NW, BR, RAGGED>;
-  __shared__ __attribute__((aligned(16))) float T[Cta::B * kLDT];
+  constexpr bool DB = NW == 16;  // two LDS buffers (see the file comment)
+  __shared__ __attribute__((aligned(16))) float T[(DB ? 2 : 1) * Cta::B * kLDT];
   __shared__ u32x4_t Hop[64];
   Cta cta(T, a);
+  cta.T2 = DB ? T + Cta::B * kLDT : nullptr;
   const int tid = threadIdx.x;
   cta.lane = tid & 63;
   cta.w = __builtin_amdgcn_readfirstlane(tid >> 6);

@@ -23,6 +23,10 @@
 // HBM.  A is read exactly once.  Row splits (for parallelism) write l x m
 // partials that a second kernel sums in fixed split order and scales by
 // 1/sqrt(l) (the product sqrt(r/l) * 1/sqrt(r) of eq. (2.3)).
+// The 16-wave instances (256-row chunks, 68 KiB of LDS) write the exchange's
+// output to a second LDS buffer that the gather reads, so the next chunk's
+// stores cannot race the gather and one of the three barriers per chunk
+// goes; the 8-wave chunk (139 KiB) leaves no room for a second buffer.
 #include <limits.h>
 
 #include <cstring>
@@ -147,6 +151,7 @@ struct FusedCta {
   static_assert(G >= 1, "need BR >= NW");
 
   float *T;
+  float *T2 = nullptr;  // second buffer: exchange output, gather input
   const FusedArgs &a;
   int lane, w, j, pos, cpb_log2, voff, row_bytes;
   bool jok;
@@ -231,16 +236,18 @@ struct FusedCta {
       if (more) load_rows<BR, BR / 2, BR>(nxt, chunk_base(qr + 1), voff, row_bytes);
     }
     __syncthreads();
-    // H_8 over w: group t holds rows t, t+BR, ..., t+7*BR.
+    // H_NW over w: group t holds rows t, t+BR, ..., t+(NW-1)*BR.
+    float *const Tx = T2 ? T2 : T;  // where the exchange writes and the gather reads
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      float *Tg = T + (w * G + g) * kLDT + lane;
+      const float *Tg = T + (w * G + g) * kLDT + lane;
+      float *Og = Tx + (w * G + g) * kLDT + lane;
       float v[NW];
 #pragma unroll
       for (int k = 0; k < NW; ++k) v[k] = Tg[k * BR * kLDT];
       fwht_regs<NW>(v);
 #pragma unroll
-      for (int k = 0; k < NW; ++k) Tg[k * BR * kLDT] = v[k];
+      for (int k = 0; k < NW; ++k) Og[k * BR * kLDT] = v[k];
     }
     __syncthreads();
     if (jok) {
@@ -252,7 +259,7 @@ struct FusedCta {
       const uint32_t xhi = (uint32_t)q & ((1u << cpb_log2) - 1u);
       const uint32_t par = (uint32_t)__popc(rhi & xhi) & 1u;
       const float sgn = (par ^ dtbit) ? -1.f : 1.f;
-      const float4 *row = reinterpret_cast<const float4 *>(T + pos * kLDT);
+      const float4 *row = reinterpret_cast<const float4 *>(Tx + pos * kLDT);
 #pragma unroll
       for (int c4 = 0; c4 < kCT / 4; ++c4) {
         const float4 v = row[c4];
@@ -262,7 +269,10 @@ struct FusedCta {
         acc[4 * c4 + 3] = fmaf(sgn, v.w, acc[4 * c4 + 3]);
       }
     }
-    __syncthreads();
+    // With one buffer the next chunk's stores must wait for every gather.
+    // With two, the next exchange writes T2 only after the next chunk's
+    // first barrier, which every wave passes after this gather.
+    if (!T2) __syncthreads();
   }
 };
 
@@ -271,9 +281,11 @@ struct FusedCta {
 // single-job kernel and the persistent batch kernel, so that a job's result
 // does not depend on which of them ran it.
 template <int NW, int BR, bool PAD = false>
-__device__ __forceinline__ void fused_tile(const FusedArgs &a, float *T, int bx, int by, int bz) {
+__device__ __forceinline__ void fused_tile(const FusedArgs &a, float *T, int bx, int by, int bz,
+                                           float *T2 = nullptr) {
   using Cta = FusedCta<NW, BR, PAD>;
   Cta cta(T, a);
+  cta.T2 = T2;
   const int tid = threadIdx.x;
   cta.lane = tid & 63;
   cta.w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -324,7 +336,8 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, float *T, int bx,
 
 template <int NW, int BR, bool PAD = false>
 __global__ __launch_bounds__(NW * 64) void fused_fp32_kernel(FusedArgs a) {
-  __shared__ __attribute__((aligned(16))) float T[NW * BR * kLDT];
+  constexpr bool DB = NW == 16;  // two LDS buffers (see the file comment)
+  __shared__ __attribute__((aligned(16))) float T[(DB ? 2 : 1) * NW * BR * kLDT];
   // XCD-aware tile order: workgroups are dealt to the 8 XCDs round-robin, so
   // linear id k runs on XCD k mod 8; give each XCD a contiguous range of
   // (split, column tile) pairs in row-major order.
@@ -338,7 +351,7 @@ __global__ __launch_bounds__(NW * 64) void fused_fp32_kernel(FusedArgs a) {
       by = idx / (int)gridDim.x;
     }
   }
-  fused_tile<NW, BR, PAD>(a, T, bx, by, (int)blockIdx.z);
+  fused_tile<NW, BR, PAD>(a, T, bx, by, (int)blockIdx.z, DB ? T + NW * BR * kLDT : nullptr);
 }
 
 // Y[j, c] = scale * sum_s part[s][j][c], splits summed in ascending order.
