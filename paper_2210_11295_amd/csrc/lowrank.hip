@@ -220,11 +220,17 @@ struct SizeOnly {
   }
 };
 
+// Leading dimensions rounded up to 4 elements: the large-tile GEMM takes
+// operands whose rows start at 16-byte boundaries, so every tall product of
+// the randomized SVD runs on it whatever l, m and k are (the logical sizes
+// are unchanged; padding columns are never read).
+inline int64_t ld4(int64_t x) { return (x + 3) & ~int64_t(3); }
+
 // ----------------------------------------------------------------------------
 // Randomized SVD workspace layout.
 template <class A>
 struct RsvdWs {
-  float *W;
+  float *W, *Wt;
   void *apply_ws;
   size_t apply_bytes;
   double *G, *Ginv, *Q1, *G2, *C2inv;
@@ -235,21 +241,23 @@ struct RsvdWs {
   SvdBufs<A> qb, sv;
   void layout(A &a, const bsrht_plan_s *pl, int64_t m, int64_t k) {
     const int64_t l = pl->l, n = pl->n, lq = std::min(l, m);
+    const int64_t l4 = ld4(l), lq4 = ld4(lq), k4 = ld4(k);
     W = a.template take<float>((size_t)(l * m));
+    Wt = a.template take<float>((size_t)(m * l4));
     apply_bytes = apply_ws_bytes(pl, m);
     apply_ws = a.template take<char>(apply_bytes);
     G = a.template take<double>((size_t)(l * l));
-    Ginv = a.template take<double>((size_t)(l * l));
-    Q1 = a.template take<double>((size_t)(m * l));
+    Ginv = a.template take<double>((size_t)(l * l4));
+    Q1 = a.template take<double>((size_t)(m * l4));
     G2 = a.template take<double>((size_t)(l * l));
-    C2inv = a.template take<double>((size_t)(l * l));
-    Q32 = a.template take<float>((size_t)(m * lq));
-    Z = a.template take<float>((size_t)(n * lq));
+    C2inv = a.template take<double>((size_t)(l * l4));
+    Q32 = a.template take<float>((size_t)(m * lq4));
+    Z = a.template take<float>((size_t)(n * lq4));
     gram_part = a.template take<double>((size_t)std::max(
         {gram_partial_elems(m, l), gram_partial_elems(n, lq), (int64_t)1}));
     Gz = a.template take<double>((size_t)(lq * lq));
-    M = a.template take<float>((size_t)(lq * k));
-    Vk = a.template take<float>((size_t)(lq * k));
+    M = a.template take<float>((size_t)(lq * k4));
+    Vk = a.template take<float>((size_t)(lq * k4));
     flag = a.template take<int32_t>(4);
     chol_state = a.template take<char>(cholesky_state_bytes());
     qb.take(a, svd_pad(l), l);
@@ -334,6 +342,7 @@ Task rsvd_task(DevCtx &ctx, const bsrht_plan_s *plan, const float *A, int64_t m,
   hipStream_t s = ctx.s;
   const int64_t n = plan->n, l = plan->l;
   int64_t lq = std::min(l, m);
+  const int64_t l4 = ld4(l), lq4 = ld4(lq), k4 = ld4(k);  // padded leading dimensions
   if (svd_pad(std::max(l, lq)) > 4096) co_return BSRHT_EUNSUPPORTED;
   Carve cv(ws, ws_bytes);
   RsvdWs<Carve> w;
@@ -353,30 +362,33 @@ Task rsvd_task(DevCtx &ctx, const bsrht_plan_s *plan, const float *A, int64_t m,
   // 2. Q = orth(W^T) (m x lq).  l >= m: range(W^T) is all of R^m, Q = I.
   if (l >= m) {
     lq = m;
-    eye_f32_kernel<<<(unsigned)((m * m + 255) / 256), 256, 0, s>>>(w.Q32, m, m);
+    eye_f32_kernel<<<(unsigned)((m * m + 255) / 256), 256, 0, s>>>(w.Q32, m, lq4);
     BSRHT_CO_LAUNCH_CHECK();
   } else {
     // Cholesky-QR2 of W^T: G = W W^T, G = C^T C, Q1 = W^T C^{-1}; then again.
+    // W^T is formed once (m x l, leading dimension l4) so that the Gram and
+    // the product take the large-tile GEMM.
+    BSRHT_CO_TRY(transpose_f32(w.W, l, m, m, w.Wt, l4, s));
     const int gs = gram_splits(m, l);
-    st = gram_f32(w.W, m, l, 1, m, w.G, l, w.gram_part, gs, s);  // X = W^T: X[r][c] = W[c][r]
+    st = gram_f32(w.Wt, m, l, l4, 1, w.G, l, w.gram_part, gs, s);
     if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); co_return st; }
     BSRHT_CO_TRY(cholesky_upper(w.G, l, l, (double)l * kU64, w.flag, w.chol_state, s));
     int32_t hf = 0;
     BSRHT_CO_TRY(co_await readback(ctx, &hf, w.flag, sizeof(hf)));
     int64_t lk = l;  // columns of Q1
     if (hf == 0) {
-      BSRHT_CO_TRY(trinv_upper(w.G, l, l, w.Ginv, l, s));
+      BSRHT_CO_TRY(trinv_upper(w.G, l, l, w.Ginv, l4, s));
       GemmDesc d;
       d.M = m; d.N = l; d.K = l;
-      d.sai = 1; d.sak = m;       // A = W^T
-      d.sbk = l; d.sbj = 1;       // B = C^{-1}
-      d.ldc = l;
-      BSRHT_CO_TRY(gemm_f32f64_f64(d, w.W, w.Ginv, w.Q1, s));
+      d.sai = l4; d.sak = 1;      // A = W^T
+      d.sbk = l4; d.sbj = 1;      // B = C^{-1}
+      d.ldc = l4;
+      BSRHT_CO_TRY(gemm_f32f64_f64(d, w.Wt, w.Ginv, w.Q1, s));
     } else {
       // W^T is rank deficient (e.g. rank(A) < l): an eigen split of
       // G = W W^T keeps the eigenvalues above l u lambda_max and
       // Q1 = W^T V_+ Lam_+^{-1/2}.
-      st = gram_f32(w.W, m, l, 1, m, w.G, l, w.gram_part, gs, s);
+      st = gram_f32(w.Wt, m, l, l4, 1, w.G, l, w.gram_part, gs, s);
       if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); co_return st; }
       BSRHT_CO_TRY(co_await small_svd_task(ctx, w.qb, w.G, l, l, true, info));
       std::vector<double> ev((size_t)l);
@@ -390,20 +402,20 @@ Task rsvd_task(DevCtx &ctx, const bsrht_plan_s *plan, const float *A, int64_t m,
                                                                     w.qb.inv);
       BSRHT_CO_LAUNCH_CHECK();
       const int64_t nce = svd_pad(l);
-      BSRHT_CO_TRY(scale_cols_f64(w.qb.Vs, l, keep, keep, nce, w.qb.inv, w.Ginv, keep, s));
+      BSRHT_CO_TRY(scale_cols_f64(w.qb.Vs, l, keep, keep, nce, w.qb.inv, w.Ginv, l4, s));
       GemmDesc d;
       d.M = m; d.N = keep; d.K = l;
-      d.sai = 1; d.sak = m;
-      d.sbk = keep; d.sbj = 1;
-      d.ldc = keep;
-      BSRHT_CO_TRY(gemm_f32f64_f64(d, w.W, w.Ginv, w.Q1, s));
+      d.sai = l4; d.sak = 1;
+      d.sbk = l4; d.sbj = 1;
+      d.ldc = l4;
+      BSRHT_CO_TRY(gemm_f32f64_f64(d, w.Wt, w.Ginv, w.Q1, s));
       lk = keep;
       or_info_kernel<<<1, 1, 0, s>>>(info, BSRHT_INFO_QB_FALLBACK);
       BSRHT_CO_LAUNCH_CHECK();
     }
     // second pass: G2 = Q1^T Q1, C2, Q = Q1 C2^{-1}
     const int gs2 = gram_splits(m, lk);
-    BSRHT_CO_TRY(gram_f64(w.Q1, m, lk, lk, 1, w.G2, lk, w.gram_part, gs2, s));
+    BSRHT_CO_TRY(gram_f64(w.Q1, m, lk, l4, 1, w.G2, lk, w.gram_part, gs2, s));
     BSRHT_CO_TRY(cholesky_upper(w.G2, lk, lk, 1e-14, w.flag + 1, w.chol_state, s));
     int32_t hf2 = 0;
     BSRHT_CO_TRY(co_await readback(ctx, &hf2, w.flag + 1, sizeof(hf2)));
@@ -411,12 +423,12 @@ Task rsvd_task(DevCtx &ctx, const bsrht_plan_s *plan, const float *A, int64_t m,
       debug_report(__FILE__, __LINE__, "second Cholesky-QR pass", BSRHT_EDEVICE);
       co_return BSRHT_EDEVICE;
     }
-    BSRHT_CO_TRY(trinv_upper(w.G2, lk, lk, w.C2inv, lk, s));
+    BSRHT_CO_TRY(trinv_upper(w.G2, lk, lk, w.C2inv, l4, s));
     GemmDesc d;
     d.M = m; d.N = lk; d.K = lk;
-    d.sai = lk; d.sak = 1;
-    d.sbk = lk; d.sbj = 1;
-    d.ldc = lk;
+    d.sai = l4; d.sak = 1;
+    d.sbk = l4; d.sbj = 1;
+    d.ldc = lq4;  // lk <= lq
     BSRHT_CO_TRY(gemm_f64f64_f32(d, w.Q1, w.C2inv, w.Q32, s));
     lq = lk;
   }
@@ -426,8 +438,8 @@ Task rsvd_task(DevCtx &ctx, const bsrht_plan_s *plan, const float *A, int64_t m,
     GemmDesc d;
     d.M = n; d.N = lq; d.K = m;
     d.sai = lda; d.sak = 1;
-    d.sbk = lq; d.sbj = 1;
-    d.ldc = lq;
+    d.sbk = lq4; d.sbj = 1;
+    d.ldc = lq4;
     const int tslot = timing_begin(BSRHT_TIMING_GEMM_AQ, s);
     st = gemm_f32(d, A, w.Q32, w.Z, s);
     timing_end(tslot, s);
@@ -435,7 +447,7 @@ Task rsvd_task(DevCtx &ctx, const bsrht_plan_s *plan, const float *A, int64_t m,
   }
   // 4. R-factor of Z: Gz = Z^T Z (FP64), Gz = R^T R.
   const int gsz = gram_splits(n, lq);
-  BSRHT_CO_TRY(gram_f32(w.Z, n, lq, lq, 1, w.Gz, lq, w.gram_part, gsz, s));
+  BSRHT_CO_TRY(gram_f32(w.Z, n, lq, lq4, 1, w.Gz, lq, w.gram_part, gsz, s));
   BSRHT_CO_TRY(cholesky_upper(w.Gz, lq, lq, (double)lq * kU32 * kU32, w.flag + 2, w.chol_state, s));
   int32_t hz = 0;
   BSRHT_CO_TRY(co_await readback(ctx, &hz, w.flag + 2, sizeof(hz)));
@@ -446,7 +458,7 @@ Task rsvd_task(DevCtx &ctx, const bsrht_plan_s *plan, const float *A, int64_t m,
     pw = 1;
   } else {
     // rank(Z) < lq: Z^T Z = Vt St^2 Vt^T from its eigen decomposition
-    BSRHT_CO_TRY(gram_f32(w.Z, n, lq, lq, 1, w.Gz, lq, w.gram_part, gsz, s));
+    BSRHT_CO_TRY(gram_f32(w.Z, n, lq, lq4, 1, w.Gz, lq, w.gram_part, gsz, s));
     BSRHT_CO_TRY(co_await small_svd_task(ctx, w.sv, w.Gz, lq, lq, true, info));
     // the Jacobi values are St^2: take square roots through the scale step
     pw = 0;
@@ -462,21 +474,21 @@ Task rsvd_task(DevCtx &ctx, const bsrht_plan_s *plan, const float *A, int64_t m,
       w.sv.S, lq, k, sqrt((double)lq * kU64), 1, w.sv.inv, S, info);
   BSRHT_CO_LAUNCH_CHECK();
   const int64_t keep = std::min(k, lq);
-  BSRHT_CO_TRY(scale_cols_f64_f32(w.sv.Vs, lq, keep, k, nce, w.sv.inv, w.M, k, s));
+  BSRHT_CO_TRY(scale_cols_f64_f32(w.sv.Vs, lq, keep, k, nce, w.sv.inv, w.M, k4, s));
   {
     GemmDesc d;
     d.M = n; d.N = k; d.K = lq;
-    d.sai = lq; d.sak = 1;
-    d.sbk = k; d.sbj = 1;
+    d.sai = lq4; d.sak = 1;
+    d.sbk = k4; d.sbj = 1;
     d.ldc = k;
     BSRHT_CO_TRY(gemm_f32(d, w.Z, w.M, U, s));
   }
-  BSRHT_CO_TRY(scale_cols_f64_f32(w.sv.Vs, lq, keep, k, nce, nullptr, w.Vk, k, s));
+  BSRHT_CO_TRY(scale_cols_f64_f32(w.sv.Vs, lq, keep, k, nce, nullptr, w.Vk, k4, s));
   {
     GemmDesc d;
     d.M = m; d.N = k; d.K = lq;
-    d.sai = lq; d.sak = 1;
-    d.sbk = k; d.sbj = 1;
+    d.sai = lq4; d.sak = 1;
+    d.sbk = k4; d.sbj = 1;
     d.ldc = k;
     BSRHT_CO_TRY(gemm_f32(d, w.Q32, w.Vk, V, s));
   }
@@ -809,10 +821,8 @@ int inv_factor(double *G, int64_t n, double tol, double *F, int64_t *nf, bool *f
 // Q32 (rows x lk, leading dimension ld4(lk)): an orthonormal basis of the
 // columns of X (rows x l, X[r][c] = X[r*sr + c*sc]) by Cholesky-QR2 in FP64;
 // a rank deficient X keeps the lk <= l directions of its Gram's eigen split.
-// Leading dimensions are rounded up to 4 elements, which the large-tile GEMM
-// kernel needs for its 16-byte loads.
-inline int64_t ld4(int64_t x) { return (x + 3) & ~int64_t(3); }
-
+// Leading dimensions are rounded up to 4 elements (ld4), which the
+// large-tile GEMM kernel needs for its 16-byte loads.
 template <class A>
 int orth_basis(const float *X, int64_t rows, int64_t l, int64_t sr, int64_t sc, float *Q32,
                int64_t *lk_out, SvWs<A> &w, int32_t *info, hipStream_t s) {
