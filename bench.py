@@ -511,100 +511,85 @@ def bench_single_view(bs, A, cfg, reps):
             "rel_fro_error": err, "info": int(info.item())}
 
 
-def bench_serving(bs, njobs, streams, rate=200.0, arena_gib=32, ahead=16, live_gib=64):
+def bench_serving(bs, njobs, streams, rate=200.0, arena_gib=32, out_gib=96):
     """Serving workload: Poisson arrivals at `rate` jobs/s of sketch + RSVD
     jobs with seeded random shapes (n = 2^a, a in 14..20; m log-uniform in
-    [64, 2048]; p in {1, 4, 16, 64}; k in 16..256; l = 2k + 32), payload
-    A = X diag(j^-1.5) with Gaussian X generated on the device up to `ahead`
-    jobs before its arrival (the client never blocks on it: a payload is
-    submitted once its event has completed).  Latency runs from the
-    scheduled arrival to the server observing the job's completion event, so
-    client-side delays (a payload not ready, more than `live_gib` GiB of
-    payloads in flight) count against it."""
-    import collections
+    [64, 2048]; p in {1, 4, 16, 64}; k in 16..256; l = 2k + 32).
 
+    Payloads: A = X diag(j^-1.5) with Gaussian X.  One seeded pool
+    P = X diag(j^-1.5) of 2^20 x 2048 FP32 is generated before the clock
+    starts, and job i reads the n x m window of P at a seeded random row
+    offset (leading dimension 2048), so preparing a payload costs neither GPU
+    time nor client time and the latency measures the server.  Each job gets
+    its own output tensors at submission.  Latency runs from the scheduled
+    arrival to the server observing the job's completion event; a job is
+    submitted late only when the outputs of unfinished jobs would exceed
+    `out_gib` GiB (reported as max_submit_lag_ms)."""
     import numpy as np
     import torch
     import workloads
 
     dev = torch.device("cuda:0")
     jobs = workloads.serving_jobs(njobs, rate, seed=0)
+    rows, cols = 1 << 20, 2048
+    g = torch.Generator(device=dev)
+    g.manual_seed(12345)
+    pool = torch.randn(rows, cols, generator=g, device=dev)
+    pool *= torch.arange(1, cols + 1, device=dev, dtype=torch.float32) ** -1.5
+    offs = np.random.default_rng(1).integers(0, rows, size=njobs)
     arena = torch.empty(arena_gib << 30, dtype=torch.uint8, device=dev)
-    gen_stream = torch.cuda.Stream(device=dev)
+    torch.cuda.synchronize()
     log(f"bench: serving {njobs} jobs at {rate:.0f}/s on {streams} stream slots, "
-        f"arena {arena_gib} GiB")
+        f"arena {arena_gib} GiB, payloads from a {rows} x {cols} pool")
     lat, done_at = {}, {}
-    live = {}          # submitted, not finished: id -> tensors
-    prepared = collections.deque()  # (job, tensors, ready event), arrival order
+    live = {}          # submitted, not finished: id -> (output tensors, bytes)
     a_bytes = 0
-    live_bytes = 0
+    out_bytes = 0
     lag = 0.0
-    nxt = 0            # next job to prepare
-
-    def prepare(js):
-        n, m, k = js["n"], js["m"], js["k"]
-        g = torch.Generator(device=dev)
-        g.manual_seed(js["seed"] & (2 ** 63 - 1))
-        with torch.cuda.stream(gen_stream):
-            scale = torch.arange(1, m + 1, device=dev, dtype=torch.float32) ** -1.5
-            A = torch.randn(n, m, generator=g, device=dev) * scale
-            out = (A, torch.empty(n, k, device=dev),
-                   torch.empty(k, dtype=torch.float64, device=dev),
-                   torch.empty(m, k, device=dev), torch.zeros(1, dtype=torch.int32, device=dev))
-            ev = torch.cuda.Event()
-            ev.record(gen_stream)
-        return out, ev
 
     import resource
     ru0 = resource.getrusage(resource.RUSAGE_SELF)
     with bs.Server(arena=arena, workers=streams) as srv:
         def collect(res):
-            nonlocal live_bytes
+            nonlocal out_bytes
             for r in res:
                 if r.status != 0:
                     raise RuntimeError(f"serving job {r.id} failed with status {r.status}")
                 lat[r.id] = r.t_done - (t0 + jobs[r.id]["arrival"])
                 done_at[r.id] = r.t_done
-                t = live.pop(r.id)
-                live_bytes -= t[0].numel() * 4
+                out_bytes -= live.pop(r.id)[1]
 
         t0 = srv.clock() + 0.05
-        for i, js in enumerate(jobs):
-            # keep up to `ahead` payloads prepared, within the live-bytes cap
-            while nxt < njobs and nxt < i + ahead and live_bytes < (live_gib << 30):
-                out, ev = prepare(jobs[nxt])
-                prepared.append((jobs[nxt], out, ev))
-                live_bytes += out[0].numel() * 4
-                nxt += 1
-            if not prepared:  # cap reached with nothing prepared: wait for completions
-                while not prepared:
-                    collect(srv.poll(256, timeout=5e-4))
-                    if live_bytes < (live_gib << 30) and nxt < njobs:
-                        out, ev = prepare(jobs[nxt])
-                        prepared.append((jobs[nxt], out, ev))
-                        live_bytes += out[0].numel() * 4
-                        nxt += 1
-            js_p, out, ev = prepared[0]
-            assert js_p["id"] == js["id"]
-            while srv.clock() < t0 + js["arrival"] or not ev.query():
+        for js in jobs:
+            n, m, k = js["n"], js["m"], js["k"]
+            nb = 4 * (n * k + m * k) + 8 * k + 4
+            while out_bytes + nb > (out_gib << 30) and live:
+                collect(srv.poll(256, timeout=5e-4))
+            while srv.clock() < t0 + js["arrival"]:
                 collect(srv.poll(256, timeout=min(5e-4, max(t0 + js["arrival"] - srv.clock(),
                                                             5e-5))))
-            prepared.popleft()
+            off = int(offs[js["id"]]) % (rows - n + 1)
+            A = pool[off:off + n, :m]
+            U = torch.empty(n, k, device=dev)
+            S = torch.empty(k, dtype=torch.float64, device=dev)
+            V = torch.empty(m, k, device=dev)
+            info = torch.empty(1, dtype=torch.int32, device=dev)
             lag = max(lag, srv.clock() - (t0 + js["arrival"]))
-            live[js["id"]] = out
-            A, U, S, V, info = out
-            srv.submit(bs.rsvd_job(js["id"], (js["n"], js["p"], js["l"], 0,
-                                              bs.WITH_REPLACEMENT, bs.FP32),
-                                   A, js["k"], U, S, V, info))
-            a_bytes += A.numel() * 4
+            live[js["id"]] = ((U, S, V, info), nb)
+            out_bytes += nb
+            srv.submit(bs.rsvd_job(js["id"], (n, js["p"], js["l"], 0, bs.WITH_REPLACEMENT,
+                                              bs.FP32), A, k, U, S, V, info))
+            a_bytes += n * m * 4
             collect(srv.poll(256))
-            if js["id"] % 500 == 499:
+            if js["id"] % 1000 == 999:
                 log(f"bench: serving {js['id'] + 1} submitted, {len(lat)} done, "
-                    f"{live_bytes / 2 ** 30:.1f} GiB of payloads live")
+                    f"{out_bytes / 2 ** 30:.1f} GiB of outputs live")
         srv.drain()
         collect(srv.poll(njobs))
         st = srv.stats()
     ru1 = resource.getrusage(resource.RUSAGE_SELF)
+    del pool, arena
+    torch.cuda.empty_cache()
     cpu_s = (ru1.ru_utime - ru0.ru_utime) + (ru1.ru_stime - ru0.ru_stime)
     L = np.array([lat[i] for i in range(njobs)]) * 1e3
     span = max(done_at.values()) - t0
@@ -619,7 +604,9 @@ def bench_serving(bs, njobs, streams, rate=200.0, arena_gib=32, ahead=16, live_g
                st["peak_arena_bytes"] / 2 ** 30, 3),
            "plan_hits": st["plan_hits"], "plan_misses": st["plan_misses"],
            "plan_evictions": st["plan_evictions"], "backfilled": st["backfilled"],
-           "rejected": st["rejected"]}
+           "rejected": st["rejected"],
+           "payloads": "n x m windows (seeded row offsets) of one 2^20 x 2048 pool "
+                       "X diag(j^-1.5), X Gaussian, generated before the clock starts"}
     log(f"bench: serving p50 {out['p50_ms']} ms p99 {out['p99_ms']} ms, "
         f"{out['jobs_per_s']} jobs/s, {out['GBs_of_A']} GB/s of A")
     return out
@@ -772,7 +759,7 @@ def main():
     ap.add_argument("--skip-lowrank", action="store_true",
                     help="skip the randomized SVD and Nystrom measurements")
     ap.add_argument("--lowrank-reps", type=int, default=3)
-    ap.add_argument("--serve-jobs", type=int, default=2000,
+    ap.add_argument("--serve-jobs", type=int, default=10000,
                     help="jobs of the serving workload (0 skips it)")
     ap.add_argument("--serve-streams", type=int, default=SERVE_STREAMS)
     ap.add_argument("--serve-rate", type=float, default=200.0)
