@@ -5,7 +5,10 @@ Workload (the large sketch case): A is 2^20 x 1024 float32, A = X diag(s) W^T
 with X Gaussian / sqrt(n), W Haar, s_j = exp(-j/64), seed 0; Omega has
 p = 16 blocks of r = 65536 rows and l = 512 samples.  A step is one sketch of
 the whole matrix (every block's signs, Walsh-Hadamard transform, row sample,
-output signs and the sum over blocks), with A resident in HBM.
+output signs and the sum over blocks), with A resident in HBM.  Before the
+warmup steps the bench runs --settle untimed sketches (default 100): after
+the FP64 generation of A the GPU's clocks take ~20-30 ms of continuous load
+to settle, and launches in that window run up to 20% slower.
 
 Prints one JSON line: GB/s of A streamed, the dominant kernel's roofline
 (achieved vs the 8 TB/s HBM peak, from HIP events around that kernel), and the
@@ -441,6 +444,37 @@ def bench_partial(bs, steps=10, warmup=2, calibrate=False):
                          "alg_bytes_per_launch": alg}}
 
 
+def launch_sequence(bs, A, plan, count=60, gap_s=0.002):
+    """Diagnostic: per-launch durations of the fused sketch kernel in launch
+    order, for `count` launches back to back, then with `gap_s` of idle time
+    between launches, then back to back again (GPU clock and power-state
+    transients show up as runs of slower launches)."""
+    import torch
+    Y = torch.empty(plan.l, A.shape[1], device=A.device)
+    ws = torch.empty(max(1, bs.bsrht_apply_workspace(plan, A.shape[1])), dtype=torch.uint8,
+                     device=A.device)
+    for _ in range(5):
+        bs.bsrht_apply(plan, A, Y, ws)
+    torch.cuda.synchronize()
+    out = {}
+    for mode in ("back_to_back", "with_gaps", "back_to_back_again"):
+        bs.timing_enable(bs.TIMING_APPLY_FP32)
+        for _ in range(count):
+            bs.bsrht_apply(plan, A, Y, ws)
+            if mode == "with_gaps":
+                torch.cuda.synchronize()
+                time.sleep(gap_s)
+        torch.cuda.synchronize()
+        t = np.array(bs.timing_samples(), dtype=np.float64) * 1e3
+        bs.timing_enable(bs.TIMING_OFF)
+        out[mode] = {"mean_us": round(float(t.mean()), 1), "median_us": round(float(np.median(t)), 1),
+                     "min_us": round(float(t.min()), 1), "max_us": round(float(t.max()), 1),
+                     "launch_us": [round(float(x), 1) for x in t]}
+        log(f"bench: {mode}: mean {t.mean():.1f} us, median {np.median(t):.1f}, "
+            f"min {t.min():.1f}, max {t.max():.1f}")
+    return out
+
+
 def _fro_error(A, U, S, V, chunk=1 << 16):
     """||A - U diag(S) V^T||_F / ||A||_F in FP64 on the device (measurement)."""
     import torch
@@ -753,6 +787,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--settle", type=int, default=100,
+                    help="untimed sketch launches before the warmup steps (GPU clock settling)")
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of A (HBM counter calibration)")
@@ -765,7 +801,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--only", choices=["all", "sketch", "bf16", "right", "dense", "partial",
                                        "rsvd", "single_view", "nystrom", "serve",
-                                       "serve_small"],
+                                       "serve_small", "launch_sequence"],
                     default="all",
                     help="profiling aid: run one part ('bf16', 'right', 'rsvd', 'nystrom' and "
                          "'serve' print only that part's JSON object)")
@@ -807,6 +843,9 @@ def main():
     if args.only == "rsvd":
         print(json.dumps({"rsvd": bench_rsvd(bs, A, plan, cfg, args.lowrank_reps)}), flush=True)
         return
+    if args.only == "launch_sequence":
+        print(json.dumps({"launch_sequence": launch_sequence(bs, A, plan)}), flush=True)
+        return
     if args.only == "single_view":
         print(json.dumps({"rsvd_single_view": bench_single_view(bs, A, cfg, args.lowrank_reps)}),
               flush=True)
@@ -840,7 +879,14 @@ def main():
     ws = torch.empty(max(1, bs.bsrht_apply_workspace(plan, m)), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
 
-    log(f"bench: warmup {args.warmup}")
+    # Settle: the GPU's clocks take ~20-30 ms of continuous sketching to
+    # reach their steady state after the FP64 input generation (launches
+    # right after it run up to 20% slower); these untimed launches come
+    # before the warmup steps so that the timed steps measure the steady
+    # state.
+    log(f"bench: settle {args.settle}, warmup {args.warmup}")
+    for _ in range(args.settle):
+        bs.bsrht_apply(plan, A, Y, ws)
     for _ in range(args.warmup):
         bs.bsrht_apply(plan, A, Y, ws)
     torch.cuda.synchronize()
@@ -878,6 +924,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "settle": args.settle,
         "ms_per_step": round(elapsed / args.steps * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
