@@ -8,7 +8,8 @@ the whole matrix (every block's signs, Walsh-Hadamard transform, row sample,
 output signs and the sum over blocks), with A resident in HBM.  Before the
 warmup steps the bench runs --settle untimed sketches (default 100): after
 the FP64 generation of A the GPU's clocks take ~20-30 ms of continuous load
-to settle, and launches in that window run up to 20% slower.
+to settle, and launches in that window run up to 30% slower.  The split-BF16
+and right-side legs settle the same way.
 
 Prints one JSON line: GB/s of A streamed, the dominant kernel's roofline
 (achieved vs the 8 TB/s HBM peak, from HIP events around that kernel), and the
@@ -263,7 +264,7 @@ def bench_stream_read(bs, A, reps=20, warmup=3):
             "kernel": "stream_read_kernel", "reps": reps, **stats}
 
 
-def bench_split_bf16(bs, A, cfg, steps, warmup, Y_fp32):
+def bench_split_bf16(bs, A, cfg, steps, warmup, Y_fp32, settle=0):
     """The same sketch with the H_16 factor on BF16 matrix cores (A split
     into BF16 hi + lo, FP32 accumulation), on the same A and plan seed."""
     import torch
@@ -273,7 +274,7 @@ def bench_split_bf16(bs, A, cfg, steps, warmup, Y_fp32):
     ws = torch.empty(max(1, bs.bsrht_apply_workspace(plan, m)), dtype=torch.uint8,
                      device=A.device)
     stream = torch.cuda.current_stream()
-    for _ in range(warmup):
+    for _ in range(settle + warmup):
         bs.bsrht_apply(plan, A, Y, ws, stream)
     torch.cuda.synchronize()
     bs.timing_enable(bs.TIMING_APPLY_BF16)
@@ -305,7 +306,7 @@ def bench_split_bf16(bs, A, cfg, steps, warmup, Y_fp32):
             "rel_diff_vs_fp32": diff}, Y
 
 
-def bench_right(bs, A, cfg, steps, warmup, Y_col):
+def bench_right(bs, A, cfg, steps, warmup, Y_col, settle=0):
     """The sketch applied from the right, Y = A^T Omega^T, on the transpose of
     the same input (1024 x 2^20 row-major: the orientation of Algorithm 1),
     with the same plan; compared with the column sketch of A."""
@@ -317,7 +318,7 @@ def bench_right(bs, A, cfg, steps, warmup, Y_col):
     ws = torch.empty(max(1, bs.bsrht_apply_right_workspace(plan, m)), dtype=torch.uint8,
                      device=A.device)
     stream = torch.cuda.current_stream()
-    for _ in range(warmup):
+    for _ in range(settle + warmup):
         bs.bsrht_apply_right(plan, At, Y, ws, stream)
     torch.cuda.synchronize()
     bs.timing_enable(bs.TIMING_APPLY_RIGHT)
@@ -852,7 +853,8 @@ def main():
         return
     if args.only == "bf16":
         Yf = bs.bsrht_apply(plan, A)
-        out_b, _ = bench_split_bf16(bs, A, cfg, args.steps, args.warmup, Yf)
+        out_b, _ = bench_split_bf16(bs, A, cfg, args.steps, args.warmup, Yf,
+                                   settle=args.settle)
         if args.copy_calibration:
             _copy_calibration(A)
         print(json.dumps({"split_bf16": out_b}), flush=True)
@@ -869,7 +871,7 @@ def main():
         return
     if args.only == "right":
         Yf = bs.bsrht_apply(plan, A)
-        out_r = bench_right(bs, A, cfg, args.steps, args.warmup, Yf)
+        out_r = bench_right(bs, A, cfg, args.steps, args.warmup, Yf, settle=args.settle)
         if args.copy_calibration:
             _copy_calibration(A)
         print(json.dumps({"right_apply": out_r}), flush=True)
@@ -946,8 +948,10 @@ def main():
     if args.only == "sketch":
         args.skip_lowrank = True
     else:
-        out["split_bf16"], Y_bf16 = bench_split_bf16(bs, A, cfg, args.steps, args.warmup, Y)
-        out["right_apply"] = bench_right(bs, A, cfg, args.steps, args.warmup, Y)
+        out["split_bf16"], Y_bf16 = bench_split_bf16(bs, A, cfg, args.steps, args.warmup, Y,
+                                                     settle=args.settle)
+        out["right_apply"] = bench_right(bs, A, cfg, args.steps, args.warmup, Y,
+                                         settle=args.settle)
         out["dense_sketch"] = bench_dense(bs, A, cfg, 5, 1, elapsed / args.steps * 1e3)
     if not args.skip_lowrank:
         out["rsvd"] = bench_rsvd(bs, A, plan, cfg, args.lowrank_reps)
