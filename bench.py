@@ -394,7 +394,7 @@ def bench_dense(bs, A, cfg, steps, warmup, bsrht_ms):
     return out
 
 
-def bench_partial(bs, steps=10, warmup=2, calibrate=False):
+def bench_partial(bs, steps=10, warmup=2, calibrate=False, settle=0):
     """The partial block SRHT (section 2: blocks padded with zeros to a power
     of two) on section 4.2's tall-skinny shape on one GPU: A 10^7 x 200 FP32
     (8 GB), p = 16 (r = 625000 rows, padded to 2^20), l = 2000.  l > 1024
@@ -409,7 +409,7 @@ def bench_partial(bs, steps=10, warmup=2, calibrate=False):
     plan = bs.Plan(n, p, l, seed, device=dev)
     Y = torch.empty(l, m, dtype=torch.float32, device=dev)
     ws = torch.empty(max(1, bs.bsrht_apply_workspace(plan, m)), dtype=torch.uint8, device=dev)
-    for _ in range(warmup):
+    for _ in range(settle + warmup):
         bs.bsrht_apply(plan, A, Y, ws)
     torch.cuda.synchronize()
     bs.timing_enable(bs.TIMING_APPLY_FP32)
@@ -443,6 +443,67 @@ def bench_partial(bs, steps=10, warmup=2, calibrate=False):
                          "kernel": "fused_fp32_kernel<16, 16, true>",
                          "kernel_avg_us": round(kern_ms * 1e3, 2), **stats,
                          "alg_bytes_per_launch": alg}}
+
+
+def bench_nystrom_sketch(bs, steps=10, warmup=2, settle=20):
+    """The two sketches of Algorithm 2 on the 65536 x 65536 SPD input
+    (p = 64, r = 1024, l = 1024: the 16-wave kernels): W = Omega A over the
+    16 GiB A, then B = Omega Y over Y = W^T (65536 x 1024), in both
+    precisions.  Per-launch kernel times of each pass; the roofline takes
+    the algorithmic bytes of both passes (A and Y read once, W and B
+    written, tables) over the summed kernel time."""
+    import torch
+    import workloads
+    c = workloads.CONFIGS["c5_nystrom"]
+    n, l, p = c["n"], c["l"], c["p"]
+    dev = torch.device("cuda:0")
+    log(f"bench: nystrom sketches, generating SPD {n}x{n}")
+    A = workloads.spd(n, c["d"], c["spectrum"], c["seed"], device=dev)
+    tables = 8 * l + 4 * ((n + 31) // 32) + 4 * p * ((l + 31) // 32)
+    alg = (n * n * 4 + l * n * 4 + tables) + (n * l * 4 + l * l * 4 + tables)
+    out = {"workload": f"A {n} x {n} float32 (s_j = j^-3), p={p}, l={l}; "
+                       f"W = Omega A, then B = Omega W^T", "alg_bytes_both_passes": alg}
+    for name, prec, hook, kern in (
+            ("fp32", bs.FP32, bs.TIMING_APPLY_FP32, "fused_fp32_kernel<16, 16>"),
+            ("split_bf16", bs.SPLIT_BF16, bs.TIMING_APPLY_BF16, "fused_bf16_kernel<16, 16>")):
+        plan = bs.Plan(n, p, l, c["seed"], precision=prec, device=dev)
+        W = torch.empty(l, n, dtype=torch.float32, device=dev)
+        Y = torch.empty(n, l, dtype=torch.float32, device=dev)
+        B = torch.empty(l, l, dtype=torch.float32, device=dev)
+        ws = torch.empty(max(1, bs.bsrht_apply_workspace(plan, n),
+                             bs.bsrht_apply_workspace(plan, l)), dtype=torch.uint8, device=dev)
+        for _ in range(settle):
+            bs.bsrht_apply(plan, A, W, ws)
+        for _ in range(warmup):
+            bs.bsrht_apply(plan, A, W, ws)
+            Y.copy_(W.t())
+            bs.bsrht_apply(plan, Y, B, ws)
+        torch.cuda.synchronize()
+        bs.timing_enable(hook)
+        for _ in range(steps):
+            bs.bsrht_apply(plan, A, W, ws)
+            Y.copy_(W.t())
+            bs.bsrht_apply(plan, Y, B, ws)
+        torch.cuda.synchronize()
+        t = np.array(bs.timing_samples(), dtype=np.float64) * 1e3
+        bs.timing_enable(bs.TIMING_OFF)
+        ta, ty = t[0::2], t[1::2]
+        both = float(ta.mean() + ty.mean())
+        achieved = alg / (both * 1e-6) / 1e9
+        out[name] = {"pass_A_us": round(float(ta.mean()), 1),
+                     "pass_A_median_us": round(float(np.median(ta)), 1),
+                     "pass_Y_us": round(float(ty.mean()), 1),
+                     "both_passes_ms": round(both / 1e3, 4),
+                     "A_GBs": round(n * n * 4 / (ta.mean() * 1e-6) / 1e9, 1),
+                     "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
+                                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": round(achieved / HBM_PEAK_GBS, 4), "kernel": kern}}
+        log(f"bench: nystrom sketches {name}: A pass {ta.mean():.1f} us, Y pass "
+            f"{ty.mean():.1f} us -> {achieved:.1f} GB/s")
+        del W, Y, B, ws
+    del A
+    torch.cuda.empty_cache()
+    return out
 
 
 def launch_sequence(bs, A, plan, count=60, gap_s=0.002):
@@ -802,7 +863,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--only", choices=["all", "sketch", "bf16", "right", "dense", "partial",
                                        "rsvd", "single_view", "nystrom", "serve",
-                                       "serve_small", "launch_sequence"],
+                                       "serve_small", "launch_sequence", "nystrom_sketch"],
                     default="all",
                     help="profiling aid: run one part ('bf16', 'right', 'rsvd', 'nystrom' and "
                          "'serve' print only that part's JSON object)")
@@ -824,13 +885,18 @@ def main():
     if args.only == "serve_small":
         print(json.dumps({"serving_small_sketch": bench_serving_small(bs)}), flush=True)
         return
+    if args.only == "nystrom_sketch":
+        print(json.dumps({"nystrom_sketch": bench_nystrom_sketch(
+            bs, steps=args.steps, warmup=args.warmup, settle=args.settle // 5)}), flush=True)
+        return
     if args.only == "nystrom":
         print(json.dumps({"nystrom": bench_nystrom(bs, args.lowrank_reps,
                                                    with_oracle=not args.skip_cpu_baseline)}),
               flush=True)
         return
     if args.only == "partial":
-        print(json.dumps({"partial_sketch": bench_partial(bs, calibrate=args.copy_calibration)}),
+        print(json.dumps({"partial_sketch": bench_partial(bs, calibrate=args.copy_calibration,
+                                                          settle=args.settle // 5)}),
               flush=True)
         return
     cfg = dict(workloads.CONFIGS["c2_fp32_apply"])
@@ -965,7 +1031,7 @@ def main():
         out["nystrom"] = bench_nystrom(bs, args.lowrank_reps,
                                        with_oracle=not args.skip_cpu_baseline)
         torch.cuda.empty_cache()
-        out["partial_sketch"] = bench_partial(bs)
+        out["partial_sketch"] = bench_partial(bs, settle=args.settle // 5)
     if args.serve_jobs > 0 and args.only == "all":
         out["serving"] = bench_serving(bs, args.serve_jobs, args.serve_streams,
                                        rate=args.serve_rate)
