@@ -935,36 +935,33 @@ __device__ __forceinline__ double jg_entry(double csi, double cpi, double csj, d
   return roti ? (diag ? gij + dgi : (pair ? 0.0 : g)) : g;
 }
 
-// 1/x and 1/sqrt(x) for normal x: the hardware approximations refined by two
-// Newton steps each (the rotation's latency chain is the sweep's critical
-// path; the IEEE division and square root sequences are several times longer).
-__device__ __forceinline__ double jg_rcp(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  y = fma(y, fma(-x, y, 1.0), y);
-  return fma(y, fma(-x, y, 1.0), y);
-}
-__device__ __forceinline__ double jg_rsqrt(double x) {
-  const double h = 0.5 * x;
-  double y = __builtin_amdgcn_rsq(x);
-  y = fma(y, fma(-h * y, y, 0.5), y);
-  return fma(y, fma(-h * y, y, 0.5), y);
-}
-
 // The rotation of pair (a, b) from the entries al = g_aa, be = g_bb, ga = g_ab.
+// Its tangent only decides how far the (a, b) entry drops, so it is formed in
+// FP32: t = 2 ga sgn(d) / (|d| + sqrt(d^2 + 4 ga^2)), d = be - al (the smaller
+// root of t^2 + 2 zeta t - 1 = 0, zeta = d / (2 ga)), with d and 2 ga first
+// scaled by the power of two that brings the larger into [1, 2), so neither
+// overflows and the smaller underflows only where the pair cannot rotate.
+// The entry then drops to ~2e-7 of its size, and the pair's next meeting
+// takes the rest.  c = 1/sqrt(1 + t^2) is refined from its FP32 value to FP64
+// by two Newton steps and s = c t, so c^2 + s^2 = 1 to working precision and
+// the accumulated J stays orthogonal.  This chain is the sweep's critical
+// path: FP64 division and square root would take several times longer.
 __device__ __forceinline__ void jg_set_rotation(JgRound &P, int a, int b, double al, double be,
                                                 double ga, double tol, double floor2,
                                                 bool &any) {
   // a column at the rounding level of the whole matrix counts as converged
   const bool rot = fabs(ga) > tol * sqrt(al * be) && ga != 0.0 && fmin(al, be) > floor2;
-  // t = tan of the angle zeroing the (a, b) entry of [al ga; ga be]: the
-  // smaller root of t^2 + 2 zeta t - 1 = 0, zeta = (be - al) / (2 ga).  It is
-  // formed whether or not the pair rotates (the test is off the critical
-  // path) and discarded when it does not.
-  const double zeta = (be - al) * jg_rcp(2.0 * ga);
-  const double az = fabs(zeta);
-  const double q = fma(zeta, zeta, 1.0);
-  const double tr = az > 1e150 ? 0.5 * jg_rcp(zeta) : copysign(jg_rcp(az + q * jg_rsqrt(q)), zeta);
-  const double cr = jg_rsqrt(fma(tr, tr, 1.0));
+  const double d = be - al, g2 = 2.0 * ga;
+  const int e = __builtin_amdgcn_frexp_exp(fmax(fabs(d), fabs(g2)));
+  const float df = (float)ldexp(d, -e), gf = (float)ldexp(g2, -e);
+  const float h = __builtin_amdgcn_sqrtf(fmaf(df, df, gf * gf));
+  const float tf = (df < 0.f ? -gf : gf) * __builtin_amdgcn_rcpf(fabsf(df) + h);
+  const float cf = __builtin_amdgcn_rsqf(fmaf(tf, tf, 1.f));
+  const double tr = (double)tf;
+  const double hx = 0.5 * fma(tr, tr, 1.0);
+  double cr = (double)cf;
+  cr = fma(cr, fma(-hx * cr, cr, 0.5), cr);
+  cr = fma(cr, fma(-hx * cr, cr, 0.5), cr);
   const double t = rot ? tr : 0.0, c = rot ? cr : 1.0, sn = rot ? cr * tr : 0.0;
   // column a of the rotation is c e_a - sn e_b, column b is sn e_a + c e_b;
   // the new diagonal entries are al - t ga and be + t ga
