@@ -570,10 +570,21 @@ def bench_rsvd(bs, A, plan, cfg, reps):
     lq = min(cfg["l"], m)
     gemm_ms = gms / max(gl, 1)
     err = _fro_error(A, U, S, V)
+    # Z = A Q runs on the BF16 matrix cores with both operands split (six
+    # products for an FP32 plan, three for a split-BF16 plan) when A's rows
+    # are 16-byte aligned, as here
+    products = 3 if plan.precision == bs.SPLIT_BF16 else 6
+    alg = 2.0 * n * m * lq
     return {"ms": round(dt * 1e3, 2), "k": k, "l": cfg["l"],
+            "precision": "split_bf16" if plan.precision == bs.SPLIT_BF16 else "fp32",
             "gemm_AQ_ms": round(gemm_ms, 3),
-            "gemm_AQ_TFLOPs": round(2.0 * n * m * lq / (gemm_ms * 1e-3) / 1e12, 2),
-            "gemm_AQ_frac_fp32_mfma_peak": round(2.0 * n * m * lq / (gemm_ms * 1e-3) / 157.3e12, 4),
+            "gemm_AQ": {"form": f"split-BF16 MFMA, {products} products",
+                        "alg_TFLOPs": round(alg / (gemm_ms * 1e-3) / 1e12, 2),
+                        "roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": 2500.0,
+                                     "achieved": round(products * alg / (gemm_ms * 1e-3) / 1e12,
+                                                       1),
+                                     "frac": round(products * alg / (gemm_ms * 1e-3) / 2.5e15,
+                                                   4)}},
             "rel_fro_error": err, "info": int(info.item())}
 
 
@@ -908,7 +919,10 @@ def main():
     torch.cuda.synchronize()
     plan = bs.Plan(n, p, l, seed, device=dev)
     if args.only == "rsvd":
-        print(json.dumps({"rsvd": bench_rsvd(bs, A, plan, cfg, args.lowrank_reps)}), flush=True)
+        print(json.dumps({"rsvd": bench_rsvd(bs, A, plan, cfg, args.lowrank_reps),
+                          "rsvd_split_bf16": bench_rsvd(
+                              bs, A, bs.Plan(n, p, l, seed, precision=bs.SPLIT_BF16, device=dev),
+                              cfg, args.lowrank_reps)}), flush=True)
         return
     if args.only == "launch_sequence":
         print(json.dumps({"launch_sequence": launch_sequence(bs, A, plan)}), flush=True)
@@ -1021,6 +1035,9 @@ def main():
         out["dense_sketch"] = bench_dense(bs, A, cfg, 5, 1, elapsed / args.steps * 1e3)
     if not args.skip_lowrank:
         out["rsvd"] = bench_rsvd(bs, A, plan, cfg, args.lowrank_reps)
+        out["rsvd_split_bf16"] = bench_rsvd(
+            bs, A, bs.Plan(n, p, l, seed, precision=bs.SPLIT_BF16, device=dev), cfg,
+            args.lowrank_reps)
         out["rsvd_single_view"] = bench_single_view(bs, A, cfg, args.lowrank_reps)
     if not args.skip_cpu_baseline:
         log("bench: the CPU oracle (timing and reference errors)")

@@ -37,6 +37,17 @@ int gemm_f32f32_f64(const GemmDesc &d, const float *A, const float *B, double *C
 int gemm_f32_splitk(const GemmDesc &d, const float *A, const float *B, float *C,
                     double *partials, int splits, hipStream_t s);
 
+// C (M x N, ldc) = A (M x K, FP32, row-major, lda a multiple of 4, 16-byte
+// aligned) times B (K x N, FP32, row stride ldb) on the BF16 matrix cores,
+// both operands split into `parts` BF16 parts (2: three products, ~2^-16
+// relative; 3: six products, the accuracy of an FP32 product).  ws: device
+// scratch of gemm_bf16x_ws_bytes(N, K, parts) bytes for B's split planes.
+int gemm_f32_bf16x(const float *A, int64_t lda, const float *B, int64_t ldb, float *C,
+                   int64_t ldc, int64_t M, int64_t N, int64_t K, int parts, void *ws,
+                   size_t ws_bytes, hipStream_t s);
+size_t gemm_bf16x_ws_bytes(int64_t N, int64_t K, int parts);
+bool gemm_bf16x_eligible(const float *A, int64_t lda);
+
 // G = X^T X (K x K FP64) for X[r][c] = X[r*sr + c*sc], r < n, c < K; the row
 // range is split into `splits` FP64 partials (K*K each, in `partials`)
 // summed in split order.

@@ -228,6 +228,28 @@ inline int64_t ld4(int64_t x) { return (x + 3) & ~int64_t(3); }
 
 // ----------------------------------------------------------------------------
 // Randomized SVD workspace layout.
+
+// BF16 parts per operand of the tall products Z = A Q and U = Z M: three
+// (FP32-level accuracy) for FP32 plans, two for split-BF16 plans.
+inline int tall_product_parts(const bsrht_plan_s *pl) {
+  return pl->precision == BSRHT_SPLIT_BF16 ? 2 : 3;
+}
+
+// C = A B for the tall products: split-BF16 matrix cores when A's rows are
+// 16-byte aligned, else the FP32 matrix-core GEMM.
+inline int tall_product(const float *A, int64_t lda, const float *B, int64_t ldb, float *C,
+                        int64_t ldc, int64_t M, int64_t N, int64_t K, int parts, void *ws,
+                        size_t ws_bytes, hipStream_t s) {
+  if (gemm_bf16x_eligible(A, lda))
+    return gemm_f32_bf16x(A, lda, B, ldb, C, ldc, M, N, K, parts, ws, ws_bytes, s);
+  GemmDesc d;
+  d.M = M; d.N = N; d.K = K;
+  d.sai = lda; d.sak = 1;
+  d.sbk = ldb; d.sbj = 1;
+  d.ldc = ldc;
+  return gemm_f32(d, A, B, C, s);
+}
+
 template <class A>
 struct RsvdWs {
   float *W, *Wt;
@@ -238,10 +260,13 @@ struct RsvdWs {
   double *gram_part, *Gz;
   int32_t *flag;
   void *chol_state;
+  void *xws;  // split BF16 planes of Q, then of M (split-BF16 tall products)
+  size_t xws_bytes;
   SvdBufs<A> qb, sv;
   void layout(A &a, const bsrht_plan_s *pl, int64_t m, int64_t k) {
     const int64_t l = pl->l, n = pl->n, lq = std::min(l, m);
     const int64_t l4 = ld4(l), lq4 = ld4(lq), k4 = ld4(k);
+    const int parts = tall_product_parts(pl);
     W = a.template take<float>((size_t)(l * m));
     Wt = a.template take<float>((size_t)(m * l4));
     apply_bytes = apply_ws_bytes(pl, m);
@@ -260,6 +285,8 @@ struct RsvdWs {
     Vk = a.template take<float>((size_t)(lq * k4));
     flag = a.template take<int32_t>(4);
     chol_state = a.template take<char>(cholesky_state_bytes());
+    xws_bytes = std::max(gemm_bf16x_ws_bytes(lq, m, parts), gemm_bf16x_ws_bytes(k, lq, parts));
+    xws = a.template take<char>(xws_bytes);
     qb.take(a, svd_pad(l), l);
     sv.take(a, svd_pad(lq), k);
   }
@@ -434,14 +461,10 @@ Task rsvd_task(DevCtx &ctx, const bsrht_plan_s *plan, const float *A, int64_t m,
   }
 
   // 3. Z = A Q  (n x lq): the paper's Z = Q^T A_p, transposed; matrix cores.
+  const int parts = tall_product_parts(plan);
   {
-    GemmDesc d;
-    d.M = n; d.N = lq; d.K = m;
-    d.sai = lda; d.sak = 1;
-    d.sbk = lq4; d.sbj = 1;
-    d.ldc = lq4;
     const int tslot = timing_begin(BSRHT_TIMING_GEMM_AQ, s);
-    st = gemm_f32(d, A, w.Q32, w.Z, s);
+    st = tall_product(A, lda, w.Q32, lq4, w.Z, lq4, n, lq, m, parts, w.xws, w.xws_bytes, s);
     timing_end(tslot, s);
     if (st != BSRHT_OK) { debug_report(__FILE__, __LINE__, "step", st); co_return st; }
   }
@@ -475,14 +498,7 @@ Task rsvd_task(DevCtx &ctx, const bsrht_plan_s *plan, const float *A, int64_t m,
   BSRHT_CO_LAUNCH_CHECK();
   const int64_t keep = std::min(k, lq);
   BSRHT_CO_TRY(scale_cols_f64_f32(w.sv.Vs, lq, keep, k, nce, w.sv.inv, w.M, k4, s));
-  {
-    GemmDesc d;
-    d.M = n; d.N = k; d.K = lq;
-    d.sai = lq4; d.sak = 1;
-    d.sbk = k4; d.sbj = 1;
-    d.ldc = k;
-    BSRHT_CO_TRY(gemm_f32(d, w.Z, w.M, U, s));
-  }
+  BSRHT_CO_TRY(tall_product(w.Z, lq4, w.M, k4, U, k, n, k, lq, parts, w.xws, w.xws_bytes, s));
   BSRHT_CO_TRY(scale_cols_f64_f32(w.sv.Vs, lq, keep, k, nce, nullptr, w.Vk, k4, s));
   {
     GemmDesc d;
