@@ -173,11 +173,21 @@ __global__ __launch_bounds__(kBThreads) void gemm_big_kernel(GemmDesc d, const T
   __shared__ __attribute__((aligned(16))) TS Bs[2][KT][kBN + kBPad];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  if (d.upper_tiles && blockIdx.x > blockIdx.y) return;  // mirrored by the caller
-  const int64_t i0 = (int64_t)blockIdx.x * kBM, j0 = (int64_t)blockIdx.y * kBN;
+  // Tile order: workgroups are dealt to the 8 XCDs round-robin by linear id
+  // L, so L runs tile (L mod 8) * (G / 8) + L / 8 of the grid's natural order
+  // (G a multiple of 8, else unchanged): each XCD takes a contiguous range,
+  // whose tiles share their row and column panels (and, for split-K, the
+  // rows of their k range) through that XCD's L2.
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int64_t G = (int64_t)gx * gy * gridDim.z;
+  const int64_t L = blockIdx.x + (int64_t)gx * (blockIdx.y + (int64_t)gy * blockIdx.z);
+  const int64_t lt = (G & 7) == 0 ? (L & 7) * (G >> 3) + (L >> 3) : L;
+  const int bxr = (int)(lt % gx), byr = (int)((lt / gx) % gy), bzr = (int)(lt / ((int64_t)gx * gy));
+  if (d.upper_tiles && bxr > byr) return;  // mirrored by the caller
+  const int64_t i0 = (int64_t)bxr * kBM, j0 = (int64_t)byr * kBN;
   int64_t kchunk = (d.K + gridDim.z - 1) / gridDim.z;
   kchunk = (kchunk + KT - 1) / KT * KT;
-  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t kb = (int64_t)bzr * kchunk;
   const int64_t ke = min(d.K, kb + kchunk);
   const int wi = (wave >> 1) * 64, wj = (wave & 1) * 64;
   const bool ij_inside = i0 + kBM <= d.M && j0 + kBN <= d.N;
@@ -283,7 +293,7 @@ __global__ __launch_bounds__(kBThreads) void gemm_big_kernel(GemmDesc d, const T
     if (more) stage(cur ^ 1);
     __syncthreads();
   }
-  TC *Cz = C + (int64_t)blockIdx.z * d.split_stride;
+  TC *Cz = C + (int64_t)bzr * d.split_stride;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
