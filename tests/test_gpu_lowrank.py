@@ -136,6 +136,53 @@ def test_rsvd_split_bf16_subsample():
     assert err <= 1.01 * err_o
 
 
+@pytest.mark.parametrize("lda_pad", [1, 4, 30])
+def test_rsvd_product_forms_agree(lda_pad):
+    """The tall products Z = A Q and U = Z M run on split-BF16 matrix cores
+    with six products when A's rows are 16-byte aligned (lda a multiple of 4)
+    and on the FP32 matrix cores otherwise.  The same A, once contiguous
+    (m = 100, aligned) and once as a view with lda = 100 + lda_pad (101 and
+    130: the FP32 form; 104: the split form with a strided A): both within 1%
+    of the oracle, and their rank-k approximations equal to FP32 accuracy."""
+    dev = device()
+    n, m, p, l, k = 8192, 100, 8, 64, 20
+    say("rsvd product forms", n, m, p, l, k, "lda", m + lda_pad)
+    A = workloads.lowrank_tall(n, m, "inv_sq", 13, device=dev)
+    big = torch.zeros(n, m + lda_pad, device=dev)
+    big[:, :m] = A
+    Av = big[:, :m]
+    assert Av.stride(0) == m + lda_pad
+    plan = bs.Plan(n, p, l, 19, device=dev)
+    Ua, Sa, Va, _ = bs.rsvd(plan, A, k)
+    Ub, Sb, Vb, _ = bs.rsvd(plan, Av, k)
+    torch.cuda.synchronize()
+    Ah = to64(A)
+    Uo, So, Vo = lowrank.rsvd(rng.Plan(n, p, l, 19), Ah, k)
+    err_o = metrics.lowrank_fro_error(Ah, Uo, So, Vo)
+    for U, S, V in ((Ua, Sa, Va), (Ub, Sb, Vb)):
+        assert metrics.lowrank_fro_error(Ah, to64(U), to64(S), to64(V)) <= 1.01 * err_o
+    Ra = (to64(Ua) * to64(Sa)) @ to64(Va).T
+    Rb = (to64(Ub) * to64(Sb)) @ to64(Vb).T
+    assert metrics.rel_fro(Ra, Rb) < 1e-5
+
+
+@pytest.mark.parametrize("n,m,p,l,k", [
+    (4096, 300, 16, 37, 11),    # ragged k tail of both products
+    (8192, 100, 8, 64, 20),
+])
+def test_rsvd_split_bf16_matches_oracle(n, m, p, l, k):
+    """Split-BF16 plans: sketch and tall products (three products) on BF16
+    matrix cores, error within 1% of the FP64 oracle's."""
+    dev = device()
+    say("rsvd split-bf16", n, m, p, l, k)
+    A = workloads.lowrank_tall(n, m, "inv_sq", 3, device=dev)
+    U, S, V, info, err, err_o, So = _rsvd_case(n, m, p, l, k, A, 7, precision=bs.SPLIT_BF16)
+    say("  err gpu", err, "oracle", err_o, "info", info)
+    assert err <= 1.01 * err_o
+    Uh = to64(U)
+    assert np.max(np.abs(Uh.T @ Uh - np.eye(k))) < 1e-3
+
+
 def test_nystrom_split_bf16():
     dev = device()
     n, p, l, k = 4096, 4, 256, 64
