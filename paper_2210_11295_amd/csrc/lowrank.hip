@@ -752,6 +752,8 @@ struct SvWs {
   double *PhQ, *Gc, *F1, *F2, *T1, *T2, *T3t, *T4t, *Ct, *Mv, *Mu;
   int32_t *flag;
   void *chol_state;
+  void *xws;  // split BF16 planes of Mu (U = Y Mu on split-BF16 matrix cores)
+  size_t xws_bytes;
   SvdBufs<A> qb, sv;
   void layout(A &a, const bsrht_plan_s *om, const bsrht_plan_s *ga, const bsrht_plan_s *ph,
               const bsrht_plan_s *ps, int64_t k) {
@@ -797,6 +799,8 @@ struct SvWs {
     Vk32 = a.template take<float>((size_t)(l * k));
     flag = a.template take<int32_t>(4);
     chol_state = a.template take<char>(cholesky_state_bytes());
+    xws_bytes = gemm_bf16x_ws_bytes(k, l, 3);
+    xws = a.template take<char>(xws_bytes);
     qb.take(a, svd_pad(l), l);
     sv.take(a, svd_pad(l), k);
   }
@@ -1072,12 +1076,8 @@ int rsvd_single_view(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi, b
     BSRHT_TRY(gemm_f64(d, w.Fq, w.Mu, w.Mv, s));
   }
   BSRHT_TRY(scale_cols_f64_f32(w.Mv, l, k, k, k, nullptr, w.Mu32, k, s));
-  GemmDesc d;
-  d.M = N1; d.N = k; d.K = l;
-  d.sai = l; d.sak = 1;
-  d.sbk = k; d.sbj = 1;
-  d.ldc = k;
-  return gemm_f32(d, w.Y, w.Mu32, U, s);
+  // the tall product with FP32-level accuracy (six split-BF16 products)
+  return tall_product(w.Y, l, w.Mu32, k, U, k, N1, k, l, 3, w.xws, w.xws_bytes, s);
 }
 
 }  // extern "C"
