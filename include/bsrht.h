@@ -99,8 +99,9 @@ size_t bsrht_plan_bytes(int64_t n, int64_t p, int64_t l);
  * power of two gives section 2's partial SRHT: Omega^(i) is the first r
  * columns of the rp-point SRHT, i.e. each block of A is treated as padded
  * with rp - r zero rows (never stored).  Such plans sketch with the FP32
- * kernels whatever their precision; bsrht_apply_right evaluates them
- * directly (O(n) per output) and bsrht_apply_batch rejects them.
+ * kernels whatever their precision; bsrht_apply_right streams them with the
+ * padded variant of its kernel when rp >= 256 (else it evaluates them
+ * directly, O(n) per output) and bsrht_apply_batch rejects them.
  *
  * n, p, l     : Omega is l x n with p blocks of r = n/p columns.  Requires
  *               p >= 1, p | n, 1 <= l <= n, and l <= rp for sampling
@@ -190,8 +191,9 @@ size_t bsrht_apply_right_workspace(bsrht_plan_t plan, int64_t m);
  * block's full transform is stored.  The sum over blocks is taken in a fixed
  * order, so results are bitwise repeatable.  The butterflies run in FP32
  * whatever the plan's precision (the split-BF16 form is a bsrht_apply
- * variant only).  Blocks of r >= 256 columns take the streaming kernel;
- * shorter blocks an O(n) per output direct evaluation.
+ * variant only).  Blocks of r >= 256 columns, or padded to rp >= 256
+ * (section 2's partial SRHT), take the streaming kernel; shorter blocks an
+ * O(n) per output direct evaluation.
  *
  * A   : device float32, m x n (n = the plan's n), row-major, leading
  *       dimension lda >= n.

@@ -27,6 +27,13 @@
 // registers); A is read once.  Column splits (for parallelism) write m x l
 // partials that a second kernel sums in fixed split order and scales by
 // 1/sqrt(l).  Blocks shorter than 256 columns use a direct evaluation.
+//
+// Padded blocks (section 2's partial SRHT: r < 2^log2r, each block of A
+// treated as r columns and zeros): the launch walks only the chunks that
+// hold columns of A (ceil(r / b) per block), each at column i*r + x_hi*b of
+// A, with its signs, H_{r/b} factor and Dt block taken at its place in the
+// padded layout; the last chunk of a block loads its columns past r as
+// zeros (addresses clamped into the block, values masked).
 #include <limits.h>
 
 #include "common.h"
@@ -60,6 +67,11 @@ struct RightArgs {
   int64_t split_stride;
   float scale;
   const int32_t *order;  // sample of each gather lane
+  // PAD plans (r < 2^log2r): the blocks hold r columns of A each and are
+  // padded with zeros; chunk qr of the launch's chunks is chunk qr mod cr of
+  // block qr / cr, and chunks past a block's r columns are skipped.
+  int64_t r_cols;
+  int cr;  // chunks per block that hold columns of A
 };
 
 // Unscaled Walsh-Hadamard transform of N values held in registers.
@@ -103,7 +115,7 @@ __device__ __forceinline__ int tofs(int x, int g4) {
   return x * kRT + 4 * (g4 ^ ((x >> 2) & 15));
 }
 
-template <int NW>
+template <int NW, bool PAD = false>
 struct RightCta {
   static constexpr int B = 64 * NW;      // chunk columns
   static constexpr int LOG2B = 6 + (NW == 8 ? 3 : 2);
@@ -124,22 +136,62 @@ struct RightCta {
 
   __device__ __forceinline__ RightCta(float *T_, const RightArgs &a_) : T(T_), a(a_) {}
 
+  // Chunk q of the launch in the padded layout: its index qp among all
+  // 2^log2r / b chunks of the blocks (which the signs and H_{r/b} use), the
+  // column of A where it starts and how many of its columns hold data.
+  __device__ __forceinline__ void locate(int q, int &qp, int64_t &xa, int &vr) const {
+    if constexpr (PAD) {
+      const int i = __builtin_amdgcn_readfirstlane(q / a.cr);
+      const int xh = q - i * a.cr;
+      qp = (i << cpb_log2) + xh;
+      xa = (int64_t)i * a.r_cols + (int64_t)xh * B;
+      const int64_t rem = a.r_cols - (int64_t)xh * B;
+      vr = rem < B ? (int)rem : B;
+    } else {
+      qp = q;
+      xa = (int64_t)q * B;
+      vr = B;
+    }
+  }
+
   // Loads chunk q into v, its D^(i) words into d and the Dt^(i) word of
   // sample j into dt (raw words: decoding them here would make the wave wait
   // for the loads just issued).
   __device__ __forceinline__ void load(float (&v)[64], uint32_t (&d)[K + 1], int q) const {
-    const int64_t x0 = (int64_t)q * B;
-    const __amdgpu_buffer_rsrc_t rs = make_rsrc(wavebase + x0);
+    int qp, vr;
+    int64_t xa;
+    locate(q, qp, xa, vr);
+    const int64_t x0 = (int64_t)qp * B;  // the chunk's first column in the padded layout
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(wavebase + xa);
     const int voff = lane * 16;
+    if (!PAD || vr == B) {
 #pragma unroll
-    for (int s = 0; s < RW; ++s) {
+      for (int s = 0; s < RW; ++s) {
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const i32x4 t = __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 1024 * k, rowoff[s], kAuxNT);
-        v[(4 * k + 0) * RW + s] = __int_as_float(t.x);
-        v[(4 * k + 1) * RW + s] = __int_as_float(t.y);
-        v[(4 * k + 2) * RW + s] = __int_as_float(t.z);
-        v[(4 * k + 3) * RW + s] = __int_as_float(t.w);
+        for (int k = 0; k < K; ++k) {
+          const i32x4 t = __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 1024 * k, rowoff[s], kAuxNT);
+          v[(4 * k + 0) * RW + s] = __int_as_float(t.x);
+          v[(4 * k + 1) * RW + s] = __int_as_float(t.y);
+          v[(4 * k + 2) * RW + s] = __int_as_float(t.z);
+          v[(4 * k + 3) * RW + s] = __int_as_float(t.w);
+        }
+      }
+    } else {
+      // the block's last chunk with data: columns past r are the padding.
+      // Each value is loaded from a column clamped into the block's data
+      // (so every address lies in A) and masked to zero past r.
+#pragma unroll
+      for (int s = 0; s < RW; ++s) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int x = 256 * k + 4 * lane + c;
+            const int xc = x < vr ? x : vr - 1;
+            const uint32_t u = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, 4 * xc, rowoff[s], kAuxNT);
+            v[(4 * k + c) * RW + s] = __uint_as_float(x < vr ? u : 0u);
+          }
+        }
       }
     }
     // D^(i) words of this lane's columns: column x0 + k*256 + 4*lane + c is
@@ -148,7 +200,7 @@ struct RightCta {
 #pragma unroll
     for (int k = 0; k < K; ++k)
       d[k] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rd, (lane >> 3) * 4 + 32 * k, 0, 0);
-    d[K] = a.Dtbits[(int64_t)(q >> cpb_log2) * a.dt_words + (jc >> 5)];
+    d[K] = a.Dtbits[(int64_t)(qp >> cpb_log2) * a.dt_words + (jc >> 5)];
   }
 
   // One chunk; with PREFETCH the next chunk's loads are issued first.
@@ -206,7 +258,10 @@ struct RightCta {
     __syncthreads();
     if (jok) {
       const uint32_t dtbit = (dcur[K] >> (j & 31)) & 1u;
-      const uint32_t xhi = (uint32_t)q & ((1u << cpb_log2) - 1u);
+      int qp, vr;
+      int64_t xa;
+      locate(q, qp, xa, vr);
+      const uint32_t xhi = (uint32_t)qp & ((1u << cpb_log2) - 1u);
       const uint32_t par = (uint32_t)__popc(rhi & xhi) & 1u;
       const float sgn = (par ^ dtbit) ? -1.f : 1.f;
       // Rows 4g .. 4g+3 of chunk column pos sit at float offset
@@ -233,9 +288,9 @@ struct RightCta {
   }
 };
 
-template <int NW>
+template <int NW, bool PAD = false>
 __global__ __launch_bounds__(NW * 64) void right_fp32_kernel(RightArgs a) {
-  using Cta = RightCta<NW>;
+  using Cta = RightCta<NW, PAD>;
   __shared__ __attribute__((aligned(16))) float T[Cta::B * kRT];
   // XCD-aware tile order (workgroup k runs on XCD k mod 8): each XCD gets a
   // contiguous range of (split, row tile) pairs.
@@ -306,9 +361,9 @@ __global__ __launch_bounds__(NW * 64) void right_fp32_kernel(RightArgs a) {
 }
 
 // Direct evaluation of eq. (2.3) from the right for blocks shorter than the
-// smallest chunk (2^log2r < 256) and for blocks padded with zeros (r <
-// 2^log2r: columns i*r .. i*r + r - 1 of A, D signs at bits i*2^log2r + x):
-// one thread per output entry, O(n) work each.
+// smallest chunk (2^log2r < 256; with padding, r < 2^log2r: columns
+// i*r .. i*r + r - 1 of A, D signs at bits i*2^log2r + x): one thread per
+// output entry, O(n) work each.
 __global__ void right_direct_kernel(const float *__restrict__ A, int64_t lda, int m,
                                     const int32_t *__restrict__ R,
                                     const uint32_t *__restrict__ Dbits,
@@ -339,23 +394,26 @@ __global__ void right_direct_kernel(const float *__restrict__ A, int64_t lda, in
 }
 
 struct RightLaunch {
-  bool direct = false;
+  bool direct = false, pad = false;
   int nw = 8;
-  int rtiles = 0, groups = 0, splits = 1, cps = 0, total_chunks = 0;
+  int rtiles = 0, groups = 0, splits = 1, cps = 0, total_chunks = 0, cr = 0;
   size_t ws = 0;
 };
 
 RightLaunch choose_right(const bsrht_plan_s *pl, int64_t m) {
   RightLaunch L;
-  if (pl->rp < 256 || pl->r != pl->rp) {
+  if (pl->rp < 256) {
     L.direct = true;
     return L;
   }
-  L.nw = pl->r >= 512 ? 8 : 4;
+  L.pad = pl->r != pl->rp;
+  L.nw = pl->rp >= 512 ? 8 : 4;
   const int b = 64 * L.nw;
   // LDS: 128 KiB per workgroup at b = 512 (one per CU), 64 KiB at b = 256.
   const int per_cu = L.nw == 8 ? 1 : 2;
-  L.total_chunks = (int)(pl->n / b);
+  // chunks holding columns of A: all of them, or ceil(r / b) per padded block
+  L.cr = (int)((pl->r + b - 1) / b);
+  L.total_chunks = L.pad ? (int)(pl->p * L.cr) : (int)(pl->n / b);
   L.rtiles = (int)((m + kRT - 1) / kRT);
   const int spp = L.nw * 64;
   L.groups = (int)((pl->l + spp - 1) / spp);
@@ -373,7 +431,10 @@ template <int NW>
 int launch_right(const RightLaunch &L, const RightArgs &a, hipStream_t s) {
   dim3 grid((unsigned)L.rtiles, (unsigned)L.splits, (unsigned)L.groups);
   const int tslot = timing_begin(BSRHT_TIMING_APPLY_RIGHT, s);
-  right_fp32_kernel<NW><<<grid, NW * 64, 0, s>>>(a);
+  if (L.pad)
+    right_fp32_kernel<NW, true><<<grid, NW * 64, 0, s>>>(a);
+  else
+    right_fp32_kernel<NW, false><<<grid, NW * 64, 0, s>>>(a);
   timing_end(tslot, s);
   BSRHT_LAUNCH_CHECK();
   return BSRHT_OK;
@@ -417,6 +478,8 @@ int apply_right_fp32(const bsrht_plan_s *pl, const float *A, int64_t m, int64_t 
   a.log2r = pl->log2r;
   a.chunks_per_split = L.cps;
   a.total_chunks = L.total_chunks;
+  a.r_cols = pl->r;
+  a.cr = L.cr;
   if (L.splits > 1) {
     a.out = static_cast<float *>(ws);
     a.ldo = pl->l;

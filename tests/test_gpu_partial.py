@@ -75,15 +75,36 @@ def test_partial_equals_power_of_two_plan_on_padded_input():
     assert metrics.rel_fro(to64(Y), to64(Yp)) < 2e-6
 
 
-def test_partial_right_sketch():
+@pytest.mark.parametrize("n,p,l,m,lda_pad", [
+    (1200, 4, 50, 19, 0),       # r = 300 -> 512: one chunk per block, partial
+    (2800, 4, 300, 70, 3),      # r = 700 -> 1024: a full and a partial chunk; odd lda
+    (800, 4, 77, 65, 0),        # r = 200 -> 256: 4-wave kernel (256-column chunks)
+    (4000, 2, 600, 130, 0),     # r = 2000 -> 2048: 3 full + 1 partial chunk, two
+                                # sample groups, a ragged second row tile
+    (3074, 2, 40, 9, 1),        # r = 1537 -> 2048: odd block starts
+    (400, 4, 30, 12, 0),        # r = 100 -> 128: direct evaluation
+])
+def test_partial_right_sketch(n, p, l, m, lda_pad):
+    """Y = A Omega^T on padded plans: the streaming right-side kernel walks
+    the chunks that hold columns of A (the last one of a block masked past
+    r); blocks padded to fewer than 256 columns take the direct evaluation."""
     dev = device()
-    n, p, l, m = 1200, 4, 50, 19        # r = 300 -> 512
+    say("partial right", n, p, l, m, lda_pad)
     plan = bs.Plan(n, p, l, 4, device=dev)
-    A = workloads.gaussian_rows(m, n, "inv_sq", 4, device=dev)
+    A0 = workloads.gaussian_rows(m, n, "inv_sq", 4, device=dev)
+    if lda_pad:
+        big = torch.zeros(m, n + lda_pad, device=dev)
+        big[:, :n] = A0
+        A = big[:, :n]
+    else:
+        A = A0
     Y = bs.bsrht_apply_right(plan, A)
+    Y2 = bs.bsrht_apply_right(plan, A)
     torch.cuda.synchronize()
-    err = metrics.rel_fro(to64(Y), sketch.sketch_right(rng.Plan(n, p, l, 4), to64(A)))
+    err = metrics.rel_fro(to64(Y), sketch.sketch_right(rng.Plan(n, p, l, 4), to64(A0)))
+    say("  rel err", err)
     assert err <= TOL
+    assert torch.equal(Y, Y2)
 
 
 def test_partial_rsvd():
