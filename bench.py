@@ -348,7 +348,7 @@ def bench_right(bs, A, cfg, steps, warmup, Y_col, settle=0):
                         f"column workload), p={p}, l={l}, seed {seed}",
             "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                         "traffic": traffic, "kernel": "right_fp32_kernel<8>",
+                         "traffic": traffic, "kernel": "right_fp32_kernel<8, false>",
                          "kernel_avg_us": round(kern_avg_ms * 1e3, 2), **stats,
                          "alg_bytes_per_launch": alg_bytes},
             "rel_diff_vs_column_sketch": diff}
