@@ -82,8 +82,8 @@ __global__ __launch_bounds__(kXThreads, 2) void gemm_bf16x_kernel(XArgs g) {
   // The loads are branch-free (a branch around them makes the wait-count pass
   // drain every load in flight where the paths join): rows past M read row
   // M - 1 and k past K re-reads the last in-range quad, and such values are
-  // zeroed by selects.  lda is a multiple of 4 and at least K, so every quad
-  // read lies inside its row.
+  // zeroed by bit masks.  lda is a multiple of 4 and at least K, so every
+  // quad read lies inside its row.
   const int srow = tid >> 1, skh = (tid & 1) * 16;
   const int64_t arow = i0 + srow;
   const bool arow_in = arow < g.M;
