@@ -1075,10 +1075,31 @@ __global__ __launch_bounds__(512) void jacobi_gram16_kernel(JacobiBlockArgs ja) 
   }
   __syncthreads();
 
+  // A pair step in which every one of the 120 column pairs passes the
+  // convergence test on the freshly formed G makes no rotation (without a
+  // rotation G never changes within the sweep), so it ends here: the last
+  // sweep of a run, and the converged pairs of the sweeps before it, cost the
+  // loads and the Gram only.  The test is the one the sweep applies.
+  const double floor2 = *ja.floor2, tol = ja.tol;
+  {
+    bool need = false;
+    if (tid < C * (C - 1) / 2) {
+      int t = tid, a = 0;  // pair tid -> (a, b), a < b, in row order
+      while (t >= C - 1 - a) {
+        t -= C - 1 - a;
+        ++a;
+      }
+      const int b = a + 1 + t;
+      const double *G = Gs[0];
+      const double al = G[a * LG + a], be = G[b * LG + b], ga = G[a * LG + b];
+      need = fabs(ga) > tol * sqrt(al * be) && ga != 0.0 && fmin(al, be) > floor2;
+    }
+    if (!__syncthreads_or(need)) return;
+  }
+
   // 2. One cyclic sweep over the 120 pairs on G, 8 disjoint pairs per round.
   // Every LDS read a thread needs in a round is issued at once: the partners
   // follow from the round number.
-  const double floor2 = *ja.floor2, tol = ja.tol;
   bool any = false;
   if (tid >= PT && tid < PT + C / 2) {
     int a, b;
