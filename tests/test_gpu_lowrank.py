@@ -166,6 +166,27 @@ def test_rsvd_product_forms_agree(lda_pad):
     assert metrics.rel_fro(Ra, Rb) < 1e-5
 
 
+@pytest.mark.parametrize("n,m,p,l,k,precision", [
+    (96, 20, 1, 16, 5, bs.FP32),          # fewer rows than one 128-row tile, K = 20 < 32
+    (256, 12, 2, 8, 1, bs.FP32),          # rank 1, K = 12 (one partial quad row)
+    (1000, 36, 8, 24, 24, bs.FP32),       # ragged rows (1000 = 7 * 128 + 104), k = l
+    (640, 44, 4, 40, 7, bs.SPLIT_BF16),   # three products on a ragged shape
+])
+def test_rsvd_small_shapes(n, m, p, l, k, precision):
+    """Shapes at the edges of the tall-product kernel's tiles (rows, k tail,
+    columns): within 1% of the oracle's error.  The samples are drawn without
+    replacement: with l of ~128 rows drawn with replacement a repeated row is
+    likely, and the sketch's range then has fewer than l directions (the GPU
+    keeps the range's directions, the oracle's QR adds an arbitrary one)."""
+    dev = device()
+    say("rsvd small", n, m, p, l, k, precision)
+    A = workloads.lowrank_tall(n, m, "inv_sq", 5, device=dev)
+    U, S, V, info, err, err_o, So = _rsvd_case(n, m, p, l, k, A, 23, mode=rng.WITHOUT_REPLACEMENT,
+                                               precision=precision)
+    say("  err gpu", err, "oracle", err_o, "info", info)
+    assert err <= 1.01 * err_o
+
+
 @pytest.mark.parametrize("n,m,p,l,k", [
     (4096, 300, 16, 37, 11),    # ragged k tail of both products
     (8192, 100, 8, 64, 20),
