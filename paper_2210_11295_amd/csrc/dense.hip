@@ -654,11 +654,17 @@ __global__ __launch_bounds__(64 * kTrinvWaves) void trinv_upper_kernel(
 //
 // Blocking: the columns form nc/W blocks of W.  One launch is one round of a
 // round-robin over block pairs; a workgroup forms the Gram matrix of its pair
-// (2W columns), runs one cyclic sweep over the 2W(2W-1)/2 column pairs on it
-// (W disjoint pairs at a time), recording the rotations in a 2W x 2W matrix
-// J, and then updates the pair's columns of X (and, when accumulating, of V)
-// as X J.  A sweep is nc/W - 1 launches; sweeps repeat until one performs no
-// rotation.
+// (2W columns), runs rounds of W disjoint 2x2 rotations on it, recording the
+// rotations in a 2W x 2W matrix J, and then updates the pair's columns of X
+// (and, when accumulating, of V) as X J.  The general form runs one cyclic
+// sweep over all 2W(2W-1)/2 column pairs at every meeting; the 16-column form
+// does so in round 0 of a sweep only, where every block meets a partner, and
+// rotates the W^2 cross pairs alone in the other rounds (the intra-block
+// pairs would otherwise be met nc/W - 1 times per sweep; a model of both
+// orders on the Nystrom and R-factor problems ends in the same number of
+// sweeps, give or take one).  Every column pair is thus tested at least once
+// per sweep.  A sweep is nc/W - 1 launches; sweeps repeat until one performs
+// no rotation.
 struct JacobiBlockArgs {
   double *X;
   int nr;
@@ -933,6 +939,24 @@ __device__ __forceinline__ int jg_partner(int r, int x) {
   return y < 0 ? y + 15 : (y >= 15 ? y - 15 : y);
 }
 
+// Inner rounds of a pair step.  Full: the cyclic order over all 16 columns
+// (15 rounds, rr_pair(16, r, .)).  Cross: the 64 pairs of a column of the
+// first block with one of the second (8 rounds; round r pairs column x < 8
+// with column 8 + ((x + r) mod 8)).
+__device__ __forceinline__ void jg_pair(bool full, int r, int p, int &a, int &b) {
+  if (full) {
+    rr_pair(16, r, p, a, b);
+  } else {
+    a = p;
+    b = 8 + ((p + r) & 7);
+  }
+}
+
+__device__ __forceinline__ int jg_part(bool full, int r, int x) {
+  if (full) return jg_partner(r, x);
+  return x < 8 ? 8 + ((x + r) & 7) : ((x - r) & 7);
+}
+
 // Entry (i, j) of J_r^T G J_r from the round's rotation coefficients of
 // columns i and j (cs: on the column itself, cp: on its partner) and the four
 // entries of G it combines; an entry of a rotated pair's own 2x2 block is set
@@ -1081,15 +1105,24 @@ __global__ __launch_bounds__(512) void jacobi_gram16_kernel(JacobiBlockArgs ja) 
   // sweep of a run, and the converged pairs of the sweeps before it, cost the
   // loads and the Gram only.  The test is the one the sweep applies.
   const double floor2 = *ja.floor2, tol = ja.tol;
+  const bool full = ja.round == 0;
+  const int nrounds = full ? C - 1 : W;
   {
     bool need = false;
-    if (tid < C * (C - 1) / 2) {
-      int t = tid, a = 0;  // pair tid -> (a, b), a < b, in row order
-      while (t >= C - 1 - a) {
-        t -= C - 1 - a;
-        ++a;
+    if (tid < (full ? C * (C - 1) / 2 : W * W)) {
+      int a, b;
+      if (full) {
+        int t = tid;  // pair tid -> (a, b), a < b, in row order
+        a = 0;
+        while (t >= C - 1 - a) {
+          t -= C - 1 - a;
+          ++a;
+        }
+        b = a + 1 + t;
+      } else {
+        a = tid >> 3;
+        b = W + (tid & 7);
       }
-      const int b = a + 1 + t;
       const double *G = Gs[0];
       const double al = G[a * LG + a], be = G[b * LG + b], ga = G[a * LG + b];
       need = fabs(ga) > tol * sqrt(al * be) && ga != 0.0 && fmin(al, be) > floor2;
@@ -1097,19 +1130,21 @@ __global__ __launch_bounds__(512) void jacobi_gram16_kernel(JacobiBlockArgs ja) 
     if (!__syncthreads_or(need)) return;
   }
 
-  // 2. One cyclic sweep over the 120 pairs on G, 8 disjoint pairs per round.
-  // Every LDS read a thread needs in a round is issued at once: the partners
-  // follow from the round number.
+  // 2. The rounds on G, 8 disjoint pairs per round: in round 0 of a sweep
+  // one cyclic pass over all 120 pairs (every block has a partner in round 0,
+  // so each intra-block pair is met once per sweep), in the other rounds the
+  // 64 cross pairs only.  Every LDS read a thread needs in a round is issued
+  // at once: the partners follow from the round number.
   bool any = false;
   if (tid >= PT && tid < PT + C / 2) {
     int a, b;
-    rr_pair(C, 0, tid - PT, a, b);
+    jg_pair(full, 0, tid - PT, a, b);
     const double *G = Gs[0];
     jg_set_rotation(Ps[0], a, b, G[a * LG + a], G[b * LG + b], G[a * LG + b], tol, floor2, any);
   }
   __syncthreads();
   int cur = 0;
-  for (int ir = 0; ir < C - 1; ++ir) {
+  for (int ir = 0; ir < nrounds; ++ir) {
     const JgRound &P = Ps[ir & 1];
     const double *G = Gs[cur];
     if (tid < C * C) {
@@ -1117,7 +1152,7 @@ __global__ __launch_bounds__(512) void jacobi_gram16_kernel(JacobiBlockArgs ja) 
       double *G2 = Gs[cur ^ 1];
       double *J2 = Js[cur ^ 1];
       const int i = tid >> 4, j = tid & 15;
-      const int pi = jg_partner(ir, i), pj = jg_partner(ir, j);
+      const int pi = jg_part(full, ir, i), pj = jg_part(full, ir, j);
       const double csi = P.cself[i], cpi = P.cpart[i], csj = P.cself[j], cpj = P.cpart[j];
       const double g = jg_entry(csi, cpi, csj, cpj, P.rotc[i], P.dg[i], j == i, j == pi,
                                 G[i * LG + j], G[i * LG + pj], G[pi * LG + j], G[pi * LG + pj]);
@@ -1127,12 +1162,12 @@ __global__ __launch_bounds__(512) void jacobi_gram16_kernel(JacobiBlockArgs ja) 
         G2[j * LG + i] = g;
       }
       J2[i * LG + j] = jn;
-    } else if (tid >= PT && tid < PT + C / 2 && ir + 1 < C - 1) {
+    } else if (tid >= PT && tid < PT + C / 2 && ir + 1 < nrounds) {
       // the next round's pair (a, b) needs entries (a, a), (b, b), (a, b) of
       // the updated G: formed here exactly as the threads above form them
       int a, b;
-      rr_pair(C, ir + 1, tid - PT, a, b);
-      const int pa = jg_partner(ir, a), pb = jg_partner(ir, b);
+      jg_pair(full, ir + 1, tid - PT, a, b);
+      const int pa = jg_part(full, ir, a), pb = jg_part(full, ir, b);
       const double csa = P.cself[a], cpa = P.cpart[a], csb = P.cself[b], cpb = P.cpart[b];
       const int rota = P.rotc[a], rotb = P.rotc[b];
       const double dga = P.dg[a], dgb = P.dg[b];
