@@ -969,6 +969,17 @@ __device__ __forceinline__ double jg_entry(double csi, double cpi, double csj, d
   return roti ? (diag ? gij + dgi : (pair ? 0.0 : g)) : g;
 }
 
+// The convergence test of pair (a, b): |g_ab| > tol sqrt(g_aa g_bb), taken on
+// the squares (tol2 = tol^2), which keeps a square root off the critical path
+// of the sweep (G's entries are squared column norms and inner products of
+// the columns, far from overflow when squared for any matrix of FP32-range
+// entries); a column at the rounding level of the whole matrix counts as
+// converged.
+__device__ __forceinline__ bool jg_needs_rotation(double al, double be, double ga, double tol2,
+                                                  double floor2) {
+  return ga * ga > tol2 * (al * be) && ga != 0.0 && fmin(al, be) > floor2;
+}
+
 // The rotation of pair (a, b) from the entries al = g_aa, be = g_bb, ga = g_ab.
 // Its tangent only decides how far the (a, b) entry drops, so it is formed in
 // FP32: t = 2 ga sgn(d) / (|d| + sqrt(d^2 + 4 ga^2)), d = be - al (the smaller
@@ -981,10 +992,9 @@ __device__ __forceinline__ double jg_entry(double csi, double cpi, double csj, d
 // the accumulated J stays orthogonal.  This chain is the sweep's critical
 // path: FP64 division and square root would take several times longer.
 __device__ __forceinline__ void jg_set_rotation(JgRound &P, int a, int b, double al, double be,
-                                                double ga, double tol, double floor2,
+                                                double ga, double tol2, double floor2,
                                                 bool &any) {
-  // a column at the rounding level of the whole matrix counts as converged
-  const bool rot = fabs(ga) > tol * sqrt(al * be) && ga != 0.0 && fmin(al, be) > floor2;
+  const bool rot = jg_needs_rotation(al, be, ga, tol2, floor2);
   const double d = be - al, g2 = 2.0 * ga;
   const int e = __builtin_amdgcn_frexp_exp(fmax(fabs(d), fabs(g2)));
   const float df = (float)ldexp(d, -e), gf = (float)ldexp(g2, -e);
@@ -1010,6 +1020,7 @@ __device__ __forceinline__ void jg_set_rotation(JgRound &P, int a, int b, double
   any |= rot;
 }
 
+template <bool FULL>
 __global__ __launch_bounds__(512) void jacobi_gram16_kernel(JacobiBlockArgs ja) {
   constexpr int W = 8, C = 16, NT = 512, LG = C + 1, NW = NT / 64;
   constexpr int LD = kJg16Ld;
@@ -1104,9 +1115,9 @@ __global__ __launch_bounds__(512) void jacobi_gram16_kernel(JacobiBlockArgs ja) 
   // rotation G never changes within the sweep), so it ends here: the last
   // sweep of a run, and the converged pairs of the sweeps before it, cost the
   // loads and the Gram only.  The test is the one the sweep applies.
-  const double floor2 = *ja.floor2, tol = ja.tol;
-  const bool full = ja.round == 0;
-  const int nrounds = full ? C - 1 : W;
+  const double floor2 = *ja.floor2, tol2 = ja.tol * ja.tol;
+  constexpr bool full = FULL;
+  constexpr int nrounds = full ? C - 1 : W;
   {
     bool need = false;
     if (tid < (full ? C * (C - 1) / 2 : W * W)) {
@@ -1125,7 +1136,7 @@ __global__ __launch_bounds__(512) void jacobi_gram16_kernel(JacobiBlockArgs ja) 
       }
       const double *G = Gs[0];
       const double al = G[a * LG + a], be = G[b * LG + b], ga = G[a * LG + b];
-      need = fabs(ga) > tol * sqrt(al * be) && ga != 0.0 && fmin(al, be) > floor2;
+      need = jg_needs_rotation(al, be, ga, tol2, floor2);
     }
     if (!__syncthreads_or(need)) return;
   }
@@ -1140,7 +1151,7 @@ __global__ __launch_bounds__(512) void jacobi_gram16_kernel(JacobiBlockArgs ja) 
     int a, b;
     jg_pair(full, 0, tid - PT, a, b);
     const double *G = Gs[0];
-    jg_set_rotation(Ps[0], a, b, G[a * LG + a], G[b * LG + b], G[a * LG + b], tol, floor2, any);
+    jg_set_rotation(Ps[0], a, b, G[a * LG + a], G[b * LG + b], G[a * LG + b], tol2, floor2, any);
   }
   __syncthreads();
   int cur = 0;
@@ -1165,19 +1176,23 @@ __global__ __launch_bounds__(512) void jacobi_gram16_kernel(JacobiBlockArgs ja) 
     } else if (tid >= PT && tid < PT + C / 2 && ir + 1 < nrounds) {
       // the next round's pair (a, b) needs entries (a, a), (b, b), (a, b) of
       // the updated G: formed here exactly as the threads above form them
+      // (G is stored exactly symmetric, so g_{pa,a} = g_{a,pa}).  All reads
+      // are issued before the arithmetic: this chain sets the round's length.
       int a, b;
       jg_pair(full, ir + 1, tid - PT, a, b);
       const int pa = jg_part(full, ir, a), pb = jg_part(full, ir, b);
       const double csa = P.cself[a], cpa = P.cpart[a], csb = P.cself[b], cpb = P.cpart[b];
       const int rota = P.rotc[a], rotb = P.rotc[b];
       const double dga = P.dg[a], dgb = P.dg[b];
-      const double al = jg_entry(csa, cpa, csa, cpa, rota, dga, true, false, G[a * LG + a],
-                                 G[a * LG + pa], G[pa * LG + a], G[pa * LG + pa]);
-      const double be = jg_entry(csb, cpb, csb, cpb, rotb, dgb, true, false, G[b * LG + b],
-                                 G[b * LG + pb], G[pb * LG + b], G[pb * LG + pb]);
-      const double ga = jg_entry(csa, cpa, csb, cpb, rota, dga, false, b == pa, G[a * LG + b],
-                                 G[a * LG + pb], G[pa * LG + b], G[pa * LG + pb]);
-      jg_set_rotation(Ps[(ir + 1) & 1], a, b, al, be, ga, tol, floor2, any);
+      const double gaa = G[a * LG + a], gapa = G[a * LG + pa], gpapa = G[pa * LG + pa];
+      const double gbb = G[b * LG + b], gbpb = G[b * LG + pb], gpbpb = G[pb * LG + pb];
+      const double gab = G[a * LG + b], gapb = G[a * LG + pb], gpab = G[pa * LG + b],
+                   gpapb = G[pa * LG + pb];
+      const double al = jg_entry(csa, cpa, csa, cpa, rota, dga, true, false, gaa, gapa, gapa, gpapa);
+      const double be = jg_entry(csb, cpb, csb, cpb, rotb, dgb, true, false, gbb, gbpb, gbpb, gpbpb);
+      const double ga = jg_entry(csa, cpa, csb, cpb, rota, dga, false, b == pa, gab, gapb, gpab,
+                                 gpapb);
+      jg_set_rotation(Ps[(ir + 1) & 1], a, b, al, be, ga, tol2, floor2, any);
     }
     __syncthreads();
     cur ^= 1;
@@ -1456,8 +1471,12 @@ static Task jacobi_sweeps_task(DevCtx &ctx, JacobiBlockArgs ja, int max_sweeps, 
     if (hipGetLastError() != hipSuccess) co_return BSRHT_EDEVICE;
     for (int r = 0; r < ja.nblocks - 1; ++r) {
       ja.round = r;
-      if constexpr (LDS16)
-        jacobi_gram16_kernel<<<(unsigned)(ja.nblocks / 2), 512, 0, ctx.s>>>(ja);
+      if constexpr (LDS16) {
+        if (r == 0)
+          jacobi_gram16_kernel<true><<<(unsigned)(ja.nblocks / 2), 512, 0, ctx.s>>>(ja);
+        else
+          jacobi_gram16_kernel<false><<<(unsigned)(ja.nblocks / 2), 512, 0, ctx.s>>>(ja);
+      }
       else
         jacobi_gram_kernel<W><<<(unsigned)(ja.nblocks / 2), 256, 0, ctx.s>>>(ja);
       if (hipGetLastError() != hipSuccess) co_return BSRHT_EDEVICE;
