@@ -117,6 +117,49 @@ __global__ void gather_scale_cols_kernel(const double *__restrict__ V, int64_t r
   M[e] = c < keep ? V[i * ldv + idx[c]] * sc[c] : 0.0;
 }
 
+// perm[r] = i where r is the rank of G's diagonal entry i in descending order
+// (ties by index; a NaN ranks last), i < n: a permutation of 0..n-1.  Every
+// workgroup stages the whole diagonal (n <= kMaxOrderN) in LDS.
+constexpr int kMaxOrderN = 4096;
+__global__ __launch_bounds__(256) void desc_diag_order_kernel(const double *__restrict__ G,
+                                                              int64_t n, int64_t ldg,
+                                                              int32_t *__restrict__ perm) {
+  __shared__ double d[kMaxOrderN];
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+    const double v = G[j * ldg + j];
+    d[j] = v == v ? v : -INFINITY;
+  }
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double di = d[i];
+  int64_t r = 0;
+  for (int64_t j = 0; j < n; ++j) r += (d[j] > di || (d[j] == di && j < i)) ? 1 : 0;
+  perm[r] = (int32_t)i;
+}
+
+// P[r][c] = G[perm[r]][perm[c]] (n x n, leading dimensions ldg and ldp).
+__global__ void permute_sym_kernel(const double *__restrict__ G, int64_t n, int64_t ldg,
+                                   const int32_t *__restrict__ perm, double *__restrict__ P,
+                                   int64_t ldp) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int64_t r = e / n, c = e - r * n;
+  P[r * ldp + c] = G[(int64_t)perm[r] * ldg + perm[c]];
+}
+
+// M[perm[i]][c] = V[i][c] * sc[c] for c < keep, 0 for keep <= c < cols
+// (i < rows): the rows of V taken back from the order perm to the original.
+__global__ void scale_cols_unpermute_kernel(const double *__restrict__ V, int64_t rows,
+                                            int64_t ldv, const int32_t *__restrict__ perm,
+                                            const double *__restrict__ sc, int64_t keep,
+                                            int64_t cols, double *__restrict__ M, int64_t ldm) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t i = e / cols, c = e - i * cols;
+  M[(int64_t)perm[i] * ldm + c] = c < keep ? V[i * ldv + c] * sc[c] : 0.0;
+}
+
 __global__ void or_info_kernel(int32_t *info, int32_t bits) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *info |= bits;
 }
@@ -304,6 +347,7 @@ struct NysWs {
   void *chol_state;
   double *ssq;  // kSsqBlocks partial sums, then nu (shifted) or ||B||_F (fallback)
   int32_t *kidx;  // fallback: indices of the kept eigenvalues
+  int32_t *zperm;  // Z's columns in descending order of norm
   SvdBufs<A> fb, sv;
   void layout(A &a, const bsrht_plan_s *pl, int64_t k) {
     const int64_t l = pl->l, n = pl->n;
@@ -325,6 +369,7 @@ struct NysWs {
     chol_state = a.template take<char>(cholesky_state_bytes());
     ssq = a.template take<double>((size_t)kSsqBlocks + 1);
     kidx = a.template take<int32_t>((size_t)l);
+    zperm = a.template take<int32_t>((size_t)l);
     fb.take(a, svd_pad(l), l);
     sv.take(a, svd_pad(l), k);
   }
@@ -661,27 +706,38 @@ Task nystrom_task(DevCtx &ctx, const bsrht_plan_s *plan, const float *A, int64_t
     or_info_kernel<<<1, 1, 0, s>>>(info, BSRHT_INFO_CHOL_FALLBACK);
     BSRHT_CO_LAUNCH_CHECK();
   }
-  // 4. R-factor of Z: Gz = Z^T Z = R^T R
+  // 4. R-factor of Z with its columns in descending order of norm:
+  // Z P = Q R, P^T Z^T Z P = R^T R.  The order makes R's rows graded, and the
+  // one-sided Jacobi on R's rows then ends in fewer sweeps (a model of this
+  // problem: 13 -> 11 at l = 512); the SVD of Z P is that of Z with the rows
+  // of the right factor permuted, which step 6 undoes.
   const int gsz = gram_splits(n, lz);
   BSRHT_CO_TRY(gram_f64(w.Z, n, lz, ldz, 1, w.Gz, lz, w.gram_part, gsz, s));
-  BSRHT_CO_TRY(scale_cols_f64(w.Gz, lz, lz, lz, lz, nullptr, w.Bs, lz, s));
+  if (lz > kMaxOrderN) co_return BSRHT_EUNSUPPORTED;
+  desc_diag_order_kernel<<<(unsigned)((lz + 255) / 256), 256, 0, s>>>(w.Gz, lz, lz, w.zperm);
+  permute_sym_kernel<<<(unsigned)((lz * lz + 255) / 256), 256, 0, s>>>(w.Gz, lz, lz, w.zperm,
+                                                                          w.Bs, lz);
+  BSRHT_CO_LAUNCH_CHECK();
+  BSRHT_CO_TRY(scale_cols_f64(w.Bs, lz, lz, lz, lz, nullptr, w.Gz, lz, s));
   BSRHT_CO_TRY(cholesky_upper(w.Gz, lz, lz, 1e-15 * (double)lz, w.flag + 1, w.chol_state, s));
   int32_t hz = 0;
   BSRHT_CO_TRY(co_await readback(ctx, &hz, w.flag + 1, sizeof(hz)));
-  // 5. SVD of R (or the eigen decomposition of Z^T Z when R is singular)
+  // 5. SVD of R (or the eigen decomposition of P^T Z^T Z P when R is singular)
   const double *Rsrc = hz == 0 ? w.Gz : w.Bs;
   BSRHT_CO_TRY(co_await small_svd_task(ctx, w.sv, Rsrc, lz, lz, hz != 0, info));
   if (hz != 0) {
     sqrt_clamp_kernel<<<(unsigned)((lz + 255) / 256), 256, 0, s>>>(w.sv.S, lz);
     BSRHT_CO_LAUNCH_CHECK();
   }
-  // 6. U = Z Vt_k St_k^{-1}; lambda = St_k^2
+  // 6. U = Z P Vt_k St_k^{-1}; lambda = St_k^2
   finish_sigma_kernel<<<(unsigned)((k + 255) / 256), 256, 0, s>>>(
       w.sv.S, lz, k, sqrt((double)lz * kU64), 2, w.sv.inv, lambda, info);
   BSRHT_CO_LAUNCH_CHECK();
   const int64_t keep = std::min(k, lz);
   const int64_t nce = svd_pad(lz);
-  BSRHT_CO_TRY(scale_cols_f64(w.sv.Vs, lz, keep, k, nce, w.sv.inv, w.Mk, k, s));
+  scale_cols_unpermute_kernel<<<(unsigned)((lz * k + 255) / 256), 256, 0, s>>>(
+      w.sv.Vs, lz, nce, w.zperm, w.sv.inv, keep, k, w.Mk, k);
+  BSRHT_CO_LAUNCH_CHECK();
   GemmDesc d;
   d.M = n; d.N = k; d.K = lz;
   d.sai = ldz; d.sak = 1;
