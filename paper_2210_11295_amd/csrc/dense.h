@@ -80,7 +80,8 @@ int fill_f64(double *p, int64_t count, double value, hipStream_t s);
 // scratch) is given, the accumulated rotations (nc x nc: the right singular
 // vectors; for symmetric X, eigenvectors that stay orthogonal to working
 // precision).  perm (nc int32) and flags (4 uint, 8-byte aligned) are
-// scratch.  Pairs with a column norm at or below u ||X||_F (u = 2^-53) count
+// scratch; S and Us also serve as scratch until the run's last launches
+// write them (S must not alias X, V or Us).  Pairs with a column norm at or below u ||X||_F (u = 2^-53) count
 // as orthogonal, so rank-deficient inputs converge.  When
 // max_sweeps sweeps still rotate, BSRHT_INFO_JACOBI_NOCONV is or-ed into
 // *info (device, may be NULL).  Synchronises the stream once per sweep.

@@ -1262,75 +1262,91 @@ __global__ __launch_bounds__(512) void jacobi_gram16_kernel(JacobiBlockArgs ja) 
   if (tid == 0) atomicAdd(ja.rot, 1u);
 }
 
-// sigma_j = ||x_j||; order by decreasing sigma (ties by index) into S, and
-// write in that order as the columns of Us either the normalised columns of X
-// (row-major nr x nc, zero where sigma = 0) or, when V is given, the columns
-// of V (row-major nc x nc).  One workgroup; nc <= 4096.
-__global__ __launch_bounds__(1024) void jacobi_finish_kernel(const double *__restrict__ X,
-                                                             int64_t nr, int64_t nc, int64_t ldx,
-                                                             const double *__restrict__ V,
-                                                             int64_t ldv,
-                                                             double *__restrict__ S,
-                                                             double *__restrict__ Us,
-                                                             int64_t ldu, int32_t *__restrict__ perm) {
-  extern __shared__ double s_sig[];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int64_t j = tid; j < nc; j += nt) {
-    double s = 0.0;
-    for (int64_t i = 0; i < nr; ++i) {
-      const double u = X[j * ldx + i];
-      s += u * u;
-    }
-    s_sig[j] = sqrt(s);
-  }
-  __syncthreads();
-  for (int64_t j = tid; j < nc; j += nt) {
-    const double sj = s_sig[j];
-    int64_t rank = 0;
-    for (int64_t t = 0; t < nc; ++t) {
-      const double st = s_sig[t];
-      rank += (st > sj) || (st == sj && t < j);
-    }
-    perm[rank] = (int32_t)j;
-    S[rank] = sj;
-  }
-  __syncthreads();
-  if (V) {
-    for (int64_t e = tid; e < nc * nc; e += nt) {
-      const int64_t i = e / nc, rnk = e % nc;
-      Us[i * ldu + rnk] = V[(int64_t)perm[rnk] * ldv + i];
-    }
-    return;
-  }
-  for (int64_t e = tid; e < nr * nc; e += nt) {
-    const int64_t i = e / nc, rnk = e % nc;
-    const int64_t col = perm[rnk];
-    const double sg = s_sig[col];
-    Us[i * ldu + rnk] = sg > 0.0 ? X[col * ldx + i] / sg : 0.0;
-  }
+// The end of a Jacobi run, in three launches over the whole chip:
+//  1. N[j] = sigma_j = ||x_j|| (one wave per column, fixed summation order);
+//  2. S in decreasing order of sigma (ties by index; a NaN norm ranks last),
+//     perm[rank] = j; every workgroup stages all of N (nc <= 4096) in LDS;
+//  3. the columns of Us in that order: the normalised columns of X (row-major
+//     nr x nc, zero where sigma = 0) or, when V is given, the columns of V
+//     (row-major nc x nc).
+constexpr int kFinishMaxN = 4096;
+__global__ __launch_bounds__(256) void col_norms_kernel(const double *__restrict__ X, int64_t nr,
+                                                        int64_t nc, int64_t ldx,
+                                                        double *__restrict__ N) {
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= nc) return;  // whole waves
+  const double *col = X + j * ldx;
+  double acc = 0.0;
+  for (int64_t i = lane; i < nr; i += 64) acc += col[i] * col[i];
+  acc = wave_sum(acc);
+  if (lane == 0) N[j] = sqrt(acc);
 }
 
-// out = (u ||X||_F)^2, u = 2^-53, for X (nr x nc, column-major, ldx).  One
-// workgroup of 1024 threads; fixed summation order.
-__global__ __launch_bounds__(1024) void noise_floor_kernel(const double *__restrict__ X,
-                                                            int64_t nr, int64_t nc, int64_t ldx,
-                                                            double *__restrict__ out) {
-  __shared__ double part[16];
+__global__ __launch_bounds__(256) void sigma_order_kernel(const double *__restrict__ N, int64_t nc,
+                                                          double *__restrict__ S,
+                                                          int32_t *__restrict__ perm) {
+  __shared__ double key[kFinishMaxN];
+  for (int64_t t = threadIdx.x; t < nc; t += blockDim.x) {
+    const double v = N[t];
+    key[t] = v == v ? v : -INFINITY;
+  }
+  __syncthreads();
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nc) return;
+  const double kj = key[j];
+  int64_t rank = 0;
+  for (int64_t t = 0; t < nc; ++t) rank += (key[t] > kj || (key[t] == kj && t < j)) ? 1 : 0;
+  perm[rank] = (int32_t)j;
+  S[rank] = N[j];
+}
+
+__global__ void finish_columns_kernel(const double *__restrict__ X, int64_t nr, int64_t nc,
+                                      int64_t ldx, const double *__restrict__ V, int64_t ldv,
+                                      const double *__restrict__ S,
+                                      const int32_t *__restrict__ perm, double *__restrict__ Us,
+                                      int64_t ldu) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (V) {
+    if (e >= nc * nc) return;
+    const int64_t i = e / nc, rnk = e - i * nc;
+    Us[i * ldu + rnk] = V[(int64_t)perm[rnk] * ldv + i];
+    return;
+  }
+  if (e >= nr * nc) return;
+  const int64_t i = e / nc, rnk = e - i * nc;
+  const double sg = S[rnk];
+  Us[i * ldu + rnk] = sg > 0.0 ? X[(int64_t)perm[rnk] * ldx + i] / sg : 0.0;
+}
+
+// out = (u ||X||_F)^2, u = 2^-53, for X (nr x nc, column-major, ldx), in two
+// launches with a fixed summation order: kFloorBlocks partial sums (block b,
+// wave w: columns 4 b + w, 4 b + w + 4 kFloorBlocks, ...) into P, then their
+// sum in index order.
+constexpr int kFloorBlocks = 32;
+__global__ __launch_bounds__(256) void noise_floor_partial_kernel(const double *__restrict__ X,
+                                                                  int64_t nr, int64_t nc,
+                                                                  int64_t ldx,
+                                                                  double *__restrict__ P) {
+  __shared__ double part[4];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double acc = 0.0;
-  for (int64_t c = w; c < nc; c += 16) {  // wave w: columns w, w + 16, ...
+  for (int64_t c = (int64_t)blockIdx.x * 4 + w; c < nc; c += 4 * kFloorBlocks) {
     const double *col = X + c * ldx;
     for (int64_t i = lane; i < nr; i += 64) acc += col[i] * col[i];
   }
   acc = wave_sum(acc);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  if (lane == 0) part[w] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < 16; ++w) t += part[w];
-    const double u = 0x1p-53;
-    *out = u * u * t;
-  }
+  if (threadIdx.x == 0) P[blockIdx.x] = ((part[0] + part[1]) + part[2]) + part[3];
+}
+
+__global__ void noise_floor_finish_kernel(const double *__restrict__ P, double *__restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double t = 0.0;
+  for (int b = 0; b < kFloorBlocks; ++b) t += P[b];
+  const double u = 0x1p-53;
+  *out = u * u * t;
 }
 
 __global__ void or_bits_kernel(int32_t *p, int32_t bits) {
@@ -1517,7 +1533,10 @@ Task jacobi_svd_task(DevCtx &ctx, double *X, int64_t nr, int64_t nc, int64_t ldx
   ja.rot = flags;
   double *floor2 = reinterpret_cast<double *>(flags + 2);
   ja.floor2 = floor2;
-  noise_floor_kernel<<<1, 1024, 0, s>>>(X, nr, nc, ldx, floor2);
+  // S is written only at the end of the run: it holds the noise floor's
+  // partial sums (nc >= 32 = kFloorBlocks) until then
+  noise_floor_partial_kernel<<<kFloorBlocks, 256, 0, s>>>(X, nr, nc, ldx, S);
+  noise_floor_finish_kernel<<<1, 64, 0, s>>>(S, floor2);
   if (hipGetLastError() != hipSuccess) co_return BSRHT_EDEVICE;
   int sweeps = 0, st;
   if (form == 1)
@@ -1529,8 +1548,13 @@ Task jacobi_svd_task(DevCtx &ctx, double *X, int64_t nr, int64_t nc, int64_t ldx
     or_bits_kernel<<<1, 1, 0, s>>>(info, BSRHT_INFO_JACOBI_NOCONV);
     if (hipGetLastError() != hipSuccess) co_return BSRHT_EDEVICE;
   }
-  jacobi_finish_kernel<<<1, 1024, (size_t)nc * sizeof(double), s>>>(X, nr, nc, ldx, V, nc, S,
-                                                                     Us, ldu, perm);
+  // Us is written only by the last launch: its first nc entries hold the
+  // unsorted norms until then
+  col_norms_kernel<<<(unsigned)((nc + 3) / 4), 256, 0, s>>>(X, nr, nc, ldx, Us);
+  sigma_order_kernel<<<(unsigned)((nc + 255) / 256), 256, 0, s>>>(Us, nc, S, perm);
+  const int64_t nout = V ? nc * nc : nr * nc;
+  finish_columns_kernel<<<(unsigned)((nout + 255) / 256), 256, 0, s>>>(X, nr, nc, ldx, V, nc, S,
+                                                                       perm, Us, ldu);
   if (hipGetLastError() != hipSuccess) co_return BSRHT_EDEVICE;
   co_return BSRHT_OK;
 }

@@ -58,25 +58,20 @@ __global__ void finish_sigma_kernel(const double *__restrict__ sigma, int64_t av
   if (!keep) atomicOr(info, BSRHT_INFO_RANK_CLAMPED);
 }
 
-// lam[j] = v_j^T B v_j for the columns of V (row-major n x n): the signed
-// eigenvalues behind the Jacobi singular values of a symmetric B.
-__global__ void rayleigh_kernel(const double *__restrict__ B, const double *__restrict__ V,
-                                int64_t n, int64_t ldb, int64_t ldv, double *__restrict__ lam) {
-  const int64_t j = (int64_t)blockIdx.x;
+// lam[j] = sum_i V[i][j] W[i][j] for the columns of V (row-major n x n); with
+// W = B V this is v_j^T B v_j, the signed eigenvalues behind the Jacobi
+// singular values of a symmetric B.  One wave per column, fixed order.
+__global__ __launch_bounds__(256) void col_dots_kernel(const double *__restrict__ V, int64_t ldv,
+                                                       const double *__restrict__ W, int64_t ldw,
+                                                       int64_t n, double *__restrict__ lam) {
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= n) return;  // whole waves
   double acc = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-    double bv = 0.0;
-    for (int64_t t = 0; t < n; ++t) bv += B[i * ldb + t] * V[t * ldv + j];
-    acc += V[i * ldv + j] * bv;
-  }
-  __shared__ double red[256];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) lam[j] = red[0];
+  for (int64_t i = lane; i < n; i += 64) acc += V[i * ldv + j] * W[i * ldw + j];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) lam[j] = acc;
 }
 
 // M[i][i] += c for i < n.
@@ -672,8 +667,17 @@ Task nystrom_task(DevCtx &ctx, const bsrht_plan_s *plan, const float *A, int64_t
     else
       BSRHT_CO_TRY(co_await small_svd_task(ctx, w.fb, w.Bs, l, l, true, info));
     const int64_t nce = svd_pad(l);
-    rayleigh_kernel<<<(unsigned)l, 256, 0, s>>>(w.Bs, w.fb.Vs, l, l, nce, w.lam);
-    BSRHT_CO_LAUNCH_CHECK();
+    {
+      // lambda_j = v_j^T (B v_j): W = B V into Cinv (unused on this path)
+      GemmDesc d;
+      d.M = l; d.N = l; d.K = l;
+      d.sai = l; d.sak = 1;
+      d.sbk = nce; d.sbj = 1;
+      d.ldc = l;
+      BSRHT_CO_TRY(gemm_f64(d, w.Bs, w.fb.Vs, w.Cinv, s));
+      col_dots_kernel<<<(unsigned)((l + 3) / 4), 256, 0, s>>>(w.fb.Vs, nce, w.Cinv, l, l, w.lam);
+      BSRHT_CO_LAUNCH_CHECK();
+    }
     std::vector<double> lam((size_t)l);
     if (co_await readback(ctx, lam.data(), w.lam, sizeof(double) * (size_t)l) != BSRHT_OK)
       co_return BSRHT_EDEVICE;
