@@ -41,7 +41,7 @@ def test_rsvd_matches_oracle(n, m, p, l, k):
     A = workloads.lowrank_tall(n, m, "inv_sq", 3, device=dev)
     U, S, V, info, err, err_o, So = _rsvd_case(n, m, p, l, k, A, 7)
     say("  err gpu", err, "oracle", err_o, "info", info)
-    assert err <= 1.01 * err_o + 1e-7
+    assert err <= 1.01 * err_o
     assert np.allclose(to64(S), So, rtol=2e-4, atol=1e-6 * So[0])
     Uh, Vh = to64(U), to64(V)
     assert np.max(np.abs(Uh.T @ Uh - np.eye(k))) < 1e-4

@@ -97,7 +97,12 @@ def test_mix_equals_alone_and_matches_oracle():
             err = metrics.lowrank_fro_error(Ah, to64(out["U"]), to64(out["S"]), to64(out["V"]))
             Uo, So, Vo = lowrank.rsvd(op, Ah, js["k"])
             err_o = metrics.lowrank_fro_error(Ah, Uo, So, Vo)
-            assert err <= 1.01 * err_o + 1e-6, (js, err, err_o)
+            if js["k"] >= min(js["n"], js["m"]):
+                # exact recovery: the oracle's error is FP64 rounding, the
+                # GPU's the FP32 floor
+                assert err < 1e-5, (js, err, err_o)
+            else:
+                assert err <= 1.01 * err_o, (js, err, err_o)
         checked += 1
     assert checked >= 4
 

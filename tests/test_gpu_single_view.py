@@ -3,8 +3,9 @@ against the FP64 oracle run with the same four block SRHTs (same plans and
 seeds), through the C ABI.
 
 Pass rule, as for Algorithm 1: the GPU's approximation error is within 1% of
-the oracle's (err_gpu <= 1.01 err_oracle, plus 1e-6 absolute for inputs the
-method recovers exactly, where FP32 rounding sets the floor); the singular
+the oracle's (err_gpu <= 1.01 err_oracle, no absolute slack) on full-rank
+inputs; on an input the method recovers exactly (oracle error at FP64
+rounding) the GPU's error must be below 1e-5, the FP32 floor.  The singular
 values agree to 2e-4 relative.  Vectors are compared through reconstructions
 and orthonormality (they are unique only up to sign and rotation)."""
 import numpy as np
@@ -59,7 +60,7 @@ def test_single_view_matches_oracle(N1, N2, l, s, k, pl, ps):
     A = workloads.lowrank_tall(N1, N2, "inv_sq", 5, device=dev)
     U, S, V, info, err, err_o, So = _case(A, l, s, k, pl, ps, 11)
     say("  err gpu", err, "oracle", err_o, "info", info)
-    assert err <= 1.01 * err_o + 1e-6
+    assert err <= 1.01 * err_o
     assert np.allclose(to64(S), So, rtol=2e-4, atol=1e-6 * So[0])
     Uh, Vh = to64(U), to64(V)
     assert np.max(np.abs(Uh.T @ Uh - np.eye(k))) < 1e-4
@@ -76,7 +77,7 @@ def test_single_view_split_bf16_column_sketches():
     A = workloads.lowrank_tall(4096, 256, "inv_sq", 6, device=dev)
     U, S, V, info, err, err_o, So = _case(A, 64, 128, 20, (4, 4), (8, 2), 13, bs.SPLIT_BF16)
     say("  bf16 err gpu", err, "oracle", err_o)
-    assert err <= 1.01 * err_o + 1e-6
+    assert err <= 1.01 * err_o
 
 
 def test_single_view_exact_recovery_and_rank_fallback():
@@ -105,7 +106,7 @@ def test_single_view_rank_clamp():
     Sh = to64(S)
     assert info & bs.INFO_RANK_CLAMPED
     assert np.all(Sh[32:] == 0.0) and np.all(Sh[:32] > 0.0)
-    assert err <= 1.01 * err_o + 1e-6
+    assert err <= 1.01 * err_o
 
 
 def test_single_view_errors():
@@ -150,4 +151,4 @@ def test_single_view_large_workload_subsample():
     A = A.contiguous()
     U, S, V, info, err, err_o, So = _case(A, l, s, k, (1, 1), (1, 1), 21)
     say("  err gpu", err, "oracle", err_o, "info", info)
-    assert err <= 1.01 * err_o + 1e-6
+    assert err <= 1.01 * err_o
