@@ -920,8 +920,8 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(JacobiBlockArgs ja) {
 //    rotations to G and J, eight threads of another wave form the three
 //    entries of G that round r + 1's pairs need (with the same arithmetic as
 //    the full update) and compute round r + 1's rotations;
-//  - the updated columns go back through LDS so that every global store is a
-//    run of consecutive rows.
+//  - the update is formed transposed on the matrix cores, so the results
+//    leave the accumulators as 128-byte runs of consecutive rows.
 constexpr int kJg16Rows = 1024, kJg16Ld = 1026;
 
 struct JgRound {  // round r's rotations, per column (16 columns)
@@ -1200,16 +1200,17 @@ __global__ __launch_bounds__(512) void jacobi_gram16_kernel(JacobiBlockArgs ja) 
   const bool rotated = __syncthreads_or(any);
   if (!rotated) return;
 
-  // 3. X_p <- X_p J and V_p <- V_p J on matrix cores, 16 rows per product:
-  // A[i][k] = P[16 rb + i][4 ks + k] (lane (k, i)), B[k][j] = J[4 ks + k][j];
-  // the result's lane (r, j) holds rows 16 rb + r + 4 v of column j.  Results
-  // are written into Xs (a wave only overwrites rows it has read) and then
-  // stored column by column.
+  // 3. X_p <- X_p J and V_p <- V_p J on matrix cores, 16 rows per product,
+  // formed transposed, D = J^T P^T: A[i][k] = J[4 ks + k][i] (lane (k, i)),
+  // B[k][j] = P[16 rb + j][4 ks + k] (lane (k, j)), so the result's lane
+  // (g, j) holds row 16 rb + j of columns g + 4 v.  Each store of a wave then
+  // writes 16 consecutive rows of four columns (128-byte runs) straight from
+  // the accumulators, with no pass through LDS.
   const double *J = Js[cur];
   double jb[C / 4];
 #pragma unroll
   for (int ks = 0; ks < C / 4; ++ks) jb[ks] = J[(4 * ks + lr) * LG + lc];
-  auto update = [&](const double (&a)[RBW][C / 4], int rows) {
+  auto update_store = [&](const double (&a)[RBW][C / 4], double *P, int64_t ldp, int rows) {
     D4 d[RBW];
 #pragma unroll
     for (int q = 0; q < RBW; ++q) d[q] = D4{0, 0, 0, 0};
@@ -1217,13 +1218,13 @@ __global__ __launch_bounds__(512) void jacobi_gram16_kernel(JacobiBlockArgs ja) 
     for (int ks = 0; ks < C / 4; ++ks)
 #pragma unroll
       for (int q = 0; q < RBW; ++q)
-        d[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q][ks], jb[ks], d[q], 0, 0, 0);
+        d[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(jb[ks], a[q][ks], d[q], 0, 0, 0);
 #pragma unroll
     for (int q = 0; q < RBW; ++q) {
-      const int rb = wave + NW * q;
-      if (16 * rb < rows)
+      const int row = 16 * (wave + NW * q) + lc;
+      if (row < rows)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Xs[lc * LD + 16 * rb + lr + 4 * v] = d[q][v];
+        for (int v = 0; v < 4; ++v) P[gcol(lr + 4 * v) * ldp + row] = d[q][v];
     }
   };
   {
@@ -1233,32 +1234,9 @@ __global__ __launch_bounds__(512) void jacobi_gram16_kernel(JacobiBlockArgs ja) 
 #pragma unroll
       for (int ks = 0; ks < C / 4; ++ks)
         xa[q][ks] = Xs[(4 * ks + lr) * LD + 16 * (wave + NW * q) + lc];
-    update(xa, nr);
+    update_store(xa, ja.X, ja.ldx, nr);
   }
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    double *col = ja.X + gcol(c) * ja.ldx;
-#pragma unroll
-    for (int h = 0; h < XH; ++h) {
-      const int i = tid + NT * h;
-      if (i < nr) col[i] = Xs[c * LD + i];
-    }
-  }
-  if (nv > 0) {
-    __syncthreads();  // Xs is free again
-    update(vv, nv);
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      double *col = ja.V + gcol(c) * ja.nc;
-#pragma unroll
-      for (int h = 0; h < XH; ++h) {
-        const int i = tid + NT * h;
-        if (i < nv) col[i] = Xs[c * LD + i];
-      }
-    }
-  }
+  if (nv > 0) update_store(vv, ja.V, ja.nc, nv);
   if (tid == 0) atomicAdd(ja.rot, 1u);
 }
 
