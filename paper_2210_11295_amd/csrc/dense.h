@@ -72,6 +72,12 @@ int trinv_upper(const double *C, int64_t n, int64_t ldc, double *Ci, int64_t ldi
 int eye(double *M, int64_t n, int64_t ld, hipStream_t s);
 int fill_f64(double *p, int64_t count, double value, hipStream_t s);
 
+// Workgroups of a block-Jacobi launch at most (nc <= 4096, 16-column pairs),
+// and the flag words a run needs: the noise floor (two words), then two
+// slots per workgroup.
+constexpr int kJacobiMaxGroups = 256;
+constexpr int kJacobiFlagWords = 2 + 2 * kJacobiMaxGroups;
+
 // One-sided block Jacobi on the columns of X (nr x nc, column-major, ldx),
 // nc a multiple of 32, nc <= 4096, nr <= 4096: X is overwritten by
 // X V = U Sigma; S (nc, descending) is written, and Us (row-major, ldu)
@@ -79,12 +85,13 @@ int fill_f64(double *p, int64_t count, double value, hipStream_t s);
 // nr x nc, the left singular vectors of X) or, when V (nc * nc doubles,
 // scratch) is given, the accumulated rotations (nc x nc: the right singular
 // vectors; for symmetric X, eigenvectors that stay orthogonal to working
-// precision).  perm (nc int32) and flags (4 uint, 8-byte aligned) are
-// scratch; S and Us also serve as scratch until the run's last launches
-// write them (S must not alias X, V or Us).  Pairs with a column norm at or below u ||X||_F (u = 2^-53) count
-// as orthogonal, so rank-deficient inputs converge.  When
-// max_sweeps sweeps still rotate, BSRHT_INFO_JACOBI_NOCONV is or-ed into
-// *info (device, may be NULL).  Synchronises the stream once per sweep.
+// precision).  perm (nc int32) and flags (kJacobiFlagWords uint, 8-byte
+// aligned) are scratch; S and Us also serve as scratch until the run's last
+// launches write them (S must not alias X, V or Us).  Pairs with a column
+// norm at or below u ||X||_F (u = 2^-53) count as orthogonal, so
+// rank-deficient inputs converge.  When max_sweeps sweeps still rotate,
+// BSRHT_INFO_JACOBI_NOCONV is or-ed into *info (device, may be NULL).
+// Synchronises the stream once per sweep.
 int jacobi_svd(double *X, int64_t nr, int64_t nc, int64_t ldx, double *V, double *S,
                double *Us, int64_t ldu, int32_t *perm, unsigned int *flags, int max_sweeps,
                int32_t *info, hipStream_t s);

@@ -664,7 +664,8 @@ __global__ __launch_bounds__(64 * kTrinvWaves) void trinv_upper_kernel(
 // orders on the Nystrom and R-factor problems ends in the same number of
 // sweeps, give or take one).  Every column pair is thus tested at least once
 // per sweep.  A sweep is nc/W - 1 launches; sweeps repeat until one performs
-// no rotation.
+// no rotation, or (16-column form) until one in which every rotated pair was
+// within 1e-8 of orthogonal, which leaves nothing the next sweep would rotate.
 struct JacobiBlockArgs {
   double *X;
   int nr;
@@ -673,8 +674,19 @@ struct JacobiBlockArgs {
   int nc, nblocks, round;
   double tol;
   const double *floor2;  // (u ||X||_F)^2: columns at or below it are rounding noise
-  unsigned int *rot;     // workgroups that rotated in this sweep
+  // Per-workgroup slots, cleared before each sweep: workgroup b of every
+  // launch of the sweep owns slot b and only ever sets it (plain stores
+  // replace atomics on one address, which all workgroups of a launch would
+  // otherwise contend for).  rot[b]: workgroup b rotated in this sweep;
+  // big[b] (16-column form): it rotated a pair with g_ab^2 / (g_aa g_bb) at
+  // or above kJacobiStopOff2.
+  unsigned int *rot;
+  unsigned int *big;
 };
+
+// Stop threshold of the 16-column form, (1e-8)^2 (see jacobi_sweeps_task).
+constexpr double kJacobiStopOff2 = 1e-16;
+
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -906,7 +918,7 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(JacobiBlockArgs ja) {
   };
   apply(ja.X, ja.ldx, nr);
   if (ja.V) apply(ja.V, ja.nc, ja.nc);
-  if (tid == 0) atomicAdd(ja.rot, 1u);
+  if (tid == 0) ja.rot[blockIdx.x] = 1u;
 }
 
 // The Gram form for block pairs of 16 columns with at most 1024 rows (and V
@@ -1033,6 +1045,7 @@ __global__ __launch_bounds__(512) void jacobi_gram16_kernel(JacobiBlockArgs ja) 
   __shared__ double Js[2][C * LG];
   __shared__ double part[NW][256];
   __shared__ JgRound Ps[2];
+  __shared__ int sbig;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int lr = lane >> 4, lc = lane & 15;
@@ -1071,6 +1084,7 @@ __global__ __launch_bounds__(512) void jacobi_gram16_kernel(JacobiBlockArgs ja) 
 #pragma unroll
     for (int h = 0; h < XH; ++h) Xs[c * LD + tid + NT * h] = xv[c][h];
   for (int e = tid; e < C * LG; e += NT) Js[0][e] = (e / LG == e % LG) ? 1.0 : 0.0;
+  if (tid == 0) sbig = 0;
   __syncthreads();
 
   // 1. G = X_p^T X_p on matrix cores (A[i][k] = B[k][j]^T: lane (k, i) holds
@@ -1137,6 +1151,7 @@ __global__ __launch_bounds__(512) void jacobi_gram16_kernel(JacobiBlockArgs ja) 
       const double *G = Gs[0];
       const double al = G[a * LG + a], be = G[b * LG + b], ga = G[a * LG + b];
       need = jg_needs_rotation(al, be, ga, tol2, floor2);
+      if (need && ga * ga >= kJacobiStopOff2 * (al * be)) sbig = 1;  // every writer stores 1
     }
     if (!__syncthreads_or(need)) return;
   }
@@ -1237,7 +1252,10 @@ __global__ __launch_bounds__(512) void jacobi_gram16_kernel(JacobiBlockArgs ja) 
     update_store(xa, ja.X, ja.ldx, nr);
   }
   if (nv > 0) update_store(vv, ja.V, ja.nc, nv);
-  if (tid == 0) atomicAdd(ja.rot, 1u);
+  if (tid == 0) {
+    ja.rot[blockIdx.x] = 1u;
+    if (sbig) ja.big[blockIdx.x] = 1u;
+  }
 }
 
 // The end of a Jacobi run, in three launches over the whole chip:
@@ -1453,31 +1471,48 @@ int eye(double *M, int64_t n, int64_t ld, hipStream_t s) {
 }
 
 // One launch per round, nblocks - 1 rounds per sweep; after each sweep the
-// rotation counter is read back and the sweeps stop at the first one without
-// rotations.  *sweeps = max_sweeps + 1 when that never happens.
-// LDS16 selects the LDS-staged kernel for 16-column block pairs (W = 8).
+// workgroups' slots are read back and the sweeps stop at the first one
+// without rotations.  The 16-column form (LDS16) also stops after a sweep in
+// which every rotated pair had g_ab^2 / (g_aa g_bb) below kJacobiStopOff2 =
+// 1e-16 before its rotation: such a sweep leaves each pair at most about nc * 1e-16 from
+// orthogonal (each later rotation of a column moves the pair's inner product
+// by at most the product of two such cosines), below the test tol of
+// 1e-15 * max(nr, 16) that a further sweep would apply, so that sweep, which
+// would rotate nothing, is not run.  *sweeps = max_sweeps + 1 when neither
+// happens.  LDS16 selects the LDS-staged kernel for 16-column block pairs
+// (W = 8).
 template <int W, bool LDS16>
 static Task jacobi_sweeps_task(DevCtx &ctx, JacobiBlockArgs ja, int max_sweeps, int *sweeps) {
   ja.nblocks = ja.nc / W;
   *sweeps = max_sweeps + 1;
+  if (ja.nblocks / 2 > kJacobiMaxGroups) co_return BSRHT_EUNSUPPORTED;
   for (int sw = 0; sw < max_sweeps; ++sw) {
-    zero_u32_kernel<<<1, 64, 0, ctx.s>>>(ja.rot, 1);
+    // slots 0 .. groups-1 of rot and of big (contiguous, see jacobi_svd_task)
+    const int groups = ja.nblocks / 2;
+    zero_u32_kernel<<<(unsigned)((2 * kJacobiMaxGroups + 255) / 256), 256, 0, ctx.s>>>(
+        ja.rot, 2 * kJacobiMaxGroups);
     if (hipGetLastError() != hipSuccess) co_return BSRHT_EDEVICE;
     for (int r = 0; r < ja.nblocks - 1; ++r) {
       ja.round = r;
       if constexpr (LDS16) {
         if (r == 0)
-          jacobi_gram16_kernel<true><<<(unsigned)(ja.nblocks / 2), 512, 0, ctx.s>>>(ja);
+          jacobi_gram16_kernel<true><<<(unsigned)groups, 512, 0, ctx.s>>>(ja);
         else
-          jacobi_gram16_kernel<false><<<(unsigned)(ja.nblocks / 2), 512, 0, ctx.s>>>(ja);
+          jacobi_gram16_kernel<false><<<(unsigned)groups, 512, 0, ctx.s>>>(ja);
+      } else {
+        jacobi_gram_kernel<W><<<(unsigned)groups, 256, 0, ctx.s>>>(ja);
       }
-      else
-        jacobi_gram_kernel<W><<<(unsigned)(ja.nblocks / 2), 256, 0, ctx.s>>>(ja);
       if (hipGetLastError() != hipSuccess) co_return BSRHT_EDEVICE;
     }
-    unsigned int rot = 0;
-    BSRHT_CO_TRY(co_await readback(ctx, &rot, ja.rot, sizeof(rot)));
-    if (rot == 0) {
+    // both slot arrays in one copy (they are contiguous)
+    unsigned int slots[2 * kJacobiMaxGroups];
+    BSRHT_CO_TRY(co_await readback(ctx, slots, ja.rot, sizeof(slots)));
+    bool any = false, big = false;
+    for (int b = 0; b < groups; ++b) {
+      any |= slots[b] != 0;
+      big |= slots[kJacobiMaxGroups + b] != 0;
+    }
+    if (!any || (LDS16 && !big)) {
       *sweeps = sw + 1;
       break;
     }
@@ -1508,8 +1543,11 @@ Task jacobi_svd_task(DevCtx &ctx, double *X, int64_t nr, int64_t nc, int64_t ldx
   ja.nblocks = 0;
   ja.round = 0;
   ja.tol = 1e-15 * (double)(nr > 16 ? nr : 16);
-  ja.rot = flags;
-  double *floor2 = reinterpret_cast<double *>(flags + 2);
+  // flags: [0..1] floor2, then G rotation slots and G threshold slots
+  // (G = kJacobiMaxGroups)
+  double *floor2 = reinterpret_cast<double *>(flags);
+  ja.rot = flags + 2;
+  ja.big = flags + 2 + kJacobiMaxGroups;
   ja.floor2 = floor2;
   // S is written only at the end of the run: it holds the noise floor's
   // partial sums (nc >= 32 = kFloorBlocks) until then

@@ -244,7 +244,7 @@ struct SvdBufs {
     Vs = a.template take<double>((size_t)(nc * nc));
     inv = a.template take<double>((size_t)std::max<int64_t>(k, nc));
     perm = a.template take<int32_t>((size_t)nc);
-    flags = a.template take<unsigned int>(4);
+    flags = a.template take<unsigned int>(kJacobiFlagWords);
   }
 };
 
