@@ -590,22 +590,28 @@ __global__ void chol_finish_kernel(double *G, int64_t n, int64_t ldg, const Chol
 // Inverse of an upper-triangular n x n matrix C (row-major): column j of
 // Ci = C^{-1} solves C x = e_j by back substitution; one wave per column, the
 // dot product of each step split across the lanes, x kept in LDS.  Lane q
-// holds the entries t = i+1+q+64u (t <= j) of row i of C in registers; the
-// next row's entries are loaded while the current step runs, at addresses
-// clamped into the row (entries past j are never used), so the loads are
-// unconditional and the wait before a step covers only the row it uses.  The
-// sum runs in the order of the plain loop over t.
-constexpr int kTrinvWaves = 4;
+// holds the entries t = i+1+q+64u of row i of C in registers (addresses
+// clamped into the row; entries past j meet x[j + 1], which stays zero).
+// Rows arrive through a ring of DEPTH register buffers, each refilled right
+// after its step with the row DEPTH steps further on: a step waits only on a
+// load issued DEPTH steps earlier.  A step has no lane-dependent branch (every
+// lane stores x_i, lane 0 into x and the others into a pad), so the
+// reciprocal of the next row's diagonal, formed during the current step, stays
+// off its dependent chain and each step multiplies instead of dividing.
+// LDS doubles per wave: x (n + 1, x[n] = 0) and the 64-entry pad.
+__host__ __device__ inline size_t trinv_lds_doubles(int64_t n) { return (size_t)n + 1 + 64; }
 
-template <int PER>  // n <= 64 * PER
-__global__ __launch_bounds__(64 * kTrinvWaves) void trinv_upper_kernel(
+template <int PER, int WAVES>  // n <= 64 * PER; WAVES columns per workgroup
+__global__ __launch_bounds__(64 * WAVES) void trinv_upper_kernel(
     const double *__restrict__ C, int64_t n, int64_t ldc, double *__restrict__ Ci, int64_t ldi) {
+  constexpr int DEPTH = PER <= 16 ? 4 : 2;
   extern __shared__ double s_x[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t j = (int64_t)blockIdx.x * kTrinvWaves + wv;
-  double *x = s_x + (int64_t)wv * n;
+  const int64_t j = (int64_t)blockIdx.x * WAVES + wv;
+  double *x = s_x + (int64_t)wv * (int64_t)trinv_lds_doubles(n);
   if (j >= n) return;
-  for (int64_t i = lane; i < n; i += 64) x[i] = 0.0;
+  for (int64_t i = lane; i <= n; i += 64) x[i] = 0.0;
+  double *const xout = lane == 0 ? x : x + n + 1 + lane;  // where this lane stores x_i
   auto load_row = [&](int64_t i, double (&v)[PER], double &d) {
     const double *row = C + i * ldc;
 #pragma unroll
@@ -615,25 +621,34 @@ __global__ __launch_bounds__(64 * kTrinvWaves) void trinv_upper_kernel(
     }
     d = row[i];
   };
-  double cur[PER], nxt[PER], dcur, dnxt = 1.0;
-  load_row(j, cur, dcur);
-  for (int64_t i = j; i >= 0; --i) {
-    if (i > 0) load_row(i - 1, nxt, dnxt);
-    double s = 0.0;
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // the zeros are in LDS before the first step
+  __builtin_amdgcn_wave_barrier();
+  // slot k holds row j - k, then j - k - DEPTH, ... (rows below 0 read row 0)
+  double ring[DEPTH][PER], dg[DEPTH];
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int64_t t = i + 1 + lane + 64 * u;
-      if (t <= j) s += cur[u] * x[t];
+  for (int k = 0; k < DEPTH; ++k) load_row(j - k >= 0 ? j - k : 0, ring[k], dg[k]);
+  double rcur = 1.0 / dg[0];
+  for (int64_t i0 = j; i0 >= 0; i0 -= DEPTH) {
+#pragma unroll
+    for (int k = 0; k < DEPTH; ++k) {
+      const int64_t i = i0 - k;  // wave-uniform
+      if (i < 0) break;
+      const double rnext = 1.0 / dg[(k + 1) % DEPTH];  // row i - 1's diagonal
+      double s = 0.0;
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int64_t t = i + 1 + lane + 64 * u;
+        s = fma(ring[k][u], x[t <= j ? t : j + 1], s);
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+      const double xi = (((i == j) ? 1.0 : 0.0) - s) * rcur;
+      xout[lane == 0 ? i : 0] = xi;
+      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): x[i] is in LDS before the next step
+      __builtin_amdgcn_wave_barrier();
+      load_row(i - DEPTH >= 0 ? i - DEPTH : 0, ring[k], dg[k]);
+      rcur = rnext;
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    const double xi = (((i == j) ? 1.0 : 0.0) - s) / dcur;
-    if (lane == 0) x[i] = xi;
-    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): x[i] is in LDS before the next step
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int u = 0; u < PER; ++u) cur[u] = nxt[u];
-    dcur = dnxt;
   }
   for (int64_t i = lane; i < n; i += 64) Ci[i * ldi + j] = x[i];
 }
@@ -1451,15 +1466,17 @@ int fill_f64(double *p, int64_t count, double value, hipStream_t s) {
 
 int trinv_upper(const double *C, int64_t n, int64_t ldc, double *Ci, int64_t ldi, hipStream_t s) {
   if (n <= 0) return BSRHT_OK;
-  if (n * kTrinvWaves * sizeof(double) > 64 * 1024) return BSRHT_EUNSUPPORTED;
-  const unsigned grid = (unsigned)((n + kTrinvWaves - 1) / kTrinvWaves);
-  const size_t lds = (size_t)n * kTrinvWaves * sizeof(double);
+  if (n > 64 * 32) return BSRHT_EUNSUPPORTED;
+  // four columns per workgroup up to n = 1024, two beyond (LDS <= 34 KiB)
+  const int waves = n <= 64 * 16 ? 4 : 2;
+  const size_t lds = trinv_lds_doubles(n) * waves * sizeof(double);
+  const unsigned grid = (unsigned)((n + waves - 1) / waves);
   if (n <= 64 * 8)
-    trinv_upper_kernel<8><<<grid, 64 * kTrinvWaves, lds, s>>>(C, n, ldc, Ci, ldi);
+    trinv_upper_kernel<8, 4><<<grid, 64 * 4, lds, s>>>(C, n, ldc, Ci, ldi);
   else if (n <= 64 * 16)
-    trinv_upper_kernel<16><<<grid, 64 * kTrinvWaves, lds, s>>>(C, n, ldc, Ci, ldi);
+    trinv_upper_kernel<16, 4><<<grid, 64 * 4, lds, s>>>(C, n, ldc, Ci, ldi);
   else
-    trinv_upper_kernel<32><<<grid, 64 * kTrinvWaves, lds, s>>>(C, n, ldc, Ci, ldi);
+    trinv_upper_kernel<32, 2><<<grid, 64 * 2, lds, s>>>(C, n, ldc, Ci, ldi);
   BSRHT_LAUNCH_CHECK();
   return BSRHT_OK;
 }
