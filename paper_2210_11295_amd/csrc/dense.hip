@@ -594,10 +594,36 @@ __global__ void chol_finish_kernel(double *G, int64_t n, int64_t ldg, const Chol
 // clamped into the row; entries past j meet x[j + 1], which stays zero).
 // Rows arrive through a ring of DEPTH register buffers, each refilled right
 // after its step with the row DEPTH steps further on: a step waits only on a
-// load issued DEPTH steps earlier.  A step has no lane-dependent branch (every
-// lane stores x_i, lane 0 into x and the others into a pad), so the
-// reciprocal of the next row's diagonal, formed during the current step, stays
-// off its dependent chain and each step multiplies instead of dividing.
+// load issued DEPTH steps earlier.  The dot product is summed by DPP into
+// lane 63.  A step has no lane-dependent branch (every lane stores x_i, lane
+// 63 into x and the others into a pad), so the reciprocal of the next row's
+// diagonal, formed during the current step, stays off its dependent chain and
+// each step multiplies instead of dividing.
+// x moved across lanes by one DPP control (32-bit halves): a lane without a
+// source reads 0 (bound_ctrl), a lane outside row_mask gets 0.
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const long long v = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, BOUND);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, ROW_MASK, 0xF, BOUND);
+  return __builtin_bit_cast(double, (long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+// Sum over the wave, left in lane 63 (other lanes hold partial sums): pairs
+// and quads by quad_perm, rows of 16 by row_shr 4 and 8, then row 0's sum
+// broadcast into rows 1 and 3 and row 1's into rows 2 and 3 (row_bcast 15 and
+// 31).  Six dependent DPP steps where a 64-bit shuffle reduction takes six
+// round trips through the LDS permute unit.
+__device__ __forceinline__ double wave_sum_to_lane63(double s) {
+  s += dpp_f64<0xb1, 0xF, true>(s);   // quad_perm [1, 0, 3, 2]
+  s += dpp_f64<0x4e, 0xF, true>(s);   // quad_perm [2, 3, 0, 1]
+  s += dpp_f64<0x114, 0xF, true>(s);  // row_shr 4
+  s += dpp_f64<0x118, 0xF, true>(s);  // row_shr 8
+  s += dpp_f64<0x142, 0xA, false>(s); // row_bcast 15 into rows 1 and 3
+  s += dpp_f64<0x143, 0xC, false>(s); // row_bcast 31 into rows 2 and 3
+  return s;
+}
+
 // LDS doubles per wave: x (n + 1, x[n] = 0) and the 64-entry pad.
 __host__ __device__ inline size_t trinv_lds_doubles(int64_t n) { return (size_t)n + 1 + 64; }
 
@@ -611,7 +637,7 @@ __global__ __launch_bounds__(64 * WAVES) void trinv_upper_kernel(
   double *x = s_x + (int64_t)wv * (int64_t)trinv_lds_doubles(n);
   if (j >= n) return;
   for (int64_t i = lane; i <= n; i += 64) x[i] = 0.0;
-  double *const xout = lane == 0 ? x : x + n + 1 + lane;  // where this lane stores x_i
+  double *const xout = lane == 63 ? x : x + n + 1 + lane;  // where this lane stores x_i
   auto load_row = [&](int64_t i, double (&v)[PER], double &d) {
     const double *row = C + i * ldc;
 #pragma unroll
@@ -640,10 +666,9 @@ __global__ __launch_bounds__(64 * WAVES) void trinv_upper_kernel(
         const int64_t t = i + 1 + lane + 64 * u;
         s = fma(ring[k][u], x[t <= j ? t : j + 1], s);
       }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+      s = wave_sum_to_lane63(s);
       const double xi = (((i == j) ? 1.0 : 0.0) - s) * rcur;
-      xout[lane == 0 ? i : 0] = xi;
+      xout[lane == 63 ? i : 0] = xi;
       __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): x[i] is in LDS before the next step
       __builtin_amdgcn_wave_barrier();
       load_row(i - DEPTH >= 0 ? i - DEPTH : 0, ring[k], dg[k]);
