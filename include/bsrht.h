@@ -295,7 +295,7 @@ size_t nystrom_workspace(bsrht_plan_t plan, int64_t k);
  * factorisation is FP64), B = V Lam V^T is used instead, keeping
  * Lam_i > l * 2^-53 * Lam_max and Z = Y V_+ Lam_+^{-1/2};
  * BSRHT_INFO_CHOL_FALLBACK is set.  rsvd and nystrom synchronise the stream
- * (to read this flag back) before returning.
+ * (to read this flag back) before returning; nystrom_start below does not.
  *
  * A      : device float32 n x n, lda >= n (only read through Omega).
  * U      : device float32 n x k (leading dimension k).
@@ -321,6 +321,47 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k,
 int nystrom_shifted(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k,
                     float *U, double *lambda, int32_t *info, void *ws,
                     size_t ws_bytes, void *stream);
+
+/*
+ * Non-blocking forms of rsvd, nystrom and nystrom_shifted (sections 3.1 and
+ * 3.2, as above).  These algorithms read a few values back from the device
+ * (Cholesky flags, the Jacobi sweep slots, the kept eigenvalues of Remark
+ * 3.1), and the blocking forms synchronise their stream at those points.
+ * The *_start forms take the blocking form's arguments plus `task`, check
+ * them the same way (an error returns its code, enqueues nothing and sets
+ * *task = NULL), queue the work up to the first readback on `stream` and
+ * return at once with a task handle in *task.
+ *
+ * bsrht_task_poll(task, &status) advances the task as far as the device
+ * allows without waiting: it returns 0 while the task waits on the device,
+ * and 1 once all of the task's work has been queued, with *status set to
+ * the blocking form's return value (BSRHT_EDEVICE if a HIP call failed).
+ * The results are then ready in stream order: synchronise the stream, or
+ * wait on an event recorded after the task, before reading them on the host.
+ * bsrht_task_wait blocks until the task has been queued in full and returns
+ * that status.  bsrht_task_destroy waits for an unfinished task and releases
+ * it: the host handle, one HIP event and 128 KiB of pinned host staging,
+ * which *_start allocates.  BSRHT_EINVAL for a NULL task.
+ *
+ * Until the task has finished, A, the outputs, info and the workspace belong
+ * to it and the plan must stay valid.  A task is advanced by one thread at a
+ * time; tasks on different streams, each with its own workspace, run
+ * concurrently.  The arithmetic is that of the blocking forms: results are
+ * bitwise the same.
+ */
+typedef struct bsrht_task_s *bsrht_task_t;
+int rsvd_start(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, int64_t k,
+               float *U, double *S, float *V, int32_t *info, void *ws,
+               size_t ws_bytes, void *stream, bsrht_task_t *task);
+int nystrom_start(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k,
+                  float *U, double *lambda, int32_t *info, void *ws,
+                  size_t ws_bytes, void *stream, bsrht_task_t *task);
+int nystrom_shifted_start(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k,
+                          float *U, double *lambda, int32_t *info, void *ws,
+                          size_t ws_bytes, void *stream, bsrht_task_t *task);
+int bsrht_task_poll(bsrht_task_t task, int *status);
+int bsrht_task_wait(bsrht_task_t task);
+int bsrht_task_destroy(bsrht_task_t task);
 
 /* Workspace bytes rsvd_single_view needs (0 for inconsistent plans or k < 1). */
 size_t rsvd_single_view_workspace(bsrht_plan_t omega, bsrht_plan_t gamma,

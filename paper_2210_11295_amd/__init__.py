@@ -98,6 +98,15 @@ _SIGS = {
                                _c_sz, _c_vp]),
     "nystrom_shifted": (ctypes.c_int, [_c_vp, _c_vp, _c_i64, _c_i64, _c_vp, _c_vp, _c_vp,
                                        _c_vp, _c_sz, _c_vp]),
+    "rsvd_start": (ctypes.c_int, [_c_vp, _c_vp, _c_i64, _c_i64, _c_i64, _c_vp, _c_vp, _c_vp,
+                                  _c_vp, _c_vp, _c_sz, _c_vp, ctypes.POINTER(_c_vp)]),
+    "nystrom_start": (ctypes.c_int, [_c_vp, _c_vp, _c_i64, _c_i64, _c_vp, _c_vp, _c_vp, _c_vp,
+                                     _c_sz, _c_vp, ctypes.POINTER(_c_vp)]),
+    "nystrom_shifted_start": (ctypes.c_int, [_c_vp, _c_vp, _c_i64, _c_i64, _c_vp, _c_vp, _c_vp,
+                                             _c_vp, _c_sz, _c_vp, ctypes.POINTER(_c_vp)]),
+    "bsrht_task_poll": (ctypes.c_int, [_c_vp, ctypes.POINTER(ctypes.c_int)]),
+    "bsrht_task_wait": (ctypes.c_int, [_c_vp]),
+    "bsrht_task_destroy": (ctypes.c_int, [_c_vp]),
 }
 
 
@@ -489,6 +498,86 @@ def nystrom(plan, A, k, ws=None, stream=None, shifted=False):
 def nystrom_shifted(plan, A, k, ws=None, stream=None):
     """Shifted Nystrom (on A + nu I, nu subtracted): returns (U, lambda, info)."""
     return nystrom(plan, A, k, ws, stream, shifted=True)
+
+
+class Task:
+    """A non-blocking rsvd / nystrom call (rsvd_start, nystrom_start of
+    include/bsrht.h).  poll() advances it without waiting and returns True once
+    all of its work is queued (raising if the call failed); wait() blocks until
+    then.  The results are ready in stream order.  The tensors the call uses
+    are kept alive until the task is closed."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self._keep = keep
+
+    def poll(self):
+        st = ctypes.c_int(0)
+        r = lib().bsrht_task_poll(self.handle, ctypes.byref(st))
+        if r < 0:
+            _check("bsrht_task_poll", r)
+        if r == 1:
+            _check("task", st.value)
+            return True
+        return False
+
+    def wait(self):
+        _check("bsrht_task_wait", lib().bsrht_task_wait(self.handle))
+
+    def close(self):
+        h, self.handle = self.handle, None
+        if h is not None and _lib is not None:
+            _check("bsrht_task_destroy", _lib.bsrht_task_destroy(h))
+        self._keep = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rsvd_start(plan, A, k, ws=None, stream=None):
+    """Non-blocking rsvd: returns (task, U, S, V, info); the outputs are
+    valid once task.poll() returned True (or task.wait()) and the stream has
+    reached the task's end."""
+    _check_matrix("A", A)
+    n, m = A.shape
+    if n != plan.n:
+        raise ValueError(f"A has {n} rows, the plan expects {plan.n}")
+    dev = A.device
+    U = torch.empty(n, k, dtype=torch.float32, device=dev)
+    S = torch.empty(k, dtype=torch.float64, device=dev)
+    V = torch.empty(m, k, dtype=torch.float32, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = _workspace(rsvd_workspace(plan, m, k), dev)
+    h = _c_vp()
+    _check("rsvd_start", lib().rsvd_start(plan.handle, _ptr(A), m, max(A.stride(0), m), k,
+                                          _ptr(U), _ptr(S), _ptr(V), _ptr(info), _ptr(ws),
+                                          ws.numel(), _stream_ptr(stream), ctypes.byref(h)))
+    return Task(h.value, (plan, A, U, S, V, info, ws)), U, S, V, info
+
+
+def nystrom_start(plan, A, k, ws=None, stream=None, shifted=False):
+    """Non-blocking nystrom (nystrom_shifted with shifted=True): returns
+    (task, U, lambda, info), valid as for rsvd_start."""
+    _check_matrix("A", A)
+    n = A.shape[0]
+    if A.shape[1] != n or n != plan.n:
+        raise ValueError("A must be n x n with n = plan.n")
+    dev = A.device
+    U = torch.empty(n, k, dtype=torch.float32, device=dev)
+    lam = torch.empty(k, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = _workspace(nystrom_workspace(plan, k), dev)
+    name = "nystrom_shifted_start" if shifted else "nystrom_start"
+    h = _c_vp()
+    _check(name, getattr(lib(), name)(plan.handle, _ptr(A), max(A.stride(0), n), k, _ptr(U),
+                                      _ptr(lam), _ptr(info), _ptr(ws), ws.numel(),
+                                      _stream_ptr(stream), ctypes.byref(h)))
+    return Task(h.value, (plan, A, U, lam, info, ws)), U, lam, info
 
 
 def bsrht_job_bytes(job):

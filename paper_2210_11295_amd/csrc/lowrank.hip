@@ -14,6 +14,7 @@
 #include <limits.h>
 
 #include <algorithm>
+#include <optional>
 #include <vector>
 
 #include "common.h"
@@ -777,6 +778,142 @@ int nystrom(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
 int nystrom_shifted(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
                     double *lambda, int32_t *info, void *ws, size_t ws_bytes, void *stream) {
   return nystrom_blocking(plan, A, lda, k, U, lambda, info, ws, ws_bytes, stream, true);
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------------
+// Non-blocking forms: the same coroutines with an asynchronous context (one
+// event, pinned staging), advanced by bsrht_task_poll / bsrht_task_wait.
+
+struct bsrht_task_s {
+  bsrht::DevCtx ctx;  // the coroutine refers to it: a task never moves
+  std::optional<bsrht::Task> task;
+  int status = BSRHT_OK;
+  bool finished = false;
+};
+
+namespace {
+
+constexpr size_t kTaskStagingHalf = 64 * 1024;  // pinned bytes per direction
+
+int task_open(void *stream, bsrht_task_s **out) {
+  auto *t = new (std::nothrow) bsrht_task_s;
+  if (!t) return BSRHT_EDEVICE;
+  t->ctx.s = (hipStream_t)stream;
+  t->ctx.blocking = false;
+  void *pin = nullptr;
+  if (hipEventCreateWithFlags(&t->ctx.ev, hipEventDisableTiming) != hipSuccess) {
+    delete t;
+    return BSRHT_EDEVICE;
+  }
+  if (hipHostMalloc(&pin, 2 * kTaskStagingHalf, hipHostMallocDefault) != hipSuccess) {
+    (void)hipEventDestroy(t->ctx.ev);
+    delete t;
+    return BSRHT_EDEVICE;
+  }
+  t->ctx.pinned = static_cast<char *>(pin);
+  t->ctx.half_bytes = kTaskStagingHalf;
+  *out = t;
+  return BSRHT_OK;
+}
+
+// Resumes the task while the event it waits on has completed; 1 once it has
+// finished (status set), 0 while the device is still busy.
+int task_advance(bsrht_task_s *t) {
+  while (!t->finished) {
+    if (t->task->done()) {
+      t->status = t->task->status();
+      t->finished = true;
+      break;
+    }
+    const hipError_t q = hipEventQuery(t->ctx.ev);
+    if (q == hipErrorNotReady) return 0;
+    if (q != hipSuccess) {
+      t->status = BSRHT_EDEVICE;
+      t->finished = true;
+      break;
+    }
+    t->ctx.resume_point.resume();
+  }
+  return 1;
+}
+
+int task_start(bsrht_task_s *t, bsrht::Task task, bsrht_task_t *out) {
+  t->task.emplace(std::move(task));
+  t->task->start();  // queues work up to the first readback
+  (void)task_advance(t);
+  *out = t;
+  return BSRHT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rsvd_start(bsrht_plan_t plan, const float *A, int64_t m, int64_t lda, int64_t k, float *U,
+               double *S, float *V, int32_t *info, void *ws, size_t ws_bytes, void *stream,
+               bsrht_task_t *task) {
+  if (!task) return BSRHT_EINVAL;
+  *task = nullptr;
+  if (!plan || !A || !U || !S || !V || !info || m < 1 || k < 1 || lda < m) return BSRHT_EINVAL;
+  if (ws_bytes < rsvd_workspace(plan, m, k) || !ws) return BSRHT_ENOMEM;
+  bsrht_task_s *t = nullptr;
+  BSRHT_TRY(task_open(stream, &t));
+  return task_start(t, rsvd_task(t->ctx, plan, A, m, lda, k, U, S, V, info, ws, ws_bytes), task);
+}
+
+static int nystrom_start_impl(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k,
+                              float *U, double *lambda, int32_t *info, void *ws,
+                              size_t ws_bytes, void *stream, bool shifted, bsrht_task_t *task) {
+  if (!task) return BSRHT_EINVAL;
+  *task = nullptr;
+  if (!plan || !A || !U || !lambda || !info || k < 1 || lda < plan->n) return BSRHT_EINVAL;
+  if (ws_bytes < nystrom_workspace(plan, k) || !ws) return BSRHT_ENOMEM;
+  bsrht_task_s *t = nullptr;
+  BSRHT_TRY(task_open(stream, &t));
+  return task_start(
+      t, nystrom_task(t->ctx, plan, A, lda, k, U, lambda, info, ws, ws_bytes, shifted), task);
+}
+
+int nystrom_start(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
+                  double *lambda, int32_t *info, void *ws, size_t ws_bytes, void *stream,
+                  bsrht_task_t *task) {
+  return nystrom_start_impl(plan, A, lda, k, U, lambda, info, ws, ws_bytes, stream, false, task);
+}
+
+int nystrom_shifted_start(bsrht_plan_t plan, const float *A, int64_t lda, int64_t k, float *U,
+                          double *lambda, int32_t *info, void *ws, size_t ws_bytes,
+                          void *stream, bsrht_task_t *task) {
+  return nystrom_start_impl(plan, A, lda, k, U, lambda, info, ws, ws_bytes, stream, true, task);
+}
+
+int bsrht_task_poll(bsrht_task_t task, int *status) {
+  if (!task || !status) return BSRHT_EINVAL;
+  if (!task_advance(task)) return 0;
+  *status = task->status;
+  return 1;
+}
+
+int bsrht_task_wait(bsrht_task_t task) {
+  if (!task) return BSRHT_EINVAL;
+  while (!task_advance(task)) {
+    if (hipEventSynchronize(task->ctx.ev) != hipSuccess) {
+      task->status = BSRHT_EDEVICE;
+      task->finished = true;
+    }
+  }
+  return task->status;
+}
+
+int bsrht_task_destroy(bsrht_task_t task) {
+  if (!task) return BSRHT_EINVAL;
+  (void)bsrht_task_wait(task);
+  int st = BSRHT_OK;
+  if (hipHostFree(task->ctx.pinned) != hipSuccess) st = BSRHT_EDEVICE;
+  if (hipEventDestroy(task->ctx.ev) != hipSuccess) st = BSRHT_EDEVICE;
+  delete task;  // the coroutine frame goes with its Task
+  return st;
 }
 
 }  // extern "C"

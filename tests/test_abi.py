@@ -79,3 +79,26 @@ def test_null_plan_is_rejected():
     assert L.bsrht_apply_workspace(None, 4) == 0
     assert L.bsrht_plan_destroy(None) == 0
     assert L.bsrht_plan_info(None, None, None, None, None, None) == -1
+
+
+def test_task_calls_reject_bad_arguments_on_the_host():
+    """rsvd_start / nystrom_start and the task calls check their arguments
+    before any HIP call (no GPU needed): NULL plans and tasks are refused and
+    the task handle is cleared."""
+    L = bs.lib()
+    h = ctypes.c_void_p(1)
+    null = ctypes.c_void_p()
+    assert L.rsvd_start(None, None, 1, 1, 1, None, None, None, None, None, 0, None,
+                        ctypes.byref(h)) == -1
+    assert h.value is None
+    h = ctypes.c_void_p(1)
+    assert L.nystrom_start(None, None, 1, 1, None, None, None, None, 0, None,
+                           ctypes.byref(h)) == -1
+    assert h.value is None
+    assert L.nystrom_shifted_start(None, None, 1, 1, None, None, None, None, 0, None,
+                                   None) == -1
+    st = ctypes.c_int(7)
+    assert L.bsrht_task_poll(null, ctypes.byref(st)) == -1 and st.value == 7
+    assert L.bsrht_task_wait(null) == -1
+    assert L.bsrht_task_destroy(null) == -1
+

@@ -1,0 +1,79 @@
+"""Non-blocking randomized SVD and Nystrom (rsvd_start, nystrom_start,
+nystrom_shifted_start and bsrht_task_poll / wait / destroy of
+include/bsrht.h; sections 3.1 and 3.2): the same coroutines as the blocking
+calls run with an asynchronous context, so on the same plan and input their
+results must equal the blocking calls' bitwise, also with two tasks in
+flight on two streams and with a task destroyed before it has finished."""
+import time
+
+import pytest
+import torch
+
+import paper_2210_11295_amd as bs
+import workloads
+from tests.gpu_util import device, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _inputs(dev):
+    A = workloads.lowrank_tall(8192, 300, "inv_sq", 3, device=dev)
+    rplan = bs.Plan(8192, 8, 128, 5, device=dev)
+    B = workloads.spd(2048, 512, "inv_sq", 11, device=dev)
+    nplan = bs.Plan(2048, 4, 256, 12, device=dev)
+    return A, rplan, B, nplan
+
+
+def test_tasks_on_two_streams_equal_blocking_calls():
+    dev = device()
+    A, rplan, B, nplan = _inputs(dev)
+    U0, S0, V0, i0 = bs.rsvd(rplan, A, 40)
+    W0, L0, j0 = bs.nystrom(nplan, B, 32)
+    X0, M0, k0 = bs.nystrom(nplan, B, 32, shifted=True)
+    torch.cuda.synchronize()
+    s1, s2, s3 = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
+    t1, U1, S1, V1, i1 = bs.rsvd_start(rplan, A, 40, stream=s1)
+    t2, W1, L1, j1 = bs.nystrom_start(nplan, B, 32, stream=s2)
+    t3, X1, M1, k1 = bs.nystrom_start(nplan, B, 32, stream=s3, shifted=True)
+    pending = {"rsvd": t1, "nystrom": t2, "nystrom_shifted": t3}
+    polls = 0
+    deadline = time.time() + 60.0
+    while pending:
+        assert time.time() < deadline, f"tasks still running: {sorted(pending)}"
+        for name in list(pending):
+            if pending[name].poll():
+                del pending[name]
+        polls += 1
+    torch.cuda.synchronize()
+    say("tasks finished after", polls, "poll rounds")
+    for got, ref in [(U1, U0), (S1, S0), (V1, V0), (i1, i0), (W1, W0), (L1, L0), (j1, j0),
+                     (X1, X0), (M1, M0), (k1, k0)]:
+        assert torch.equal(got, ref)
+    for t in (t1, t2, t3):
+        t.close()
+
+
+def test_task_wait_and_destroy_before_finish():
+    dev = device()
+    A, rplan, B, nplan = _inputs(dev)
+    U0, S0, V0, i0 = bs.rsvd(rplan, A, 40)
+    W0, L0, j0 = bs.nystrom(nplan, B, 32)
+    torch.cuda.synchronize()
+    t, U1, S1, V1, i1 = bs.rsvd_start(rplan, A, 40)
+    t.wait()
+    assert t.poll()
+    t.close()
+    t, W1, L1, j1 = bs.nystrom_start(nplan, B, 32)
+    t.close()  # destroy waits for the unfinished task
+    torch.cuda.synchronize()
+    assert torch.equal(U1, U0) and torch.equal(S1, S0) and torch.equal(V1, V0)
+    assert torch.equal(W1, W0) and torch.equal(L1, L0) and torch.equal(j1, j0)
+
+
+def test_task_start_argument_errors():
+    dev = device()
+    A, rplan, B, nplan = _inputs(dev)
+    with pytest.raises(bs.BsrhtError):
+        bs.rsvd_start(rplan, A, 40, ws=torch.zeros(16, dtype=torch.uint8, device=dev))
+    with pytest.raises(bs.BsrhtError):
+        bs.nystrom_start(nplan, B, 0)
