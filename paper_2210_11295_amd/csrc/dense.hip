@@ -1164,11 +1164,13 @@ __global__ __launch_bounds__(512) void jacobi_gram16_kernel(JacobiBlockArgs ja) 
   }
   __syncthreads();
 
-  // A pair step in which every one of the 120 column pairs passes the
-  // convergence test on the freshly formed G makes no rotation (without a
-  // rotation G never changes within the sweep), so it ends here: the last
-  // sweep of a run, and the converged pairs of the sweeps before it, cost the
-  // loads and the Gram only.  The test is the one the sweep applies.
+  // A pair step in which every column pair it would rotate (all 120 in a
+  // full round, the 64 cross pairs otherwise) passes the convergence test on
+  // the freshly formed G makes no rotation (without a rotation G never
+  // changes within the step), so it ends here: the last sweep of a run, and
+  // the converged pairs of the sweeps before it, cost the loads and the Gram
+  // only.  The test is the one the rounds apply.  The same pass notes whether
+  // a pair that needs rotating is still at or above the stop threshold.
   const double floor2 = *ja.floor2, tol2 = ja.tol * ja.tol;
   constexpr bool full = FULL;
   constexpr int nrounds = full ? C - 1 : W;
