@@ -4,7 +4,8 @@ two, i.e. each block padded with zeros) against the FP64 oracle.
 
 Tables bit-exact (D in the padded layout: bit i*r' + x); the FP32 sketch
 within 1e-5; the padded identity against the power-of-two plan on a padded
-copy of A; the right-side sketch and the randomized SVD on such plans."""
+copy of A; the right-side sketch, the randomized SVD and the Nystrom
+approximation on such plans."""
 import numpy as np
 import pytest
 import torch
@@ -119,6 +120,26 @@ def test_partial_rsvd():
     Uo, So, Vo = lowrank.rsvd(rng.Plan(n, p, l, 7), Ah, k)
     err_o = metrics.lowrank_fro_error(Ah, Uo, So, Vo)
     say("  partial rsvd err", err, "oracle", err_o)
+    assert err <= 1.01 * err_o
+
+
+@pytest.mark.parametrize("n,p,l,k", [
+    (3000, 3, 128, 20),   # r = 1000 -> 1024: padded blocks in both sketches of Algorithm 2
+    (2400, 4, 600, 40),   # r = 600 -> 1024: l > 512 (16-wave kernel); rank-512 A, so
+                          # Omega A Omega^T is singular and Remark 3.1's split is taken
+])
+def test_partial_nystrom(n, p, l, k):
+    dev = device()
+    A = workloads.spd(n, 512, "inv_sq", 11, device=dev)
+    plan = bs.Plan(n, p, l, 9, device=dev)
+    U, lam, info = bs.nystrom(plan, A, k)
+    torch.cuda.synchronize()
+    Ah = to64(A)
+    err = metrics.trace_error(Ah, to64(U), to64(lam))
+    Uo, lo, fb = lowrank.nystrom(rng.Plan(n, p, l, 9), Ah, k)
+    err_o = metrics.trace_error(Ah, Uo, lo)
+    say("  partial nystrom err", err, "oracle", err_o, "info", int(info.item()),
+        "oracle fallback", fb)
     assert err <= 1.01 * err_o
 
 
