@@ -50,6 +50,7 @@ SV_CASES = [
     (512, 2048, 64, 96, 30, (16, 2), (2, 8)),       # wide
     (8192, 512, 128, 256, 50, (2, 8), (16, 1)),     # chunk widths 256 and 512 in the row sketches
     (2048, 512, 70, 150, 25, (2, 4), (4, 2)),       # bases with a padded leading dimension
+    (3000, 600, 64, 128, 20, (1, 3), (3, 1)),       # partial SRHTs: r = 600 and 1000 -> 1024
 ]
 
 
