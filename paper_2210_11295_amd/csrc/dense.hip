@@ -136,6 +136,15 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(GemmDesc d, const TA
 constexpr int kBM = 128, kBN = 128, kBK = 16, kBPad = 4;
 constexpr int kBThreads = 256;
 
+// A symmetric product on upper tiles computes the tiles on or above the
+// diagonal, and in a diagonal tile not the lower-left quadrant (the wave that
+// owns it skips its matrix-core work, which frees its SIMD for the other
+// workgroup there); the skipped elements are mirrored from their partners.
+__host__ __device__ inline bool upper_tiles_skipped(int64_t i, int64_t j) {
+  const int64_t ti = i / kBM, tj = j / kBN;
+  return ti > tj || (ti == tj && i % kBM >= kBM / 2 && j % kBN < kBN / 2);
+}
+
 template <typename T>
 struct Vec4 {
   T v[4];
@@ -190,6 +199,9 @@ __global__ __launch_bounds__(kBThreads) void gemm_big_kernel(GemmDesc d, const T
   const int64_t kb = (int64_t)bzr * kchunk;
   const int64_t ke = min(d.K, kb + kchunk);
   const int wi = (wave >> 1) * 64, wj = (wave & 1) * 64;
+  // lower-left quadrant of a diagonal tile of a symmetric product (uniform
+  // per wave): the wave still moves its share of the tiles through LDS
+  const bool quad_skip = d.upper_tiles && bxr == byr && wi > wj;
   const bool ij_inside = i0 + kBM <= d.M && j0 + kBN <= d.N;
   using Acc = typename std::conditional<F64, double __attribute__((ext_vector_type(4))),
                                         float __attribute__((ext_vector_type(4)))>::type;
@@ -273,7 +285,7 @@ __global__ __launch_bounds__(kBThreads) void gemm_big_kernel(GemmDesc d, const T
     const bool more = t + 1 < ntiles;
     if (more) fetch(kb + (t + 1) * KT);
 #pragma unroll
-    for (int ks = 0; ks < KT; ks += 4) {
+    for (int ks = 0; ks < (quad_skip ? 0 : KT); ks += 4) {
       const int kk = ks + (lane >> 4);
       TS av[4], bv[4];
 #pragma unroll
@@ -294,6 +306,7 @@ __global__ __launch_bounds__(kBThreads) void gemm_big_kernel(GemmDesc d, const T
     __syncthreads();
   }
   TC *Cz = C + (int64_t)bzr * d.split_stride;
+  if (quad_skip) return;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -323,19 +336,19 @@ __global__ void reduce_partials_kernel(const double *__restrict__ P, int splits,
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < M * N;
        idx += stride) {
     const int64_t i = idx / N, j = idx - i * N;
-    const int64_t src = (mirror && i / kBM > j / kBN) ? j * N + i : idx;
+    const int64_t src = (mirror && upper_tiles_skipped(i, j)) ? j * N + i : idx;
     double s = 0.0;
     for (int sp = 0; sp < splits; ++sp) s += P[(int64_t)sp * M * N + src];
     C[i * ldc + j] = (TC)s;
   }
 }
 
-// C[i][j] = C[j][i] for the elements of tiles below the diagonal.
+// C[i][j] = C[j][i] for the elements an upper-tile product skipped.
 __global__ void mirror_tiles_kernel(double *__restrict__ C, int64_t n, int64_t ldc) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n * n) return;
   const int64_t i = idx / n, j = idx - i * n;
-  if (i / kBM > j / kBN) C[i * ldc + j] = C[j * ldc + i];
+  if (upper_tiles_skipped(i, j)) C[i * ldc + j] = C[j * ldc + i];
 }
 
 }  // namespace
