@@ -381,7 +381,8 @@ size_t rsvd_single_view_workspace(bsrht_plan_t omega, bsrht_plan_t gamma,
  * returns A ~= U diag(S) V^T with U = Q Ut_k, S = St_k, V = P Vt_k.  Entries
  * beyond the numerical rank of C are zero (BSRHT_INFO_RANK_CLAMPED).  A is
  * read three times.  Synchronises the stream where a Cholesky flag or the
- * eigenvalues of a fallback are needed.
+ * eigenvalues of a fallback are needed (rsvd_single_view_start below does
+ * not).
  *
  * omega, gamma, phi, psi: plans with omega->n == psi->n == N2,
  *     gamma->n == phi->n == N1, omega->l == gamma->l == l,
@@ -400,6 +401,17 @@ int rsvd_single_view(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi,
                      bsrht_plan_t psi, const float *A, int64_t lda, int64_t k,
                      float *U, double *S, float *V, int32_t *info, void *ws,
                      size_t ws_bytes, void *stream);
+
+/*
+ * Non-blocking form of rsvd_single_view (section 3.3, as above), under the
+ * rules of the *_start forms before it: the same arguments plus `task`,
+ * checked the same way, advanced by bsrht_task_poll / bsrht_task_wait and
+ * released by bsrht_task_destroy; results bitwise those of the blocking form.
+ */
+int rsvd_single_view_start(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi,
+                           bsrht_plan_t psi, const float *A, int64_t lda, int64_t k,
+                           float *U, double *S, float *V, int32_t *info, void *ws,
+                           size_t ws_bytes, void *stream, bsrht_task_t *task);
 
 /*
  * Dense comparison sketches (section 4 compares the block SRHT with Gaussian

@@ -25,7 +25,8 @@ __all__ = [
     "batch_table_bytes", "ApplyItem", "BATCH_MAX", "bsrht_apply_right",
     "bsrht_apply_right_workspace", "rsvd_single_view", "rsvd_single_view_workspace",
     "bsrht_dense_sketch", "bsrht_dense_workspace", "DENSE_GAUSSIAN", "DENSE_RADEMACHER",
-    "nystrom_shifted", "nystrom_job", "finalize",
+    "nystrom_shifted", "nystrom_job", "finalize", "Task", "rsvd_start", "nystrom_start",
+    "rsvd_single_view_start",
 ]
 
 WITH_REPLACEMENT = 0
@@ -104,6 +105,9 @@ _SIGS = {
                                      _c_sz, _c_vp, ctypes.POINTER(_c_vp)]),
     "nystrom_shifted_start": (ctypes.c_int, [_c_vp, _c_vp, _c_i64, _c_i64, _c_vp, _c_vp, _c_vp,
                                              _c_vp, _c_sz, _c_vp, ctypes.POINTER(_c_vp)]),
+    "rsvd_single_view_start": (ctypes.c_int, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_i64, _c_i64,
+                                              _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_sz, _c_vp,
+                                              ctypes.POINTER(_c_vp)]),
     "bsrht_task_poll": (ctypes.c_int, [_c_vp, ctypes.POINTER(ctypes.c_int)]),
     "bsrht_task_wait": (ctypes.c_int, [_c_vp]),
     "bsrht_task_destroy": (ctypes.c_int, [_c_vp]),
@@ -447,10 +451,7 @@ def rsvd_single_view_workspace(omega, gamma, phi, psi, k):
                                                 psi.handle, k))
 
 
-def rsvd_single_view(omega, gamma, phi, psi, A, k, ws=None, stream=None):
-    """Single-view RSVD (Algorithm 3) of the N1 x N2 A with Omega (l x N2),
-    Gamma (l x N1), Phi (s x N1), Psi (s x N2): returns (U N1 x k, S k
-    float64, V N2 x k, info), A ~= U diag(S) V^T."""
+def _single_view_args(omega, gamma, phi, psi, A, k, ws):
     _check_matrix("A", A)
     N1, N2 = A.shape
     if N1 != gamma.n or N2 != omega.n:
@@ -465,10 +466,28 @@ def rsvd_single_view(omega, gamma, phi, psi, A, k, ws=None, stream=None):
         if need == 0:
             raise ValueError("inconsistent single-view plans")
         ws = _workspace(need, dev)
-    _check("rsvd_single_view", lib().rsvd_single_view(
-        omega.handle, gamma.handle, phi.handle, psi.handle, _ptr(A), max(A.stride(0), N2), k,
-        _ptr(U), _ptr(S), _ptr(V), _ptr(info), _ptr(ws), ws.numel(), _stream_ptr(stream)))
+    args = (omega.handle, gamma.handle, phi.handle, psi.handle, _ptr(A), max(A.stride(0), N2), k,
+            _ptr(U), _ptr(S), _ptr(V), _ptr(info), _ptr(ws), ws.numel())
+    return args, U, S, V, info, ws
+
+
+def rsvd_single_view(omega, gamma, phi, psi, A, k, ws=None, stream=None):
+    """Single-view RSVD (Algorithm 3) of the N1 x N2 A with Omega (l x N2),
+    Gamma (l x N1), Phi (s x N1), Psi (s x N2): returns (U N1 x k, S k
+    float64, V N2 x k, info), A ~= U diag(S) V^T."""
+    args, U, S, V, info, _ = _single_view_args(omega, gamma, phi, psi, A, k, ws)
+    _check("rsvd_single_view", lib().rsvd_single_view(*args, _stream_ptr(stream)))
     return U, S, V, info
+
+
+def rsvd_single_view_start(omega, gamma, phi, psi, A, k, ws=None, stream=None):
+    """Non-blocking rsvd_single_view: returns (task, U, S, V, info), valid as
+    for rsvd_start."""
+    args, U, S, V, info, ws = _single_view_args(omega, gamma, phi, psi, A, k, ws)
+    h = _c_vp()
+    _check("rsvd_single_view_start",
+           lib().rsvd_single_view_start(*args, _stream_ptr(stream), ctypes.byref(h)))
+    return Task(h.value, (omega, gamma, phi, psi, A, U, S, V, info, ws)), U, S, V, info
 
 
 def nystrom_workspace(plan, k):
@@ -501,8 +520,8 @@ def nystrom_shifted(plan, A, k, ws=None, stream=None):
 
 
 class Task:
-    """A non-blocking rsvd / nystrom call (rsvd_start, nystrom_start of
-    include/bsrht.h).  poll() advances it without waiting and returns True once
+    """A non-blocking rsvd / nystrom / single-view call (rsvd_start,
+    nystrom_start, rsvd_single_view_start of include/bsrht.h).  poll() advances it without waiting and returns True once
     all of its work is queued (raising if the call failed); wait() blocks until
     then.  The results are ready in stream order.  The tensors the call uses
     are kept alive until the task is closed."""

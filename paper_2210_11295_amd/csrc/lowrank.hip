@@ -228,10 +228,6 @@ __global__ void unshift_kernel(double *__restrict__ lam, int64_t k, const double
 // column blocks of up to 16); the padding is zero rows and columns.
 inline int64_t svd_pad(int64_t x) { return (x + 31) & ~int64_t(31); }
 
-inline int read_i32(const int32_t *dev, hipStream_t s, int32_t *out) {
-  return copy_to_host(out, dev, sizeof(int32_t), s);
-}
-
 // Workspace of the small SVD stage for an nc x nc problem (nc even).
 template <class A>
 struct SvdBufs {
@@ -391,13 +387,6 @@ Task small_svd_task(DevCtx &ctx, SvdBufs<A> &b, const double *R, int64_t nc0, in
                                      b.perm, b.flags, kMaxSweeps, info, 0);
 }
 
-template <class A>
-int small_svd(SvdBufs<A> &b, const double *R, int64_t nc0, int64_t ldr, bool eigen,
-              int32_t *info, hipStream_t s) {
-  DevCtx ctx;
-  ctx.s = s;
-  return run_blocking(small_svd_task(ctx, b, R, nc0, ldr, eigen, info));
-}
 
 }  // namespace
 }  // namespace bsrht
@@ -1009,30 +998,31 @@ struct SvWs {
 // F = V_+ Lam_+^{-1/2} from G's eigen split with the eigenvalues above
 // n u lambda_max (then F F^T = G^+ and *fell_back is set).
 template <class A>
-int inv_factor(double *G, int64_t n, double tol, double *F, int64_t *nf, bool *fell_back,
-               SvWs<A> &w, int32_t *info, hipStream_t s) {
-  BSRHT_TRY(scale_cols_f64(G, n, n, n, n, nullptr, w.Gs, n, s));
-  BSRHT_TRY(cholesky_upper(G, n, n, tol, w.flag, w.chol_state, s));
+Task inv_factor_task(DevCtx &ctx, double *G, int64_t n, double tol, double *F, int64_t *nf,
+                     bool *fell_back, SvWs<A> &w, int32_t *info) {
+  hipStream_t s = ctx.s;
+  BSRHT_CO_TRY(scale_cols_f64(G, n, n, n, n, nullptr, w.Gs, n, s));
+  BSRHT_CO_TRY(cholesky_upper(G, n, n, tol, w.flag, w.chol_state, s));
   int32_t hf = 0;
-  BSRHT_TRY(read_i32(w.flag, s, &hf));
+  BSRHT_CO_TRY(co_await readback(ctx, &hf, w.flag, sizeof(hf)));
   *fell_back = hf != 0;
   if (hf == 0) {
     *nf = n;
-    return trinv_upper(G, n, n, F, n, s);
+    co_return trinv_upper(G, n, n, F, n, s);
   }
-  BSRHT_TRY(small_svd(w.qb, w.Gs, n, n, true, info, s));
+  BSRHT_CO_TRY(co_await small_svd_task(ctx, w.qb, w.Gs, n, n, true, info));
   std::vector<double> ev((size_t)n);
-  if (copy_to_host(ev.data(), w.qb.S, sizeof(double) * (size_t)n, s) != BSRHT_OK)
-    return BSRHT_EDEVICE;
+  if (co_await readback(ctx, ev.data(), w.qb.S, sizeof(double) * (size_t)n) != BSRHT_OK)
+    co_return BSRHT_EDEVICE;
   int64_t keep = 0;
   for (int64_t i = 0; i < n; ++i)
     if (ev[(size_t)i] > (double)n * kU64 * ev[0] && ev[(size_t)i] > 0.0) ++keep;
   if (keep < 1) keep = 1;
   inv_sqrt_kernel<<<(unsigned)((keep + 255) / 256), 256, 0, s>>>(w.qb.S, nullptr, keep, w.qb.inv);
-  BSRHT_LAUNCH_CHECK();
-  BSRHT_TRY(scale_cols_f64(w.qb.Vs, n, keep, keep, svd_pad(n), w.qb.inv, F, keep, s));
+  BSRHT_CO_LAUNCH_CHECK();
+  BSRHT_CO_TRY(scale_cols_f64(w.qb.Vs, n, keep, keep, svd_pad(n), w.qb.inv, F, keep, s));
   *nf = keep;
-  return BSRHT_OK;
+  co_return BSRHT_OK;
 }
 
 // Q32 (rows x lk, leading dimension ld4(lk)): an orthonormal basis of the
@@ -1041,16 +1031,18 @@ int inv_factor(double *G, int64_t n, double tol, double *F, int64_t *nf, bool *f
 // Leading dimensions are rounded up to 4 elements (ld4), which the
 // large-tile GEMM kernel needs for its 16-byte loads.
 template <class A>
-int orth_basis(const float *X, int64_t rows, int64_t l, int64_t sr, int64_t sc, float *Q32,
-               int64_t *lk_out, SvWs<A> &w, int32_t *info, hipStream_t s) {
-  BSRHT_TRY(gram_f32(X, rows, l, sr, sc, w.G, l, w.gram_part, gram_splits(rows, l), s));
+Task orth_basis_task(DevCtx &ctx, const float *X, int64_t rows, int64_t l, int64_t sr,
+                     int64_t sc, float *Q32, int64_t *lk_out, SvWs<A> &w, int32_t *info) {
+  hipStream_t s = ctx.s;
+  BSRHT_CO_TRY(gram_f32(X, rows, l, sr, sc, w.G, l, w.gram_part, gram_splits(rows, l), s));
   int64_t lk = l;
   bool fb = false;
-  BSRHT_TRY(inv_factor(w.G, l, (double)l * kU64, w.F, &lk, &fb, w, info, s));
+  BSRHT_CO_TRY(
+      co_await inv_factor_task(ctx, w.G, l, (double)l * kU64, w.F, &lk, &fb, w, info));
   const int64_t ldk = ld4(lk);
   if (ldk != lk) {  // F (l x lk) into a zero padded l x ldk copy in C2inv
-    BSRHT_TRY(scale_cols_f64(w.F, l, lk, ldk, lk, nullptr, w.C2inv, ldk, s));
-    BSRHT_TRY(scale_cols_f64(w.C2inv, l, ldk, ldk, ldk, nullptr, w.F, ldk, s));
+    BSRHT_CO_TRY(scale_cols_f64(w.F, l, lk, ldk, lk, nullptr, w.C2inv, ldk, s));
+    BSRHT_CO_TRY(scale_cols_f64(w.C2inv, l, ldk, ldk, ldk, nullptr, w.F, ldk, s));
   }
   {
     GemmDesc d;
@@ -1058,32 +1050,32 @@ int orth_basis(const float *X, int64_t rows, int64_t l, int64_t sr, int64_t sc, 
     d.sai = sr; d.sak = sc;
     d.sbk = ldk; d.sbj = 1;
     d.ldc = ldk;
-    BSRHT_TRY(gemm_f32f64_f64(d, X, w.F, w.Q1, s));
+    BSRHT_CO_TRY(gemm_f32f64_f64(d, X, w.F, w.Q1, s));
   }
   if (fb) {
     or_info_kernel<<<1, 1, 0, s>>>(info, BSRHT_INFO_QB_FALLBACK);
-    BSRHT_LAUNCH_CHECK();
+    BSRHT_CO_LAUNCH_CHECK();
   }
   // second pass: G2 = Q1^T Q1 = C2^T C2, Q = Q1 C2^{-1} (padding columns stay 0)
-  BSRHT_TRY(gram_f64(w.Q1, rows, lk, ldk, 1, w.G2, lk, w.gram_part, gram_splits(rows, lk), s));
-  BSRHT_TRY(cholesky_upper(w.G2, lk, lk, 1e-14, w.flag + 1, w.chol_state, s));
+  BSRHT_CO_TRY(gram_f64(w.Q1, rows, lk, ldk, 1, w.G2, lk, w.gram_part, gram_splits(rows, lk), s));
+  BSRHT_CO_TRY(cholesky_upper(w.G2, lk, lk, 1e-14, w.flag + 1, w.chol_state, s));
   int32_t hf2 = 0;
-  BSRHT_TRY(read_i32(w.flag + 1, s, &hf2));
+  BSRHT_CO_TRY(co_await readback(ctx, &hf2, w.flag + 1, sizeof(hf2)));
   if (hf2 != 0) {  // Q1 is orthonormal to O(eps kappa^2): should not happen
     debug_report(__FILE__, __LINE__, "second Cholesky-QR pass", BSRHT_EDEVICE);
-    return BSRHT_EDEVICE;
+    co_return BSRHT_EDEVICE;
   }
-  BSRHT_TRY(trinv_upper(w.G2, lk, lk, w.F, ldk, s));
-  BSRHT_TRY(scale_cols_f64(w.F, lk, lk, ldk, ldk, nullptr, w.C2inv, ldk, s));
-  if (ldk > lk) BSRHT_TRY(fill_f64(w.C2inv + lk * ldk, (ldk - lk) * ldk, 0.0, s));
+  BSRHT_CO_TRY(trinv_upper(w.G2, lk, lk, w.F, ldk, s));
+  BSRHT_CO_TRY(scale_cols_f64(w.F, lk, lk, ldk, ldk, nullptr, w.C2inv, ldk, s));
+  if (ldk > lk) BSRHT_CO_TRY(fill_f64(w.C2inv + lk * ldk, (ldk - lk) * ldk, 0.0, s));
   GemmDesc d;
   d.M = rows; d.N = ldk; d.K = ldk;
   d.sai = ldk; d.sak = 1;
   d.sbk = ldk; d.sbj = 1;
   d.ldc = ldk;
-  BSRHT_TRY(gemm_f64f64_f32(d, w.Q1, w.C2inv, Q32, s));
+  BSRHT_CO_TRY(gemm_f64f64_f32(d, w.Q1, w.C2inv, Q32, s));
   *lk_out = lk;
-  return BSRHT_OK;
+  co_return BSRHT_OK;
 }
 
 int sketch_cols(const bsrht_plan_s *pl, const float *X, int64_t m, int64_t ldx, float *Y,
@@ -1113,63 +1105,81 @@ size_t rsvd_single_view_workspace(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_
   return align256(so.sz.used);
 }
 
-int rsvd_single_view(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi, bsrht_plan_t psi,
-                     const float *A, int64_t lda, int64_t k, float *U, double *S, float *V,
-                     int32_t *info, void *ws, size_t ws_bytes, void *stream) {
+}  // extern "C"
+
+namespace bsrht {
+namespace {
+
+// The argument checks of rsvd_single_view and rsvd_single_view_start.
+int sv_args(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi, bsrht_plan_t psi,
+            const float *A, int64_t lda, int64_t k, float *U, double *S, float *V,
+            int32_t *info, void *ws, size_t ws_bytes) {
   if (!sv_shapes_ok(omega, gamma, phi, psi) || !A || !U || !S || !V || !info || k < 1 ||
       lda < omega->n)
     return BSRHT_EINVAL;
-  const int64_t N1 = gamma->n, N2 = omega->n, l = omega->l, s_ = phi->l;
+  const int64_t N1 = gamma->n, N2 = omega->n, l = omega->l;
   if (svd_pad(l) > 4096 || N1 > INT_MAX || N2 > INT_MAX) return BSRHT_EUNSUPPORTED;
   if (ws_bytes < rsvd_single_view_workspace(omega, gamma, phi, psi, k) || !ws)
     return BSRHT_ENOMEM;
-  hipStream_t s = (hipStream_t)stream;
+  return BSRHT_OK;
+}
+
+// Algorithm 3 (argument checks done by the caller).
+Task rsvd_single_view_task(DevCtx &ctx, const bsrht_plan_s *omega, const bsrht_plan_s *gamma,
+                           const bsrht_plan_s *phi, const bsrht_plan_s *psi, const float *A,
+                           int64_t lda, int64_t k, float *U, double *S, float *V,
+                           int32_t *info, void *ws, size_t ws_bytes) {
+  const int64_t N1 = gamma->n, N2 = omega->n, l = omega->l, s_ = phi->l;
+  hipStream_t s = ctx.s;
   Carve cv(ws, ws_bytes);
   SvWs<Carve> w;
   w.layout(cv, omega, gamma, phi, psi, k);
-  if (cv.overflow) return BSRHT_ENOMEM;
+  if (cv.overflow) co_return BSRHT_ENOMEM;
   zero_i32_kernel<<<1, 64, 0, s>>>(info, 1);
-  BSRHT_LAUNCH_CHECK();
+  BSRHT_CO_LAUNCH_CHECK();
 
   // 1. the three sketches
-  BSRHT_TRY(sketch_cols(gamma, A, N2, lda, w.Xt, N2, w.apply_ws, w.apply_bytes, s));
-  BSRHT_TRY(apply_right_fp32(omega, A, N1, lda, w.Y, l, w.apply_ws, w.apply_bytes, s));
-  BSRHT_TRY(sketch_cols(phi, A, N2, lda, w.W, N2, w.apply_ws, w.apply_bytes, s));
-  BSRHT_TRY(apply_right_fp32(psi, w.W, s_, N2, w.Zs, s_, w.apply_ws, w.apply_bytes, s));
+  BSRHT_CO_TRY(sketch_cols(gamma, A, N2, lda, w.Xt, N2, w.apply_ws, w.apply_bytes, s));
+  BSRHT_CO_TRY(apply_right_fp32(omega, A, N1, lda, w.Y, l, w.apply_ws, w.apply_bytes, s));
+  BSRHT_CO_TRY(sketch_cols(phi, A, N2, lda, w.W, N2, w.apply_ws, w.apply_bytes, s));
+  BSRHT_CO_TRY(apply_right_fp32(psi, w.W, s_, N2, w.Zs, s_, w.apply_ws, w.apply_bytes, s));
   // 2. Q = Y Fq implicitly (N1 x lq), P = orth(X) = orth(Xt^T) (N2 x lp)
   int64_t lq = l, lp = l;
   {
     bool fbq = false;
-    BSRHT_TRY(gram_f32(w.Y, N1, l, l, 1, w.G, l, w.gram_part, gram_splits(N1, l), s));
-    BSRHT_TRY(inv_factor(w.G, l, (double)l * kU64, w.Fq, &lq, &fbq, w, info, s));
+    BSRHT_CO_TRY(gram_f32(w.Y, N1, l, l, 1, w.G, l, w.gram_part, gram_splits(N1, l), s));
+    BSRHT_CO_TRY(co_await inv_factor_task(ctx, w.G, l, (double)l * kU64, w.Fq, &lq, &fbq, w,
+                                       info));
     if (fbq) {
       or_info_kernel<<<1, 1, 0, s>>>(info, BSRHT_INFO_QB_FALLBACK);
-      BSRHT_LAUNCH_CHECK();
+      BSRHT_CO_LAUNCH_CHECK();
     }
   }
-  BSRHT_TRY(orth_basis(w.Xt, N2, l, 1, N2, w.P32, &lp, w, info, s));
+  BSRHT_CO_TRY(co_await orth_basis_task(ctx, w.Xt, N2, l, 1, N2, w.P32, &lp, w, info));
   const int64_t ldp = ld4(lp);  // leading dimension of P32
   // 3. Phi Q = (Phi Y) Fq (s x lq, FP64), Psi P (s x lp)
-  BSRHT_TRY(sketch_cols(phi, w.Y, l, l, w.PhY, l, w.apply_ws, w.apply_bytes, s));
+  BSRHT_CO_TRY(sketch_cols(phi, w.Y, l, l, w.PhY, l, w.apply_ws, w.apply_bytes, s));
   {
     GemmDesc d;
     d.M = s_; d.N = lq; d.K = l;
     d.sai = l; d.sak = 1;
     d.sbk = lq; d.sbj = 1;
     d.ldc = lq;
-    BSRHT_TRY(gemm_f32f64_f64(d, w.PhY, w.Fq, w.PhQ, s));
+    BSRHT_CO_TRY(gemm_f32f64_f64(d, w.PhY, w.Fq, w.PhQ, s));
   }
-  BSRHT_TRY(sketch_cols(psi, w.P32, lp, ldp, w.PsP, lp, w.apply_ws, w.apply_bytes, s));
+  BSRHT_CO_TRY(sketch_cols(psi, w.P32, lp, ldp, w.PsP, lp, w.apply_ws, w.apply_bytes, s));
   // 4. C = (Phi Q)^+ Z ((Psi P)^T)^+, computed as C^T (lp x lq) in Ct
   int64_t nf1 = lq, nf2 = lp;
   bool fb1 = false, fb2 = false;
-  BSRHT_TRY(gram_f64(w.PhQ, s_, lq, lq, 1, w.Gc, lq, w.gram_part, gram_splits(s_, lq), s));
-  BSRHT_TRY(inv_factor(w.Gc, lq, (double)lq * kU64, w.F1, &nf1, &fb1, w, info, s));
-  BSRHT_TRY(gram_f32(w.PsP, s_, lp, lp, 1, w.Gc, lp, w.gram_part, gram_splits(s_, lp), s));
-  BSRHT_TRY(inv_factor(w.Gc, lp, (double)lp * kU64, w.F2, &nf2, &fb2, w, info, s));
+  BSRHT_CO_TRY(gram_f64(w.PhQ, s_, lq, lq, 1, w.Gc, lq, w.gram_part, gram_splits(s_, lq), s));
+  BSRHT_CO_TRY(co_await inv_factor_task(ctx, w.Gc, lq, (double)lq * kU64, w.F1, &nf1, &fb1, w,
+                                       info));
+  BSRHT_CO_TRY(gram_f32(w.PsP, s_, lp, lp, 1, w.Gc, lp, w.gram_part, gram_splits(s_, lp), s));
+  BSRHT_CO_TRY(co_await inv_factor_task(ctx, w.Gc, lp, (double)lp * kU64, w.F2, &nf2, &fb2, w,
+                                       info));
   if (fb1 || fb2) {
     or_info_kernel<<<1, 1, 0, s>>>(info, BSRHT_INFO_CHOL_FALLBACK);
-    BSRHT_LAUNCH_CHECK();
+    BSRHT_CO_LAUNCH_CHECK();
   }
   {
     GemmDesc d;  // T1^T = Z^T (Phi Q)  (s x lq), in T1
@@ -1177,7 +1187,7 @@ int rsvd_single_view(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi, b
     d.sai = 1; d.sak = s_;
     d.sbk = lq; d.sbj = 1;
     d.ldc = lq;
-    BSRHT_TRY(gemm_f32f64_f64(d, w.Zs, w.PhQ, w.T1, s));
+    BSRHT_CO_TRY(gemm_f32f64_f64(d, w.Zs, w.PhQ, w.T1, s));
   }
   {
     GemmDesc d;  // T2 = F1^T T1  (nf1 x s), T1[kk][j] read from T1^T
@@ -1185,7 +1195,7 @@ int rsvd_single_view(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi, b
     d.sai = 1; d.sak = nf1;
     d.sbk = 1; d.sbj = lq;
     d.ldc = s_;
-    BSRHT_TRY(gemm_f64(d, w.F1, w.T1, w.T2, s));
+    BSRHT_CO_TRY(gemm_f64(d, w.F1, w.T1, w.T2, s));
   }
   {
     GemmDesc d;  // C1 = F1 T2 = (Phi Q)^+ Z  (lq x s), into T1
@@ -1193,7 +1203,7 @@ int rsvd_single_view(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi, b
     d.sai = nf1; d.sak = 1;
     d.sbk = s_; d.sbj = 1;
     d.ldc = s_;
-    BSRHT_TRY(gemm_f64(d, w.F1, w.T2, w.T1, s));
+    BSRHT_CO_TRY(gemm_f64(d, w.F1, w.T2, w.T1, s));
   }
   {
     GemmDesc d;  // T3t = (Psi P)^T C1^T  (lp x lq)
@@ -1201,7 +1211,7 @@ int rsvd_single_view(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi, b
     d.sai = 1; d.sak = lp;
     d.sbk = 1; d.sbj = s_;
     d.ldc = lq;
-    BSRHT_TRY(gemm_f32f64_f64(d, w.PsP, w.T1, w.T3t, s));
+    BSRHT_CO_TRY(gemm_f32f64_f64(d, w.PsP, w.T1, w.T3t, s));
   }
   {
     GemmDesc d;  // T4t = F2^T T3t  (nf2 x lq)
@@ -1209,7 +1219,7 @@ int rsvd_single_view(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi, b
     d.sai = 1; d.sak = nf2;
     d.sbk = lq; d.sbj = 1;
     d.ldc = lq;
-    BSRHT_TRY(gemm_f64(d, w.F2, w.T3t, w.T4t, s));
+    BSRHT_CO_TRY(gemm_f64(d, w.F2, w.T3t, w.T4t, s));
   }
   {
     GemmDesc d;  // Ct = F2 T4t = C^T  (lp x lq)
@@ -1217,7 +1227,7 @@ int rsvd_single_view(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi, b
     d.sai = nf2; d.sak = 1;
     d.sbk = lq; d.sbj = 1;
     d.ldc = lq;
-    BSRHT_TRY(gemm_f64(d, w.F2, w.T4t, w.Ct, s));
+    BSRHT_CO_TRY(gemm_f64(d, w.F2, w.T4t, w.Ct, s));
   }
   // 5. SVD of C (lq x lp), preconditioned: the Cholesky factor R of the FP64
   // Gram C^T C = R^T R has the singular values and right singular vectors of
@@ -1227,42 +1237,42 @@ int rsvd_single_view(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi, b
   // order, and the rotations (Vt) are accumulated.
   const int64_t L = svd_pad(std::max(lq, lp));
   int64_t ldv = L;  // leading dimension of the right singular vectors in sv.Vs
-  BSRHT_TRY(gram_f64(w.Ct, lq, lp, 1, lq, w.Gc, lp, w.gram_part, gram_splits(lq, lp), s));
-  BSRHT_TRY(cholesky_upper(w.Gc, lp, lp, (double)lp * kU64, w.flag + 2, w.chol_state, s));
+  BSRHT_CO_TRY(gram_f64(w.Ct, lq, lp, 1, lq, w.Gc, lp, w.gram_part, gram_splits(lq, lp), s));
+  BSRHT_CO_TRY(cholesky_upper(w.Gc, lp, lp, (double)lp * kU64, w.flag + 2, w.chol_state, s));
   int32_t hc = 0;
-  BSRHT_TRY(read_i32(w.flag + 2, s, &hc));
+  BSRHT_CO_TRY(co_await readback(ctx, &hc, w.flag + 2, sizeof(hc)));
   if (hc == 0) {
-    BSRHT_TRY(small_svd(w.sv, w.Gc, lp, lp, false, info, s));
+    BSRHT_CO_TRY(co_await small_svd_task(ctx, w.sv, w.Gc, lp, lp, false, info));
     ldv = svd_pad(lp);
   } else {
-    BSRHT_TRY(fill_f64(w.sv.X, L * L, 0.0, s));
-    BSRHT_TRY(scale_cols_f64(w.Ct, lp, lq, lq, lq, nullptr, w.sv.X, L, s));
-    BSRHT_TRY(jacobi_svd(w.sv.X, L, L, L, w.sv.V, w.sv.S, w.sv.Vs, L, w.sv.perm, w.sv.flags,
+    BSRHT_CO_TRY(fill_f64(w.sv.X, L * L, 0.0, s));
+    BSRHT_CO_TRY(scale_cols_f64(w.Ct, lp, lq, lq, lq, nullptr, w.sv.X, L, s));
+    BSRHT_CO_TRY(jacobi_svd(w.sv.X, L, L, L, w.sv.V, w.sv.S, w.sv.Vs, L, w.sv.perm, w.sv.flags,
                          kMaxSweeps, info, s));
   }
   // 6. S = St_k, V = P Vt_k, U = Q (C Vt_k St_k^{-1})
   const int64_t avail = std::min(lq, lp);
   finish_sigma_kernel<<<(unsigned)((k + 255) / 256), 256, 0, s>>>(
       w.sv.S, avail, k, sqrt((double)L * kU64), 1, w.sv.inv, S, info);
-  BSRHT_LAUNCH_CHECK();
+  BSRHT_CO_LAUNCH_CHECK();
   const int64_t keep = std::min(k, avail);
-  BSRHT_TRY(scale_cols_f64_f32(w.sv.Vs, lp, keep, k, ldv, nullptr, w.Vk32, k, s));
+  BSRHT_CO_TRY(scale_cols_f64_f32(w.sv.Vs, lp, keep, k, ldv, nullptr, w.Vk32, k, s));
   {
     GemmDesc d;
     d.M = N2; d.N = k; d.K = lp;
     d.sai = ldp; d.sak = 1;
     d.sbk = k; d.sbj = 1;
     d.ldc = k;
-    BSRHT_TRY(gemm_f32(d, w.P32, w.Vk32, V, s));
+    BSRHT_CO_TRY(gemm_f32(d, w.P32, w.Vk32, V, s));
   }
-  BSRHT_TRY(scale_cols_f64(w.sv.Vs, lp, keep, k, ldv, w.sv.inv, w.Mv, k, s));
+  BSRHT_CO_TRY(scale_cols_f64(w.sv.Vs, lp, keep, k, ldv, w.sv.inv, w.Mv, k, s));
   {
     GemmDesc d;  // Mu = C Mv = Ct^T Mv  (lq x k)
     d.M = lq; d.N = k; d.K = lp;
     d.sai = 1; d.sak = lq;
     d.sbk = k; d.sbj = 1;
     d.ldc = k;
-    BSRHT_TRY(gemm_f64(d, w.Ct, w.Mv, w.Mu, s));
+    BSRHT_CO_TRY(gemm_f64(d, w.Ct, w.Mv, w.Mu, s));
   }
   {
     GemmDesc d;  // Mq = Fq Mu  (l x k), in Mv: U = Q Mu = Y Mq
@@ -1270,11 +1280,40 @@ int rsvd_single_view(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi, b
     d.sai = lq; d.sak = 1;
     d.sbk = k; d.sbj = 1;
     d.ldc = k;
-    BSRHT_TRY(gemm_f64(d, w.Fq, w.Mu, w.Mv, s));
+    BSRHT_CO_TRY(gemm_f64(d, w.Fq, w.Mu, w.Mv, s));
   }
-  BSRHT_TRY(scale_cols_f64_f32(w.Mv, l, k, k, k, nullptr, w.Mu32, k, s));
+  BSRHT_CO_TRY(scale_cols_f64_f32(w.Mv, l, k, k, k, nullptr, w.Mu32, k, s));
   // the tall product with FP32-level accuracy (six split-BF16 products)
-  return tall_product(w.Y, l, w.Mu32, k, U, k, N1, k, l, 3, w.xws, w.xws_bytes, s);
+  co_return tall_product(w.Y, l, w.Mu32, k, U, k, N1, k, l, 3, w.xws, w.xws_bytes, s);
+}
+
+}  // namespace
+}  // namespace bsrht
+
+extern "C" {
+
+int rsvd_single_view(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi, bsrht_plan_t psi,
+                     const float *A, int64_t lda, int64_t k, float *U, double *S, float *V,
+                     int32_t *info, void *ws, size_t ws_bytes, void *stream) {
+  BSRHT_TRY(sv_args(omega, gamma, phi, psi, A, lda, k, U, S, V, info, ws, ws_bytes));
+  DevCtx ctx;
+  ctx.s = (hipStream_t)stream;
+  return run_blocking(rsvd_single_view_task(ctx, omega, gamma, phi, psi, A, lda, k, U, S, V,
+                                            info, ws, ws_bytes));
+}
+
+int rsvd_single_view_start(bsrht_plan_t omega, bsrht_plan_t gamma, bsrht_plan_t phi,
+                           bsrht_plan_t psi, const float *A, int64_t lda, int64_t k, float *U,
+                           double *S, float *V, int32_t *info, void *ws, size_t ws_bytes,
+                           void *stream, bsrht_task_t *task) {
+  if (!task) return BSRHT_EINVAL;
+  *task = nullptr;
+  BSRHT_TRY(sv_args(omega, gamma, phi, psi, A, lda, k, U, S, V, info, ws, ws_bytes));
+  bsrht_task_s *t = nullptr;
+  BSRHT_TRY(task_open(stream, &t));
+  return task_start(t, rsvd_single_view_task(t->ctx, omega, gamma, phi, psi, A, lda, k, U, S, V,
+                                             info, ws, ws_bytes),
+                    task);
 }
 
 }  // extern "C"

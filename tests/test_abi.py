@@ -82,7 +82,7 @@ def test_null_plan_is_rejected():
 
 
 def test_task_calls_reject_bad_arguments_on_the_host():
-    """rsvd_start / nystrom_start and the task calls check their arguments
+    """rsvd_start / nystrom_start / rsvd_single_view_start and the task calls check their arguments
     before any HIP call (no GPU needed): NULL plans and tasks are refused and
     the task handle is cleared."""
     L = bs.lib()
@@ -97,6 +97,10 @@ def test_task_calls_reject_bad_arguments_on_the_host():
     assert h.value is None
     assert L.nystrom_shifted_start(None, None, 1, 1, None, None, None, None, 0, None,
                                    None) == -1
+    h = ctypes.c_void_p(1)
+    assert L.rsvd_single_view_start(None, None, None, None, None, 1, 1, None, None, None, None,
+                                    None, 0, None, ctypes.byref(h)) == -1
+    assert h.value is None
     st = ctypes.c_int(7)
     assert L.bsrht_task_poll(null, ctypes.byref(st)) == -1 and st.value == 7
     assert L.bsrht_task_wait(null) == -1

@@ -1,6 +1,7 @@
-"""Non-blocking randomized SVD and Nystrom (rsvd_start, nystrom_start,
-nystrom_shifted_start and bsrht_task_poll / wait / destroy of
-include/bsrht.h; sections 3.1 and 3.2): the same coroutines as the blocking
+"""Non-blocking randomized SVD, Nystrom and single-view SVD (rsvd_start,
+nystrom_start, nystrom_shifted_start, rsvd_single_view_start and
+bsrht_task_poll / wait / destroy of include/bsrht.h; sections 3.1 to 3.3):
+the same coroutines as the blocking
 calls run with an asynchronous context, so on the same plan and input their
 results must equal the blocking calls' bitwise, also with two tasks in
 flight on two streams and with a task destroyed before it has finished."""
@@ -77,3 +78,46 @@ def test_task_start_argument_errors():
         bs.rsvd_start(rplan, A, 40, ws=torch.zeros(16, dtype=torch.uint8, device=dev))
     with pytest.raises(bs.BsrhtError):
         bs.nystrom_start(nplan, B, 0)
+
+
+def _sv_plans(N1, N2, l, s, seed, dev):
+    """Omega (l x N2), Gamma (l x N1), Phi (s x N1), Psi (s x N2)."""
+    return [bs.Plan(N2, 4, l, seed, device=dev), bs.Plan(N1, 4, l, seed + 1, device=dev),
+            bs.Plan(N1, 8, s, seed + 2, device=dev), bs.Plan(N2, 2, s, seed + 3, device=dev)]
+
+
+def test_single_view_tasks_equal_blocking_calls():
+    """rsvd_single_view_start on a full-rank input and on a rank-30 input with
+    l = 64 (the bases then come from the eigen split, whose eigenvalues are
+    read back mid-task), both in flight at once on two streams, against the
+    blocking call."""
+    dev = device()
+    A = workloads.lowrank_tall(4096, 512, "inv_sq", 5, device=dev)
+    rs = torch.Generator(device=dev).manual_seed(4)
+    B = torch.randn(2048, 30, generator=rs, device=dev, dtype=torch.float64)
+    C = torch.randn(30, 512, generator=rs, device=dev, dtype=torch.float64)
+    R = (B @ C).float()
+    pa = _sv_plans(4096, 512, 64, 128, 21, dev)
+    pr = _sv_plans(2048, 512, 64, 128, 31, dev)
+    ref_a = bs.rsvd_single_view(*pa, A, 30)
+    ref_r = bs.rsvd_single_view(*pr, R, 30)
+    torch.cuda.synchronize()
+    assert int(ref_r[3].item()) & bs.INFO_QB_FALLBACK
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    ta, *got_a = bs.rsvd_single_view_start(*pa, A, 30, stream=s1)
+    tr, *got_r = bs.rsvd_single_view_start(*pr, R, 30, stream=s2)
+    pending = {"full rank": ta, "rank 30": tr}
+    deadline = time.time() + 60.0
+    while pending:
+        assert time.time() < deadline, f"tasks still running: {sorted(pending)}"
+        for name in list(pending):
+            if pending[name].poll():
+                del pending[name]
+    torch.cuda.synchronize()
+    for got, ref in zip(got_a + got_r, list(ref_a) + list(ref_r)):
+        assert torch.equal(got, ref)
+    ta.close()
+    tr.close()
+    ws = torch.zeros(bs.rsvd_single_view_workspace(*pa, 30), dtype=torch.uint8, device=dev)
+    with pytest.raises(bs.BsrhtError):  # Phi and Gamma swapped: inconsistent plans
+        bs.rsvd_single_view_start(pa[0], pa[2], pa[1], pa[3], A, 30, ws=ws)
