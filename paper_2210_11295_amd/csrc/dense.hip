@@ -9,6 +9,7 @@
 //     Algorithms: block pairs swept in LDS, one launch per round;
 //   - small helpers (identity, transpose/convert, column scaling, sort).
 #include <algorithm>
+#include <climits>
 
 #include "common.h"
 #include "dense.h"
@@ -351,6 +352,204 @@ __global__ void mirror_tiles_kernel(double *__restrict__ C, int64_t n, int64_t l
   if (upper_tiles_skipped(i, j)) C[i * ldc + j] = C[j * ldc + i];
 }
 
+// ---------------------------------------------------------------------------
+// Gram of a tall FP32 matrix on the int8 matrix cores, exact to FP64 level.
+// Column c of X is scaled by 2^-e_c (|x| < 2^e_c over the column) and written
+// in seven signed base-128 digits by round-to-nearest,
+//   x = 2^(e_c - 6) * sum_{a<7} d_a 2^(-7a) + rem,  |d_a| <= 64,
+//   |rem| <= 2^(e_c - 50),
+// so x_i x_j = 2^(e_i + e_j - 12) sum_{a,b} d_a d'_b 2^(-7(a+b)).  The digit
+// products are exact in int32 (v_mfma_i32_16x16x64_i8); the 28 pairs with
+// a + b <= 6 are accumulated per level a + b and the levels combined in FP64
+// once per row chunk.  A digit of 64 times 64, seven pairs to a level and
+// at most kI8MaxChunk rows keep every level below 2^31.  Elements at least
+// 2^-24 of their column's maximum are represented exactly, the dropped pairs
+// sit below 2^-49 of the column maxima's product: the error is at the level
+// of an FP64 accumulation of the exact products.
+constexpr int kI8Digits = 7;
+constexpr int kI8T = 64;      // output tile (and column block) width
+constexpr int kI8Rows = 64;   // rows per step
+constexpr int64_t kI8MaxChunk = 65536;
+constexpr int kI8NonFinite = 1 << 20;  // column exponent marking an Inf / NaN column
+
+using I4 = int __attribute__((ext_vector_type(4)));
+
+// part[b][c] = max |X[r][c]| (as float bits, NaN above Inf above finite) over
+// the rows of block b.
+__global__ __launch_bounds__(256) void colmax_partial_kernel(const float *__restrict__ X,
+                                                             int64_t n, int64_t K, int64_t sr,
+                                                             int64_t rows_per,
+                                                             unsigned *__restrict__ part) {
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per;
+  const int64_t r1 = min(n, r0 + rows_per);
+  for (int64_t c = threadIdx.x; c < K; c += blockDim.x) {
+    unsigned m = 0;
+#pragma unroll 8
+    for (int64_t r = r0; r < r1; ++r) m = max(m, __float_as_uint(X[r * sr + c]) & 0x7fffffffu);
+    part[(int64_t)blockIdx.x * K + c] = m;
+  }
+}
+
+// ex[c]: the exponent e with max |X[.][c]| < 2^e (0 for a zero column,
+// kI8NonFinite for a column holding Inf or NaN).
+__global__ void colexp_kernel(const unsigned *__restrict__ part, int blocks, int64_t K,
+                              int *__restrict__ ex) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= K) return;
+  unsigned m = 0;
+  for (int b = 0; b < blocks; ++b) m = max(m, part[(int64_t)b * K + c]);
+  int e = 0;
+  if (m >= 0x7f800000u)
+    e = kI8NonFinite;
+  else if (m != 0)
+    (void)frexpf(__uint_as_float(m), &e);
+  ex[c] = e;
+}
+
+struct I8GramArgs {
+  const float *X;
+  int64_t n, K, sr;
+  int64_t rows_per;  // rows per split, a multiple of kI8Rows, <= kI8MaxChunk
+  const int *ex;
+  double *P;  // [splits][K][K] FP64 partials
+  int nt;     // column blocks of kI8T
+  int tiles;  // nt (nt + 1) / 2 tiles on or above the diagonal
+  int items;  // tiles * splits
+};
+
+// Byte offset of the 16-row group g of column col in a digit plane: 64 bytes
+// per column, the groups XOR-swizzled by column so that the 16 lanes of a
+// 128-bit read hit distinct banks.
+__device__ __forceinline__ int i8_off(int col, int g) {
+  return col * kI8Rows + 16 * (g ^ ((col >> 2) & 3));
+}
+
+// One workgroup: a 64 x 64 tile of partial G over the rows of one split.
+// Wave w owns rows 16w..16w+15 of the tile and all four 16-column subtiles.
+__global__ __launch_bounds__(256) void gram_i8_kernel(I8GramArgs g) {
+  __shared__ __attribute__((aligned(16))) unsigned char sl[2][kI8Digits][kI8T * kI8Rows];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // consecutive workgroups go round-robin over the eight XCDs: give each XCD
+  // a contiguous run of work items (split-major), so that the tiles of one
+  // row range share that XCD's L2
+  int w = (int)blockIdx.x;
+  if (g.items % 8 == 0) w = (w % 8) * (g.items / 8) + w / 8;
+  const int split = w / g.tiles;
+  int t = w - split * g.tiles, bi = 0;
+  while (t >= g.nt - bi) {
+    t -= g.nt - bi;
+    ++bi;
+  }
+  const int bj = bi + t;
+  const bool diag = bi == bj;
+  const int64_t ci0 = (int64_t)bi * kI8T, cj0 = (int64_t)bj * kI8T;
+  const int64_t rb = (int64_t)split * g.rows_per;
+  const int64_t re = min(g.n, rb + g.rows_per);
+  const int steps = re > rb ? (int)((re - rb + kI8Rows - 1) / kI8Rows) : 0;
+
+  // loader: column c of the block, rows 8q..8q+7 and 32+8q..32+8q+7 of a step
+  const int c = lane, q = wave;
+  const int64_t coli = ci0 + c, colj = cj0 + c;
+  const bool ini = coli < g.K, inj = colj < g.K;
+  const int ei = ini ? g.ex[coli] : 0, ej = inj ? g.ex[colj] : 0;
+  const int shi = ei == kI8NonFinite ? 0 : 6 - ei;
+  const int shj = ej == kI8NonFinite ? 0 : 6 - ej;
+  float xi[16], xj[16];
+  auto load = [&](int step) {
+    const int64_t r0 = rb + (int64_t)step * kI8Rows;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int64_t r = r0 + 32 * (u >> 3) + 8 * q + (u & 7);
+      xi[u] = (ini && r < re) ? g.X[r * g.sr + coli] : 0.0f;
+      if (!diag) xj[u] = (inj && r < re) ? g.X[r * g.sr + colj] : 0.0f;
+    }
+  };
+  // digits of 16 values into the planes of buffer b
+  auto convert = [&](const float *x, int sh, int b) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      float r[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) r[u] = ldexpf(x[8 * m + u], sh);
+      const int off = i8_off(c, 2 * m + (q >> 1)) + 8 * (q & 1);
+#pragma unroll
+      for (int a = 0; a < kI8Digits; ++a) {
+        const float M = 12582912.0f * __builtin_ldexpf(1.0f, -7 * a);  // 1.5 * 2^(23 - 7a)
+        unsigned bits[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const float tt = r[u] + M;  // r rounded to a multiple of 2^-7a, plus M
+          bits[u] = __float_as_uint(tt);
+          if (a + 1 < kI8Digits) r[u] -= tt - M;
+        }
+        const unsigned p01 = __builtin_amdgcn_perm(bits[1], bits[0], 0x0c0c0400u);
+        const unsigned p23 = __builtin_amdgcn_perm(bits[3], bits[2], 0x0c0c0400u);
+        const unsigned p45 = __builtin_amdgcn_perm(bits[5], bits[4], 0x0c0c0400u);
+        const unsigned p67 = __builtin_amdgcn_perm(bits[7], bits[6], 0x0c0c0400u);
+        uint2 v;
+        v.x = __builtin_amdgcn_perm(p23, p01, 0x05040100u);
+        v.y = __builtin_amdgcn_perm(p67, p45, 0x05040100u);
+        *reinterpret_cast<uint2 *>(&sl[b][a][off]) = v;
+      }
+    }
+  };
+
+  I4 acc[4][kI8Digits];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int d = 0; d < kI8Digits; ++d) acc[s][d] = I4{0, 0, 0, 0};
+
+  const int li = lane & 15, lg = lane >> 4;
+  const int jb = diag ? 0 : 1;
+  if (steps > 0) load(0);
+  for (int step = 0; step < steps; ++step) {
+    __syncthreads();  // the previous step's reads of the planes are done
+    convert(xi, shi, 0);
+    if (!diag) convert(xj, shj, 1);
+    __syncthreads();
+    if (step + 1 < steps) load(step + 1);
+    I4 av[kI8Digits];
+#pragma unroll
+    for (int a = 0; a < kI8Digits; ++a)
+      av[a] = *reinterpret_cast<const I4 *>(&sl[0][a][i8_off(16 * wave + li, lg)]);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int b = 0; b < kI8Digits; ++b) {
+        const I4 bv = *reinterpret_cast<const I4 *>(&sl[jb][b][i8_off(16 * s + li, lg)]);
+#pragma unroll
+        for (int a = 0; a + b < kI8Digits; ++a)
+          acc[s][a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(av[a], bv, acc[s][a + b], 0, 0, 0);
+      }
+  }
+
+  // D[4 lg + v][li] of subtile s: G[ci0 + 16 wave + 4 lg + v][cj0 + 16 s + li]
+  double *P = g.P + (int64_t)split * g.K * g.K;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t i = ci0 + 16 * wave + 4 * lg + v;
+    if (i >= g.K) continue;
+    const int eri = g.ex[i];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int64_t j = cj0 + 16 * s + li;
+      if (j >= g.K) continue;
+      const int erj = g.ex[j];
+      double val;
+      if (eri == kI8NonFinite || erj == kI8NonFinite) {
+        val = __builtin_nan("");
+      } else {
+        val = 0.0;
+#pragma unroll
+        for (int d = kI8Digits - 1; d >= 0; --d)
+          val += ldexp((double)acc[s][d][v], eri + erj - 12 - 7 * d);
+      }
+      P[i * g.K + j] = val;
+    }
+  }
+}
+
 }  // namespace
 
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
@@ -462,8 +661,63 @@ static int gram_impl(const TX *X, int64_t n, int64_t K, int64_t sr, int64_t sc, 
   return BSRHT_OK;
 }
 
+// Whether gram_f32 takes the int8 path (gram_i8_kernel): a tall X with unit
+// column stride; *s8 row splits (at most the caller's `splits`, whose
+// partials buffer they use, and enough for kI8MaxChunk rows each) and *cmb
+// column-max blocks.
+constexpr int64_t kI8MinRows = 16384;
+static bool gram_i8_shape(int64_t n, int64_t K, int64_t sr, int64_t sc, int splits, int *s8,
+                          int *cmb) {
+  if (sc != 1 || sr < K || n < kI8MinRows || K < 1 || K > 4096 || splits < 2) return false;
+  const int64_t nt = (K + kI8T - 1) / kI8T, tiles = nt * (nt + 1) / 2;
+  const int64_t need = (n + kI8MaxChunk - 1) / kI8MaxChunk;
+  // two rounds of two workgroups per CU
+  int64_t want = std::max<int64_t>(4 * (int64_t)device_cu_count() / tiles, need);
+  want = std::min<int64_t>({want, (int64_t)splits, (n + kI8Rows - 1) / kI8Rows});
+  if (want < need || tiles * want > INT_MAX) return false;
+  *s8 = (int)want;
+  *cmb = (int)std::min<int64_t>({1024, 2 * K - 1, n});
+  return true;
+}
+
+// G = X^T X through int8 digit planes.  The column exponents and the
+// column-max partials are kept in G itself (K + cmb*K <= 2 K^2 words) until
+// the reduction of the split partials overwrites it.
+static int gram_i8(const float *X, int64_t n, int64_t K, int64_t sr, double *G, int64_t ldg,
+                   double *partials, int s8, int cmb, hipStream_t s) {
+  int *ex = reinterpret_cast<int *>(G);
+  unsigned *part = reinterpret_cast<unsigned *>(G) + K;
+  const int64_t rows_cm = (n + cmb - 1) / cmb;
+  const int blocks = (int)((n + rows_cm - 1) / rows_cm);
+  colmax_partial_kernel<<<blocks, 256, 0, s>>>(X, n, K, sr, rows_cm, part);
+  BSRHT_LAUNCH_CHECK();
+  colexp_kernel<<<(unsigned)((K + 255) / 256), 256, 0, s>>>(part, blocks, K, ex);
+  BSRHT_LAUNCH_CHECK();
+  I8GramArgs a;
+  a.X = X;
+  a.n = n;
+  a.K = K;
+  a.sr = sr;
+  a.rows_per = ((n + s8 - 1) / s8 + kI8Rows - 1) / kI8Rows * kI8Rows;
+  a.ex = ex;
+  a.P = partials;
+  a.nt = (int)((K + kI8T - 1) / kI8T);
+  a.tiles = a.nt * (a.nt + 1) / 2;
+  a.items = a.tiles * s8;
+  gram_i8_kernel<<<a.items, 256, 0, s>>>(a);
+  BSRHT_LAUNCH_CHECK();
+  // the 64-wide tiles cover every element the 128-wide upper-tile reduction reads
+  reduce_partials_kernel<double><<<stride_grid(K * K, 256), 256, 0, s>>>(
+      partials, s8, K, K, G, ldg, true);
+  BSRHT_LAUNCH_CHECK();
+  return BSRHT_OK;
+}
+
 int gram_f32(const float *X, int64_t n, int64_t K, int64_t sr, int64_t sc, double *G,
              int64_t ldg, double *partials, int splits, hipStream_t s) {
+  int s8 = 0, cmb = 0;
+  if (gram_i8_shape(n, K, sr, sc, splits, &s8, &cmb))
+    return gram_i8(X, n, K, sr, G, ldg, partials, s8, cmb, s);
   return gram_impl<float>(X, n, K, sr, sc, G, ldg, partials, splits, s);
 }
 int gram_f64(const double *X, int64_t n, int64_t K, int64_t sr, int64_t sc, double *G,
