@@ -391,13 +391,23 @@ __global__ __launch_bounds__(256) void colmax_partial_kernel(const float *__rest
 }
 
 // ex[c]: the exponent e with max |X[.][c]| < 2^e (0 for a zero column,
-// kI8NonFinite for a column holding Inf or NaN).
-__global__ void colexp_kernel(const unsigned *__restrict__ part, int blocks, int64_t K,
-                              int *__restrict__ ex) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= K) return;
+// kI8NonFinite for a column holding Inf or NaN).  64 columns per workgroup,
+// the partials' blocks shared by 16 groups of 64 threads.
+__global__ __launch_bounds__(1024) void colexp_kernel(const unsigned *__restrict__ part,
+                                                      int blocks, int64_t K,
+                                                      int *__restrict__ ex) {
+  __shared__ unsigned red[16][64];
+  const int cl = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int64_t c = (int64_t)blockIdx.x * 64 + cl;
   unsigned m = 0;
-  for (int b = 0; b < blocks; ++b) m = max(m, part[(int64_t)b * K + c]);
+  if (c < K) {
+#pragma unroll 8
+    for (int b = grp; b < blocks; b += 16) m = max(m, part[(int64_t)b * K + c]);
+  }
+  red[grp][cl] = m;
+  __syncthreads();
+  if (grp != 0 || c >= K) return;
+  for (int r = 1; r < 16; ++r) m = max(m, red[r][cl]);
   int e = 0;
   if (m >= 0x7f800000u)
     e = kI8NonFinite;
@@ -418,10 +428,10 @@ struct I8GramArgs {
 };
 
 // Byte offset of the 16-row group g of column col in a digit plane: 64 bytes
-// per column, the groups XOR-swizzled by column so that the 16 lanes of a
-// 128-bit read hit distinct banks.
+// per column, the groups XOR-swizzled by column so that any 8 (and any 16)
+// consecutive lanes of a 128-bit read hit distinct banks.
 __device__ __forceinline__ int i8_off(int col, int g) {
-  return col * kI8Rows + 16 * (g ^ ((col >> 2) & 3));
+  return col * kI8Rows + 16 * (g ^ (((col >> 1) ^ (col >> 3)) & 3));
 }
 
 // One workgroup: a 64 x 64 tile of partial G over the rows of one split.
@@ -447,21 +457,29 @@ __global__ __launch_bounds__(256) void gram_i8_kernel(I8GramArgs g) {
   const int64_t re = min(g.n, rb + g.rows_per);
   const int steps = re > rb ? (int)((re - rb + kI8Rows - 1) / kI8Rows) : 0;
 
-  // loader: column c of the block, rows 8q..8q+7 and 32+8q..32+8q+7 of a step
+  // loader: column c of the block, rows 8q..8q+7 and 32+8q..32+8q+7 of a
+  // step.  A column past K reads column K-1 instead: it only reaches
+  // outputs past K, which are not stored.  Buffer loads over the split's
+  // rows: the descriptor's range check returns 0 for rows past its end.
   const int c = lane, q = wave;
-  const int64_t coli = ci0 + c, colj = cj0 + c;
-  const bool ini = coli < g.K, inj = colj < g.K;
-  const int ei = ini ? g.ex[coli] : 0, ej = inj ? g.ex[colj] : 0;
+  const int64_t coli = min(ci0 + c, g.K - 1), colj = min(cj0 + c, g.K - 1);
+  const int ei = g.ex[coli], ej = g.ex[colj];
   const int shi = ei == kI8NonFinite ? 0 : 6 - ei;
   const int shj = ej == kI8NonFinite ? 0 : 6 - ej;
+  const int sr4 = (int)g.sr * 4;
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float *>(g.X + rb * g.sr), 0, re > rb ? (int)((re - rb) * sr4) : 0,
+      0x00020000);
+  const int vi = 8 * q * sr4 + 4 * (int)coli, vj = 8 * q * sr4 + 4 * (int)colj;
   float xi[16], xj[16];
   auto load = [&](int step) {
-    const int64_t r0 = rb + (int64_t)step * kI8Rows;
+    const int so = step * kI8Rows * sr4;
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const int64_t r = r0 + 32 * (u >> 3) + 8 * q + (u & 7);
-      xi[u] = (ini && r < re) ? g.X[r * g.sr + coli] : 0.0f;
-      if (!diag) xj[u] = (inj && r < re) ? g.X[r * g.sr + colj] : 0.0f;
+      const int o = so + (32 * (u >> 3) + (u & 7)) * sr4;
+      // (on a diagonal tile xj repeats xi's column and is not converted)
+      xi[u] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vi + o, 0, 0));
+      xj[u] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vj + o, 0, 0));
     }
   };
   // digits of 16 values into the planes of buffer b
@@ -675,6 +693,9 @@ static bool gram_i8_shape(int64_t n, int64_t K, int64_t sr, int64_t sc, int spli
   int64_t want = std::max<int64_t>(4 * (int64_t)device_cu_count() / tiles, need);
   want = std::min<int64_t>({want, (int64_t)splits, (n + kI8Rows - 1) / kI8Rows});
   if (want < need || tiles * want > INT_MAX) return false;
+  // byte offsets within a split's rows are 32-bit
+  const int64_t rows_per = ((n + want - 1) / want + kI8Rows - 1) / kI8Rows * kI8Rows;
+  if (rows_per * sr * 4 > INT_MAX) return false;
   *s8 = (int)want;
   *cmb = (int)std::min<int64_t>({1024, 2 * K - 1, n});
   return true;
@@ -691,7 +712,7 @@ static int gram_i8(const float *X, int64_t n, int64_t K, int64_t sr, double *G, 
   const int blocks = (int)((n + rows_cm - 1) / rows_cm);
   colmax_partial_kernel<<<blocks, 256, 0, s>>>(X, n, K, sr, rows_cm, part);
   BSRHT_LAUNCH_CHECK();
-  colexp_kernel<<<(unsigned)((K + 255) / 256), 256, 0, s>>>(part, blocks, K, ex);
+  colexp_kernel<<<(unsigned)((K + 63) / 64), 1024, 0, s>>>(part, blocks, K, ex);
   BSRHT_LAUNCH_CHECK();
   I8GramArgs a;
   a.X = X;
