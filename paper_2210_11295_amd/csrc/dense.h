@@ -50,7 +50,9 @@ bool gemm_bf16x_eligible(const float *A, int64_t lda);
 
 // G = X^T X (K x K FP64) for X[r][c] = X[r*sr + c*sc], r < n, c < K; the row
 // range is split into `splits` FP64 partials (K*K each, in `partials`)
-// summed in split order.
+// summed in split order.  gram_f32 of a tall X (n >= 16384, sc == 1) runs on
+// the int8 matrix cores with exact digit products (FP64-level accuracy, at
+// most `splits` partials) and uses G itself as scratch before writing it.
 int gram_f32(const float *X, int64_t n, int64_t K, int64_t sr, int64_t sc, double *G,
              int64_t ldg, double *partials, int splits, hipStream_t s);
 int gram_f64(const double *X, int64_t n, int64_t K, int64_t sr, int64_t sc, double *G,

@@ -34,6 +34,7 @@ def _rsvd_case(n, m, p, l, k, A, seed, mode=0, precision=bs.FP32):
     (8192, 100, 8, 64, 20),     # ragged m
     (4096, 300, 16, 37, 11),    # odd l
     (2048, 64, 4, 128, 16),     # l >= m: Q = I
+    (20000, 300, 16, 100, 30),  # Gram of Z on the int8 digit path: ragged rows and columns
 ])
 def test_rsvd_matches_oracle(n, m, p, l, k):
     dev = device()

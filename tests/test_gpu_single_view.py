@@ -51,6 +51,7 @@ SV_CASES = [
     (8192, 512, 128, 256, 50, (2, 8), (16, 1)),     # chunk widths 256 and 512 in the row sketches
     (2048, 512, 70, 150, 25, (2, 4), (4, 2)),       # bases with a padded leading dimension
     (3000, 600, 64, 128, 20, (1, 3), (3, 1)),       # partial SRHTs: r = 600 and 1000 -> 1024
+    (20000, 300, 72, 144, 25, (3, 16), (16, 3)),    # Gram of Y on the int8 digit path, ragged
 ]
 
 
