@@ -457,10 +457,11 @@ __global__ __launch_bounds__(256) void gram_i8_kernel(I8GramArgs g) {
   const int64_t re = min(g.n, rb + g.rows_per);
   const int steps = re > rb ? (int)((re - rb + kI8Rows - 1) / kI8Rows) : 0;
 
-  // loader: column c of the block, rows 8q..8q+7 and 32+8q..32+8q+7 of a
-  // step.  A column past K reads column K-1 instead: it only reaches
-  // outputs past K, which are not stored.  Buffer loads over the split's
-  // rows: the descriptor's range check returns 0 for rows past its end.
+  // loader: column c of the block, rows 16q..16q+15 of a step (one 16-row
+  // group of the digit planes, written with one 128-bit store per digit).
+  // A column past K reads column K-1 instead: it only reaches outputs past
+  // K, which are not stored.  Buffer loads over the split's rows: the
+  // descriptor's range check returns 0 for rows past its end.
   const int c = lane, q = wave;
   const int64_t coli = min(ci0 + c, g.K - 1), colj = min(cj0 + c, g.K - 1);
   const int ei = g.ex[coli], ej = g.ex[colj];
@@ -470,45 +471,43 @@ __global__ __launch_bounds__(256) void gram_i8_kernel(I8GramArgs g) {
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float *>(g.X + rb * g.sr), 0, re > rb ? (int)((re - rb) * sr4) : 0,
       0x00020000);
-  const int vi = 8 * q * sr4 + 4 * (int)coli, vj = 8 * q * sr4 + 4 * (int)colj;
+  const int vi = 16 * q * sr4 + 4 * (int)coli, vj = 16 * q * sr4 + 4 * (int)colj;
   float xi[16], xj[16];
   auto load = [&](int step) {
     const int so = step * kI8Rows * sr4;
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const int o = so + (32 * (u >> 3) + (u & 7)) * sr4;
+      const int o = so + u * sr4;
       // (on a diagonal tile xj repeats xi's column and is not converted)
       xi[u] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vi + o, 0, 0));
       xj[u] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vj + o, 0, 0));
     }
   };
-  // digits of 16 values into the planes of buffer b
+  // digits of 16 values (rows 16q..16q+15 of column c) into the planes of
+  // buffer b
   auto convert = [&](const float *x, int sh, int b) {
+    float r[16];
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      float r[8];
+    for (int u = 0; u < 16; ++u) r[u] = ldexpf(x[u], sh);
+    const int off = i8_off(c, q);
 #pragma unroll
-      for (int u = 0; u < 8; ++u) r[u] = ldexpf(x[8 * m + u], sh);
-      const int off = i8_off(c, 2 * m + (q >> 1)) + 8 * (q & 1);
+    for (int a = 0; a < kI8Digits; ++a) {
+      const float M = 12582912.0f * __builtin_ldexpf(1.0f, -7 * a);  // 1.5 * 2^(23 - 7a)
+      unsigned w[4];
 #pragma unroll
-      for (int a = 0; a < kI8Digits; ++a) {
-        const float M = 12582912.0f * __builtin_ldexpf(1.0f, -7 * a);  // 1.5 * 2^(23 - 7a)
-        unsigned bits[8];
+      for (int h = 0; h < 4; ++h) {
+        unsigned bits[4];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const float tt = r[u] + M;  // r rounded to a multiple of 2^-7a, plus M
+        for (int u = 0; u < 4; ++u) {
+          const float tt = r[4 * h + u] + M;  // r rounded to a multiple of 2^-7a, plus M
           bits[u] = __float_as_uint(tt);
-          if (a + 1 < kI8Digits) r[u] -= tt - M;
+          if (a + 1 < kI8Digits) r[4 * h + u] -= tt - M;
         }
         const unsigned p01 = __builtin_amdgcn_perm(bits[1], bits[0], 0x0c0c0400u);
         const unsigned p23 = __builtin_amdgcn_perm(bits[3], bits[2], 0x0c0c0400u);
-        const unsigned p45 = __builtin_amdgcn_perm(bits[5], bits[4], 0x0c0c0400u);
-        const unsigned p67 = __builtin_amdgcn_perm(bits[7], bits[6], 0x0c0c0400u);
-        uint2 v;
-        v.x = __builtin_amdgcn_perm(p23, p01, 0x05040100u);
-        v.y = __builtin_amdgcn_perm(p67, p45, 0x05040100u);
-        *reinterpret_cast<uint2 *>(&sl[b][a][off]) = v;
+        w[h] = __builtin_amdgcn_perm(p23, p01, 0x05040100u);
       }
+      *reinterpret_cast<uint4 *>(&sl[b][a][off]) = uint4{w[0], w[1], w[2], w[3]};
     }
   };
 
