@@ -56,6 +56,7 @@ def test_rsvd_matches_oracle(n, m, p, l, k):
     (8192, 1500, 2, 1100, 50),    # SVD of R on 1120 columns: streamed 32-column pairs
     (8192, 2600, 1, 2200, 40),    # 2208 columns: streamed 32-column pairs
     (4096, 900, 4, 700, 30),      # 704 columns: 16-column pairs staged in LDS
+    (16400, 900, 4, 700, 30),     # and the int8 Gram of Z over 700 columns (66 tiles)
 ])
 def test_rsvd_large_sketch_sizes(n, m, p, l, k):
     """Sketch sizes that take both forms of the Jacobi SVD's block step."""
