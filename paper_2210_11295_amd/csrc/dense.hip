@@ -581,10 +581,11 @@ static bool gemm_big_eligible(const GemmDesc &d, const TA *A, const TB *B) {
 }
 
 template <typename TA, typename TB, typename TC, bool F64>
-static int gemm_launch(const GemmDesc &d, const TA *A, const TB *B, TC *C, hipStream_t s) {
+static int gemm_launch(const GemmDesc &d, const TA *A, const TB *B, TC *C, hipStream_t s,
+                       bool small_tiles = false) {
   if (d.M <= 0 || d.N <= 0) return BSRHT_OK;
   const bool a_k = d.sak == 1 && d.sai % 4 == 0;
-  if (gemm_big_eligible(d, A, B)) {
+  if (!small_tiles && gemm_big_eligible(d, A, B)) {
     dim3 grid((unsigned)((d.M + kBM - 1) / kBM), (unsigned)((d.N + kBN - 1) / kBN),
               (unsigned)d.splits);
     if (a_k)
@@ -1761,7 +1762,9 @@ int cholesky_upper(double *G, int64_t n, int64_t ldg, double tol, int32_t *info,
     d.beta = 1.0;
     const double *C12 = G + kb * ldg + kb + nb;
     double *G22 = G + (kb + nb) * ldg + kb + nb;
-    int rc = gemm_launch<double, double, double, true>(d, C12, C12, G22, s);
+    // a rank-nb update of at most a few thousand rows: the 64 x 64 tiles
+    // give four times the workgroups of the large tiles
+    int rc = gemm_launch<double, double, double, true>(d, C12, C12, G22, s, true);
     if (rc != BSRHT_OK) return rc;
   }
   chol_finish_kernel<<<(unsigned)((n * n + 255) / 256), 256, 0, s>>>(G, n, ldg, st);
