@@ -357,7 +357,7 @@ __global__ void mirror_tiles_kernel(double *__restrict__ C, int64_t n, int64_t l
 // Column c of X is scaled by 2^-e_c (|x| < 2^e_c over the column) and written
 // in seven signed base-128 digits by round-to-nearest,
 //   x = 2^(e_c - 6) * sum_{a<7} d_a 2^(-7a) + rem,  |d_a| <= 64,
-//   |rem| <= 2^(e_c - 50),
+//   |rem| <= 2^(e_c - 49) (half the last digit's unit),
 // so x_i x_j = 2^(e_i + e_j - 12) sum_{a,b} d_a d'_b 2^(-7(a+b)).  The digit
 // products are exact in int32 (v_mfma_i32_16x16x64_i8); the 28 pairs with
 // a + b <= 6 are accumulated per level a + b and the levels combined in FP64
